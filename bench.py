@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark: block-updates/s of the multiresolution step on one MI355X.
+
+Workload: the 2D swirl set-up (three seeded Gaussian blobs, beta = 0.01, Bs = 33,
+Jmax = 7, eps = 1e-4, dt = 2^-13, 500 steps).  A step is the whole hot path:
+refine all blocks (safety zone), one RK4 step with ghost synchronisation on the
+refined grid, and multiresolution analysis + coarsening until nothing merges.
+value = sum over timed steps of the refined block count |G~| / wall time.
+
+Forms timed: FP64 plain (stored ghosts, per-level launches), FP64 fused and
+mixed fused (FP32 stencil and slopes, FP64 state).  The headline value is the
+mixed fused form.  Per-kernel device times come from HIP events on the solver's
+stream in a second, instrumented pass over the same steps.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "block-updates/s (RK4 step, all blocks) FP64 vs mixed; % HBM roofline"
+
+
+def run_form(M, W, torch, cfg, steps, warmup):
+    s = M.Solver(cfg)
+    s.init_grid()
+    lv0, co0 = s.read_forest()
+    data0 = s.read_blocks()
+    t = 0.0
+    for _ in range(warmup):
+        s.step(t, cfg.dt)
+        t += cfg.dt
+
+    def reset():
+        s.init_forest(lv0, co0)
+        s.load_blocks(data0)
+        torch.cuda.synchronize()
+
+    # timed pass (no per-kernel instrumentation)
+    reset()
+    b0 = s.stats()["block_updates"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(0.0, cfg.dt, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = s.stats()
+    bu = st["block_updates"] - b0
+    wall = t1 - t0
+    final_blocks = st["blocks"]
+    # instrumented pass: per-kernel device time from HIP events
+    reset()
+    s.timing(True)
+    s.step(0.0, cfg.dt, steps)
+    kst = s.stats()["kernels"]
+    s.timing(False)
+    s.close()
+    sweep_ms = sum(kst[k]["ms"] for k in ("stage", "ghost", "rhs_plain"))
+    return {
+        "value": bu / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "block_updates": bu,
+        "blocks_initial": int(len(lv0)),
+        "blocks_final": final_blocks,
+        "sweep_block_updates_per_s": bu / (sweep_ms * 1e-3) if sweep_ms > 0 else None,
+        "kernels": kst,
+    }
+
+
+def cpu_baseline(W, cfg, budget_s):
+    import oracle
+    o = oracle.Oracle(cfg)
+    o.init_grid()
+    t = 0.0
+    nbu = 0
+    nsteps = 0
+    elapsed = 0.0
+    while elapsed < budget_s or nsteps < 3:
+        t0 = time.perf_counter()
+        o.refine_all()
+        nbu += o.num_blocks()
+        o.rk4(t, cfg.dt)
+        o.adapt()
+        elapsed += time.perf_counter() - t0
+        t += cfg.dt
+        nsteps += 1
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": nbu / elapsed, "unit": "block-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {nsteps} steps of the same workload from the same initial grid "
+                      f"({nbu} block-updates in {elapsed:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--forms", default="fp64_plain,fp64_fused,mixed_fused")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the multi-GPU path (sharding the block forest along the "
+              f"space-filling curve) is not built, so --gpus {args.gpus} is not supported.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_1902_00088_amd as M
+
+    base = W.C2()
+    forms = {"fp64_plain": (W.FP64, W.FORM_PLAIN), "fp64_fused": (W.FP64, W.FORM_FUSED),
+             "mixed_fused": (W.MIXED, W.FORM_FUSED)}
+    res = {}
+    for name in args.forms.split(","):
+        prec, form = forms[name]
+        print(f"bench: {name} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+        res[name] = run_form(M, W, torch, base.replace(precision=prec, form=form), args.steps, args.warmup)
+    head = res.get("mixed_fused") or next(iter(res.values()))
+    head_name = "mixed_fused" if "mixed_fused" in res else next(iter(res))
+    ks = head["kernels"]
+    dom = max(ks, key=lambda k: ks[k]["ms"])
+    ach = ks[dom]["bytes"] / (ks[dom]["ms"] * 1e-3) / 1e9 if ks[dom]["ms"] > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
+                "launches": ks[dom]["launches"], "avg_launch_us": 1e3 * ks[dom]["ms"] / max(1, ks[dom]["launches"])}
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "block-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-stencil/f64-state" if head_name.startswith("mixed") else "f64",
+        "data": "synthetic",
+        "config": {"workload": "C2 2D swirl advection: 3 seeded Gaussian blobs (beta=0.01), Bs=33, Jmax=7, "
+                               "eps=1e-4, dt=2^-13, 500 steps", "form": head_name,
+                   "blocks_initial": head["blocks_initial"], "parallelism": "single GPU"},
+        "roofline": roofline,
+        "forms": res,
+    }
+    if "fp64_plain" in res and "mixed_fused" in res:
+        out["speedup_mixed_fused_vs_fp64_plain"] = res["mixed_fused"]["value"] / res["fp64_plain"]["value"]
+    if not args.no_cpu:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(W, base, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

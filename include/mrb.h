@@ -1,0 +1,150 @@
+/*
+ * mrb.h -- C ABI of the MI355X block-multiresolution solver (arXiv 1902.00088).
+ *
+ * The library advances an evolutionary PDE  d(phi)/dt = N(phi)  (Sec. 2, first
+ * paragraph) on a graded, periodic quad/octree forest of blocks (Sec. 2.2),
+ * following the multiresolution step of Sec. 2.1: refine every block by one
+ * level (safety zone), synchronise ghost nodes and evolve with 4th-order central
+ * finite differences and classic RK4 (Sec. 3, Sec. 4), then coarsen blocks whose
+ * details fall below eps (Sec. 2.3).
+ *
+ * Conventions shared by every entry point
+ *  - Blocks.  A block at level l (1 = coarsest .. jmax) with integer coordinates
+ *    c in [0, 2^l)^dim covers the level-l node indices c*(bs-1) + i, i = 0..bs-1,
+ *    of a periodic unit domain with N_l = 2^l*(bs-1) unique nodes per direction
+ *    (block definition, Sec. 2.2; the printed index range "0..B_s" is read as
+ *    0..B_s-1).  Node data of one block is [field][k][j][i], i fastest.
+ *  - Forest order.  Every array that lists blocks ("forest order") is sorted by
+ *    the Morton key of (coords << (jmax - level)) with x as the least significant
+ *    bit (the space-filling-curve order of Sec. 2.5).  It does not depend on
+ *    pool slots.
+ *  - Ownership.  The caller owns every buffer passed in: the device pool arrays
+ *    given to mrb_create and all host or device arrays of later calls.  The
+ *    library never frees them.  It allocates only its own descriptor, staging
+ *    and scratch memory, released by mrb_destroy.
+ *  - Errors.  Every call returns an mrb_status; none aborts or throws across the
+ *    ABI.  On error the solver state is unchanged (capacity and topology are
+ *    checked before any device write) and mrb_last_error() describes the cause.
+ *  - Streams.  All device work is enqueued on the HIP stream given to mrb_create.
+ *    Calls that return host data (mrb_num_blocks, mrb_read_*, mrb_get_flags,
+ *    mrb_mr_pass, mrb_adapt, mrb_step) synchronise that stream before returning.
+ *  - A context is not thread safe; use one per host thread.
+ */
+#ifndef MRB_H_
+#define MRB_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mrb_ctx mrb_ctx;
+
+typedef enum {
+  MRB_OK = 0,
+  MRB_E_ARG = -1,        /* invalid argument or unsupported configuration            */
+  MRB_E_CAPACITY = -2,   /* pool (max_blocks) too small for the requested topology   */
+  MRB_E_TOPOLOGY = -3,   /* forest does not tile the domain, overlaps or is not graded */
+  MRB_E_STATE = -4,      /* call out of order (e.g. step before init_forest)         */
+  MRB_E_DEVICE = -5,     /* a HIP runtime call failed                                */
+  MRB_E_NONFINITE = -6   /* a detail norm was NaN or Inf                              */
+} mrb_status;
+
+/* physics: right-hand side N(phi) */
+enum {
+  MRB_ADV_CONST = 0,  /* -c.grad(phi), phys[0..2] = c                                   (Sec. 3 eq. form) */
+  MRB_ADV_SWIRL = 1,  /* -u(x,y,t).grad(phi), the swirl field of Sec. 3; phys[0] = t_a (0 = steady)      */
+  MRB_NS2D = 2        /* compressible Navier-Stokes, fields rho,u,v,p; phys = {gamma, mu, Pr}  (Sec. 4) */
+};
+enum { MRB_FP64 = 0, MRB_MIXED = 1 };          /* MIXED: FP32 stencil + FP32 slopes, FP64 state     */
+enum { MRB_FORM_PLAIN = 0, MRB_FORM_FUSED = 1 };/* PLAIN: stored ghosts, per-level launches           */
+
+typedef struct {
+  int dim;             /* 2 or 3                                                            */
+  int bs;              /* points per block and direction: 17 or 33 in 2D, 17 in 3D          */
+  int hw;              /* ghost width of the RHS stencil: 2 (advection) or 4 (NS)            */
+  int nfields;         /* 1 (advection) or 4 (NS)                                            */
+  int jmax;            /* finest level, 2..12                                                */
+  int max_blocks;      /* pool capacity in blocks (N_max of Sec. 2.4)                         */
+  double eps;          /* detail threshold (Sec. 2.3)                                        */
+  int physics;         /* MRB_ADV_CONST / MRB_ADV_SWIRL / MRB_NS2D                           */
+  double phys[8];      /* see physics                                                        */
+  const double *swirl_s2;   /* host, 2^jmax*(bs-1) values sin^2(pi x_i), x_i = i/N_jmax (swirl only; copied) */
+  const double *swirl_s;    /* host, same length, sin(2 pi x_i)                                               */
+  const double *field_scale;  /* host, nfields values or NULL: field f coarsens if max|d_f| < eps*scale[f] */
+  const double *field_offset; /* host, nfields values or NULL: MIXED stages work on (y - offset[f]) in FP32 */
+  int precision;       /* MRB_FP64 or MRB_MIXED                                              */
+  int form;            /* MRB_FORM_PLAIN or MRB_FORM_FUSED                                    */
+} mrb_config;
+
+/* Create a solver.  u, u_new: device double arrays of max_blocks*nfields*bs^dim
+ * elements; k1..k3: device arrays of the same element count, double (FP64) or
+ * float (MIXED).  stream: a hipStream_t (NULL = default stream).  The arrays
+ * must stay valid until mrb_destroy.  Sec. 2.4 (heavy data preallocated to N_max). */
+mrb_status mrb_create(const mrb_config *cfg, double *u, double *u_new, void *k1, void *k2, void *k3,
+                      void *stream, mrb_ctx **out);
+mrb_status mrb_destroy(mrb_ctx *ctx);
+const char *mrb_last_error(const mrb_ctx *ctx);
+
+/* Set the forest: n blocks, host arrays level[n], coords[n*dim] (any order).
+ * Rejects forests that overlap, leave holes or are not graded (Sec. 2.2, graded
+ * grid: touching blocks differ by at most one level, diagonals included).
+ * Block data is undefined until mrb_load_blocks. */
+mrb_status mrb_init_forest(mrb_ctx *ctx, int n, const int8_t *level, const int32_t *coords);
+
+/* Copy block data [n][nfields][bs^dim] in forest order into the pool.  data is
+ * host memory (on_device = 0) or device memory (on_device = 1).  Nodes shared by
+ * blocks of the same level must hold equal values (Sec. 2.5). */
+mrb_status mrb_load_blocks(mrb_ctx *ctx, const double *data, int on_device);
+
+/* Safety zone (Sec. 2.1 item 1): every block below jmax becomes its 2^dim
+ * children, whose nodes take the synchronised value at the finer level
+ * (prediction P of Sec. 2.3 where the finer node is new). */
+mrb_status mrb_refine_all(mrb_ctx *ctx);
+
+/* One classic RK4 step of size dt from time t on the current grid (Sec. 2.1 item
+ * 2): each stage synchronises ghost nodes (same-level copy, injection from finer
+ * blocks, prediction from coarser ones) and evaluates the 4th-order FD RHS. */
+mrb_status mrb_rk4(mrb_ctx *ctx, double t, double dt);
+
+/* One multiresolution analysis (Sec. 2.3): synchronise the stored state, compute
+ * details D = B - P(R(B)), and set flag -1 where max|d_f| < eps*scale[f] for every
+ * field (0 otherwise, and always 0 at level 1).  flags[n] (int8) and maxd[n*nfields]
+ * (double, may be NULL) receive the result in forest order (host arrays). */
+mrb_status mrb_mr_pass(mrb_ctx *ctx, int8_t *flags, double *maxd);
+
+/* Coarsen with the given flags (host, forest order): families of 2^dim sister
+ * blocks all flagged -1 merge into their mother when the result stays graded
+ * (completeness + gradedness, Sec. 2.3 last paragraph; the largest such set).
+ * The mother keeps every second node (restriction R).  *n_coarsened (may be
+ * NULL) receives the number of merged families. */
+mrb_status mrb_coarsen(mrb_ctx *ctx, const int8_t *flags, int *n_coarsened);
+
+/* Repeat {mrb_mr_pass; mrb_coarsen} until no family merges (Sec. 2.1 item 3).
+ * *n_passes (may be NULL) receives the number of analyses. */
+mrb_status mrb_adapt(mrb_ctx *ctx, int *n_passes);
+
+/* nsteps multiresolution time steps: {refine_all; rk4(t, dt); adapt}, t advancing by dt. */
+mrb_status mrb_step(mrb_ctx *ctx, double t0, double dt, int nsteps);
+
+mrb_status mrb_num_blocks(mrb_ctx *ctx, int *n);
+/* Forest in forest order: level[n], coords[n*dim] (host). */
+mrb_status mrb_read_forest(mrb_ctx *ctx, int8_t *level, int32_t *coords);
+/* Synchronised block values [n][nfields][bs^dim] in forest order (redundant nodes
+ * carry the owner's value).  out is host (on_device = 0) or device memory. */
+mrb_status mrb_read_blocks(mrb_ctx *ctx, double *out, int on_device);
+/* Last analysis: flags[n], maxd[n*nfields] in forest order (host; maxd may be NULL). */
+mrb_status mrb_get_flags(mrb_ctx *ctx, int8_t *flags, double *maxd);
+/* Counters and timings as one JSON object (NUL-terminated, at most cap bytes).
+ * Synchronises the stream when kernel timing is on. */
+mrb_status mrb_stats(mrb_ctx *ctx, char *json, int cap);
+/* Kernel timing: when enable != 0, every sweep-kernel launch is bracketed by HIP
+ * events on the solver's stream and mrb_stats reports the accumulated device
+ * time and algorithmic bytes per kernel kind; enable = 0 stops and clears. */
+mrb_status mrb_timing(mrb_ctx *ctx, int enable);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRB_H_ */

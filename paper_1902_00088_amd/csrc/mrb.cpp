@@ -1,0 +1,967 @@
+// Host side of the MI355X block-multiresolution solver: forest manager (keys,
+// Morton order, neighbour relations, validation), plans for refinement and
+// coarsening (completeness + gradedness fixed point), descriptor upload and the
+// C ABI declared in include/mrb.h.
+#include "../../include/mrb.h"
+#include "internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+using namespace mrb;
+
+namespace {
+
+struct Leaf {
+  int level;
+  int c[3];
+  int slot;
+  uint64_t morton;
+};
+
+inline uint64_t pack_key(int l, const int* c) {
+  return ((uint64_t)l << 60) | (uint64_t)(uint32_t)c[0] | ((uint64_t)(uint32_t)c[1] << 20) |
+         ((uint64_t)(uint32_t)c[2] << 40);
+}
+
+inline int wrapi(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// Pinned host staging buffer; an event guards reuse while a copy is in flight.
+struct Staging {
+  void* h = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+
+}  // namespace
+
+struct mrb_ctx {
+  mrb_config cfg;
+  Shape shape;
+  int np = 0;
+  size_t bsz = 0;  // nf * np
+  hipStream_t stream = nullptr;
+  double* u = nullptr;
+  double* unew = nullptr;
+  void* k[3] = {nullptr, nullptr, nullptr};
+  std::vector<double> thr, off;
+
+  std::vector<Leaf> leaves;                  // forest order
+  std::unordered_map<uint64_t, int> index;   // key -> position in leaves
+  std::vector<int> free_slots;
+  bool have_forest = false, have_data = false;
+
+  std::vector<BlockDesc> hblk;
+  std::vector<NbEntry> hnb;
+  std::vector<int> hlist, level_off;         // blocks grouped by level (plain form)
+  int max_entries = 0;
+
+  BlockDesc* dblk = nullptr;
+  NbEntry* dnb = nullptr;
+  int* dcount = nullptr;
+  int* dlist = nullptr;
+  RefineDesc* dref = nullptr;
+  FamilyDesc* dfam = nullptr;
+  int8_t* dflags = nullptr;
+  double* dmaxd = nullptr;
+  double* ds2 = nullptr;
+  double* ds = nullptr;
+  double* dghost = nullptr;
+  double* dscratch = nullptr;
+  size_t scratch_cap = 0;
+  int* dslots = nullptr;
+
+  Staging st_blk, st_nb, st_cnt, st_ref, st_fam, st_list, st_slots, st_data;
+  int8_t* h_flags = nullptr;   // pinned
+  double* h_maxd = nullptr;    // pinned
+  int hcount[4] = {0, 0, 0, 0};
+
+  LevelTab lt;
+  Physics ph;
+  int grid = 2048;
+
+  std::vector<int8_t> last_flags;
+  std::vector<double> last_maxd;
+  bool have_flags = false;
+
+  // statistics
+  long n_steps = 0, n_rk4 = 0, n_block_updates = 0, n_mr = 0, n_fam = 0, n_refined = 0;
+  // kernel timing: event pairs per kernel kind, resolved in mrb_stats
+  bool timing = false;
+  struct Timed { int kind; hipEvent_t a, b; double bytes; };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> ev_pool;
+  double t_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double t_bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long t_launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  std::string err;
+};
+
+namespace {
+
+mrb_status fail(mrb_ctx* c, mrb_status s, const std::string& m) {
+  c->err = m;
+  return s;
+}
+
+// kernel kinds for timing
+enum { T_STAGE = 0, T_GHOST = 1, T_RHS_PLAIN = 2, T_MR = 3, T_REFINE = 4, T_COARSEN = 5, T_READ = 6, T_NKIND = 7 };
+const char* kKindName[T_NKIND] = {"stage", "ghost", "rhs_plain", "mr", "refine", "coarsen", "read"};
+
+hipEvent_t take_event(mrb_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Bracket one launch with events when timing is on; `bytes` are the algorithmic
+// bytes the launch moves.
+struct TimeScope {
+  mrb_ctx* c;
+  int kind;
+  double bytes;
+  hipEvent_t a = nullptr;
+  TimeScope(mrb_ctx* c_, int k, double b) : c(c_), kind(k), bytes(b) {
+    if (c->timing && (a = take_event(c))) (void)hipEventRecord(a, c->stream);
+  }
+  ~TimeScope() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) { c->ev_pool.push_back(a); return; }
+    (void)hipEventRecord(b, c->stream);
+    c->timed.push_back(mrb_ctx::Timed{kind, a, b, bytes});
+  }
+};
+
+void resolve_timing(mrb_ctx* c) {
+  if (c->timed.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& t : c->timed) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      c->t_ms[t.kind] += ms;
+      c->t_bytes[t.kind] += t.bytes;
+      c->t_launches[t.kind]++;
+    }
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->timed.clear();
+}
+
+#define HIPCHK(ctx, call)                                                                          \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return fail(ctx, MRB_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+uint64_t morton_of(const mrb_ctx* c, int l, const int* co) {
+  uint64_t key = 0;
+  const int d = c->cfg.dim, sh = c->cfg.jmax - l;
+  for (int bit = 0; bit < 21; ++bit)
+    for (int a = 0; a < d; ++a) {
+      uint64_t v = (uint64_t)co[a] << sh;
+      key |= ((v >> bit) & 1ULL) << (bit * d + a);
+    }
+  return key;
+}
+
+mrb_status stage_upload(mrb_ctx* c, Staging& s, const void* src, size_t bytes, void* dst) {
+  if (bytes == 0) return MRB_OK;
+  if (s.pending) {
+    HIPCHK(c, hipEventSynchronize(s.ev));
+    s.pending = false;
+  }
+  if (!s.ev) HIPCHK(c, hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+  if (bytes > s.cap) {
+    if (s.h) HIPCHK(c, hipHostFree(s.h));
+    s.h = nullptr;
+    size_t cap = std::max(bytes, (size_t)4096);
+    HIPCHK(c, hipHostMalloc(&s.h, cap, hipHostMallocDefault));
+    s.cap = cap;
+  }
+  std::memcpy(s.h, src, bytes);
+  HIPCHK(c, hipMemcpyAsync(dst, s.h, bytes, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipEventRecord(s.ev, c->stream));
+  s.pending = true;
+  return MRB_OK;
+}
+
+void release_staging(Staging& s) {
+  if (s.pending) (void)hipEventSynchronize(s.ev);
+  if (s.h) (void)hipHostFree(s.h);
+  if (s.ev) (void)hipEventDestroy(s.ev);
+  s = Staging();
+}
+
+void sort_and_index(mrb_ctx* c) {
+  for (auto& L : c->leaves) L.morton = morton_of(c, L.level, L.c);
+  std::sort(c->leaves.begin(), c->leaves.end(), [](const Leaf& a, const Leaf& b) { return a.morton < b.morton; });
+  c->index.clear();
+  c->index.reserve(c->leaves.size() * 2);
+  for (size_t i = 0; i < c->leaves.size(); ++i) c->index[pack_key(c->leaves[i].level, c->leaves[i].c)] = (int)i;
+}
+
+const Leaf* find_leaf(const mrb_ctx* c, int l, const int* co) {
+  if (l < 1 || l > c->cfg.jmax) return nullptr;
+  int w[3] = {0, 0, 0};
+  for (int a = 0; a < c->cfg.dim; ++a) w[a] = wrapi(co[a], 1 << l);
+  auto it = c->index.find(pack_key(l, w));
+  return it == c->index.end() ? nullptr : &c->leaves[it->second];
+}
+
+// Neighbour entries of every leaf; fails with MRB_E_TOPOLOGY if the forest is not graded.
+mrb_status build_descriptors(mrb_ctx* c) {
+  const int d = c->cfg.dim, bs = c->cfg.bs, jmax = c->cfg.jmax;
+  const int n = (int)c->leaves.size();
+  std::vector<BlockDesc> hblk(n);
+  std::vector<NbEntry> hnb;
+  hnb.reserve((size_t)n * (d == 2 ? 13 : 57));
+  std::vector<NbEntry> co, sa, fi;
+  for (int i = 0; i < n; ++i) {
+    const Leaf& L = c->leaves[i];
+    co.clear();
+    sa.clear();
+    fi.clear();
+    sa.push_back(NbEntry{L.slot, 0, {0, 0, 0}});
+    auto add = [](std::vector<NbEntry>& v, const NbEntry& e) {
+      for (auto& x : v)
+        if (x.slot == e.slot && x.o[0] == e.o[0] && x.o[1] == e.o[1] && x.o[2] == e.o[2]) return;
+      v.push_back(e);
+    };
+    const int nd = d == 2 ? 9 : 27;
+    for (int q = 0; q < nd; ++q) {
+      int dlt[3] = {q % 3 - 1, (q / 3) % 3 - 1, d > 2 ? q / 9 - 1 : 0};
+      if (dlt[0] == 0 && dlt[1] == 0 && dlt[2] == 0) continue;
+      int cn[3] = {0, 0, 0};
+      for (int a = 0; a < d; ++a) cn[a] = L.c[a] + dlt[a];
+      if (const Leaf* s = find_leaf(c, L.level, cn)) {
+        NbEntry e{s->slot, 0, {0, 0, 0}};
+        for (int a = 0; a < d; ++a) e.o[a] = dlt[a] * (bs - 1);
+        add(sa, e);
+        continue;
+      }
+      int pc[3] = {0, 0, 0};
+      for (int a = 0; a < d; ++a) pc[a] = cn[a] >> 1;  // floor division
+      if (L.level > 1) {
+        if (const Leaf* s = find_leaf(c, L.level - 1, pc)) {
+          NbEntry e{s->slot, -1, {0, 0, 0}};
+          for (int a = 0; a < d; ++a) e.o[a] = (2 * pc[a] - L.c[a]) * (bs - 1);
+          add(co, e);
+          continue;
+        }
+      }
+      if (L.level >= jmax)
+        return fail(c, MRB_E_TOPOLOGY, "forest is not graded or leaves a hole next to a level-jmax block");
+      // the region is split: its children touching this block must all be leaves
+      int nb = 1 << d;
+      for (int b = 0; b < nb; ++b) {
+        int beta[3] = {0, 0, 0};
+        bool ok = true;
+        for (int a = 0; a < d; ++a) {
+          beta[a] = (b >> a) & 1;
+          if (dlt[a] == 1 && beta[a] != 0) ok = false;
+          if (dlt[a] == -1 && beta[a] != 1) ok = false;
+        }
+        if (!ok) continue;
+        int ch[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) ch[a] = 2 * wrapi(cn[a], 1 << L.level) + beta[a];
+        const Leaf* s = find_leaf(c, L.level + 1, ch);
+        if (!s) return fail(c, MRB_E_TOPOLOGY, "forest is not graded (a neighbour differs by two or more levels)");
+        NbEntry e{s->slot, 1, {0, 0, 0}};
+        for (int a = 0; a < d; ++a) e.o[a] = dlt[a] * (bs - 1) + beta[a] * ((bs - 1) / 2);
+        add(fi, e);
+      }
+    }
+    BlockDesc& B = hblk[i];
+    B.slot = L.slot;
+    B.level = L.level;
+    for (int a = 0; a < 3; ++a) B.c[a] = L.c[a];
+    B.nb_begin = (int)hnb.size();
+    B.n_coarse = (int)co.size();
+    B.n_same = (int)sa.size();
+    B.n_fine = (int)fi.size();
+    hnb.insert(hnb.end(), co.begin(), co.end());
+    hnb.insert(hnb.end(), sa.begin(), sa.end());
+    hnb.insert(hnb.end(), fi.begin(), fi.end());
+  }
+  // blocks grouped by level (plain form launches one sweep per level)
+  std::vector<int> level_off(jmax + 2, 0), hlist(n, 0);
+  for (auto& L : c->leaves) level_off[L.level + 1]++;
+  for (int l = 1; l <= jmax + 1; ++l) level_off[l] += level_off[l - 1];
+  std::vector<int> fill(level_off.begin(), level_off.end());
+  for (int i = 0; i < n; ++i) hlist[fill[c->leaves[i].level]++] = i;
+  c->hblk.swap(hblk);
+  c->hnb.swap(hnb);
+  c->level_off.swap(level_off);
+  c->hlist.swap(hlist);
+  return MRB_OK;
+}
+
+mrb_status upload_descriptors(mrb_ctx* c) {
+  mrb_status s;
+  const size_t n = c->hblk.size();
+  if (c->hnb.size() > (size_t)c->max_entries) return fail(c, MRB_E_CAPACITY, "neighbour table overflow");
+  if ((s = stage_upload(c, c->st_blk, c->hblk.data(), n * sizeof(BlockDesc), c->dblk))) return s;
+  if ((s = stage_upload(c, c->st_nb, c->hnb.data(), c->hnb.size() * sizeof(NbEntry), c->dnb))) return s;
+  if ((s = stage_upload(c, c->st_list, c->hlist.data(), n * sizeof(int), c->dlist))) return s;
+  c->hcount[0] = (int)n;
+  return stage_upload(c, c->st_cnt, c->hcount, sizeof(c->hcount), c->dcount);
+}
+
+mrb_status set_counts(mrb_ctx* c) { return stage_upload(c, c->st_cnt, c->hcount, sizeof(c->hcount), c->dcount); }
+
+int grid_for(const mrb_ctx* c, long n) { return (int)std::max(1L, std::min((long)c->grid, n)); }
+
+mrb_status check_forest(mrb_ctx* c) {
+  const int d = c->cfg.dim, jmax = c->cfg.jmax;
+  // no duplicates, no leaf inside another, volumes sum to the domain
+  unsigned __int128 vol = 0, total = (unsigned __int128)1 << (d * jmax);
+  for (auto& L : c->leaves) {
+    vol += (unsigned __int128)1 << (d * (jmax - L.level));
+    int pc[3] = {L.c[0], L.c[1], L.c[2]};
+    for (int l = L.level - 1; l >= 1; --l) {
+      for (int a = 0; a < d; ++a) pc[a] >>= 1;
+      if (c->index.count(pack_key(l, pc))) return fail(c, MRB_E_TOPOLOGY, "blocks overlap");
+    }
+  }
+  if (vol != total) return fail(c, MRB_E_TOPOLOGY, "forest does not tile the domain");
+  return MRB_OK;
+}
+
+// Algorithmic HBM bytes per interior node and field of RK stage s: stage 1 reads
+// u and writes k1; stages 2-3 read u and k_{s-1} and write k_s; stage 4 reads u,
+// k3, k1, k2 and writes u_new (FP64: 16+24+24+40 = 104; mixed: 12+16+16+28 = 72).
+double stage_bytes(const mrb_ctx* c, int s) {
+  const double kb = c->cfg.precision == MRB_MIXED ? 4.0 : 8.0;
+  switch (s) {
+    case 1: return 8.0 + kb;
+    case 2: case 3: return 8.0 + 2.0 * kb;
+    default: return 8.0 + 3.0 * kb + 8.0;
+  }
+}
+
+// launch one RK stage (fused) or ghost + RHS per level (plain)
+mrb_status run_stage(mrb_ctx* c, int s, const StageArgs& a0) {
+  StageArgs a = a0;
+  const int n = (int)c->hblk.size();
+  if (c->cfg.form == MRB_FORM_PLAIN) {
+    for (int l = 1; l <= c->cfg.jmax; ++l) {
+      const int b0 = c->level_off[l], b1 = c->level_off[l + 1];
+      if (b1 == b0) continue;
+      a.list = c->dlist + b0;
+      a.list_n = b1 - b0;
+      const double nodes = (double)(b1 - b0) * c->bsz;
+      {
+        TimeScope ts(c, T_GHOST, 0.0);
+        HIPCHK(c, launch_ghost(c->shape, grid_for(c, b1 - b0), a, c->stream));
+      }
+      {
+        TimeScope ts(c, T_RHS_PLAIN, nodes * stage_bytes(c, s));
+        HIPCHK(c, launch_stage(c->shape, 0, 1, grid_for(c, b1 - b0), a, c->stream));
+      }
+    }
+    return MRB_OK;
+  }
+  TimeScope ts(c, T_STAGE, (double)n * c->bsz * stage_bytes(c, s));
+  HIPCHK(c, launch_stage(c->shape, c->cfg.precision, 0, grid_for(c, n), a, c->stream));
+  return MRB_OK;
+}
+
+mrb_status do_rk4(mrb_ctx* c, double t, double dt) {
+  const double h2 = dt * 0.5, h6 = dt / 6.0;
+  const double ts[4] = {t, t + h2, t + h2, t + dt};
+  StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.blk = c->dblk;
+  a.nb = c->dnb;
+  a.count = c->dcount;
+  a.list = nullptr;
+  a.u = c->u;
+  a.unew = c->unew;
+  a.k1 = c->k[0];
+  a.k2 = c->k[1];
+  a.k3 = c->k[2];
+  a.h6 = h6;
+  for (int f = 0; f < 4; ++f) a.off[f] = f < (int)c->off.size() ? c->off[f] : 0.0;
+  a.lt = c->lt;
+  a.ph = c->ph;
+  a.ghost = c->dghost;
+  const double alpha[4] = {0.0, h2, h2, dt};
+  for (int s = 1; s <= 4; ++s) {
+    a.stage = s;
+    a.alpha = alpha[s - 1];
+    a.kprev = s > 1 ? c->k[s - 2] : nullptr;
+    a.kout = s < 4 ? c->k[s - 1] : nullptr;
+    a.cfac = 1.0;
+    if (c->cfg.physics == MRB_ADV_SWIRL && c->cfg.phys[0] > 0.0) a.cfac = std::cos(M_PI * ts[s - 1] / c->cfg.phys[0]);
+    mrb_status r = run_stage(c, s, a);
+    if (r) return r;
+  }
+  std::swap(c->u, c->unew);
+  c->n_rk4++;
+  c->n_block_updates += (long)c->hblk.size();
+  return MRB_OK;
+}
+
+mrb_status do_refine_all(mrb_ctx* c) {
+  const int d = c->cfg.dim, nch = 1 << d;
+  std::vector<int> par;
+  for (int i = 0; i < (int)c->leaves.size(); ++i)
+    if (c->leaves[i].level < c->cfg.jmax) par.push_back(i);
+  if (par.empty()) return MRB_OK;
+  if (c->free_slots.size() < par.size() * nch) return fail(c, MRB_E_CAPACITY, "refine_all: pool too small");
+  std::vector<RefineDesc> ref(par.size());
+  std::vector<Leaf> kids;
+  kids.reserve(par.size() * nch);
+  for (size_t r = 0; r < par.size(); ++r) {
+    const Leaf& P = c->leaves[par[r]];
+    ref[r].blk = par[r];
+    for (int b = 0; b < nch; ++b) {
+      const int slot = c->free_slots.back();
+      c->free_slots.pop_back();
+      ref[r].child[b] = slot;
+      Leaf K;
+      K.level = P.level + 1;
+      K.c[0] = K.c[1] = K.c[2] = 0;
+      for (int a = 0; a < d; ++a) K.c[a] = 2 * P.c[a] + ((b >> a) & 1);
+      K.slot = slot;
+      kids.push_back(K);
+    }
+    for (int b = nch; b < 8; ++b) ref[r].child[b] = -1;
+  }
+  mrb_status s;
+  if ((s = stage_upload(c, c->st_ref, ref.data(), ref.size() * sizeof(RefineDesc), c->dref))) return s;
+  c->hcount[1] = (int)ref.size();
+  if ((s = set_counts(c))) return s;
+  RefineArgs a{c->dblk, c->dnb, c->dref, c->dcount + 1, c->u};
+  {
+    TimeScope ts(c, T_REFINE, (double)ref.size() * c->bsz * 8.0 * (1 + nch));
+    HIPCHK(c, launch_refine(c->shape, grid_for(c, (long)ref.size()), a, c->stream));
+  }
+  // new forest: parents leave, children join; parent slots return to the pool
+  std::vector<char> gone(c->leaves.size(), 0);
+  for (int i : par) gone[i] = 1;
+  std::vector<Leaf> nl;
+  nl.reserve(c->leaves.size() - par.size() + kids.size());
+  for (size_t i = 0; i < c->leaves.size(); ++i) {
+    if (gone[i]) c->free_slots.push_back(c->leaves[i].slot);
+    else nl.push_back(c->leaves[i]);
+  }
+  nl.insert(nl.end(), kids.begin(), kids.end());
+  c->leaves.swap(nl);
+  sort_and_index(c);
+  if ((s = build_descriptors(c))) return s;
+  c->n_refined += (long)par.size();
+  c->have_flags = false;
+  return upload_descriptors(c);
+}
+
+mrb_status do_mr_pass(mrb_ctx* c) {
+  const int n = (int)c->hblk.size();
+  MrArgs a;
+  a.blk = c->dblk;
+  a.nb = c->dnb;
+  a.count = c->dcount;
+  a.u = c->u;
+  a.flags = c->dflags;
+  a.maxd = c->dmaxd;
+  for (int f = 0; f < 4; ++f) a.thr[f] = f < (int)c->thr.size() ? c->thr[f] : 0.0;
+  {
+    TimeScope ts(c, T_MR, (double)n * c->bsz * 8.0);
+    HIPCHK(c, launch_mr(c->shape, grid_for(c, n), a, c->stream));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->h_flags, c->dflags, n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->h_maxd, c->dmaxd, sizeof(double) * n * c->cfg.nfields, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->last_flags.assign(c->h_flags, c->h_flags + n);
+  c->last_maxd.assign(c->h_maxd, c->h_maxd + (size_t)n * c->cfg.nfields);
+  c->have_flags = true;
+  c->n_mr++;
+  for (double v : c->last_maxd)
+    if (!std::isfinite(v)) return fail(c, MRB_E_NONFINITE, "detail norm is not finite");
+  return MRB_OK;
+}
+
+// largest set of complete, flagged families whose merge keeps the grid graded
+std::vector<uint64_t> coarsenable(mrb_ctx* c, const int8_t* flags) {
+  const int d = c->cfg.dim, nch = 1 << d;
+  std::unordered_set<uint64_t> cand;
+  for (size_t i = 0; i < c->leaves.size(); ++i) {
+    const Leaf& L = c->leaves[i];
+    if (L.level < 2 || flags[i] != -1) continue;
+    int p[3] = {L.c[0] >> 1, L.c[1] >> 1, L.c[2] >> 1};
+    if (d < 3) p[2] = 0;
+    const uint64_t pk = pack_key(L.level - 1, p);
+    if (cand.count(pk)) continue;
+    bool all = true;
+    for (int b = 0; b < nch && all; ++b) {
+      int ch[3] = {0, 0, 0};
+      for (int a = 0; a < d; ++a) ch[a] = 2 * p[a] + ((b >> a) & 1);
+      auto it = c->index.find(pack_key(L.level, ch));
+      if (it == c->index.end() || flags[it->second] != -1) all = false;
+    }
+    if (all) cand.insert(pk);
+  }
+  // demote families with a finer neighbour outside the set, until stable
+  bool changed = true;
+  while (changed) {
+    changed = false;
+    std::vector<uint64_t> cur(cand.begin(), cand.end());
+    for (uint64_t pk : cur) {
+      const int l = (int)(pk >> 60) + 1;
+      int p[3] = {(int)(pk & 0xFFFFF), (int)((pk >> 20) & 0xFFFFF), (int)((pk >> 40) & 0xFFFFF)};
+      bool ok = true;
+      for (int b = 0; b < nch && ok; ++b) {
+        int ch[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) ch[a] = 2 * p[a] + ((b >> a) & 1);
+        const int mi = c->index.at(pack_key(l, ch));
+        const BlockDesc& B = c->hblk[mi];
+        const int f0 = B.nb_begin + B.n_coarse + B.n_same;
+        for (int e = f0; e < f0 + B.n_fine && ok; ++e) {
+          // the finer neighbour's family (its mother at this member's level)
+          const NbEntry& E = c->hnb[e];
+          int fc[3] = {0, 0, 0};
+          for (int a = 0; a < d; ++a) {
+            const int fine = 2 * ch[a] + (E.o[a] * 2) / (c->cfg.bs - 1);  // coords of the finer leaf (unwrapped)
+            fc[a] = wrapi(fine, 1 << (l + 1)) >> 1;
+          }
+          if (!cand.count(pack_key(l, fc))) ok = false;
+        }
+      }
+      if (!ok) {
+        cand.erase(pk);
+        changed = true;
+      }
+    }
+  }
+  std::vector<uint64_t> out(cand.begin(), cand.end());
+  std::sort(out.begin(), out.end());
+  return out;
+}
+
+mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
+  const int d = c->cfg.dim, nch = 1 << d;
+  std::vector<uint64_t> fams = coarsenable(c, flags);
+  if (ncoarse) *ncoarse = (int)fams.size();
+  if (fams.empty()) return MRB_OK;
+  if (c->free_slots.size() < fams.size()) return fail(c, MRB_E_CAPACITY, "coarsen: pool too small");
+  std::vector<FamilyDesc> fd(fams.size());
+  std::vector<char> gone(c->leaves.size(), 0);
+  std::vector<Leaf> parents;
+  for (size_t i = 0; i < fams.size(); ++i) {
+    const uint64_t pk = fams[i];
+    const int l = (int)(pk >> 60);
+    int p[3] = {(int)(pk & 0xFFFFF), (int)((pk >> 20) & 0xFFFFF), (int)((pk >> 40) & 0xFFFFF)};
+    Leaf P;
+    P.level = l;
+    for (int a = 0; a < 3; ++a) P.c[a] = p[a];
+    P.slot = c->free_slots.back();
+    c->free_slots.pop_back();
+    fd[i].parent = P.slot;
+    for (int b = 0; b < 8; ++b) fd[i].child[b] = -1;
+    for (int b = 0; b < nch; ++b) {
+      int ch[3] = {0, 0, 0};
+      for (int a = 0; a < d; ++a) ch[a] = 2 * p[a] + ((b >> a) & 1);
+      const int mi = c->index.at(pack_key(l + 1, ch));
+      fd[i].child[b] = c->leaves[mi].slot;
+      gone[mi] = 1;
+    }
+    parents.push_back(P);
+  }
+  mrb_status s;
+  if ((s = stage_upload(c, c->st_fam, fd.data(), fd.size() * sizeof(FamilyDesc), c->dfam))) return s;
+  c->hcount[2] = (int)fd.size();
+  if ((s = set_counts(c))) return s;
+  CoarsenArgs a{c->dfam, c->dcount + 2, c->u};
+  const long total = (long)fd.size() * c->np;
+  {
+    TimeScope ts(c, T_COARSEN, (double)total * c->cfg.nfields * 16.0);
+    HIPCHK(c, launch_coarsen(c->shape, (int)std::min(4096L, (total + kNT - 1) / kNT), a, c->stream));
+  }
+  std::vector<Leaf> nl;
+  for (size_t i = 0; i < c->leaves.size(); ++i) {
+    if (gone[i]) c->free_slots.push_back(c->leaves[i].slot);
+    else nl.push_back(c->leaves[i]);
+  }
+  nl.insert(nl.end(), parents.begin(), parents.end());
+  c->leaves.swap(nl);
+  sort_and_index(c);
+  if ((s = build_descriptors(c))) return s;
+  c->n_fam += (long)fams.size();
+  c->have_flags = false;
+  return upload_descriptors(c);
+}
+
+mrb_status do_adapt(mrb_ctx* c, int* npass) {
+  int passes = 0;
+  for (;;) {
+    mrb_status s = do_mr_pass(c);
+    ++passes;
+    if (s) return s;
+    int nc = 0;
+    std::vector<int8_t> fl = c->last_flags;
+    if ((s = do_coarsen(c, fl.data(), &nc))) return s;
+    if (nc == 0) break;
+    if (passes > c->cfg.jmax + 2) return fail(c, MRB_E_STATE, "adapt did not reach a fixed point");
+  }
+  if (npass) *npass = passes;
+  return MRB_OK;
+}
+
+mrb_status ensure_scratch(mrb_ctx* c, size_t bytes) {
+  if (bytes <= c->scratch_cap) return MRB_OK;
+  if (c->dscratch) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipFree(c->dscratch));
+    c->dscratch = nullptr;
+  }
+  HIPCHK(c, hipMalloc(&c->dscratch, bytes));
+  c->scratch_cap = bytes;
+  return MRB_OK;
+}
+
+bool check_state(mrb_ctx* c, bool need_data) {
+  if (!c->have_forest) { c->err = "no forest (call mrb_init_forest first)"; return false; }
+  if (need_data && !c->have_data) { c->err = "no block data (call mrb_load_blocks first)"; return false; }
+  return true;
+}
+
+}  // namespace
+
+// scatter/gather of whole blocks between a contiguous array and pool slots
+namespace mrb {
+hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst, hipStream_t st);
+}
+
+extern "C" {
+
+const char* mrb_last_error(const mrb_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1, void* k2, void* k3, void* stream,
+                      mrb_ctx** out) {
+  if (!out || !cfg) return MRB_E_ARG;
+  *out = nullptr;
+  mrb_ctx* c = new mrb_ctx();
+  c->cfg = *cfg;
+  c->cfg.swirl_s2 = c->cfg.swirl_s = c->cfg.field_scale = c->cfg.field_offset = nullptr;
+  auto bad = [&](const char* m) {
+    c->err = m;
+    *out = c;  // hand back the context so the caller can read the message
+    return MRB_E_ARG;
+  };
+  if (!u || !u_new || !k1 || !k2 || !k3) return bad("pool pointers must be non-null");
+  if (cfg->dim < 2 || cfg->dim > 3) return bad("dim must be 2 or 3");
+  if (cfg->bs < 5 || cfg->bs % 2 == 0) return bad("bs must be odd");
+  if (cfg->hw < 2 || cfg->hw % 2) return bad("hw must be even and >= 2");
+  if ((cfg->bs - 1) / 2 < cfg->hw + 2) return bad("need (bs-1)/2 >= hw + 2");
+  if (cfg->nfields < 1 || cfg->nfields > 4) return bad("nfields must be 1..4");
+  if (cfg->jmax < 2 || cfg->jmax >= kMaxLevels - 1) return bad("jmax out of range");
+  if (cfg->max_blocks < (1 << cfg->dim)) return bad("max_blocks too small");
+  if (cfg->precision != MRB_FP64 && cfg->precision != MRB_MIXED) return bad("precision");
+  if (cfg->form != MRB_FORM_PLAIN && cfg->form != MRB_FORM_FUSED) return bad("form");
+  if (cfg->form == MRB_FORM_PLAIN && cfg->precision != MRB_FP64) return bad("the plain form is FP64 only");
+  if (cfg->physics < 0 || cfg->physics > 2) return bad("physics");
+  if (cfg->physics == MRB_ADV_SWIRL && (cfg->dim != 2 || !cfg->swirl_s2 || !cfg->swirl_s))
+    return bad("swirl needs dim 2 and both tables");
+  c->shape = Shape{cfg->dim, cfg->bs, cfg->hw, cfg->nfields};
+  if (!shape_supported(c->shape)) return bad("unsupported (dim, bs, hw, nfields) combination");
+  c->np = 1;
+  for (int a = 0; a < cfg->dim; ++a) c->np *= cfg->bs;
+  c->bsz = (size_t)cfg->nfields * c->np;
+  c->stream = (hipStream_t)stream;
+  c->u = u;
+  c->unew = u_new;
+  c->k[0] = k1;
+  c->k[1] = k2;
+  c->k[2] = k3;
+  for (int f = 0; f < cfg->nfields; ++f) {
+    c->thr.push_back(cfg->field_scale ? cfg->eps * cfg->field_scale[f] : cfg->eps);
+    c->off.push_back(cfg->field_offset && cfg->precision == MRB_MIXED ? cfg->field_offset[f] : 0.0);
+  }
+  for (int l = 0; l < kMaxLevels; ++l) {
+    const long nl = l >= 1 ? (1L << l) * (cfg->bs - 1) : (cfg->bs - 1);
+    c->lt.nl[l] = (int)nl;
+    c->lt.r[l] = (double)nl / 12.0;
+    c->lt.rf[l] = (float)c->lt.r[l];
+  }
+  std::memset(&c->ph, 0, sizeof c->ph);
+  c->ph.kind = cfg->physics;
+  c->ph.jmax = cfg->jmax;
+  for (int a = 0; a < 3; ++a) {
+    c->ph.c[a] = cfg->phys[a];
+    c->ph.cf[a] = (float)cfg->phys[a];
+  }
+  const int maxe = cfg->dim == 2 ? 13 : 57;
+  c->max_entries = cfg->max_blocks * maxe;
+  auto dev = [&](void** p, size_t bytes) -> bool {
+    hipError_t e = hipMalloc(p, std::max(bytes, (size_t)256));
+    if (e != hipSuccess) { c->err = std::string("hipMalloc: ") + hipGetErrorString(e); return false; }
+    return true;
+  };
+  const size_t mb = cfg->max_blocks;
+  bool ok = dev((void**)&c->dblk, mb * sizeof(BlockDesc)) && dev((void**)&c->dnb, (size_t)c->max_entries * sizeof(NbEntry)) &&
+            dev((void**)&c->dcount, 16 * sizeof(int)) && dev((void**)&c->dlist, mb * sizeof(int)) &&
+            dev((void**)&c->dref, mb * sizeof(RefineDesc)) && dev((void**)&c->dfam, mb * sizeof(FamilyDesc)) &&
+            dev((void**)&c->dflags, mb) && dev((void**)&c->dmaxd, mb * cfg->nfields * sizeof(double)) &&
+            dev((void**)&c->dslots, mb * sizeof(int));
+  if (ok && cfg->physics == MRB_ADV_SWIRL) {
+    const size_t n = (size_t)(1L << cfg->jmax) * (cfg->bs - 1);
+    ok = dev((void**)&c->ds2, n * sizeof(double)) && dev((void**)&c->ds, n * sizeof(double));
+    if (ok) {
+      ok = hipMemcpy(c->ds2, cfg->swirl_s2, n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(c->ds, cfg->swirl_s, n * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+      if (!ok) c->err = "copying swirl tables failed";
+    }
+    c->ph.s2 = c->ds2;
+    c->ph.s = c->ds;
+  }
+  if (ok && cfg->form == MRB_FORM_PLAIN) {
+    size_t g = 1;
+    for (int a = 0; a < cfg->dim; ++a) g *= (size_t)(cfg->bs + 2 * cfg->hw);
+    ok = dev((void**)&c->dghost, mb * cfg->nfields * g * sizeof(double));
+  }
+  if (ok) {
+    ok = hipHostMalloc((void**)&c->h_flags, mb, hipHostMallocDefault) == hipSuccess &&
+         hipHostMalloc((void**)&c->h_maxd, mb * cfg->nfields * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    if (!ok) c->err = "hipHostMalloc failed";
+  }
+  if (ok) {
+    int dev_id = 0, ncu = 0;
+    (void)hipGetDevice(&dev_id);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) == hipSuccess && ncu > 0)
+      c->grid = ncu * 8;
+  }
+  *out = c;
+  if (!ok) return MRB_E_DEVICE;
+  return MRB_OK;
+}
+
+mrb_status mrb_destroy(mrb_ctx* c) {
+  if (!c) return MRB_E_ARG;
+  (void)hipStreamSynchronize(c->stream);
+  Staging* sts[] = {&c->st_blk, &c->st_nb, &c->st_cnt, &c->st_ref, &c->st_fam, &c->st_list, &c->st_slots, &c->st_data};
+  for (Staging* s : sts) release_staging(*s);
+  for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  void* ptrs[] = {c->dblk, c->dnb, c->dcount, c->dlist, c->dref, c->dfam, c->dflags, c->dmaxd,
+                  c->ds2, c->ds, c->dghost, c->dscratch, c->dslots};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->h_flags) (void)hipHostFree(c->h_flags);
+  if (c->h_maxd) (void)hipHostFree(c->h_maxd);
+  delete c;
+  return MRB_OK;
+}
+
+mrb_status mrb_init_forest(mrb_ctx* c, int n, const int8_t* level, const int32_t* coords) {
+  if (!c) return MRB_E_ARG;
+  if (n <= 0 || !level || !coords) return fail(c, MRB_E_ARG, "init_forest: empty forest or null arrays");
+  if (n > c->cfg.max_blocks) return fail(c, MRB_E_CAPACITY, "init_forest: more blocks than max_blocks");
+  const int d = c->cfg.dim;
+  // a rejected forest leaves the previous state unchanged
+  std::vector<Leaf> old_leaves;
+  old_leaves.swap(c->leaves);
+  auto old_index = c->index;
+  auto restore = [&](mrb_status s) {
+    c->leaves.swap(old_leaves);
+    c->index = old_index;
+    return s;
+  };
+  for (int i = 0; i < n; ++i) {
+    Leaf L;
+    L.level = level[i];
+    L.c[0] = L.c[1] = L.c[2] = 0;
+    if (L.level < 1 || L.level > c->cfg.jmax) return restore(fail(c, MRB_E_TOPOLOGY, "level out of range"));
+    for (int a = 0; a < d; ++a) {
+      L.c[a] = coords[(size_t)i * d + a];
+      if (L.c[a] < 0 || L.c[a] >= (1 << L.level)) return restore(fail(c, MRB_E_TOPOLOGY, "coords out of range"));
+    }
+    L.slot = -1;
+    c->leaves.push_back(L);
+  }
+  sort_and_index(c);
+  if (c->index.size() != c->leaves.size()) return restore(fail(c, MRB_E_TOPOLOGY, "duplicate block"));
+  mrb_status s = check_forest(c);
+  if (s) return restore(s);
+  for (int i = 0; i < n; ++i) c->leaves[i].slot = i;
+  if ((s = build_descriptors(c))) return restore(s);
+  c->free_slots.clear();
+  for (int sl = c->cfg.max_blocks - 1; sl >= n; --sl) c->free_slots.push_back(sl);
+  c->have_forest = true;
+  c->have_data = false;
+  c->have_flags = false;
+  return upload_descriptors(c);
+}
+
+mrb_status mrb_load_blocks(mrb_ctx* c, const double* data, int on_device) {
+  if (!c) return MRB_E_ARG;
+  if (!check_state(c, false)) return MRB_E_STATE;
+  if (!data) return fail(c, MRB_E_ARG, "load_blocks: null data");
+  const int n = (int)c->leaves.size();
+  const size_t bytes = (size_t)n * c->bsz * sizeof(double);
+  mrb_status s;
+  const double* src = data;
+  if (!on_device) {
+    if ((s = ensure_scratch(c, bytes))) return s;
+    HIPCHK(c, hipMemcpyAsync(c->dscratch, data, bytes, hipMemcpyHostToDevice, c->stream));
+    src = c->dscratch;
+  }
+  std::vector<int> slots(n);
+  for (int i = 0; i < n; ++i) slots[i] = c->leaves[i].slot;
+  if ((s = stage_upload(c, c->st_slots, slots.data(), n * sizeof(int), c->dslots))) return s;
+  HIPCHK(c, launch_scatter(src, c->dslots, n, c->bsz, c->u, c->stream));
+  if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->have_data = true;
+  c->have_flags = false;
+  return MRB_OK;
+}
+
+mrb_status mrb_refine_all(mrb_ctx* c) {
+  if (!c) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  return do_refine_all(c);
+}
+
+mrb_status mrb_rk4(mrb_ctx* c, double t, double dt) {
+  if (!c) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  if (!(dt > 0.0) || !std::isfinite(t)) return fail(c, MRB_E_ARG, "rk4: dt must be positive");
+  c->have_flags = false;
+  return do_rk4(c, t, dt);
+}
+
+mrb_status mrb_mr_pass(mrb_ctx* c, int8_t* flags, double* maxd) {
+  if (!c) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  mrb_status s = do_mr_pass(c);
+  if (flags) std::memcpy(flags, c->last_flags.data(), c->last_flags.size());
+  if (maxd) std::memcpy(maxd, c->last_maxd.data(), c->last_maxd.size() * sizeof(double));
+  return s;
+}
+
+mrb_status mrb_coarsen(mrb_ctx* c, const int8_t* flags, int* n_coarsened) {
+  if (!c) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  if (!flags) return fail(c, MRB_E_ARG, "coarsen: null flags");
+  std::vector<int8_t> fl(flags, flags + c->leaves.size());
+  return do_coarsen(c, fl.data(), n_coarsened);
+}
+
+mrb_status mrb_adapt(mrb_ctx* c, int* n_passes) {
+  if (!c) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  return do_adapt(c, n_passes);
+}
+
+mrb_status mrb_step(mrb_ctx* c, double t0, double dt, int nsteps) {
+  if (!c) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  if (nsteps < 0 || !(dt > 0.0)) return fail(c, MRB_E_ARG, "step: bad dt or nsteps");
+  for (int s = 0; s < nsteps; ++s) {
+    mrb_status r;
+    if ((r = do_refine_all(c))) return r;
+    if ((r = do_rk4(c, t0 + s * dt, dt))) return r;
+    if ((r = do_adapt(c, nullptr))) return r;
+    c->n_steps++;
+  }
+  return MRB_OK;
+}
+
+mrb_status mrb_num_blocks(mrb_ctx* c, int* n) {
+  if (!c || !n) return MRB_E_ARG;
+  if (!check_state(c, false)) return MRB_E_STATE;
+  *n = (int)c->leaves.size();
+  return MRB_OK;
+}
+
+mrb_status mrb_read_forest(mrb_ctx* c, int8_t* level, int32_t* coords) {
+  if (!c || !level || !coords) return MRB_E_ARG;
+  if (!check_state(c, false)) return MRB_E_STATE;
+  const int d = c->cfg.dim;
+  for (size_t i = 0; i < c->leaves.size(); ++i) {
+    level[i] = (int8_t)c->leaves[i].level;
+    for (int a = 0; a < d; ++a) coords[i * d + a] = c->leaves[i].c[a];
+  }
+  return MRB_OK;
+}
+
+mrb_status mrb_read_blocks(mrb_ctx* c, double* out, int on_device) {
+  if (!c || !out) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  const int n = (int)c->leaves.size();
+  const size_t bytes = (size_t)n * c->bsz * sizeof(double);
+  mrb_status s;
+  double* dst = out;
+  if (!on_device) {
+    if ((s = ensure_scratch(c, bytes))) return s;
+    dst = c->dscratch;
+  }
+  ReadArgs a{c->dblk, c->dnb, c->dcount, c->u, dst};
+  HIPCHK(c, launch_read(c->shape, grid_for(c, n), a, c->stream));
+  if (!on_device) HIPCHK(c, hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MRB_OK;
+}
+
+mrb_status mrb_get_flags(mrb_ctx* c, int8_t* flags, double* maxd) {
+  if (!c || !flags) return MRB_E_ARG;
+  if (!c->have_flags) return fail(c, MRB_E_STATE, "no analysis on the current grid");
+  std::memcpy(flags, c->last_flags.data(), c->last_flags.size());
+  if (maxd) std::memcpy(maxd, c->last_maxd.data(), c->last_maxd.size() * sizeof(double));
+  return MRB_OK;
+}
+
+mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
+  if (!c || !json || cap <= 0) return MRB_E_ARG;
+  resolve_timing(c);
+  std::string kern = "{";
+  for (int k = 0; k < T_NKIND; ++k) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"bytes\": %.17g}", k ? ", " : "",
+                  kKindName[k], c->t_launches[k], c->t_ms[k], c->t_bytes[k]);
+    kern += buf;
+  }
+  kern += "}";
+  int w = std::snprintf(json, cap,
+                "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
+                "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
+                "\"kernels\": %s}",
+                c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
+                c->free_slots.size(), c->grid, kern.c_str());
+  if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
+  return MRB_OK;
+}
+
+mrb_status mrb_timing(mrb_ctx* c, int enable) {
+  if (!c) return MRB_E_ARG;
+  resolve_timing(c);
+  c->timing = enable != 0;
+  for (int k = 0; k < 8; ++k) {
+    c->t_ms[k] = 0.0;
+    c->t_bytes[k] = 0.0;
+    c->t_launches[k] = 0;
+  }
+  return MRB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+"""The C-ABI library: exports (CPU) and parity against the CPU oracle (GPU).
+
+FP64 results are compared bit for bit (the tolerance the method allows is 1e-12
+relative per field; the design reaches exact equality because both sides round
+every operation in the same order).  Flags and forests must match exactly.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+import paper_1902_00088_amd as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mrb.h")).read()
+    return sorted(set(re.findall(r"\b(mrb_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_entry_point():
+    import ctypes
+    if not os.path.exists(M.LIB_PATH):
+        M.build()
+    L = ctypes.CDLL(M.LIB_PATH)
+    names = _declared()
+    assert set(names) == set(M.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_solver_refuses_to_run_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(RuntimeError):
+        M.Solver(W.C1())
+
+
+# ------------------------------------------------------------------------------------------
+# GPU parity
+# ------------------------------------------------------------------------------------------
+
+def _bits(a):
+    return np.ascontiguousarray(a).view(np.uint64)
+
+
+def assert_same(s, o, what=""):
+    lv1, co1 = s.read_forest()
+    lv2, co2 = o.read_forest()
+    assert np.array_equal(lv1, lv2) and np.array_equal(co1, co2), f"forest differs {what}"
+    a, b = s.read_blocks(), o.read_blocks()
+    if not np.array_equal(_bits(a), _bits(b)):
+        den = np.maximum(np.max(np.abs(b), axis=(0, 2)), 1e-300)
+        rel = np.max(np.abs(a - b), axis=(0, 2)) / den
+        bad = np.argwhere(_bits(a) != _bits(b))
+        raise AssertionError(f"values differ {what}: rel per field {rel}, first {bad[:5].tolist()}, n={len(bad)}")
+
+
+def _pair(cfg, levels=None, coords=None, fn=None):
+    s = M.Solver(cfg)
+    o = oracle.Oracle(cfg)
+    if levels is None:
+        s.init_grid(fn=fn)
+        o.init_grid(fn=fn)
+    else:
+        for x in (s, o):
+            x.init_forest(levels, coords)
+            x.load_blocks(W.sample(cfg, *x.read_forest(), fn=fn))
+    return s, o
+
+
+def _two_level():
+    keys = [(2, x, y) for x in range(4) for y in range(4) if (x, y) != (1, 1)]
+    keys += [(3, 2 + bx, 2 + by) for bx in range(2) for by in range(2)]
+    return np.array([k[0] for k in keys], np.int8), np.array([k[1:] for k in keys], np.int32)
+
+
+SMOOTH2 = lambda x, y: np.sin(2 * np.pi * x + 0.3) * np.cos(4 * np.pi * y) + 0.5 * np.cos(2 * np.pi * (x - y))
+SMOOTH3 = lambda x, y, z: np.sin(2 * np.pi * x + 0.3) * np.cos(2 * np.pi * y) + 0.3 * np.sin(2 * np.pi * (z - x))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("form", [W.FORM_FUSED, W.FORM_PLAIN])
+def test_rk4_on_two_level_forest_is_bitwise(form):
+    cfg = W.C1(jmax=3, form=form)
+    lv, co = _two_level()
+    s, o = _pair(cfg, lv, co, fn=SMOOTH2)
+    assert_same(s, o, "after load")
+    s.rk4(0.0, cfg.dt)
+    o.rk4(0.0, cfg.dt)
+    assert_same(s, o, "after rk4")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("seed", range(4))
+def test_random_graded_forest_refine_rk4_mr(seed):
+    lv, co = W.random_graded_forest(2, 4, seed, p_refine=0.5)
+    cfg = W.C2(jmax=5, eps=3e-3).replace(bs=17, max_blocks=3 * 4 ** 5)
+    s, o = _pair(cfg, lv, co, fn=SMOOTH2)
+    s.rk4(0.0, cfg.dt)
+    o.rk4(0.0, cfg.dt)
+    assert_same(s, o, "rk4")
+    fs, ms = s.mr_pass()
+    fo, mo = o.mr_pass()
+    assert np.array_equal(fs, fo) and np.array_equal(_bits(ms), _bits(mo))
+    assert_same(s, o, "after mr sync")
+    ns, no = s.coarsen(fs), o.coarsen(fo)
+    assert ns == no
+    assert_same(s, o, "coarsen")
+    s.refine_all()
+    o.refine_all()
+    assert_same(s, o, "refine")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("form", [W.FORM_PLAIN, W.FORM_FUSED])
+def test_c1_full_run_is_bitwise(form):
+    """C1: 2D advection, Bs=17, Jmax=4, eps=1e-3, 100 steps, FP64."""
+    cfg = W.C1(form=form)
+    s, o = _pair(cfg)
+    assert_same(s, o, "initial grid")
+    t = 0.0
+    for n in range(cfg.steps):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+        if n % 25 == 24:
+            assert_same(s, o, f"step {n + 1}")
+    assert_same(s, o, "end")
+
+
+@pytest.mark.gpu
+def test_c2_full_size_sampled_steps():
+    """C2 at its full configuration (Bs=33, Jmax=7, eps=1e-4) in the benchmark's launch
+    configuration (fused FP64): 40 steps, every 10th compared."""
+    cfg = W.C2(form=W.FORM_FUSED)
+    s, o = _pair(cfg)
+    assert_same(s, o, "initial grid")
+    t = 0.0
+    for n in range(40):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+        if n % 10 == 9:
+            assert_same(s, o, f"step {n + 1}")
+
+
+@pytest.mark.gpu
+def test_c2_narrow_blobs_deep_forest():
+    """Swirl with narrow blobs: a deep, ragged forest (levels 2..6) that changes each step."""
+    cfg = W.C2(jmax=6, eps=1e-4, blob_beta=4e-4, form=W.FORM_FUSED)
+    s, o = _pair(cfg)
+    lv, _ = s.read_forest()
+    assert len(np.unique(lv)) >= 3
+    t = 0.0
+    for n in range(6):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    assert_same(s, o, "after 6 steps")
+
+
+@pytest.mark.gpu
+def test_3d_small_run_is_bitwise():
+    cfg = W.C4(jmax=3, eps=1e-3, form=W.FORM_FUSED).replace(max_blocks=3 * 8 ** 3)
+    s, o = _pair(cfg)
+    assert_same(s, o, "initial grid")
+    t = 0.0
+    for n in range(3):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    assert_same(s, o, "after 3 steps")
+
+
+@pytest.mark.gpu
+def test_mixed_precision_within_1e5_on_replayed_topology():
+    """Mixed form (FP32 stencil and slopes, FP64 state): per-field relative error
+    against the FP64 oracle <= 1e-5, with the oracle's coarsening flags replayed."""
+    cfg = W.C2(jmax=6, eps=1e-4, blob_beta=4e-4)
+    s = M.Solver(cfg.replace(precision=W.MIXED, form=W.FORM_FUSED))
+    o = oracle.Oracle(cfg)
+    o.init_grid()
+    s.init_forest(*o.read_forest())
+    s.load_blocks(W.sample(cfg, *o.read_forest()))
+    t = 0.0
+    worst = 0.0
+    for n in range(20):
+        for x in (s, o):
+            x.refine_all()
+            x.rk4(t, cfg.dt)
+        while True:
+            fo, _ = o.mr_pass()
+            fs, _ = s.mr_pass()
+            if o.coarsen(fo) == 0:
+                assert s.coarsen(fo) == 0
+                break
+            s.coarsen(fo)
+        t += cfg.dt
+        a, b = s.read_blocks(), o.read_blocks()
+        assert np.array_equal(s.read_forest()[0], o.read_forest()[0])
+        rel = np.max(np.abs(a - b)) / np.max(np.abs(b))
+        worst = max(worst, rel)
+    assert worst <= 1e-5, worst
+    assert worst > 0.0
+
+
+@pytest.mark.gpu
+def test_runs_are_deterministic():
+    cfg = W.C2(jmax=5, eps=1e-4, blob_beta=1e-3, form=W.FORM_FUSED)
+    outs = []
+    for _ in range(2):
+        s = M.Solver(cfg)
+        s.init_grid()
+        s.step(0.0, cfg.dt, 5)
+        outs.append((s.read_forest(), s.read_blocks()))
+        s.close()
+    assert np.array_equal(outs[0][0][0], outs[1][0][0])
+    assert np.array_equal(_bits(outs[0][1]), _bits(outs[1][1]))
+
+
+@pytest.mark.gpu
+def test_error_paths_leave_state_unchanged():
+    cfg = W.C1(jmax=3)
+    s = M.Solver(cfg.replace(max_blocks=64))
+    with pytest.raises(M.MrbError) as e:
+        s.step(0.0, cfg.dt)
+    assert e.value.code == -4                            # no forest yet
+    lv, co = W.uniform_forest(cfg, 2)
+    with pytest.raises(M.MrbError) as e:
+        s.init_forest(lv[1:], co[1:])
+    assert e.value.code == -3                            # hole
+    s.init_forest(lv, co)
+    s.load_blocks(W.sample(cfg, lv, co))
+    before = s.read_blocks()
+    with pytest.raises(M.MrbError) as e:
+        s.refine_all()                                   # 16 + 64 > 64 slots
+    assert e.value.code == -2
+    assert s.num_blocks() == 16
+    assert np.array_equal(_bits(s.read_blocks()), _bits(before))
+    keys = [(1, 1, 0), (1, 0, 1), (1, 1, 1), (2, 0, 1), (2, 1, 0), (2, 1, 1)] + \
+           [(3, x, y) for x in range(2) for y in range(2)]
+    with pytest.raises(M.MrbError) as e:
+        s.init_forest([k[0] for k in keys], [k[1:] for k in keys])
+    assert e.value.code == -3                            # not graded
+    assert s.num_blocks() == 16
+    with pytest.raises(M.MrbError):
+        M.Solver(cfg.replace(bs=16))                     # even block size
