@@ -28,7 +28,7 @@ STATUS = {0: "MRB_OK", -1: "MRB_E_ARG", -2: "MRB_E_CAPACITY", -3: "MRB_E_TOPOLOG
 EXPORTS = ("mrb_create", "mrb_destroy", "mrb_last_error", "mrb_init_forest", "mrb_load_blocks",
            "mrb_refine_all", "mrb_rk4", "mrb_mr_pass", "mrb_coarsen", "mrb_adapt", "mrb_step",
            "mrb_num_blocks", "mrb_read_forest", "mrb_read_blocks", "mrb_get_flags", "mrb_stats",
-           "mrb_timing")
+           "mrb_timing", "mrb_tune")
 
 
 class MrbError(RuntimeError):
@@ -82,6 +82,7 @@ def lib():
             "mrb_get_flags": [_vp, _i8p, _dp],
             "mrb_stats": [_vp, ctypes.c_char_p, ctypes.c_int],
             "mrb_timing": [_vp, ctypes.c_int],
+            "mrb_tune": [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -236,6 +237,12 @@ class Solver:
         md = np.zeros((n, self.cfg.nf))
         self._chk(lib().mrb_get_flags(self.h, _ptr(fl, _i8p), _ptr(md, _dp)))
         return fl, md
+
+    def tune(self, nsub: int = 0, reps: int = 0) -> int:
+        """Force (nsub > 0), autotune (reps > 0) or reset the stage tiling; returns the tiling in use."""
+        ch = ctypes.c_int()
+        self._chk(lib().mrb_tune(self.h, nsub, reps, self.cfg.dt, ctypes.byref(ch)))
+        return ch.value
 
     def timing(self, enable: bool):
         self._chk(lib().mrb_timing(self.h, 1 if enable else 0))

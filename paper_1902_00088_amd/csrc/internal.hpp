@@ -8,17 +8,16 @@
 namespace mrb {
 
 constexpr int kMaxLevels = 16;
-constexpr int kNT = 256;  // threads per workgroup of the block kernels (4 wave64)
+constexpr int kMaxEnt = 64;   // neighbour entries per block (3D needs at most 57)
 
-// One active block of the current grid, in forest (Morton) order.
+// One active block, in forest (Morton) order.
 struct BlockDesc {
   int slot;       // pool slot of the block's data
   int level;
   int c[3];       // integer coordinates at its level
   int nb_begin;   // first neighbour entry
-  int n_coarse;   // entries are stored coarser leaves first,
-  int n_same;     // then same-level leaves (the block itself included),
-  int n_fine;     // then finer leaves
+  int n_ent;      // entries: coarser leaves first, then same-level leaves (the block
+  int n_coarse;   // itself included), then finer leaves
 };
 
 // A leaf whose closed region touches the block (diagonal neighbours included).
@@ -30,10 +29,10 @@ struct NbEntry {
   int o[3];
 };
 
-// Refinement of one block of the previous grid: its descriptor index and the
-// slots of its 2^dim children (child bit a = coordinate bit along axis a).
+// Refinement work: the parent's descriptor index (parent section) and the slots of
+// its 2^dim children (child bit a = coordinate bit along axis a).
 struct RefineDesc {
-  int blk;
+  int pblk;
   int child[8];
 };
 
@@ -41,6 +40,28 @@ struct RefineDesc {
 struct FamilyDesc {
   int parent;
   int child[8];
+};
+
+// Header of the packed topology buffer (one host->device copy per topology change).
+// Offsets are in bytes from the start of the buffer.
+struct TopoHeader {
+  int n_blocks;   // current grid
+  int n_ref;      // refinement work items
+  int n_fam;      // coarsening families
+  int n_pblk;     // parents (refinement)
+  int off_blk, off_nb, off_list, off_pblk, off_pnb, off_ref, off_fam;
+  int pad[5];
+};
+
+struct Topo {
+  const TopoHeader* h;
+  __device__ __forceinline__ const BlockDesc* blk() const { return (const BlockDesc*)((const char*)h + h->off_blk); }
+  __device__ __forceinline__ const NbEntry* nb() const { return (const NbEntry*)((const char*)h + h->off_nb); }
+  __device__ __forceinline__ const int* list() const { return (const int*)((const char*)h + h->off_list); }
+  __device__ __forceinline__ const BlockDesc* pblk() const { return (const BlockDesc*)((const char*)h + h->off_pblk); }
+  __device__ __forceinline__ const NbEntry* pnb() const { return (const NbEntry*)((const char*)h + h->off_pnb); }
+  __device__ __forceinline__ const RefineDesc* ref() const { return (const RefineDesc*)((const char*)h + h->off_ref); }
+  __device__ __forceinline__ const FamilyDesc* fam() const { return (const FamilyDesc*)((const char*)h + h->off_fam); }
 };
 
 struct LevelTab {
@@ -52,7 +73,6 @@ struct LevelTab {
 struct Physics {
   int kind;               // MRB_ADV_CONST / MRB_ADV_SWIRL / MRB_NS2D
   double c[3];            // advection velocity
-  float cf[3];
   const double* s2;       // device swirl tables (finest lattice)
   const double* s;
   int jmax;
@@ -63,11 +83,8 @@ struct Physics {
 // (stage 1: y = u) over block + halo and evaluates the RHS; stages 1-3 store
 // k_s into kout, stage 4 stores u + h6*((k1 + k4) + 2 (k2 + k3)) into unew.
 struct StageArgs {
-  const BlockDesc* blk;
-  const NbEntry* nb;
-  const int* count;       // device: number of blocks
-  const int* list;        // optional block-index list (plain form per level), else null
-  int list_n;
+  Topo topo;
+  int lvl_begin, lvl_end; // plain form: range of the level-sorted block list (else 0, -1)
   const double* u;
   const void* kprev;
   double alpha;
@@ -86,9 +103,7 @@ struct StageArgs {
 };
 
 struct MrArgs {
-  const BlockDesc* blk;
-  const NbEntry* nb;
-  const int* count;
+  Topo topo;
   double* u;              // read; redundant nodes owned by finer blocks are written back
   int8_t* flags;          // [n]
   double* maxd;           // [n][nf]
@@ -96,40 +111,40 @@ struct MrArgs {
 };
 
 struct RefineArgs {
-  const BlockDesc* blk;   // descriptors of the grid before refinement
-  const NbEntry* nb;
-  const RefineDesc* ref;
-  const int* count;       // device: number of refined blocks
+  Topo topo;
   double* u;
 };
 
 struct CoarsenArgs {
-  const FamilyDesc* fam;
-  const int* count;
+  Topo topo;
   double* u;
 };
 
 struct ReadArgs {
-  const BlockDesc* blk;
-  const NbEntry* nb;
-  const int* count;
+  Topo topo;
   const double* u;
   double* out;            // [n][nf][bs^dim]
 };
 
-// Kernel variant key: one compiled instantiation per supported shape.
 struct Shape {
   int dim, bs, hw, nf;
 };
 
-// Launchers (kernels.hip).  Each returns a hipError_t; grid = number of workgroups.
-hipError_t launch_stage(const Shape& s, int precision, int form_plain_rhs, int grid, const StageArgs& a,
-                        hipStream_t st);
-hipError_t launch_ghost(const Shape& s, int grid, const StageArgs& a, hipStream_t st);
+// Kernel variant of the stage sweep: sub-tiles per axis (1, 2 or 4).
+struct Variant {
+  int nsub;
+};
+
+// Launchers (kernels.hip).  grid = number of workgroups (grid-stride loops inside).
+hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, const StageArgs& a, hipStream_t st);
+hipError_t launch_plain(const Shape& s, int grid, const StageArgs& a, hipStream_t st);  // ghost + RHS kernels
 hipError_t launch_mr(const Shape& s, int grid, const MrArgs& a, hipStream_t st);
 hipError_t launch_refine(const Shape& s, int grid, const RefineArgs& a, hipStream_t st);
 hipError_t launch_coarsen(const Shape& s, int grid, const CoarsenArgs& a, hipStream_t st);
 hipError_t launch_read(const Shape& s, int grid, const ReadArgs& a, hipStream_t st);
+hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst, hipStream_t st);
 bool shape_supported(const Shape& s);
+// sub-tile counts compiled for this shape and precision, best first; returns count
+int stage_variants(const Shape& s, int precision, int* nsub, int cap);
 
 }  // namespace mrb

@@ -1,17 +1,21 @@
 // HIP kernels of the block-multiresolution sweep (gfx950).
 //
-// Every kernel works on one block per workgroup iteration (grid-stride over the
-// block list, so a launch is independent of the block count and can be replayed
-// from a graph).  A block's synchronised values over block + halo are built in
-// LDS by "painting": each leaf whose closed region touches the block (coarser
-// leaves first, then same-level leaves including the block itself, then finer
-// leaves) writes its lattice points that fall inside the tile, so a point held by
-// several leaves ends with the value of the finest one (finer blocks own the
-// redundant nodes, Sec. 2.2 and Sec. 2.5).  Points that lie inside a coarser leaf
-// but off its lattice are then predicted from the painted coarse-lattice points
-// with the 4th-order central midpoint rule, tensor product x -> y -> z (the
-// prediction operator of Sec. 2.3).  The stencil work is bandwidth bound and uses
-// plain vector ALUs (no MFMA).
+// A workgroup handles one block (or one sub-tile of a block) per iteration of a
+// grid-stride loop, so a launch does not depend on the block count (it is read from
+// the device topology header) and can be replayed from a graph.
+//
+// Ghost synchronisation is a single gather into LDS.  The block's neighbour
+// entries (every leaf whose closed region touches the block: coarser leaves first,
+// then same-level leaves including the block itself, then finer leaves) are loaded
+// into LDS, and for each axis a 64-bit mask per tile coordinate records which
+// entries hold that coordinate on their own lattice.  The owner of a tile point is
+// the highest set bit of the AND of its axis masks: the finest leaf holding the
+// point (finer blocks own the redundant nodes, Sec. 2.2 and Sec. 2.5).  All loads of
+// a tile are issued in one round.  A point held by no leaf lies inside a coarser
+// leaf off its lattice and is predicted from the gathered coarse-lattice points by
+// the 4th-order central midpoint rule, tensor product x -> y -> z (the prediction
+// operator of Sec. 2.3).  The stencil work is bandwidth bound and uses plain vector
+// ALUs (no MFMA).
 #include "internal.hpp"
 
 #include <hip/hip_runtime.h>
@@ -57,17 +61,24 @@ __device__ __forceinline__ T tensor_p(const AT& at, const int* base, const int* 
   return nz == 4 ? P4(vz[0], vz[1], vz[2], vz[3]) : vz[0];
 }
 
-template <int DIM, int BS, int H>
-struct TileGeo {
-  static constexpr int TW = BS + 2 * H;
+// Tile over a region of S nodes per axis (block-local origin r0) with a halo of H.
+template <int DIM, int BS, int S, int H>
+struct Geo {
+  static constexpr int TW = S + 2 * H;
   static constexpr int TSZ = Pow<DIM, TW>::v;
   static constexpr int NP = Pow<DIM, BS>::v;
-  __device__ static __forceinline__ int at(int x, int y, int z) {
-    return (x + H) + TW * (y + H) + (DIM > 2 ? TW * TW * (z + H) : 0);
+  __device__ static __forceinline__ int idx(int ix, int iy, int iz) {  // tile coordinates
+    return ix + TW * iy + (DIM > 2 ? TW * TW * iz : 0);
   }
 };
 
-// Stage value sources: y = u (+ alpha * k), optionally shifted by a per-field offset.
+template <int DIM, int TW>
+struct GState {
+  NbEntry ent[kMaxEnt];
+  unsigned long long m[DIM][TW];
+};
+
+// Stage value source: y = u (+ alpha * k), minus a per-field offset in FP32 tiles.
 template <typename TT, typename KT, bool HASK>
 struct YSrc {
   const double* u;
@@ -82,164 +93,332 @@ struct YSrc {
   }
 };
 
-// Paint the tile [-H, BS-1+H]^DIM of block d; group by group with a barrier in
-// between so that finer leaves overwrite coarser ones.  mask (if non-null)
-// receives dl + 2 for every painted point.
-template <int DIM, int BS, int H, int NF, typename TT, typename SRC>
-__device__ void paint(TT* tile, uint8_t* mask, const BlockDesc& d, const NbEntry* nb, const SRC& src) {
-  using G = TileGeo<DIM, BS, H>;
-  constexpr int NP = G::NP;
-  int e = d.nb_begin;
-  const int ng[3] = {d.n_coarse, d.n_same, d.n_fine};
-  for (int g = 0; g < 3; ++g) {
-    for (int q = 0; q < ng[g]; ++q, ++e) {
-      const NbEntry E = nb[e];
-      const int dl = E.dl;
+// Load the block's entries and build the per-axis candidate masks of the tile.
+template <int DIM, int BS, int S, int H>
+__device__ void gsetup(GState<DIM, S + 2 * H>& g, const BlockDesc& d, const NbEntry* nb, const int* r0) {
+  constexpr int TW = S + 2 * H;
+  const int ne = d.n_ent;
+  for (int i = threadIdx.x; i < ne; i += blockDim.x) g.ent[i] = nb[d.nb_begin + i];
+  __syncthreads();
+  for (int q = threadIdx.x; q < DIM * TW; q += blockDim.x) {
+    const int a = q / TW, it = q % TW, t = r0[a] - H + it;
+    unsigned long long mm = 0;
+    for (int e = 0; e < ne; ++e) {
+      const int dl = g.ent[e].dl;
       const int ext = dl > 0 ? (BS - 1) / 2 : (dl == 0 ? BS - 1 : 2 * (BS - 1));
-      const int step = dl < 0 ? 2 : 1;
-      int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
-      bool empty = false;
-      for (int a = 0; a < DIM; ++a) {
-        int a0 = max(E.o[a], -H), a1 = min(E.o[a] + ext, BS - 1 + H);
-        if (dl < 0 && ((a0 - E.o[a]) & 1)) ++a0;
-        if (a1 < a0) empty = true;
-        lo[a] = a0;
-        cnt[a] = (a1 - a0) / step + 1;
-      }
-      if (empty) continue;
-      const int total = cnt[0] * cnt[1] * (DIM > 2 ? cnt[2] : 1);
-      const size_t sbase = (size_t)E.slot * NF * NP;
-      for (int p = threadIdx.x; p < total; p += blockDim.x) {
-        int t[3] = {0, 0, 0}, s[3] = {0, 0, 0};
-        int rem = p;
-        t[0] = lo[0] + (rem % cnt[0]) * step;
-        rem /= cnt[0];
-        t[1] = lo[1] + (DIM > 2 ? (rem % cnt[1]) : rem) * step;
-        if (DIM > 2) t[2] = lo[2] + (rem / cnt[1]) * step;
-        for (int a = 0; a < DIM; ++a) {
-          const int l = t[a] - E.o[a];
-          s[a] = dl > 0 ? 2 * l : (dl == 0 ? l : l / 2);
-        }
-        const int sidx = s[0] + BS * s[1] + (DIM > 2 ? BS * BS * s[2] : 0);
-        const int tidx = G::at(t[0], t[1], t[2]);
-#pragma unroll
-        for (int f = 0; f < NF; ++f) tile[f * G::TSZ + tidx] = src(sbase + (size_t)f * NP + sidx, f);
-        if (mask) mask[tidx] = (uint8_t)(dl + 2);
-      }
+      const int l = t - g.ent[e].o[a];
+      if (l >= 0 && l <= ext && (dl >= 0 || (l & 1) == 0)) mm |= 1ull << e;
     }
-    __syncthreads();
+    g.m[a][it] = mm;
   }
-}
-
-template <int DIM, int BS, int H>
-__device__ void clear_mask(uint8_t* mask) {
-  using G = TileGeo<DIM, BS, H>;
-  for (int p = threadIdx.x; p < G::TSZ; p += blockDim.x) mask[p] = 0;
   __syncthreads();
 }
 
-// Predict every unpainted point of [-HW, BS-1+HW]^DIM from the even (coarse
-// lattice) points around it.
-template <int DIM, int BS, int H, int HW, int NF, typename TT>
-__device__ void predict_missing(TT* tile, const uint8_t* mask) {
-  using G = TileGeo<DIM, BS, H>;
-  constexpr int W2 = BS + 2 * HW;
-  constexpr int TOT = Pow<DIM, W2>::v;
-  for (int p = threadIdx.x; p < TOT; p += blockDim.x) {
-    int t[3] = {0, 0, 0};
-    t[0] = p % W2 - HW;
-    t[1] = (p / W2) % W2 - HW;
-    if (DIM > 2) t[2] = p / (W2 * W2) - HW;
-    const int tidx = G::at(t[0], t[1], t[2]);
-    if (mask[tidx]) continue;
-    int base[3], stride[3] = {2, 2, 2}, n[3] = {1, 1, 1};
-    for (int a = 0; a < 3; ++a) base[a] = t[a];
+// Tile point p -> tile coords, block-local coords, distance to the region, parity,
+// and the candidate mask.
+template <int DIM, int S, int H>
+struct PointInfo {
+  int i[3], t[3], dist;
+  bool even;
+  unsigned long long cand;
+  __device__ __forceinline__ PointInfo(int p, const GState<DIM, S + 2 * H>& g, const int* r0, const int* cnt) {
+    constexpr int TW = S + 2 * H;
+    i[0] = p % TW;
+    i[1] = DIM > 2 ? (p / TW) % TW : p / TW;
+    i[2] = DIM > 2 ? p / (TW * TW) : 0;
+    t[2] = 0;
+    dist = 0;
+    even = true;
+    cand = ~0ull;
+    for (int a = 0; a < DIM; ++a) {
+      const int u = i[a] - H;
+      t[a] = r0[a] + u;
+      const int da = u < 0 ? -u : (u >= cnt[a] ? u - cnt[a] + 1 : 0);
+      dist = da > dist ? da : dist;
+      if (t[a] & 1) even = false;
+      cand &= g.m[a][i[a]];
+    }
+  }
+};
+
+// Gather the tile: points within hw_all of the region, and even points within
+// h_even (coarse-lattice inputs of the prediction).  One load round per thread batch.
+template <int DIM, int BS, int S, int H, int NF, typename TT, typename SRC>
+__device__ void gfill(TT* tile, const GState<DIM, S + 2 * H>& g, const int* r0, const int* cnt, int hw_all, int h_even,
+                      const SRC& src) {
+  using G = Geo<DIM, BS, S, H>;
+  constexpr int TSZ = G::TSZ, NP = G::NP;
+  constexpr int B = 4;
+  for (int base = 0; base < TSZ; base += B * blockDim.x) {
+    size_t addr[B];
+    int pos[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int p = base + q * blockDim.x + threadIdx.x;
+      pos[q] = -1;
+      addr[q] = 0;
+      if (p >= TSZ) continue;
+      PointInfo<DIM, S, H> P(p, g, r0, cnt);
+      const bool need = P.dist <= hw_all || (P.even && P.dist <= h_even);
+      if (!need || P.cand == 0) continue;
+      const NbEntry& E = g.ent[63 - __clzll((long long)P.cand)];
+      int sidx = 0, mul = 1;
+      for (int a = 0; a < DIM; ++a) {
+        const int l = P.t[a] - E.o[a];
+        sidx += (E.dl > 0 ? 2 * l : (E.dl == 0 ? l : l >> 1)) * mul;
+        mul *= BS;
+      }
+      addr[q] = (size_t)E.slot * NF * NP + sidx;
+      pos[q] = p;
+    }
+    TT v[B][NF];
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      if (pos[q] >= 0) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[q][f] = src(addr[q] + (size_t)f * NP, f);
+      }
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      if (pos[q] >= 0) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) tile[f * TSZ + pos[q]] = v[q][f];
+      }
+  }
+  __syncthreads();
+}
+
+// Predict the points within hw_all of the region that no leaf holds on its lattice.
+template <int DIM, int BS, int S, int H, int NF, typename TT>
+__device__ void gpredict(TT* tile, const GState<DIM, S + 2 * H>& g, const int* r0, const int* cnt, int hw_all) {
+  using G = Geo<DIM, BS, S, H>;
+  constexpr int TSZ = G::TSZ;
+  for (int p = threadIdx.x; p < TSZ; p += blockDim.x) {
+    PointInfo<DIM, S, H> P(p, g, r0, cnt);
+    if (P.dist > hw_all || P.cand != 0) continue;
+    int base[3] = {P.i[0], P.i[1], P.i[2]}, stride[3] = {2, 2, 2}, n[3] = {1, 1, 1};
     for (int a = 0; a < DIM; ++a)
-      if (t[a] & 1) { base[a] = t[a] - 3; n[a] = 4; }
+      if (P.t[a] & 1) { base[a] = P.i[a] - 3; n[a] = 4; }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      const TT* T = tile + f * G::TSZ;
-      auto at = [&](int x, int y, int z) { return T[G::at(x, y, z)]; };
-      tile[f * G::TSZ + tidx] = tensor_p<DIM, TT>(at, base, stride, n);
+      const TT* T = tile + f * TSZ;
+      auto at = [&](int x, int y, int z) { return T[G::idx(x, y, z)]; };
+      tile[f * TSZ + p] = tensor_p<DIM, TT>(at, base, stride, n);
     }
   }
   __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// right-hand sides on a synchronised tile (advection)
-// ---------------------------------------------------------------------------
-template <int DIM, int BS, int H, typename TT, int PHYS>
-__device__ __forceinline__ TT rhs_adv(const TT* T, const BlockDesc& d, int i, int j, int k, TT r,
-                                      const Physics& ph, double cfac, int nl, int shift) {
-  using G = TileGeo<DIM, BS, H>;
-  TT dx = D4(T[G::at(i - 2, j, k)], T[G::at(i - 1, j, k)], T[G::at(i + 1, j, k)], T[G::at(i + 2, j, k)], r);
-  TT dy = D4(T[G::at(i, j - 2, k)], T[G::at(i, j - 1, k)], T[G::at(i, j + 1, k)], T[G::at(i, j + 2, k)], r);
-  if constexpr (PHYS == 0) {
-    TT c0, c1, c2;
-    if constexpr (sizeof(TT) == 8) { c0 = ph.c[0]; c1 = ph.c[1]; c2 = ph.c[2]; }
-    else { c0 = ph.cf[0]; c1 = ph.cf[1]; c2 = ph.cf[2]; }
-    TT acc = c0 * dx;
-    acc = acc + c1 * dy;
-    if constexpr (DIM > 2) {
-      TT dz = D4(T[G::at(i, j, k - 2)], T[G::at(i, j, k - 1)], T[G::at(i, j, k + 1)], T[G::at(i, j, k + 2)], r);
-      acc = acc + c2 * dz;
-    }
-    return -acc;
-  } else {
-    int gx = d.c[0] * (BS - 1) + i;
-    int gy = d.c[1] * (BS - 1) + j;
-    if (gx >= nl) gx -= nl;
-    if (gy >= nl) gy -= nl;
-    gx <<= shift;
-    gy <<= shift;
-    const double U = (ph.s2[gx] * ph.s[gy]) * cfac;
-    const double W = -((ph.s2[gy] * ph.s[gx]) * cfac);
-    return -(((TT)U * dx) + ((TT)W * dy));
+template <int DIM>
+__device__ __forceinline__ void subregion(int sub, int nsub, int S, int BS, int* r0, int* cnt) {
+  r0[0] = r0[1] = r0[2] = 0;
+  cnt[0] = cnt[1] = cnt[2] = 1;
+  for (int a = 0; a < DIM; ++a) {
+    const int sa = sub % nsub;
+    sub /= nsub;
+    r0[a] = sa * S;
+    cnt[a] = min(S, BS - r0[a]);
   }
 }
 
 // ---------------------------------------------------------------------------
-// fused stage kernel: paint y_s, predict missing ghosts, RHS, store
+// advection right-hand side at block-local node t (tile coordinates i)
 // ---------------------------------------------------------------------------
-template <int DIM, int BS, int HW, int NF, typename TT, typename KT, int PHYS>
-__global__ void __launch_bounds__(kNT) k_stage(StageArgs A) {
-  constexpr int H = HW + 2;
-  using G = TileGeo<DIM, BS, H>;
-  constexpr int NP = G::NP;
+template <int DIM, int BS, int S, int H, typename TT>
+__device__ __forceinline__ TT rhs_adv(const TT* T, const int* i, const int* t, const BlockDesc& d, TT r,
+                                      const StageArgs& A) {
+  using G = Geo<DIM, BS, S, H>;
+  const int x = i[0], y = i[1], z = i[2];
+  const TT dx = D4(T[G::idx(x - 2, y, z)], T[G::idx(x - 1, y, z)], T[G::idx(x + 1, y, z)], T[G::idx(x + 2, y, z)], r);
+  const TT dy = D4(T[G::idx(x, y - 2, z)], T[G::idx(x, y - 1, z)], T[G::idx(x, y + 1, z)], T[G::idx(x, y + 2, z)], r);
+  if (A.ph.kind == 0) {
+    TT acc = (TT)A.ph.c[0] * dx;
+    acc = acc + (TT)A.ph.c[1] * dy;
+    if constexpr (DIM > 2) {
+      const TT dz = D4(T[G::idx(x, y, z - 2)], T[G::idx(x, y, z - 1)], T[G::idx(x, y, z + 1)], T[G::idx(x, y, z + 2)], r);
+      acc = acc + (TT)A.ph.c[2] * dz;
+    }
+    return -acc;
+  }
+  // swirl: u = sin^2(pi x) sin(2 pi y), v = -sin^2(pi y) sin(2 pi x) from tables on the finest lattice
+  const int nl = A.lt.nl[d.level], shift = A.ph.jmax - d.level;
+  int gx = d.c[0] * (BS - 1) + t[0];
+  int gy = d.c[1] * (BS - 1) + t[1];
+  if (gx >= nl) gx -= nl;
+  if (gy >= nl) gy -= nl;
+  gx <<= shift;
+  gy <<= shift;
+  const double U = (A.ph.s2[gx] * A.ph.s[gy]) * A.cfac;
+  const double W = -((A.ph.s2[gy] * A.ph.s[gx]) * A.cfac);
+  return -(((TT)U * dx) + ((TT)W * dy));
+}
+
+// ---------------------------------------------------------------------------
+// Navier-Stokes (2D, primitive variables rho, u, v, p): stresses and heat flux
+// on [-2, cnt+1]^2 around the region, then the RHS at the region's nodes.
+// The tile is FP64.  CT is the arithmetic type: FP64, or FP32 in the mixed form,
+// where neighbour differences are still formed in FP64 (exact for close values,
+// which FP32 cannot resolve next to a mean flow of O(1)) and everything after the
+// difference -- scaling, products, sums, the stress and flux fields -- is FP32.
+// ---------------------------------------------------------------------------
+template <typename CT>
+struct NsConst {
+  CT mu, kap, gam, c23, r;
+};
+
+// first derivative from four FP64 samples: differences in FP64, the rest in CT
+template <typename CT>
+__device__ __forceinline__ CT D4d(double um2, double um1, double up1, double up2, CT r) {
+  if constexpr (sizeof(CT) == 8) return D4(um2, um1, up1, up2, r);
+  else return (8.0f * (CT)(up1 - um1) - (CT)(up2 - um2)) * r;
+}
+
+template <int BS, int S, int H, typename CT>
+__device__ void ns_fluxes(const double* T, CT* W, const int* cnt, const NsConst<CT>& K) {
+  using G = Geo<2, BS, S, H>;
+  constexpr int TSZ = G::TSZ, SW = S + 4, SSZ = SW * SW;
+  const double* fr = T;
+  const double* fu = T + TSZ;
+  const double* fv = T + 2 * TSZ;
+  const double* fp = T + 3 * TSZ;
+  const int nx = cnt[0] + 4, ny = cnt[1] + 4;
+  for (int p = threadIdx.x; p < nx * ny; p += blockDim.x) {
+    const int ux0 = p % nx - 2, uy0 = p / nx - 2;       // region-local position
+    const int x = ux0 + H, y = uy0 + H;                  // tile coordinates
+    auto A = [&](const double* F, int xx, int yy) { return F[G::idx(xx, yy, 0)]; };
+    auto Tt = [&](int xx, int yy) { return A(fp, xx, yy) / A(fr, xx, yy); };
+    const CT ux = D4d<CT>(A(fu, x - 2, y), A(fu, x - 1, y), A(fu, x + 1, y), A(fu, x + 2, y), K.r);
+    const CT uy = D4d<CT>(A(fu, x, y - 2), A(fu, x, y - 1), A(fu, x, y + 1), A(fu, x, y + 2), K.r);
+    const CT vx = D4d<CT>(A(fv, x - 2, y), A(fv, x - 1, y), A(fv, x + 1, y), A(fv, x + 2, y), K.r);
+    const CT vy = D4d<CT>(A(fv, x, y - 2), A(fv, x, y - 1), A(fv, x, y + 1), A(fv, x, y + 2), K.r);
+    const CT div = ux + vy;
+    const CT tx = D4d<CT>(Tt(x - 2, y), Tt(x - 1, y), Tt(x + 1, y), Tt(x + 2, y), K.r);
+    const CT ty = D4d<CT>(Tt(x, y - 2), Tt(x, y - 1), Tt(x, y + 1), Tt(x, y + 2), K.r);
+    const int w = (ux0 + 2) + SW * (uy0 + 2);
+    W[w] = K.mu * (CT(2) * ux - K.c23 * div);           // tau_xx
+    W[SSZ + w] = K.mu * (CT(2) * vy - K.c23 * div);     // tau_yy
+    W[2 * SSZ + w] = K.mu * (uy + vx);                  // tau_xy
+    W[3 * SSZ + w] = -(K.kap * tx);                     // q_x
+    W[4 * SSZ + w] = -(K.kap * ty);                     // q_y
+  }
+  __syncthreads();
+}
+
+template <int BS, int S, int H, typename CT>
+__device__ __forceinline__ void ns_rhs(const double* T, const CT* W, int ux0, int uy0, const NsConst<CT>& K, CT* out) {
+  using G = Geo<2, BS, S, H>;
+  constexpr int TSZ = G::TSZ, SW = S + 4, SSZ = SW * SW;
+  const int x = ux0 + H, y = uy0 + H;
+  const double* fr = T;
+  const double* fu = T + TSZ;
+  const double* fv = T + 2 * TSZ;
+  const double* fp = T + 3 * TSZ;
+  auto A = [&](const double* F, int xx, int yy) { return F[G::idx(xx, yy, 0)]; };
+  auto mxx = [&](int xx, int yy) { return A(fr, xx, yy) * A(fu, xx, yy); };
+  auto myy = [&](int xx, int yy) { return A(fr, xx, yy) * A(fv, xx, yy); };
+  auto Wl = [&](int k, int lx, int ly) { return W[k * SSZ + (lx + 2) + SW * (ly + 2)]; };
+  const CT rho = (CT)A(fr, x, y), uu = (CT)A(fu, x, y), vv = (CT)A(fv, x, y), pp = (CT)A(fp, x, y);
+  const CT ux = D4d<CT>(A(fu, x - 2, y), A(fu, x - 1, y), A(fu, x + 1, y), A(fu, x + 2, y), K.r);
+  const CT uy = D4d<CT>(A(fu, x, y - 2), A(fu, x, y - 1), A(fu, x, y + 1), A(fu, x, y + 2), K.r);
+  const CT vx = D4d<CT>(A(fv, x - 2, y), A(fv, x - 1, y), A(fv, x + 1, y), A(fv, x + 2, y), K.r);
+  const CT vy = D4d<CT>(A(fv, x, y - 2), A(fv, x, y - 1), A(fv, x, y + 1), A(fv, x, y + 2), K.r);
+  const CT px = D4d<CT>(A(fp, x - 2, y), A(fp, x - 1, y), A(fp, x + 1, y), A(fp, x + 2, y), K.r);
+  const CT py = D4d<CT>(A(fp, x, y - 2), A(fp, x, y - 1), A(fp, x, y + 1), A(fp, x, y + 2), K.r);
+  const CT dmx = D4d<CT>(mxx(x - 2, y), mxx(x - 1, y), mxx(x + 1, y), mxx(x + 2, y), K.r);
+  const CT dmy = D4d<CT>(myy(x, y - 2), myy(x, y - 1), myy(x, y + 1), myy(x, y + 2), K.r);
+  const CT dtxx = D4(Wl(0, ux0 - 2, uy0), Wl(0, ux0 - 1, uy0), Wl(0, ux0 + 1, uy0), Wl(0, ux0 + 2, uy0), K.r);
+  const CT dtxy_y = D4(Wl(2, ux0, uy0 - 2), Wl(2, ux0, uy0 - 1), Wl(2, ux0, uy0 + 1), Wl(2, ux0, uy0 + 2), K.r);
+  const CT dtxy_x = D4(Wl(2, ux0 - 2, uy0), Wl(2, ux0 - 1, uy0), Wl(2, ux0 + 1, uy0), Wl(2, ux0 + 2, uy0), K.r);
+  const CT dtyy = D4(Wl(1, ux0, uy0 - 2), Wl(1, ux0, uy0 - 1), Wl(1, ux0, uy0 + 1), Wl(1, ux0, uy0 + 2), K.r);
+  const CT dqx = D4(Wl(3, ux0 - 2, uy0), Wl(3, ux0 - 1, uy0), Wl(3, ux0 + 1, uy0), Wl(3, ux0 + 2, uy0), K.r);
+  const CT dqy = D4(Wl(4, ux0, uy0 - 2), Wl(4, ux0, uy0 - 1), Wl(4, ux0, uy0 + 1), Wl(4, ux0, uy0 + 2), K.r);
+  const CT txx = Wl(0, ux0, uy0), tyy = Wl(1, ux0, uy0), txy = Wl(2, ux0, uy0);
+  out[0] = -(dmx + dmy);
+  out[1] = -(uu * ux + vv * uy) - px / rho + (dtxx + dtxy_y) / rho;
+  out[2] = -(uu * vx + vv * vy) - py / rho + (dtxy_x + dtyy) / rho;
+  const CT phi = txx * ux + txy * (uy + vx) + tyy * vy;
+  const CT divq = dqx + dqy;
+  out[3] = -(uu * px + vv * py) - K.gam * pp * (ux + vy) + (K.gam - CT(1)) * (phi - divq);
+}
+
+// ---------------------------------------------------------------------------
+// fused stage kernel: gather y_s, predict missing ghosts, RHS, store
+// ---------------------------------------------------------------------------
+template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
+__global__ void __launch_bounds__(256) k_stage(StageArgs A) {
+  constexpr int S = (BS + NSUB - 1) / NSUB, H = HW + 3;
+  using G = Geo<DIM, BS, S, H>;
+  constexpr int NP = G::NP, TSZ = G::TSZ;
+  constexpr int NSUBT = Pow<DIM, NSUB>::v;
+  constexpr bool NS = NF == 4;
+  __shared__ GState<DIM, G::TW> g;
   extern __shared__ __align__(16) char smem[];
   TT* tile = reinterpret_cast<TT*>(smem);
-  uint8_t* mask = reinterpret_cast<uint8_t*>(smem + sizeof(TT) * NF * G::TSZ);
-  const int nblk = A.list ? A.list_n : *A.count;
-  for (int bi = blockIdx.x; bi < nblk; bi += gridDim.x) {
-    const int b = A.list ? A.list[bi] : bi;
-    const BlockDesc d = A.blk[b];
-    clear_mask<DIM, BS, H>(mask);
+  CT* W = reinterpret_cast<CT*>(tile + NF * TSZ);  // NS stresses / fluxes
+  const int nblk = A.topo.h->n_blocks;
+  const BlockDesc* blk = A.topo.blk();
+  const NbEntry* nb = A.topo.nb();
+  for (int w = blockIdx.x; w < nblk * NSUBT; w += gridDim.x) {
+    const int b = w / NSUBT;
+    const BlockDesc d = blk[b];
+    int r0[3], cnt[3];
+    subregion<DIM>(w % NSUBT, NSUB, S, BS, r0, cnt);
+    gsetup<DIM, BS, S, H>(g, d, nb, r0);
+    const int h_even = d.n_coarse > 0 ? H : 0;
     if (A.stage == 1) {
       YSrc<TT, KT, false> src{A.u, nullptr, 0.0, A.off};
-      paint<DIM, BS, H, NF, TT>(tile, mask, d, A.nb, src);
+      gfill<DIM, BS, S, H, NF, TT>(tile, g, r0, cnt, HW, h_even, src);
     } else {
       YSrc<TT, KT, true> src{A.u, (const KT*)A.kprev, A.alpha, A.off};
-      paint<DIM, BS, H, NF, TT>(tile, mask, d, A.nb, src);
+      gfill<DIM, BS, S, H, NF, TT>(tile, g, r0, cnt, HW, h_even, src);
     }
-    predict_missing<DIM, BS, H, HW, NF, TT>(tile, mask);
+    if (d.n_coarse > 0) gpredict<DIM, BS, S, H, NF, TT>(tile, g, r0, cnt, HW);
     TT r;
     if constexpr (sizeof(TT) == 8) r = A.lt.r[d.level];
     else r = A.lt.rf[d.level];
-    const int nl = A.lt.nl[d.level];
-    const int shift = A.ph.jmax - d.level;
     const size_t base = (size_t)d.slot * NF * NP;
-    for (int p = threadIdx.x; p < NP; p += blockDim.x) {
-      const int i = p % BS, j = (p / BS) % BS, k = DIM > 2 ? p / (BS * BS) : 0;
-      const TT kv = rhs_adv<DIM, BS, H, TT, PHYS>(tile, d, i, j, k, r, A.ph, A.cfac, nl, shift);
-      if (A.stage < 4) {
-        ((KT*)A.kout)[base + p] = (KT)kv;
-      } else {
-        const double k1 = (double)((const KT*)A.k1)[base + p];
-        const double k2 = (double)((const KT*)A.k2)[base + p];
-        const double k3 = (double)((const KT*)A.k3)[base + p];
-        const double k4 = (double)kv;
-        A.unew[base + p] = A.u[base + p] + A.h6 * ((k1 + k4) + 2.0 * (k2 + k3));
+    const int nn = cnt[0] * cnt[1] * (DIM > 2 ? cnt[2] : 1);
+    if constexpr (NS) {
+      static_assert(sizeof(TT) == 8, "the NS tile is FP64");
+      NsConst<CT> K;
+      K.mu = (CT)A.ph.mu;
+      K.kap = (CT)A.ph.kap;
+      K.gam = (CT)A.ph.gamma;
+      K.c23 = (CT)(2.0 / 3.0);
+      if constexpr (sizeof(CT) == 8) K.r = A.lt.r[d.level];
+      else K.r = A.lt.rf[d.level];
+      ns_fluxes<BS, S, H, CT>(tile, W, cnt, K);
+      for (int p = threadIdx.x; p < nn; p += blockDim.x) {
+        const int lx = p % cnt[0], ly = p / cnt[0];
+        CT kv[4];
+        ns_rhs<BS, S, H, CT>(tile, W, lx, ly, K, kv);
+        const int node = (r0[0] + lx) + BS * (r0[1] + ly);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const size_t q = base + (size_t)f * NP + node;
+          if (A.stage < 4) {
+            ((KT*)A.kout)[q] = (KT)kv[f];
+          } else {
+            const double k1 = (double)((const KT*)A.k1)[q], k2 = (double)((const KT*)A.k2)[q];
+            const double k3 = (double)((const KT*)A.k3)[q], k4 = (double)kv[f];
+            A.unew[q] = A.u[q] + A.h6 * ((k1 + k4) + 2.0 * (k2 + k3));
+          }
+        }
+      }
+    } else {
+      for (int p = threadIdx.x; p < nn; p += blockDim.x) {
+        int l[3] = {p % cnt[0], DIM > 2 ? (p / cnt[0]) % cnt[1] : p / cnt[0], DIM > 2 ? p / (cnt[0] * cnt[1]) : 0};
+        int t[3] = {r0[0] + l[0], r0[1] + l[1], r0[2] + l[2]};
+        int i[3] = {l[0] + H, l[1] + H, DIM > 2 ? l[2] + H : 0};
+        const TT kv = rhs_adv<DIM, BS, S, H, TT>(tile, i, t, d, r, A);
+        const size_t q = base + t[0] + BS * t[1] + (DIM > 2 ? BS * BS * t[2] : 0);
+        if (A.stage < 4) {
+          ((KT*)A.kout)[q] = (KT)kv;
+        } else {
+          const double k1 = (double)((const KT*)A.k1)[q], k2 = (double)((const KT*)A.k2)[q];
+          const double k3 = (double)((const KT*)A.k3)[q], k4 = (double)kv;
+          A.unew[q] = A.u[q] + A.h6 * ((k1 + k4) + 2.0 * (k2 + k3));
+        }
       }
     }
     __syncthreads();
@@ -247,56 +426,57 @@ __global__ void __launch_bounds__(kNT) k_stage(StageArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// plain form: ghost fill into HBM, then a separate RHS + update kernel
+// plain form: ghost fill into HBM per level, then a separate RHS + update kernel
 // ---------------------------------------------------------------------------
-template <int DIM, int BS, int HW, int NF>
-__global__ void __launch_bounds__(kNT) k_ghost(StageArgs A) {
-  constexpr int H = HW + 2;
-  using G = TileGeo<DIM, BS, H>;
+template <int DIM, int BS, int HW>
+__global__ void __launch_bounds__(256) k_ghost(StageArgs A) {
+  constexpr int H = HW + 3, S = BS;
+  using G = Geo<DIM, BS, S, H>;
   constexpr int GW = BS + 2 * HW;
   constexpr int GSZ = Pow<DIM, GW>::v;
+  __shared__ GState<DIM, G::TW> g;
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
-  uint8_t* mask = reinterpret_cast<uint8_t*>(smem + sizeof(double) * NF * G::TSZ);
-  const int nblk = A.list ? A.list_n : *A.count;
-  for (int bi = blockIdx.x; bi < nblk; bi += gridDim.x) {
-    const int b = A.list ? A.list[bi] : bi;
-    const BlockDesc d = A.blk[b];
-    clear_mask<DIM, BS, H>(mask);
+  const int n = A.lvl_end - A.lvl_begin;
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int b = A.topo.list()[A.lvl_begin + w];
+    const BlockDesc d = A.topo.blk()[b];
+    int r0[3] = {0, 0, 0}, cnt[3] = {BS, DIM > 1 ? BS : 1, DIM > 2 ? BS : 1};
+    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(), r0);
+    const int h_even = d.n_coarse > 0 ? H : 0;
     if (A.stage == 1) {
       YSrc<double, double, false> src{A.u, nullptr, 0.0, A.off};
-      paint<DIM, BS, H, NF, double>(tile, mask, d, A.nb, src);
+      gfill<DIM, BS, S, H, 1, double>(tile, g, r0, cnt, HW, h_even, src);
     } else {
       YSrc<double, double, true> src{A.u, (const double*)A.kprev, A.alpha, A.off};
-      paint<DIM, BS, H, NF, double>(tile, mask, d, A.nb, src);
+      gfill<DIM, BS, S, H, 1, double>(tile, g, r0, cnt, HW, h_even, src);
     }
-    predict_missing<DIM, BS, H, HW, NF, double>(tile, mask);
-    double* g = A.ghost + (size_t)d.slot * NF * GSZ;
+    if (d.n_coarse > 0) gpredict<DIM, BS, S, H, 1, double>(tile, g, r0, cnt, HW);
+    double* gh = A.ghost + (size_t)d.slot * GSZ;
     for (int p = threadIdx.x; p < GSZ; p += blockDim.x) {
-      const int x = p % GW - HW, y = (p / GW) % GW - HW, z = DIM > 2 ? p / (GW * GW) - HW : 0;
-#pragma unroll
-      for (int f = 0; f < NF; ++f) g[(size_t)f * GSZ + p] = tile[f * G::TSZ + G::at(x, y, z)];
+      const int x = p % GW, y = (p / GW) % GW, z = DIM > 2 ? p / (GW * GW) : 0;
+      gh[p] = tile[G::idx(x + 3, y + 3, DIM > 2 ? z + 3 : 0)];
     }
     __syncthreads();
   }
 }
 
-template <int DIM, int BS, int HW, int NF, int PHYS>
-__global__ void __launch_bounds__(kNT) k_rhs_plain(StageArgs A) {
-  using G = TileGeo<DIM, BS, HW>;
-  constexpr int NP = G::NP;
-  const int nblk = A.list ? A.list_n : *A.count;
-  for (int bi = blockIdx.x; bi < nblk; bi += gridDim.x) {
-    const int b = A.list ? A.list[bi] : bi;
-    const BlockDesc d = A.blk[b];
-    const double* T = A.ghost + (size_t)d.slot * NF * G::TSZ;
+template <int DIM, int BS, int HW>
+__global__ void __launch_bounds__(256) k_rhs_plain(StageArgs A) {
+  constexpr int GW = BS + 2 * HW;
+  constexpr int NP = Pow<DIM, BS>::v, GSZ = Pow<DIM, GW>::v;
+  using G = Geo<DIM, BS, BS, HW>;
+  const int n = A.lvl_end - A.lvl_begin;
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int b = A.topo.list()[A.lvl_begin + w];
+    const BlockDesc d = A.topo.blk()[b];
+    const double* T = A.ghost + (size_t)d.slot * GSZ;
     const double r = A.lt.r[d.level];
-    const int nl = A.lt.nl[d.level];
-    const int shift = A.ph.jmax - d.level;
-    const size_t base = (size_t)d.slot * NF * NP;
+    const size_t base = (size_t)d.slot * NP;
     for (int p = threadIdx.x; p < NP; p += blockDim.x) {
-      const int i = p % BS, j = (p / BS) % BS, k = DIM > 2 ? p / (BS * BS) : 0;
-      const double kv = rhs_adv<DIM, BS, HW, double, PHYS>(T, d, i, j, k, r, A.ph, A.cfac, nl, shift);
+      int t[3] = {p % BS, (p / BS) % BS, DIM > 2 ? p / (BS * BS) : 0};
+      int i[3] = {t[0] + HW, t[1] + HW, DIM > 2 ? t[2] + HW : 0};
+      const double kv = rhs_adv<DIM, BS, BS, HW, double>(T, i, t, d, r, A);
       if (A.stage < 4) {
         ((double*)A.kout)[base + p] = kv;
       } else {
@@ -306,6 +486,7 @@ __global__ void __launch_bounds__(kNT) k_rhs_plain(StageArgs A) {
         A.unew[base + p] = A.u[base + p] + A.h6 * ((k1 + kv) + 2.0 * (k2 + k3));
       }
     }
+    (void)G::TSZ;
   }
 }
 
@@ -320,46 +501,49 @@ __device__ __forceinline__ double nanmax(double a, double b) {
 }
 
 template <int DIM, int BS, int NF>
-__global__ void __launch_bounds__(kNT) k_mr(MrArgs A) {
-  constexpr int H = 2;
-  using G = TileGeo<DIM, BS, H>;
-  constexpr int NP = G::NP;
+__global__ void __launch_bounds__(256) k_mr(MrArgs A) {
+  constexpr int H = 2, S = BS;
+  using G = Geo<DIM, BS, S, H>;
+  constexpr int NP = G::NP, TSZ = G::TSZ;
+  __shared__ GState<DIM, G::TW> g;
+  __shared__ double red[4][4];
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
-  uint8_t* mask = reinterpret_cast<uint8_t*>(smem + sizeof(double) * NF * G::TSZ);
-  __shared__ double red[kNT / 64][4];
-  const int nblk = *A.count;
+  const int nblk = A.topo.h->n_blocks;
   for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
-    const BlockDesc d = A.blk[b];
-    clear_mask<DIM, BS, H>(mask);
+    const BlockDesc d = A.topo.blk()[b];
+    int r0[3] = {0, 0, 0}, cnt[3] = {BS, BS, DIM > 2 ? BS : 1};
+    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(), r0);
     YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
-    paint<DIM, BS, H, NF, double>(tile, mask, d, A.nb, src);
+    gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, 0, H, src);
     double m[4] = {0.0, 0.0, 0.0, 0.0};
     const size_t base = (size_t)d.slot * NF * NP;
     for (int p = threadIdx.x; p < NP; p += blockDim.x) {
-      int ii[3] = {p % BS, (p / BS) % BS, DIM > 2 ? p / (BS * BS) : 0};
-      const int tidx = G::at(ii[0], ii[1], ii[2]);
+      const int t[3] = {p % BS, (p / BS) % BS, DIM > 2 ? p / (BS * BS) : 0};
+      const int ti = G::idx(t[0] + H, t[1] + H, DIM > 2 ? t[2] + H : 0);
       bool bnd = false, allEven = true;
+      unsigned long long cand = ~0ull;
       for (int a = 0; a < DIM; ++a) {
-        if (ii[a] == 0 || ii[a] == BS - 1) bnd = true;
-        if (ii[a] & 1) allEven = false;
+        if (t[a] == 0 || t[a] == BS - 1) bnd = true;
+        if (t[a] & 1) allEven = false;
+        cand &= g.m[a][t[a] + H];
       }
-      if (bnd && mask[tidx] == 3) {
+      if (bnd && g.ent[63 - __clzll((long long)cand)].dl > 0) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) A.u[base + (size_t)f * NP + p] = tile[f * G::TSZ + tidx];
+        for (int f = 0; f < NF; ++f) A.u[base + (size_t)f * NP + p] = tile[f * TSZ + ti];
       }
       if (allEven) continue;   // restriction then prediction returns these nodes unchanged
-      int bb[3], stride[3] = {2, 2, 2}, n[3] = {1, 1, 1};
-      for (int a = 0; a < 3; ++a) bb[a] = ii[a];
-      for (int a = 0; a < DIM; ++a)
-        if (ii[a] & 1) { bb[a] = ii[a] - 3; n[a] = 4; }
+      int bb[3] = {0, 0, 0}, stride[3] = {2, 2, 2}, n[3] = {1, 1, 1};
+      for (int a = 0; a < DIM; ++a) {
+        bb[a] = t[a] + H;
+        if (t[a] & 1) { bb[a] -= 3; n[a] = 4; }
+      }
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        const double* T = tile + f * G::TSZ;
-        auto at = [&](int x, int y, int z) { return T[G::at(x, y, z)]; };
+        const double* T = tile + f * TSZ;
+        auto at = [&](int x, int y, int z) { return T[G::idx(x, y, z)]; };
         const double pred = tensor_p<DIM, double>(at, bb, stride, n);
-        const double dd = fabs(T[tidx] - pred);
-        m[f] = nanmax(m[f], dd);
+        m[f] = nanmax(m[f], fabs(T[ti] - pred));
       }
     }
 #pragma unroll
@@ -384,30 +568,35 @@ __global__ void __launch_bounds__(kNT) k_mr(MrArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// refinement: children take the synchronised value at level l+1 -- the finer
-// neighbour's stored value where one holds the node, else the parent tile value
-// (even nodes) or its prediction (odd nodes)
+// refinement, one workgroup per (parent, child): the child's nodes take the
+// synchronised value at level l+1 -- a finer neighbour's stored value where one
+// holds the node, else the parent's value (even nodes) or its prediction (odd)
 // ---------------------------------------------------------------------------
 template <int DIM, int BS, int NF>
-__global__ void __launch_bounds__(kNT) k_refine(RefineArgs A) {
-  constexpr int HW = 2, H = 4;
-  using G = TileGeo<DIM, BS, H>;
-  constexpr int NP = G::NP;
-  constexpr int NCH = 1 << DIM;
+__global__ void __launch_bounds__(256) k_refine(RefineArgs A) {
+  constexpr int HWR = 2, H = HWR + 3, S = (BS - 1) / 2 + 1;
+  using G = Geo<DIM, BS, S, H>;
+  constexpr int NP = G::NP, TSZ = G::TSZ, NCH = 1 << DIM;
+  __shared__ GState<DIM, G::TW> g;
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
-  uint8_t* mask = reinterpret_cast<uint8_t*>(smem + sizeof(double) * NF * G::TSZ);
-  const int nref = *A.count;
-  for (int r = blockIdx.x; r < nref; r += gridDim.x) {
-    const RefineDesc R = A.ref[r];
-    const BlockDesc d = A.blk[R.blk];
-    clear_mask<DIM, BS, H>(mask);
+  const int nref = A.topo.h->n_ref;
+  for (int w = blockIdx.x; w < nref * NCH; w += gridDim.x) {
+    const int ri = w / NCH, ch = w % NCH;
+    const RefineDesc R = A.topo.ref()[ri];
+    const BlockDesc d = A.topo.pblk()[R.pblk];
+    int r0[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+    for (int a = 0; a < DIM; ++a) {
+      r0[a] = ((ch >> a) & 1) * ((BS - 1) / 2);
+      cnt[a] = S;
+    }
+    gsetup<DIM, BS, S, H>(g, d, A.topo.pnb(), r0);
+    const int h_even = d.n_coarse > 0 ? H : 0;
     YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
-    paint<DIM, BS, H, NF, double>(tile, mask, d, A.nb, src);
-    predict_missing<DIM, BS, H, HW, NF, double>(tile, mask);
-    const int fine0 = d.nb_begin + d.n_coarse + d.n_same;
-    for (int p = threadIdx.x; p < NCH * NP; p += blockDim.x) {
-      const int ch = p / NP, q = p % NP;
+    gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, HWR, h_even, src);
+    if (d.n_coarse > 0) gpredict<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, HWR);
+    const size_t cbase = (size_t)R.child[ch] * NF * NP;
+    for (int q = threadIdx.x; q < NP; q += blockDim.x) {
       int Q[3] = {q % BS, (q / BS) % BS, DIM > 2 ? q / (BS * BS) : 0};
       bool bnd = false, allEven = true;
       for (int a = 0; a < DIM; ++a) {
@@ -415,11 +604,11 @@ __global__ void __launch_bounds__(kNT) k_refine(RefineArgs A) {
         if (Q[a] == 0 || Q[a] == 2 * (BS - 1)) bnd = true;
         if (Q[a] & 1) allEven = false;
       }
-      const size_t cbase = (size_t)R.child[ch] * NF * NP + q;
       int src_slot = -1, sidx = 0;
       if (bnd && !allEven) {
-        for (int e = fine0; e < fine0 + d.n_fine; ++e) {
-          const NbEntry E = A.nb[e];
+        for (int e = 0; e < d.n_ent && src_slot < 0; ++e) {
+          const NbEntry& E = g.ent[e];
+          if (E.dl <= 0) continue;
           bool in = true;
           int s = 0, mul = 1;
           for (int a = 0; a < DIM; ++a) {
@@ -428,25 +617,25 @@ __global__ void __launch_bounds__(kNT) k_refine(RefineArgs A) {
             s += l * mul;
             mul *= BS;
           }
-          if (in) { src_slot = E.slot; sidx = s; break; }
+          if (in) { src_slot = E.slot; sidx = s; }
         }
       }
       if (src_slot >= 0) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f)
-          A.u[cbase + (size_t)f * NP] = A.u[((size_t)src_slot * NF + f) * NP + sidx];
+        for (int f = 0; f < NF; ++f) A.u[cbase + (size_t)f * NP + q] = A.u[((size_t)src_slot * NF + f) * NP + sidx];
         continue;
       }
       int bb[3] = {0, 0, 0}, stride[3] = {1, 1, 1}, n[3] = {1, 1, 1};
       for (int a = 0; a < DIM; ++a) {
-        if (Q[a] & 1) { bb[a] = (Q[a] - 3) / 2; n[a] = 4; }
-        else bb[a] = Q[a] / 2;
+        // parent-local coordinate -> region-local -> tile coordinate
+        if (Q[a] & 1) { bb[a] = (Q[a] - 3) / 2 - r0[a] + H; n[a] = 4; }
+        else bb[a] = Q[a] / 2 - r0[a] + H;
       }
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        const double* T = tile + f * G::TSZ;
-        auto at = [&](int x, int y, int z) { return T[G::at(x, y, z)]; };
-        A.u[cbase + (size_t)f * NP] = tensor_p<DIM, double>(at, bb, stride, n);
+        const double* T = tile + f * TSZ;
+        auto at = [&](int x, int y, int z) { return T[G::idx(x, y, z)]; };
+        A.u[cbase + (size_t)f * NP + q] = tensor_p<DIM, double>(at, bb, stride, n);
       }
     }
     __syncthreads();
@@ -456,13 +645,14 @@ __global__ void __launch_bounds__(kNT) k_refine(RefineArgs A) {
 // coarsening: the mother keeps every second node of her children (restriction R);
 // a node shared by several children is taken from the lowest child index
 template <int DIM, int BS, int NF>
-__global__ void __launch_bounds__(kNT) k_coarsen(CoarsenArgs A) {
+__global__ void __launch_bounds__(256) k_coarsen(CoarsenArgs A) {
   constexpr int NP = Pow<DIM, BS>::v;
-  const int nfam = *A.count;
+  const int nfam = A.topo.h->n_fam;
   const long total = (long)nfam * NP;
+  const FamilyDesc* fam = A.topo.fam();
   for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < total; p += (long)gridDim.x * blockDim.x) {
     const int fi = (int)(p / NP), q = (int)(p % NP);
-    const FamilyDesc F = A.fam[fi];
+    const FamilyDesc& F = fam[fi];
     int ii[3] = {q % BS, (q / BS) % BS, DIM > 2 ? q / (BS * BS) : 0};
     int ch = 0, s = 0, mul = 1;
     for (int a = 0; a < DIM; ++a) {
@@ -479,24 +669,27 @@ __global__ void __launch_bounds__(kNT) k_coarsen(CoarsenArgs A) {
 
 // read-back of synchronised block values in forest order
 template <int DIM, int BS, int NF>
-__global__ void __launch_bounds__(kNT) k_read(ReadArgs A) {
-  constexpr int H = 0;
-  using G = TileGeo<DIM, BS, H>;
+__global__ void __launch_bounds__(256) k_read(ReadArgs A) {
+  constexpr int H = 0, S = BS;
+  using G = Geo<DIM, BS, S, H>;
   constexpr int NP = G::NP;
+  __shared__ GState<DIM, G::TW> g;
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
-  const int nblk = *A.count;
+  const int nblk = A.topo.h->n_blocks;
   for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
-    const BlockDesc d = A.blk[b];
+    const BlockDesc d = A.topo.blk()[b];
+    int r0[3] = {0, 0, 0}, cnt[3] = {BS, BS, DIM > 2 ? BS : 1};
+    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(), r0);
     YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
-    paint<DIM, BS, H, NF, double>(tile, nullptr, d, A.nb, src);
+    gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, 0, 0, src);
     for (int p = threadIdx.x; p < NF * NP; p += blockDim.x) A.out[(size_t)b * NF * NP + p] = tile[p];
     __syncthreads();
   }
 }
 
 // whole-block copy from a contiguous [n][bsz] array into pool slots
-__global__ void __launch_bounds__(kNT) k_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst) {
+__global__ void __launch_bounds__(256) k_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst) {
   const size_t total = (size_t)n * bsz;
   for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < total; p += (size_t)gridDim.x * blockDim.x) {
     const size_t b = p / bsz, q = p % bsz;
@@ -504,98 +697,64 @@ __global__ void __launch_bounds__(kNT) k_scatter(const double* src, const int* s
   }
 }
 
-hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst, hipStream_t st) {
-  const size_t total = (size_t)n * bsz;
-  const int grid = (int)std::min<size_t>(8192, (total + kNT - 1) / kNT);
-  hipLaunchKernelGGL(k_scatter, dim3(grid > 0 ? grid : 1), dim3(kNT), 0, st, src, slots, n, bsz, dst);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename K>
-static hipError_t prep(K kern, size_t lds) {
-  if (lds > 65536) return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  return hipSuccess;
-}
-
-template <int DIM, int BS, int HW, int NF>
-static hipError_t stage_impl(int precision, int grid, const StageArgs& a, hipStream_t st) {
-  constexpr int H = HW + 2;
-  using G = TileGeo<DIM, BS, H>;
-  const bool swirl = a.ph.kind == 1;
-  if (precision == 0) {
-    const size_t lds = sizeof(double) * NF * G::TSZ + G::TSZ;
-    auto kern = swirl ? k_stage<DIM, BS, HW, NF, double, double, 1> : k_stage<DIM, BS, HW, NF, double, double, 0>;
-    hipError_t e = prep(kern, lds);
+template <typename K, typename Arg>
+static hipError_t go(K kern, int grid, size_t lds, hipStream_t st, const Arg& a) {
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), lds, st, a);
-  } else {
-    const size_t lds = sizeof(float) * NF * G::TSZ + G::TSZ;
-    auto kern = swirl ? k_stage<DIM, BS, HW, NF, float, float, 1> : k_stage<DIM, BS, HW, NF, float, float, 0>;
-    hipError_t e = prep(kern, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), lds, st, a);
   }
+  hipLaunchKernelGGL(kern, dim3(grid > 0 ? grid : 1), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
-template <int DIM, int BS, int HW, int NF>
-static hipError_t ghost_impl(int grid, const StageArgs& a, hipStream_t st) {
-  constexpr int H = HW + 2;
-  using G = TileGeo<DIM, BS, H>;
-  const size_t lds = sizeof(double) * NF * G::TSZ + G::TSZ;
-  auto kern = k_ghost<DIM, BS, HW, NF>;
-  hipError_t e = prep(kern, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), lds, st, a);
-  return hipGetLastError();
+// TT: tile type, KT: slope storage type, CT: arithmetic type
+template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
+static hipError_t stage_go(int grid, const StageArgs& a, hipStream_t st) {
+  constexpr int S = (BS + NSUB - 1) / NSUB, H = HW + 3;
+  using G = Geo<DIM, BS, S, H>;
+  size_t lds = sizeof(TT) * NF * G::TSZ;
+  if (NF == 4) lds += sizeof(CT) * 5 * (S + 4) * (S + 4);
+  return go(k_stage<DIM, BS, HW, NF, NSUB, TT, KT, CT>, grid, lds, st, a);
 }
 
-template <int DIM, int BS, int HW, int NF>
-static hipError_t rhs_plain_impl(int grid, const StageArgs& a, hipStream_t st) {
-  if (a.ph.kind == 1) hipLaunchKernelGGL((k_rhs_plain<DIM, BS, HW, NF, 1>), dim3(grid), dim3(kNT), 0, st, a);
-  else hipLaunchKernelGGL((k_rhs_plain<DIM, BS, HW, NF, 0>), dim3(grid), dim3(kNT), 0, st, a);
-  return hipGetLastError();
+// FP64: FP64 tile, slopes and arithmetic.  Mixed: FP32 slopes and arithmetic; the
+// tile is FP32 (stage values minus a per-field offset) for advection and FP64 for
+// Navier-Stokes (neighbour differences formed in FP64, see ns_fluxes).
+template <int D, int B, int W, int F, int NS, int P>
+static hipError_t stage_pick(int grid, const StageArgs& a, hipStream_t st) {
+  if constexpr (P == 0) return stage_go<D, B, W, F, NS, double, double, double>(grid, a, st);
+  else if constexpr (F == 4) return stage_go<D, B, W, F, NS, double, float, float>(grid, a, st);
+  else return stage_go<D, B, W, F, NS, float, float, float>(grid, a, st);
 }
 
-template <int DIM, int BS, int NF>
-static hipError_t mr_impl(int grid, const MrArgs& a, hipStream_t st) {
-  using G = TileGeo<DIM, BS, 2>;
-  const size_t lds = sizeof(double) * NF * G::TSZ + G::TSZ;
-  auto kern = k_mr<DIM, BS, NF>;
-  hipError_t e = prep(kern, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), lds, st, a);
-  return hipGetLastError();
-}
-
-template <int DIM, int BS, int NF>
-static hipError_t refine_impl(int grid, const RefineArgs& a, hipStream_t st) {
-  using G = TileGeo<DIM, BS, 4>;
-  const size_t lds = sizeof(double) * NF * G::TSZ + G::TSZ;
-  auto kern = k_refine<DIM, BS, NF>;
-  hipError_t e = prep(kern, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), lds, st, a);
-  return hipGetLastError();
-}
-
-template <int DIM, int BS, int NF>
-static hipError_t read_impl(int grid, const ReadArgs& a, hipStream_t st) {
-  using G = TileGeo<DIM, BS, 0>;
-  const size_t lds = sizeof(double) * NF * G::TSZ;
-  auto kern = k_read<DIM, BS, NF>;
-  hipError_t e = prep(kern, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kNT), lds, st, a);
-  return hipGetLastError();
-}
+// compiled stage variants: shape, precision (0 FP64, 1 mixed), sub-tiles per axis
+#define MRB_STAGE_VARIANTS(X) \
+  X(2, 17, 2, 1, 0, 1)        \
+  X(2, 17, 2, 1, 0, 2)        \
+  X(2, 17, 2, 1, 1, 1)        \
+  X(2, 17, 2, 1, 1, 2)        \
+  X(2, 33, 2, 1, 0, 1)        \
+  X(2, 33, 2, 1, 0, 2)        \
+  X(2, 33, 2, 1, 0, 4)        \
+  X(2, 33, 2, 1, 1, 1)        \
+  X(2, 33, 2, 1, 1, 2)        \
+  X(2, 33, 2, 1, 1, 4)        \
+  X(2, 33, 4, 4, 0, 2)        \
+  X(2, 33, 4, 4, 0, 4)        \
+  X(2, 33, 4, 4, 1, 1)        \
+  X(2, 33, 4, 4, 1, 2)        \
+  X(2, 33, 4, 4, 1, 4)        \
+  X(3, 17, 2, 1, 0, 2)        \
+  X(3, 17, 2, 1, 1, 1)        \
+  X(3, 17, 2, 1, 1, 2)
 
 #define MRB_SHAPES(X) \
   X(2, 17, 2, 1)      \
   X(2, 33, 2, 1)      \
+  X(2, 33, 4, 4)      \
   X(3, 17, 2, 1)
 
 bool shape_supported(const Shape& s) {
@@ -605,52 +764,79 @@ bool shape_supported(const Shape& s) {
   return false;
 }
 
-hipError_t launch_stage(const Shape& s, int precision, int plain_rhs, int grid, const StageArgs& a, hipStream_t st) {
-#define X(D, B, W, F)                                                        \
-  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F)                     \
-    return plain_rhs ? rhs_plain_impl<D, B, W, F>(grid, a, st) : stage_impl<D, B, W, F>(precision, grid, a, st);
-  MRB_SHAPES(X)
+int stage_variants(const Shape& s, int precision, int* nsub, int cap) {
+  int n = 0;
+#define X(D, B, W, F, P, NS) \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && precision == P && n < cap) nsub[n++] = NS;
+  MRB_STAGE_VARIANTS(X)
+#undef X
+  return n;
+}
+
+hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, const StageArgs& a, hipStream_t st) {
+#define X(D, B, W, F, P, NS)                                                                     \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && precision == P && v.nsub == NS)      \
+    return stage_pick<D, B, W, F, NS, P>(grid, a, st);
+  MRB_STAGE_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_ghost(const Shape& s, int grid, const StageArgs& a, hipStream_t st) {
-#define X(D, B, W, F) if (s.dim == D && s.bs == B && s.hw == W && s.nf == F) return ghost_impl<D, B, W, F>(grid, a, st);
+template <int DIM, int BS, int HW>
+static hipError_t plain_go(int grid, const StageArgs& a, hipStream_t st) {
+  using G = Geo<DIM, BS, BS, HW + 3>;
+  hipError_t e = go(k_ghost<DIM, BS, HW>, grid, sizeof(double) * G::TSZ, st, a);
+  if (e != hipSuccess) return e;
+  return go(k_rhs_plain<DIM, BS, HW>, grid, 0, st, a);
+}
+
+hipError_t launch_plain(const Shape& s, int grid, const StageArgs& a, hipStream_t st) {
+  if (s.nf != 1) return hipErrorInvalidValue;
+#define X(D, B, W, F) if (s.dim == D && s.bs == B && s.hw == W && F == 1) return plain_go<D, B, W>(grid, a, st);
   MRB_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_mr(const Shape& s, int grid, const MrArgs& a, hipStream_t st) {
-#define X(D, B, W, F) if (s.dim == D && s.bs == B && s.hw == W && s.nf == F) return mr_impl<D, B, F>(grid, a, st);
+#define X(D, B, W, F)                                                               \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F)                            \
+    return go(k_mr<D, B, F>, grid, sizeof(double) * F * Geo<D, B, B, 2>::TSZ, st, a);
   MRB_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_refine(const Shape& s, int grid, const RefineArgs& a, hipStream_t st) {
-#define X(D, B, W, F) if (s.dim == D && s.bs == B && s.hw == W && s.nf == F) return refine_impl<D, B, F>(grid, a, st);
+#define X(D, B, W, F)                                                                                \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F)                                             \
+    return go(k_refine<D, B, F>, grid, sizeof(double) * F * Geo<D, B, (B - 1) / 2 + 1, 5>::TSZ, st, a);
   MRB_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_coarsen(const Shape& s, int grid, const CoarsenArgs& a, hipStream_t st) {
-#define X(D, B, W, F)                                                                   \
-  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F) {                              \
-    hipLaunchKernelGGL((k_coarsen<D, B, F>), dim3(grid), dim3(kNT), 0, st, a);          \
-    return hipGetLastError();                                                           \
-  }
+#define X(D, B, W, F) if (s.dim == D && s.bs == B && s.hw == W && s.nf == F) return go(k_coarsen<D, B, F>, grid, 0, st, a);
   MRB_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_read(const Shape& s, int grid, const ReadArgs& a, hipStream_t st) {
-#define X(D, B, W, F) if (s.dim == D && s.bs == B && s.hw == W && s.nf == F) return read_impl<D, B, F>(grid, a, st);
+#define X(D, B, W, F)                                                                   \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F)                                \
+    return go(k_read<D, B, F>, grid, sizeof(double) * F * Geo<D, B, B, 0>::TSZ, st, a);
   MRB_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst, hipStream_t st) {
+  const size_t total = (size_t)n * bsz;
+  const int grid = (int)((total + 255) / 256 < 8192 ? (total + 255) / 256 : 8192);
+  hipLaunchKernelGGL(k_scatter, dim3(grid > 0 ? grid : 1), dim3(256), 0, st, src, slots, n, bsz, dst);
+  return hipGetLastError();
 }
 
 }  // namespace mrb

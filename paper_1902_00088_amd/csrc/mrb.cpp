@@ -67,14 +67,9 @@ struct mrb_ctx {
   std::vector<BlockDesc> hblk;
   std::vector<NbEntry> hnb;
   std::vector<int> hlist, level_off;         // blocks grouped by level (plain form)
-  int max_entries = 0;
 
-  BlockDesc* dblk = nullptr;
-  NbEntry* dnb = nullptr;
-  int* dcount = nullptr;
-  int* dlist = nullptr;
-  RefineDesc* dref = nullptr;
-  FamilyDesc* dfam = nullptr;
+  char* arena = nullptr;        // packed topology: header, blocks, entries, lists, plans
+  size_t arena_cap = 0;
   int8_t* dflags = nullptr;
   double* dmaxd = nullptr;
   double* ds2 = nullptr;
@@ -84,10 +79,13 @@ struct mrb_ctx {
   size_t scratch_cap = 0;
   int* dslots = nullptr;
 
-  Staging st_blk, st_nb, st_cnt, st_ref, st_fam, st_list, st_slots, st_data;
+  Staging st_topo[2], st_slots;
+  int st_cur = 0;
   int8_t* h_flags = nullptr;   // pinned
   double* h_maxd = nullptr;    // pinned
-  int hcount[4] = {0, 0, 0, 0};
+  int ncu = 256;
+  int nsub = 0;                // stage sub-tiles per axis (0 = choose by block count)
+  std::string tune_log;
 
   LevelTab lt;
   Physics ph;
@@ -297,9 +295,9 @@ mrb_status build_descriptors(mrb_ctx* c) {
     B.level = L.level;
     for (int a = 0; a < 3; ++a) B.c[a] = L.c[a];
     B.nb_begin = (int)hnb.size();
+    B.n_ent = (int)(co.size() + sa.size() + fi.size());
     B.n_coarse = (int)co.size();
-    B.n_same = (int)sa.size();
-    B.n_fine = (int)fi.size();
+    if (B.n_ent > kMaxEnt) return fail(c, MRB_E_TOPOLOGY, "too many neighbour entries");
     hnb.insert(hnb.end(), co.begin(), co.end());
     hnb.insert(hnb.end(), sa.begin(), sa.end());
     hnb.insert(hnb.end(), fi.begin(), fi.end());
@@ -317,18 +315,74 @@ mrb_status build_descriptors(mrb_ctx* c) {
   return MRB_OK;
 }
 
-mrb_status upload_descriptors(mrb_ctx* c) {
-  mrb_status s;
-  const size_t n = c->hblk.size();
-  if (c->hnb.size() > (size_t)c->max_entries) return fail(c, MRB_E_CAPACITY, "neighbour table overflow");
-  if ((s = stage_upload(c, c->st_blk, c->hblk.data(), n * sizeof(BlockDesc), c->dblk))) return s;
-  if ((s = stage_upload(c, c->st_nb, c->hnb.data(), c->hnb.size() * sizeof(NbEntry), c->dnb))) return s;
-  if ((s = stage_upload(c, c->st_list, c->hlist.data(), n * sizeof(int), c->dlist))) return s;
-  c->hcount[0] = (int)n;
-  return stage_upload(c, c->st_cnt, c->hcount, sizeof(c->hcount), c->dcount);
+size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// One host->device copy of the packed topology: header, current blocks and
+// entries, the level-sorted block list, and optionally the refinement parents
+// (with their entries) or the coarsening families.
+mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
+                       const std::vector<NbEntry>* pnb = nullptr, const std::vector<RefineDesc>* ref = nullptr,
+                       const std::vector<FamilyDesc>* fam = nullptr) {
+  TopoHeader h;
+  std::memset(&h, 0, sizeof h);
+  h.n_blocks = (int)c->hblk.size();
+  h.n_ref = ref ? (int)ref->size() : 0;
+  h.n_fam = fam ? (int)fam->size() : 0;
+  h.n_pblk = pblk ? (int)pblk->size() : 0;
+  size_t off = align16(sizeof(TopoHeader));
+  auto place = [&](size_t bytes) {
+    size_t o = off;
+    off = align16(off + bytes);
+    return (int)o;
+  };
+  h.off_blk = place(c->hblk.size() * sizeof(BlockDesc));
+  h.off_nb = place(c->hnb.size() * sizeof(NbEntry));
+  h.off_list = place(c->hlist.size() * sizeof(int));
+  h.off_pblk = place(pblk ? pblk->size() * sizeof(BlockDesc) : 0);
+  h.off_pnb = place(pnb ? pnb->size() * sizeof(NbEntry) : 0);
+  h.off_ref = place(ref ? ref->size() * sizeof(RefineDesc) : 0);
+  h.off_fam = place(fam ? fam->size() * sizeof(FamilyDesc) : 0);
+  const size_t total = off;
+  if (total > (size_t)0x7fffffff) return fail(c, MRB_E_CAPACITY, "topology buffer exceeds 2 GiB");
+  if (total > c->arena_cap) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->arena) HIPCHK(c, hipFree(c->arena));
+    c->arena = nullptr;
+    const size_t cap = total + total / 2 + 4096;
+    HIPCHK(c, hipMalloc((void**)&c->arena, cap));
+    c->arena_cap = cap;
+  }
+  Staging& S = c->st_topo[c->st_cur];
+  c->st_cur ^= 1;
+  if (S.pending) {
+    HIPCHK(c, hipEventSynchronize(S.ev));
+    S.pending = false;
+  }
+  if (!S.ev) HIPCHK(c, hipEventCreateWithFlags(&S.ev, hipEventDisableTiming));
+  if (total > S.cap) {
+    if (S.h) HIPCHK(c, hipHostFree(S.h));
+    S.h = nullptr;
+    const size_t cap = total + total / 2 + 4096;
+    HIPCHK(c, hipHostMalloc(&S.h, cap, hipHostMallocDefault));
+    S.cap = cap;
+  }
+  char* b = (char*)S.h;
+  std::memcpy(b, &h, sizeof h);
+  auto put = [&](int o, const void* p, size_t n) { if (n) std::memcpy(b + o, p, n); };
+  put(h.off_blk, c->hblk.data(), c->hblk.size() * sizeof(BlockDesc));
+  put(h.off_nb, c->hnb.data(), c->hnb.size() * sizeof(NbEntry));
+  put(h.off_list, c->hlist.data(), c->hlist.size() * sizeof(int));
+  if (pblk) put(h.off_pblk, pblk->data(), pblk->size() * sizeof(BlockDesc));
+  if (pnb) put(h.off_pnb, pnb->data(), pnb->size() * sizeof(NbEntry));
+  if (ref) put(h.off_ref, ref->data(), ref->size() * sizeof(RefineDesc));
+  if (fam) put(h.off_fam, fam->data(), fam->size() * sizeof(FamilyDesc));
+  HIPCHK(c, hipMemcpyAsync(c->arena, S.h, total, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipEventRecord(S.ev, c->stream));
+  S.pending = true;
+  return MRB_OK;
 }
 
-mrb_status set_counts(mrb_ctx* c) { return stage_upload(c, c->st_cnt, c->hcount, sizeof(c->hcount), c->dcount); }
+Topo topo(const mrb_ctx* c) { return Topo{(const TopoHeader*)c->arena}; }
 
 int grid_for(const mrb_ctx* c, long n) { return (int)std::max(1L, std::min((long)c->grid, n)); }
 
@@ -360,6 +414,26 @@ double stage_bytes(const mrb_ctx* c, int s) {
   }
 }
 
+// sub-tiles per axis for the fused stage: the tuned choice, else the smallest
+// count whose workgroups cover the chip twice
+int pick_nsub(const mrb_ctx* c) {
+  int v[8];
+  const int nv = stage_variants(c->shape, c->cfg.precision, v, 8);
+  if (nv == 0) return 0;
+  if (c->nsub) {
+    for (int i = 0; i < nv; ++i)
+      if (v[i] == c->nsub) return c->nsub;
+  }
+  std::sort(v, v + nv);
+  const long n = (long)c->hblk.size();
+  for (int i = 0; i < nv; ++i) {
+    long w = n;
+    for (int a = 0; a < c->cfg.dim; ++a) w *= v[i];
+    if (w >= 2L * c->ncu) return v[i];
+  }
+  return v[nv - 1];
+}
+
 // launch one RK stage (fused) or ghost + RHS per level (plain)
 mrb_status run_stage(mrb_ctx* c, int s, const StageArgs& a0) {
   StageArgs a = a0;
@@ -368,44 +442,45 @@ mrb_status run_stage(mrb_ctx* c, int s, const StageArgs& a0) {
     for (int l = 1; l <= c->cfg.jmax; ++l) {
       const int b0 = c->level_off[l], b1 = c->level_off[l + 1];
       if (b1 == b0) continue;
-      a.list = c->dlist + b0;
-      a.list_n = b1 - b0;
-      const double nodes = (double)(b1 - b0) * c->bsz;
-      {
-        TimeScope ts(c, T_GHOST, 0.0);
-        HIPCHK(c, launch_ghost(c->shape, grid_for(c, b1 - b0), a, c->stream));
-      }
-      {
-        TimeScope ts(c, T_RHS_PLAIN, nodes * stage_bytes(c, s));
-        HIPCHK(c, launch_stage(c->shape, 0, 1, grid_for(c, b1 - b0), a, c->stream));
-      }
+      a.lvl_begin = b0;
+      a.lvl_end = b1;
+      TimeScope ts(c, T_RHS_PLAIN, (double)(b1 - b0) * c->bsz * stage_bytes(c, s));
+      HIPCHK(c, launch_plain(c->shape, grid_for(c, b1 - b0), a, c->stream));
     }
     return MRB_OK;
   }
+  const int nsub = pick_nsub(c);
+  long work = n;
+  for (int d = 0; d < c->cfg.dim; ++d) work *= nsub;
   TimeScope ts(c, T_STAGE, (double)n * c->bsz * stage_bytes(c, s));
-  HIPCHK(c, launch_stage(c->shape, c->cfg.precision, 0, grid_for(c, n), a, c->stream));
+  HIPCHK(c, launch_stage(c->shape, c->cfg.precision, Variant{nsub}, grid_for(c, work), a, c->stream));
   return MRB_OK;
 }
 
-mrb_status do_rk4(mrb_ctx* c, double t, double dt) {
-  const double h2 = dt * 0.5, h6 = dt / 6.0;
-  const double ts[4] = {t, t + h2, t + h2, t + dt};
+StageArgs stage_args(mrb_ctx* c) {
   StageArgs a;
   std::memset(&a, 0, sizeof a);
-  a.blk = c->dblk;
-  a.nb = c->dnb;
-  a.count = c->dcount;
-  a.list = nullptr;
+  a.topo = topo(c);
+  a.lvl_begin = 0;
+  a.lvl_end = -1;
   a.u = c->u;
   a.unew = c->unew;
   a.k1 = c->k[0];
   a.k2 = c->k[1];
   a.k3 = c->k[2];
-  a.h6 = h6;
   for (int f = 0; f < 4; ++f) a.off[f] = f < (int)c->off.size() ? c->off[f] : 0.0;
   a.lt = c->lt;
   a.ph = c->ph;
   a.ghost = c->dghost;
+  return a;
+}
+
+// the four stages of one RK4 step; results go to k1..k3 and u_new (u is read only)
+mrb_status sweep(mrb_ctx* c, double t, double dt) {
+  const double h2 = dt * 0.5, h6 = dt / 6.0;
+  const double ts[4] = {t, t + h2, t + h2, t + dt};
+  StageArgs a = stage_args(c);
+  a.h6 = h6;
   const double alpha[4] = {0.0, h2, h2, dt};
   for (int s = 1; s <= 4; ++s) {
     a.stage = s;
@@ -417,6 +492,12 @@ mrb_status do_rk4(mrb_ctx* c, double t, double dt) {
     mrb_status r = run_stage(c, s, a);
     if (r) return r;
   }
+  return MRB_OK;
+}
+
+mrb_status do_rk4(mrb_ctx* c, double t, double dt) {
+  mrb_status r = sweep(c, t, dt);
+  if (r) return r;
   std::swap(c->u, c->unew);
   c->n_rk4++;
   c->n_block_updates += (long)c->hblk.size();
@@ -430,15 +511,25 @@ mrb_status do_refine_all(mrb_ctx* c) {
     if (c->leaves[i].level < c->cfg.jmax) par.push_back(i);
   if (par.empty()) return MRB_OK;
   if (c->free_slots.size() < par.size() * nch) return fail(c, MRB_E_CAPACITY, "refine_all: pool too small");
+  // parents' descriptors and entries on the grid before refinement
+  std::vector<BlockDesc> pblk(par.size());
+  std::vector<NbEntry> pnb;
   std::vector<RefineDesc> ref(par.size());
   std::vector<Leaf> kids;
   kids.reserve(par.size() * nch);
+  std::vector<int> taken;
   for (size_t r = 0; r < par.size(); ++r) {
     const Leaf& P = c->leaves[par[r]];
-    ref[r].blk = par[r];
+    pblk[r] = c->hblk[par[r]];
+    pblk[r].nb_begin = (int)pnb.size();
+    pnb.insert(pnb.end(), c->hnb.begin() + c->hblk[par[r]].nb_begin,
+               c->hnb.begin() + c->hblk[par[r]].nb_begin + c->hblk[par[r]].n_ent);
+    ref[r].pblk = (int)r;
+    for (int b = 0; b < 8; ++b) ref[r].child[b] = -1;
     for (int b = 0; b < nch; ++b) {
       const int slot = c->free_slots.back();
       c->free_slots.pop_back();
+      taken.push_back(slot);
       ref[r].child[b] = slot;
       Leaf K;
       K.level = P.level + 1;
@@ -447,41 +538,45 @@ mrb_status do_refine_all(mrb_ctx* c) {
       K.slot = slot;
       kids.push_back(K);
     }
-    for (int b = nch; b < 8; ++b) ref[r].child[b] = -1;
-  }
-  mrb_status s;
-  if ((s = stage_upload(c, c->st_ref, ref.data(), ref.size() * sizeof(RefineDesc), c->dref))) return s;
-  c->hcount[1] = (int)ref.size();
-  if ((s = set_counts(c))) return s;
-  RefineArgs a{c->dblk, c->dnb, c->dref, c->dcount + 1, c->u};
-  {
-    TimeScope ts(c, T_REFINE, (double)ref.size() * c->bsz * 8.0 * (1 + nch));
-    HIPCHK(c, launch_refine(c->shape, grid_for(c, (long)ref.size()), a, c->stream));
   }
   // new forest: parents leave, children join; parent slots return to the pool
+  std::vector<Leaf> old = c->leaves;
   std::vector<char> gone(c->leaves.size(), 0);
   for (int i : par) gone[i] = 1;
   std::vector<Leaf> nl;
   nl.reserve(c->leaves.size() - par.size() + kids.size());
+  std::vector<int> freed;
   for (size_t i = 0; i < c->leaves.size(); ++i) {
-    if (gone[i]) c->free_slots.push_back(c->leaves[i].slot);
+    if (gone[i]) freed.push_back(c->leaves[i].slot);
     else nl.push_back(c->leaves[i]);
   }
   nl.insert(nl.end(), kids.begin(), kids.end());
   c->leaves.swap(nl);
   sort_and_index(c);
-  if ((s = build_descriptors(c))) return s;
+  mrb_status s = build_descriptors(c);
+  if (!s) s = upload_topo(c, &pblk, &pnb, &ref, nullptr);
+  if (s) {  // internal failure: restore the previous forest
+    c->leaves.swap(old);
+    sort_and_index(c);
+    for (int sl : taken) c->free_slots.push_back(sl);
+    build_descriptors(c);
+    return s;
+  }
+  for (int sl : freed) c->free_slots.push_back(sl);
+  RefineArgs a{topo(c), c->u};
+  {
+    TimeScope ts(c, T_REFINE, (double)ref.size() * c->bsz * 8.0 * (1 + nch));
+    HIPCHK(c, launch_refine(c->shape, grid_for(c, (long)ref.size() * nch), a, c->stream));
+  }
   c->n_refined += (long)par.size();
   c->have_flags = false;
-  return upload_descriptors(c);
+  return MRB_OK;
 }
 
 mrb_status do_mr_pass(mrb_ctx* c) {
   const int n = (int)c->hblk.size();
   MrArgs a;
-  a.blk = c->dblk;
-  a.nb = c->dnb;
-  a.count = c->dcount;
+  a.topo = topo(c);
   a.u = c->u;
   a.flags = c->dflags;
   a.maxd = c->dmaxd;
@@ -536,10 +631,10 @@ std::vector<uint64_t> coarsenable(mrb_ctx* c, const int8_t* flags) {
         for (int a = 0; a < d; ++a) ch[a] = 2 * p[a] + ((b >> a) & 1);
         const int mi = c->index.at(pack_key(l, ch));
         const BlockDesc& B = c->hblk[mi];
-        const int f0 = B.nb_begin + B.n_coarse + B.n_same;
-        for (int e = f0; e < f0 + B.n_fine && ok; ++e) {
+        for (int e = B.nb_begin; e < B.nb_begin + B.n_ent && ok; ++e) {
           // the finer neighbour's family (its mother at this member's level)
           const NbEntry& E = c->hnb[e];
+          if (E.dl <= 0) continue;
           int fc[3] = {0, 0, 0};
           for (int a = 0; a < d; ++a) {
             const int fine = 2 * ch[a] + (E.o[a] * 2) / (c->cfg.bs - 1);  // coords of the finer leaf (unwrapped)
@@ -588,28 +683,35 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
     }
     parents.push_back(P);
   }
-  mrb_status s;
-  if ((s = stage_upload(c, c->st_fam, fd.data(), fd.size() * sizeof(FamilyDesc), c->dfam))) return s;
-  c->hcount[2] = (int)fd.size();
-  if ((s = set_counts(c))) return s;
-  CoarsenArgs a{c->dfam, c->dcount + 2, c->u};
-  const long total = (long)fd.size() * c->np;
-  {
-    TimeScope ts(c, T_COARSEN, (double)total * c->cfg.nfields * 16.0);
-    HIPCHK(c, launch_coarsen(c->shape, (int)std::min(4096L, (total + kNT - 1) / kNT), a, c->stream));
-  }
+  std::vector<Leaf> old = c->leaves;
   std::vector<Leaf> nl;
+  std::vector<int> freed;
   for (size_t i = 0; i < c->leaves.size(); ++i) {
-    if (gone[i]) c->free_slots.push_back(c->leaves[i].slot);
+    if (gone[i]) freed.push_back(c->leaves[i].slot);
     else nl.push_back(c->leaves[i]);
   }
   nl.insert(nl.end(), parents.begin(), parents.end());
   c->leaves.swap(nl);
   sort_and_index(c);
-  if ((s = build_descriptors(c))) return s;
+  mrb_status s = build_descriptors(c);
+  if (!s) s = upload_topo(c, nullptr, nullptr, nullptr, &fd);
+  if (s) {
+    c->leaves.swap(old);
+    sort_and_index(c);
+    for (auto& P : parents) c->free_slots.push_back(P.slot);
+    build_descriptors(c);
+    return s;
+  }
+  for (int sl : freed) c->free_slots.push_back(sl);
+  CoarsenArgs a{topo(c), c->u};
+  const long total = (long)fd.size() * c->np;
+  {
+    TimeScope ts(c, T_COARSEN, (double)total * c->cfg.nfields * 16.0);
+    HIPCHK(c, launch_coarsen(c->shape, (int)std::min(4096L, (total + 255) / 256), a, c->stream));
+  }
   c->n_fam += (long)fams.size();
   c->have_flags = false;
-  return upload_descriptors(c);
+  return MRB_OK;
 }
 
 mrb_status do_adapt(mrb_ctx* c, int* npass) {
@@ -683,6 +785,11 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
   if (cfg->physics < 0 || cfg->physics > 2) return bad("physics");
   if (cfg->physics == MRB_ADV_SWIRL && (cfg->dim != 2 || !cfg->swirl_s2 || !cfg->swirl_s))
     return bad("swirl needs dim 2 and both tables");
+  if ((cfg->physics == MRB_NS2D) != (cfg->nfields == 4) || (cfg->physics == MRB_NS2D && (cfg->dim != 2 || cfg->hw != 4)))
+    return bad("Navier-Stokes needs dim 2, hw 4 and 4 fields (and only it has 4 fields)");
+  if (cfg->physics == MRB_NS2D && (cfg->phys[0] <= 1.0 || cfg->phys[1] < 0.0 || cfg->phys[2] <= 0.0))
+    return bad("Navier-Stokes needs gamma > 1, mu >= 0, Pr > 0");
+  if (cfg->form == MRB_FORM_PLAIN && cfg->nfields != 1) return bad("the plain form covers the advection shapes only");
   c->shape = Shape{cfg->dim, cfg->bs, cfg->hw, cfg->nfields};
   if (!shape_supported(c->shape)) return bad("unsupported (dim, bs, hw, nfields) combination");
   c->np = 1;
@@ -707,22 +814,20 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
   std::memset(&c->ph, 0, sizeof c->ph);
   c->ph.kind = cfg->physics;
   c->ph.jmax = cfg->jmax;
-  for (int a = 0; a < 3; ++a) {
-    c->ph.c[a] = cfg->phys[a];
-    c->ph.cf[a] = (float)cfg->phys[a];
+  for (int a = 0; a < 3; ++a) c->ph.c[a] = cfg->phys[a];
+  if (cfg->physics == MRB_NS2D) {
+    const double gam = cfg->phys[0], mu = cfg->phys[1], pr = cfg->phys[2];
+    c->ph.gamma = gam;
+    c->ph.mu = mu;
+    c->ph.kap = mu * gam / ((gam - 1.0) * pr);
   }
-  const int maxe = cfg->dim == 2 ? 13 : 57;
-  c->max_entries = cfg->max_blocks * maxe;
   auto dev = [&](void** p, size_t bytes) -> bool {
     hipError_t e = hipMalloc(p, std::max(bytes, (size_t)256));
     if (e != hipSuccess) { c->err = std::string("hipMalloc: ") + hipGetErrorString(e); return false; }
     return true;
   };
   const size_t mb = cfg->max_blocks;
-  bool ok = dev((void**)&c->dblk, mb * sizeof(BlockDesc)) && dev((void**)&c->dnb, (size_t)c->max_entries * sizeof(NbEntry)) &&
-            dev((void**)&c->dcount, 16 * sizeof(int)) && dev((void**)&c->dlist, mb * sizeof(int)) &&
-            dev((void**)&c->dref, mb * sizeof(RefineDesc)) && dev((void**)&c->dfam, mb * sizeof(FamilyDesc)) &&
-            dev((void**)&c->dflags, mb) && dev((void**)&c->dmaxd, mb * cfg->nfields * sizeof(double)) &&
+  bool ok = dev((void**)&c->dflags, mb) && dev((void**)&c->dmaxd, mb * cfg->nfields * sizeof(double)) &&
             dev((void**)&c->dslots, mb * sizeof(int));
   if (ok && cfg->physics == MRB_ADV_SWIRL) {
     const size_t n = (size_t)(1L << cfg->jmax) * (cfg->bs - 1);
@@ -748,8 +853,10 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
   if (ok) {
     int dev_id = 0, ncu = 0;
     (void)hipGetDevice(&dev_id);
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) == hipSuccess && ncu > 0)
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) == hipSuccess && ncu > 0) {
+      c->ncu = ncu;
       c->grid = ncu * 8;
+    }
   }
   *out = c;
   if (!ok) return MRB_E_DEVICE;
@@ -759,11 +866,11 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
 mrb_status mrb_destroy(mrb_ctx* c) {
   if (!c) return MRB_E_ARG;
   (void)hipStreamSynchronize(c->stream);
-  Staging* sts[] = {&c->st_blk, &c->st_nb, &c->st_cnt, &c->st_ref, &c->st_fam, &c->st_list, &c->st_slots, &c->st_data};
+  Staging* sts[] = {&c->st_topo[0], &c->st_topo[1], &c->st_slots};
   for (Staging* s : sts) release_staging(*s);
   for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
-  void* ptrs[] = {c->dblk, c->dnb, c->dcount, c->dlist, c->dref, c->dfam, c->dflags, c->dmaxd,
+  void* ptrs[] = {c->arena, c->dflags, c->dmaxd,
                   c->ds2, c->ds, c->dghost, c->dscratch, c->dslots};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -810,7 +917,7 @@ mrb_status mrb_init_forest(mrb_ctx* c, int n, const int8_t* level, const int32_t
   c->have_forest = true;
   c->have_data = false;
   c->have_flags = false;
-  return upload_descriptors(c);
+  return upload_topo(c);
 }
 
 mrb_status mrb_load_blocks(mrb_ctx* c, const double* data, int on_device) {
@@ -916,7 +1023,7 @@ mrb_status mrb_read_blocks(mrb_ctx* c, double* out, int on_device) {
     if ((s = ensure_scratch(c, bytes))) return s;
     dst = c->dscratch;
   }
-  ReadArgs a{c->dblk, c->dnb, c->dcount, c->u, dst};
+  ReadArgs a{topo(c), c->u, dst};
   HIPCHK(c, launch_read(c->shape, grid_for(c, n), a, c->stream));
   if (!on_device) HIPCHK(c, hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -945,10 +1052,59 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"kernels\": %s}",
+                "\"stage_tiles\": %d, \"tune_ms\": {%s}, \"kernels\": %s}",
                 c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
-                c->free_slots.size(), c->grid, kern.c_str());
+                c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
+                c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
+  return MRB_OK;
+}
+
+mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
+  if (!c) return MRB_E_ARG;
+  int v[8];
+  const int nv = stage_variants(c->shape, c->cfg.precision, v, 8);
+  if (nsub > 0) {
+    bool ok = false;
+    for (int i = 0; i < nv; ++i) ok = ok || v[i] == nsub;
+    if (!ok) return fail(c, MRB_E_ARG, "tune: tiling not compiled for this shape and precision");
+    c->nsub = nsub;
+  } else if (reps > 0) {
+    if (!check_state(c, true)) return MRB_E_STATE;
+    if (!(dt > 0.0)) return fail(c, MRB_E_ARG, "tune: dt must be positive");
+    if (c->cfg.form != MRB_FORM_FUSED) return fail(c, MRB_E_ARG, "tune: only the fused form has tilings");
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_v = 0;
+    c->tune_log.clear();
+    const bool was_timing = c->timing;
+    c->timing = false;
+    for (int i = 0; i < nv; ++i) {
+      c->nsub = v[i];
+      mrb_status r = sweep(c, 0.0, dt);  // warm-up
+      if (r) return r;
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      for (int k = 0; k < reps; ++k)
+        if ((r = sweep(c, 0.0, dt))) return r;
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      char buf[64];
+      std::snprintf(buf, sizeof buf, "%s\"%d\": %.4f", c->tune_log.empty() ? "" : ", ", v[i], ms / reps);
+      c->tune_log += buf;
+      if (ms < best) { best = ms; best_v = v[i]; }
+    }
+    c->timing = was_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->nsub = best_v;
+  } else {
+    c->nsub = 0;
+  }
+  if (chosen) *chosen = c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1;
   return MRB_OK;
 }
 

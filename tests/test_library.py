@@ -85,11 +85,13 @@ SMOOTH3 = lambda x, y, z: np.sin(2 * np.pi * x + 0.3) * np.cos(2 * np.pi * y) + 
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("form", [W.FORM_FUSED, W.FORM_PLAIN])
-def test_rk4_on_two_level_forest_is_bitwise(form):
+@pytest.mark.parametrize("form,nsub", [(W.FORM_FUSED, 1), (W.FORM_FUSED, 2), (W.FORM_PLAIN, 0)])
+def test_rk4_on_two_level_forest_is_bitwise(form, nsub):
     cfg = W.C1(jmax=3, form=form)
     lv, co = _two_level()
     s, o = _pair(cfg, lv, co, fn=SMOOTH2)
+    if nsub:
+        assert s.tune(nsub=nsub) == nsub
     assert_same(s, o, "after load")
     s.rk4(0.0, cfg.dt)
     o.rk4(0.0, cfg.dt)
@@ -97,11 +99,12 @@ def test_rk4_on_two_level_forest_is_bitwise(form):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("seed", range(6))
 def test_random_graded_forest_refine_rk4_mr(seed):
     lv, co = W.random_graded_forest(2, 4, seed, p_refine=0.5)
-    cfg = W.C2(jmax=5, eps=3e-3).replace(bs=17, max_blocks=3 * 4 ** 5)
+    cfg = W.C2(jmax=5, eps=3e-3).replace(bs=17 if seed % 2 == 0 else 33, max_blocks=3 * 4 ** 5)
     s, o = _pair(cfg, lv, co, fn=SMOOTH2)
+    s.tune(nsub=[1, 2, 1, 4, 2, 2][seed])
     s.rk4(0.0, cfg.dt)
     o.rk4(0.0, cfg.dt)
     assert_same(s, o, "rk4")
@@ -163,6 +166,24 @@ def test_c2_narrow_blobs_deep_forest():
         o.step(t, cfg.dt)
         t += cfg.dt
     assert_same(s, o, "after 6 steps")
+
+
+@pytest.mark.gpu
+def test_3d_random_forest_rk4_mr_refine():
+    lv, co = W.random_graded_forest(3, 3, 1, p_refine=0.4)
+    cfg = W.C4(jmax=4, eps=1e-3, form=W.FORM_FUSED).replace(max_blocks=3 * 8 ** 4)
+    s, o = _pair(cfg, lv, co, fn=SMOOTH3)
+    assert len(np.unique(lv)) >= 2
+    s.rk4(0.0, cfg.dt)
+    o.rk4(0.0, cfg.dt)
+    assert_same(s, o, "rk4")
+    fs, ms = s.mr_pass()
+    fo, mo = o.mr_pass()
+    assert np.array_equal(fs, fo) and np.array_equal(_bits(ms), _bits(mo))
+    assert s.coarsen(fs) == o.coarsen(fo)
+    s.refine_all()
+    o.refine_all()
+    assert_same(s, o, "coarsen + refine")
 
 
 @pytest.mark.gpu
@@ -251,3 +272,72 @@ def test_error_paths_leave_state_unchanged():
     assert s.num_blocks() == 16
     with pytest.raises(M.MrbError):
         M.Solver(cfg.replace(bs=16))                     # even block size
+
+
+@pytest.mark.gpu
+def test_ns_mixing_layer_fp64_is_bitwise():
+    """C3 set-up (compressible NS mixing layer) at Jmax 4 with eps = 1e-4, so that the
+    grid has two levels (at eps = 1e-3 it is uniform on level 3): initial grid, 3 steps."""
+    cfg = W.C3(jmax=4, eps=1e-4, form=W.FORM_FUSED)
+    s, o = _pair(cfg)
+    lv, _ = s.read_forest()
+    assert len(np.unique(lv)) >= 2
+    assert_same(s, o, "initial grid")
+    t = 0.0
+    for n in range(3):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    assert_same(s, o, "after 3 steps")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("nsub", [2, 4])
+def test_ns_tilings_agree_bitwise(nsub):
+    cfg = W.C3(jmax=4, form=W.FORM_FUSED)
+    lv, co = _two_level()
+    s, o = _pair(cfg.replace(jmax=3), lv, co)
+    s.tune(nsub=nsub)
+    s.rk4(0.0, cfg.dt)
+    o.rk4(0.0, cfg.dt)
+    assert_same(s, o, "rk4")
+
+
+@pytest.mark.gpu
+def test_ns_mixed_within_1e5():
+    cfg = W.C3(jmax=4, eps=1e-4)
+    s = M.Solver(cfg.replace(precision=W.MIXED, form=W.FORM_FUSED))
+    o = oracle.Oracle(cfg)
+    o.init_grid()
+    s.init_forest(*o.read_forest())
+    s.load_blocks(W.sample(cfg, *o.read_forest()))
+    t = 0.0
+    for n in range(4):
+        for x in (s, o):
+            x.refine_all()
+            x.rk4(t, cfg.dt)
+        while True:
+            fo, _ = o.mr_pass()
+            s.mr_pass()
+            if o.coarsen(fo) == 0:
+                assert s.coarsen(fo) == 0
+                break
+            s.coarsen(fo)
+        t += cfg.dt
+    a, b = s.read_blocks(), o.read_blocks()
+    rel = np.max(np.abs(a - b), axis=(0, 2)) / np.max(np.abs(b), axis=(0, 2))
+    assert np.all(rel <= 1e-5), rel
+    assert np.any(rel > 0)
+
+
+@pytest.mark.gpu
+def test_autotune_picks_a_compiled_tiling_and_keeps_state():
+    cfg = W.C2(form=W.FORM_FUSED)
+    s = M.Solver(cfg)
+    s.init_grid()
+    before = s.read_blocks()
+    ch = s.tune(reps=3)
+    assert ch in (1, 2, 4)
+    st = s.stats()
+    assert len(st["tune_ms"]) == 3
+    assert np.array_equal(_bits(s.read_blocks()), _bits(before))
