@@ -27,9 +27,13 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "block-updates/s (RK4 step, all blocks) FP64 vs mixed; % HBM roofline"
 
 
-def run_form(M, W, torch, cfg, steps, warmup):
+def run_form(M, W, torch, cfg, steps, warmup, tune=False):
     s = M.Solver(cfg)
     s.init_grid()
+    if tune:
+        s.refine_all()
+        s.tune(reps=3)
+        s.init_grid()
     lv0, co0 = s.read_forest()
     data0 = s.read_blocks()
     t = 0.0
@@ -44,13 +48,15 @@ def run_form(M, W, torch, cfg, steps, warmup):
 
     # timed pass (no per-kernel instrumentation)
     reset()
-    b0 = s.stats()["block_updates"]
+    st0 = s.stats()
+    b0 = st0["block_updates"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step(0.0, cfg.dt, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = s.stats()
+    host_us = {k: (v - st0["host_us"][k]) / steps for k, v in st["host_us"].items()}
     bu = st["block_updates"] - b0
     wall = t1 - t0
     final_blocks = st["blocks"]
@@ -70,6 +76,7 @@ def run_form(M, W, torch, cfg, steps, warmup):
         "blocks_final": final_blocks,
         "sweep_block_updates_per_s": bu / (sweep_ms * 1e-3) if sweep_ms > 0 else None,
         "kernels": kst,
+        "host_us_per_step": host_us,
     }
 
 
@@ -104,6 +111,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="fp64_plain,fp64_fused,mixed_fused")
+    ap.add_argument("--c4-steps", type=int, default=20, help="steps of the 3D workload (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the multi-GPU path (sharding the block forest along the "
@@ -151,6 +159,19 @@ def main():
     }
     if "fp64_plain" in res and "mixed_fused" in res:
         out["speedup_mixed_fused_vs_fp64_plain"] = res["mixed_fused"]["value"] / res["fp64_plain"]["value"]
+    if args.c4_steps > 0:
+        # the 3D set-up: a ragged forest of ~3,000 blocks of 17^3 after refine-all, HBM bound
+        c4 = {}
+        for name in ("fp64_fused", "mixed_fused"):
+            prec, form = forms[name]
+            print(f"bench: C4 {name} steps={args.c4_steps}", file=sys.stderr, flush=True)
+            c4[name] = run_form(M, W, torch, W.C4().replace(precision=prec, form=form), args.c4_steps, 2, tune=True)
+        ks4 = c4["mixed_fused"]["kernels"]["stage"]
+        ach4 = ks4["bytes"] / (ks4["ms"] * 1e-3) / 1e9 if ks4["ms"] > 0 else 0.0
+        out["c4"] = {"workload": "C4 3D advection: 4 seeded blobs sigma=0.04, Bs=17^3, Jmax=6, eps=1e-4, dt=2^-11",
+                     "forms": c4,
+                     "roofline_stage_mixed": {"bound": "hbm", "achieved": ach4, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                              "frac": ach4 / PEAK_HBM_GBS}}
     if not args.no_cpu:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W, base, args.cpu_seconds)

@@ -28,7 +28,7 @@ STATUS = {0: "MRB_OK", -1: "MRB_E_ARG", -2: "MRB_E_CAPACITY", -3: "MRB_E_TOPOLOG
 EXPORTS = ("mrb_create", "mrb_destroy", "mrb_last_error", "mrb_init_forest", "mrb_load_blocks",
            "mrb_refine_all", "mrb_rk4", "mrb_mr_pass", "mrb_coarsen", "mrb_adapt", "mrb_step",
            "mrb_num_blocks", "mrb_read_forest", "mrb_read_blocks", "mrb_get_flags", "mrb_stats",
-           "mrb_timing", "mrb_tune")
+           "mrb_timing", "mrb_tune", "mrb_set_graph")
 
 
 class MrbError(RuntimeError):
@@ -83,6 +83,7 @@ def lib():
             "mrb_stats": [_vp, ctypes.c_char_p, ctypes.c_int],
             "mrb_timing": [_vp, ctypes.c_int],
             "mrb_tune": [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int)],
+            "mrb_set_graph": [_vp, ctypes.c_int],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -112,10 +113,12 @@ class Solver:
         n = cfg.max_blocks * cfg.nf * cfg.npts
         kdt = torch.float64 if cfg.precision == W.FP64 else torch.float32
         with torch.cuda.device(self.device):
-            self.stream = torch.cuda.current_stream(self.device)
+            # a stream of its own (default priority): graph capture needs a non-default stream
+            self.stream = torch.cuda.Stream(self.device)
             self.u = torch.zeros(n, dtype=torch.float64, device=self.device)
             self.u_new = torch.zeros(n, dtype=torch.float64, device=self.device)
             self.k = [torch.zeros(n, dtype=kdt, device=self.device) for _ in range(3)]
+            torch.cuda.synchronize(self.device)
         c = mrb_config()
         c.dim, c.bs, c.hw, c.nfields, c.jmax, c.max_blocks = cfg.dim, cfg.bs, cfg.hw, cfg.nf, cfg.jmax, cfg.max_blocks
         c.eps = cfg.eps
@@ -185,6 +188,7 @@ class Solver:
         if hasattr(data, "data_ptr"):
             t = data.to(device=self.device, dtype=self.torch.float64).contiguous()
             assert t.numel() == self.num_blocks() * self.cfg.nf * self.cfg.npts
+            self.torch.cuda.current_stream(self.device).synchronize()
             self._chk(lib().mrb_load_blocks(self.h, _vp(t.data_ptr()), 1))
             self.stream.synchronize()
             return
@@ -243,6 +247,9 @@ class Solver:
         ch = ctypes.c_int()
         self._chk(lib().mrb_tune(self.h, nsub, reps, self.cfg.dt, ctypes.byref(ch)))
         return ch.value
+
+    def set_graph(self, enable: bool):
+        self._chk(lib().mrb_set_graph(self.h, 1 if enable else 0))
 
     def timing(self, enable: bool):
         self._chk(lib().mrb_timing(self.h, 1 if enable else 0))

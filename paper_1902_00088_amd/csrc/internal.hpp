@@ -107,6 +107,8 @@ struct MrArgs {
   double* u;              // read; redundant nodes owned by finer blocks are written back
   int8_t* flags;          // [n]
   double* maxd;           // [n][nf]
+  unsigned long long* acc;// [max_blocks][nf] partial maxima (bit patterns), zero between passes
+  int* done;              // [max_blocks] sub-tiles finished, zero between passes
   double thr[4];
 };
 
@@ -138,13 +140,15 @@ struct Variant {
 // Launchers (kernels.hip).  grid = number of workgroups (grid-stride loops inside).
 hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, const StageArgs& a, hipStream_t st);
 hipError_t launch_plain(const Shape& s, int grid, const StageArgs& a, hipStream_t st);  // ghost + RHS kernels
-hipError_t launch_mr(const Shape& s, int grid, const MrArgs& a, hipStream_t st);
-hipError_t launch_refine(const Shape& s, int grid, const RefineArgs& a, hipStream_t st);
+hipError_t launch_mr(const Shape& s, int nsub, int grid, const MrArgs& a, hipStream_t st);
+hipError_t launch_refine(const Shape& s, int nsub, int grid, const RefineArgs& a, hipStream_t st);
 hipError_t launch_coarsen(const Shape& s, int grid, const CoarsenArgs& a, hipStream_t st);
 hipError_t launch_read(const Shape& s, int grid, const ReadArgs& a, hipStream_t st);
 hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst, hipStream_t st);
 bool shape_supported(const Shape& s);
-// sub-tile counts compiled for this shape and precision, best first; returns count
+// sub-tile counts compiled for this shape and precision; returns count
 int stage_variants(const Shape& s, int precision, int* nsub, int cap);
+// sub-tile counts of the analysis (kind 0) and refinement (kind 1) kernels
+int aux_variants(const Shape& s, int kind, int* nsub, int cap);
 
 }  // namespace mrb

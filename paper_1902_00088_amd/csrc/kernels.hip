@@ -61,6 +61,75 @@ __device__ __forceinline__ T tensor_p(const AT& at, const int* base, const int* 
   return nz == 4 ? P4(vz[0], vz[1], vz[2], vz[3]) : vz[0];
 }
 
+// Same, with the number of points per axis fixed at compile time (fully unrolled).
+template <int NX, int NY, int NZ, typename T, typename AT>
+__device__ __forceinline__ T tensor_fixed(const AT& at, const int* base, const int* stride) {
+  T vz[4];
+#pragma unroll
+  for (int iz = 0; iz < NZ; ++iz) {
+    T vy[4];
+#pragma unroll
+    for (int iy = 0; iy < NY; ++iy) {
+      T vx[4];
+#pragma unroll
+      for (int ix = 0; ix < NX; ++ix)
+        vx[ix] = at(base[0] + ix * stride[0], base[1] + iy * stride[1], base[2] + iz * stride[2]);
+      vy[iy] = NX == 4 ? P4(vx[0], vx[1], vx[2], vx[3]) : vx[0];
+    }
+    vz[iz] = NY == 4 ? P4(vy[0], vy[1], vy[2], vy[3]) : vy[0];
+  }
+  return NZ == 4 ? P4(vz[0], vz[1], vz[2], vz[3]) : vz[0];
+}
+
+// Nodes of [r0, r0+cnt) whose parity pattern is `cls` (bit a set: odd along axis a):
+// per-axis first coordinate and count, for a loop without divergence between classes.
+template <int DIM>
+struct ParityClass {
+  int first[3], n[3], total;
+  __device__ __forceinline__ ParityClass(int cls, const int* r0, const int* cnt) {
+    total = 1;
+    for (int a = 0; a < 3; ++a) { first[a] = 0; n[a] = 1; }
+    for (int a = 0; a < DIM; ++a) {
+      const int odd = (cls >> a) & 1;
+      first[a] = r0[a] + (((r0[a] & 1) != odd) ? 1 : 0);
+      const int last = r0[a] + cnt[a] - 1;
+      n[a] = first[a] <= last ? (last - first[a]) / 2 + 1 : 0;
+      total *= n[a];
+    }
+  }
+  __device__ __forceinline__ void coords(int p, int* t) const {
+    t[0] = first[0] + 2 * (p % n[0]);
+    if (DIM > 2) {
+      t[1] = first[1] + 2 * ((p / n[0]) % n[1]);
+      t[2] = first[2] + 2 * (p / (n[0] * n[1]));
+    } else {
+      t[1] = first[1] + 2 * (p / n[0]);
+      t[2] = 0;
+    }
+  }
+};
+
+// Run body.template operator()<NX, NY, NZ>(cls) for every parity class except all-even.
+template <int DIM, typename B>
+__device__ __forceinline__ void for_odd_classes(B& body) {
+  body.template go<4, 1, 1>(1);
+  body.template go<1, 4, 1>(2);
+  body.template go<4, 4, 1>(3);
+  if constexpr (DIM > 2) {
+    body.template go<1, 1, 4>(4);
+    body.template go<4, 1, 4>(5);
+    body.template go<1, 4, 4>(6);
+    body.template go<4, 4, 4>(7);
+  }
+}
+
+// maximum that propagates NaN (a NaN detail must block coarsening)
+__device__ __forceinline__ double nanmax(double a, double b) {
+  if (a != a) return a;
+  if (b != b) return b;
+  return a > b ? a : b;
+}
+
 // Tile over a region of S nodes per axis (block-local origin r0) with a halo of H.
 template <int DIM, int BS, int S, int H>
 struct Geo {
@@ -141,15 +210,58 @@ struct PointInfo {
   }
 };
 
-// Gather the tile: points within hw_all of the region, and even points within
-// h_even (coarse-lattice inputs of the prediction).  One load round per thread batch.
+// Work items of a launch, XCD-aware: workgroups are dealt round-robin to the 8 XCDs
+// (each with its own L2), so XCD x takes the contiguous chunk x of the work list
+// (neighbouring blocks in forest order share halo lines in one L2) and its
+// workgroups stride through it.  The grid is a multiple of 8.
+struct XcdWork {
+  int w, end, step;
+  __device__ __forceinline__ explicit XcdWork(int total) {
+    const int x = blockIdx.x & 7, per = gridDim.x >> 3;
+    const int chunk = (total + 7) >> 3;
+    w = x * chunk + (blockIdx.x >> 3);
+    end = min(total, (x + 1) * chunk);
+    step = per;
+  }
+  __device__ __forceinline__ bool ok() const { return w < end; }
+  __device__ __forceinline__ void next() { w += step; }
+};
+
+template <int DIM, int TW>
+__device__ __forceinline__ unsigned long long cand_at(const GState<DIM, TW>& g, const int* i) {
+  unsigned long long c = g.m[0][i[0]] & g.m[1][i[1]];
+  if (DIM > 2) c &= g.m[2][i[2]];
+  return c;
+}
+
+// Gather the tile: every point within hw_all of the region (box A), and the even
+// (coarse-lattice) points within h_even (box B, inputs of the prediction; only when
+// h_even > hw_all).  A point's owner is the highest set bit of its candidate mask;
+// points with no owner are left for gpredict.  Loads go out in batches of B per thread.
 template <int DIM, int BS, int S, int H, int NF, typename TT, typename SRC>
 __device__ void gfill(TT* tile, const GState<DIM, S + 2 * H>& g, const int* r0, const int* cnt, int hw_all, int h_even,
                       const SRC& src) {
   using G = Geo<DIM, BS, S, H>;
   constexpr int TSZ = G::TSZ, NP = G::NP;
-  constexpr int B = 4;
-  for (int base = 0; base < TSZ; base += B * blockDim.x) {
+  constexpr int B = 8;
+  int a0[3] = {0, 0, 0}, an[3] = {1, 1, 1}, b0[3] = {0, 0, 0}, bn[3] = {1, 1, 1};
+  int nA = 1, nB = 0;
+  for (int a = 0; a < DIM; ++a) {
+    a0[a] = r0[a] - hw_all;
+    an[a] = cnt[a] + 2 * hw_all;
+    nA *= an[a];
+  }
+  if (h_even > hw_all) {
+    nB = 1;
+    for (int a = 0; a < DIM; ++a) {
+      const int lo = r0[a] - h_even, hi = r0[a] + cnt[a] - 1 + h_even;
+      b0[a] = lo + (lo & 1);
+      bn[a] = (hi - b0[a]) / 2 + 1;
+      nB *= bn[a];
+    }
+  }
+  const int total = nA + nB;
+  for (int base = 0; base < total; base += B * blockDim.x) {
     size_t addr[B];
     int pos[B];
 #pragma unroll
@@ -157,19 +269,43 @@ __device__ void gfill(TT* tile, const GState<DIM, S + 2 * H>& g, const int* r0, 
       const int p = base + q * blockDim.x + threadIdx.x;
       pos[q] = -1;
       addr[q] = 0;
-      if (p >= TSZ) continue;
-      PointInfo<DIM, S, H> P(p, g, r0, cnt);
-      const bool need = P.dist <= hw_all || (P.even && P.dist <= h_even);
-      if (!need || P.cand == 0) continue;
-      const NbEntry& E = g.ent[63 - __clzll((long long)P.cand)];
+      if (p >= total) continue;
+      int t[3] = {0, 0, 0};
+      if (p < nA) {
+        t[0] = a0[0] + p % an[0];
+        if (DIM > 2) {
+          t[1] = a0[1] + (p / an[0]) % an[1];
+          t[2] = a0[2] + p / (an[0] * an[1]);
+        } else {
+          t[1] = a0[1] + p / an[0];
+        }
+      } else {
+        const int pb = p - nA;
+        t[0] = b0[0] + 2 * (pb % bn[0]);
+        if (DIM > 2) {
+          t[1] = b0[1] + 2 * ((pb / bn[0]) % bn[1]);
+          t[2] = b0[2] + 2 * (pb / (bn[0] * bn[1]));
+        } else {
+          t[1] = b0[1] + 2 * (pb / bn[0]);
+        }
+        bool inA = true;
+        for (int a = 0; a < DIM; ++a)
+          if (t[a] < a0[a] || t[a] >= a0[a] + an[a]) inA = false;
+        if (inA) continue;  // loaded with box A
+      }
+      int i[3] = {0, 0, 0};
+      for (int a = 0; a < DIM; ++a) i[a] = t[a] - r0[a] + H;
+      const unsigned long long cand = cand_at<DIM, S + 2 * H>(g, i);
+      if (cand == 0) continue;
+      const NbEntry& E = g.ent[63 - __clzll((long long)cand)];
       int sidx = 0, mul = 1;
       for (int a = 0; a < DIM; ++a) {
-        const int l = P.t[a] - E.o[a];
+        const int l = t[a] - E.o[a];
         sidx += (E.dl > 0 ? 2 * l : (E.dl == 0 ? l : l >> 1)) * mul;
         mul *= BS;
       }
       addr[q] = (size_t)E.slot * NF * NP + sidx;
-      pos[q] = p;
+      pos[q] = G::idx(i[0], i[1], i[2]);
     }
     TT v[B][NF];
 #pragma unroll
@@ -193,17 +329,30 @@ template <int DIM, int BS, int S, int H, int NF, typename TT>
 __device__ void gpredict(TT* tile, const GState<DIM, S + 2 * H>& g, const int* r0, const int* cnt, int hw_all) {
   using G = Geo<DIM, BS, S, H>;
   constexpr int TSZ = G::TSZ;
-  for (int p = threadIdx.x; p < TSZ; p += blockDim.x) {
-    PointInfo<DIM, S, H> P(p, g, r0, cnt);
-    if (P.dist > hw_all || P.cand != 0) continue;
-    int base[3] = {P.i[0], P.i[1], P.i[2]}, stride[3] = {2, 2, 2}, n[3] = {1, 1, 1};
+  int an[3] = {1, 1, 1}, nA = 1;
+  for (int a = 0; a < DIM; ++a) {
+    an[a] = cnt[a] + 2 * hw_all;
+    nA *= an[a];
+  }
+  for (int p = threadIdx.x; p < nA; p += blockDim.x) {
+    int i[3] = {0, 0, 0};
+    i[0] = H - hw_all + p % an[0];
+    if (DIM > 2) {
+      i[1] = H - hw_all + (p / an[0]) % an[1];
+      i[2] = H - hw_all + p / (an[0] * an[1]);
+    } else {
+      i[1] = H - hw_all + p / an[0];
+    }
+    if (cand_at<DIM, S + 2 * H>(g, i) != 0) continue;
+    int base[3] = {i[0], i[1], i[2]}, stride[3] = {2, 2, 2}, n[3] = {1, 1, 1};
     for (int a = 0; a < DIM; ++a)
-      if (P.t[a] & 1) { base[a] = P.i[a] - 3; n[a] = 4; }
+      if ((r0[a] + i[a] - H) & 1) { base[a] = i[a] - 3; n[a] = 4; }
+    const int ti = G::idx(i[0], i[1], i[2]);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const TT* T = tile + f * TSZ;
       auto at = [&](int x, int y, int z) { return T[G::idx(x, y, z)]; };
-      tile[f * TSZ + p] = tensor_p<DIM, TT>(at, base, stride, n);
+      tile[f * TSZ + ti] = tensor_p<DIM, TT>(at, base, stride, n);
     }
   }
   __syncthreads();
@@ -226,7 +375,7 @@ __device__ __forceinline__ void subregion(int sub, int nsub, int S, int BS, int*
 // ---------------------------------------------------------------------------
 template <int DIM, int BS, int S, int H, typename TT>
 __device__ __forceinline__ TT rhs_adv(const TT* T, const int* i, const int* t, const BlockDesc& d, TT r,
-                                      const StageArgs& A) {
+                                      const StageArgs& A, const double* sw, const int* l) {
   using G = Geo<DIM, BS, S, H>;
   const int x = i[0], y = i[1], z = i[2];
   const TT dx = D4(T[G::idx(x - 2, y, z)], T[G::idx(x - 1, y, z)], T[G::idx(x + 1, y, z)], T[G::idx(x + 2, y, z)], r);
@@ -240,17 +389,45 @@ __device__ __forceinline__ TT rhs_adv(const TT* T, const int* i, const int* t, c
     }
     return -acc;
   }
-  // swirl: u = sin^2(pi x) sin(2 pi y), v = -sin^2(pi y) sin(2 pi x) from tables on the finest lattice
-  const int nl = A.lt.nl[d.level], shift = A.ph.jmax - d.level;
-  int gx = d.c[0] * (BS - 1) + t[0];
-  int gy = d.c[1] * (BS - 1) + t[1];
-  if (gx >= nl) gx -= nl;
-  if (gy >= nl) gy -= nl;
-  gx <<= shift;
-  gy <<= shift;
-  const double U = (A.ph.s2[gx] * A.ph.s[gy]) * A.cfac;
-  const double W = -((A.ph.s2[gy] * A.ph.s[gx]) * A.cfac);
+  // swirl: u = sin^2(pi x) sin(2 pi y), v = -sin^2(pi y) sin(2 pi x) from tables on the
+  // finest lattice; sw (LDS) holds the region's slices: s2(x), s(x), s2(y), s(y)
+  double s2x, sx, s2y, sy;
+  if (sw) {
+    s2x = sw[l[0]];
+    sx = sw[S + l[0]];
+    s2y = sw[2 * S + l[1]];
+    sy = sw[3 * S + l[1]];
+  } else {
+    const int nl = A.lt.nl[d.level], shift = A.ph.jmax - d.level;
+    int gx = d.c[0] * (BS - 1) + t[0];
+    int gy = d.c[1] * (BS - 1) + t[1];
+    if (gx >= nl) gx -= nl;
+    if (gy >= nl) gy -= nl;
+    gx <<= shift;
+    gy <<= shift;
+    s2x = A.ph.s2[gx];
+    sx = A.ph.s[gx];
+    s2y = A.ph.s2[gy];
+    sy = A.ph.s[gy];
+  }
+  const double U = (s2x * sy) * A.cfac;
+  const double W = -((s2y * sx) * A.cfac);
   return -(((TT)U * dx) + ((TT)W * dy));
+}
+
+// swirl table slices of a region into LDS: s2(x), s(x), s2(y), s(y) at its nodes
+template <int BS, int S>
+__device__ __forceinline__ void load_swirl(double* sw, const BlockDesc& d, const int* r0, const int* cnt,
+                                           const StageArgs& A) {
+  const int nl = A.lt.nl[d.level], shift = A.ph.jmax - d.level;
+  for (int q = threadIdx.x; q < 4 * S; q += blockDim.x) {
+    const int k = q / S, l = q % S, ax = k / 2;
+    if (l >= cnt[ax]) continue;
+    int gg = d.c[ax] * (BS - 1) + r0[ax] + l;
+    if (gg >= nl) gg -= nl;
+    gg <<= shift;
+    sw[q] = (k & 1) ? A.ph.s[gg] : A.ph.s2[gg];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -352,18 +529,22 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs A) {
   constexpr int NSUBT = Pow<DIM, NSUB>::v;
   constexpr bool NS = NF == 4;
   __shared__ GState<DIM, G::TW> g;
+  __shared__ double swirl[DIM == 2 && NF == 1 ? 4 * S : 1];
   extern __shared__ __align__(16) char smem[];
   TT* tile = reinterpret_cast<TT*>(smem);
   CT* W = reinterpret_cast<CT*>(tile + NF * TSZ);  // NS stresses / fluxes
   const int nblk = A.topo.h->n_blocks;
   const BlockDesc* blk = A.topo.blk();
   const NbEntry* nb = A.topo.nb();
-  for (int w = blockIdx.x; w < nblk * NSUBT; w += gridDim.x) {
+  for (XcdWork it(nblk * NSUBT); it.ok(); it.next()) {
+    const int w = it.w;
     const int b = w / NSUBT;
     const BlockDesc d = blk[b];
     int r0[3], cnt[3];
     subregion<DIM>(w % NSUBT, NSUB, S, BS, r0, cnt);
     gsetup<DIM, BS, S, H>(g, d, nb, r0);
+    const bool sw_lds = DIM == 2 && NF == 1 && A.ph.kind == 1;
+    if (sw_lds) load_swirl<BS, S>(swirl, d, r0, cnt, A);
     const int h_even = d.n_coarse > 0 ? H : 0;
     if (A.stage == 1) {
       YSrc<TT, KT, false> src{A.u, nullptr, 0.0, A.off};
@@ -410,7 +591,7 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs A) {
         int l[3] = {p % cnt[0], DIM > 2 ? (p / cnt[0]) % cnt[1] : p / cnt[0], DIM > 2 ? p / (cnt[0] * cnt[1]) : 0};
         int t[3] = {r0[0] + l[0], r0[1] + l[1], r0[2] + l[2]};
         int i[3] = {l[0] + H, l[1] + H, DIM > 2 ? l[2] + H : 0};
-        const TT kv = rhs_adv<DIM, BS, S, H, TT>(tile, i, t, d, r, A);
+        const TT kv = rhs_adv<DIM, BS, S, H, TT>(tile, i, t, d, r, A, sw_lds ? swirl : nullptr, l);
         const size_t q = base + t[0] + BS * t[1] + (DIM > 2 ? BS * BS * t[2] : 0);
         if (A.stage < 4) {
           ((KT*)A.kout)[q] = (KT)kv;
@@ -476,7 +657,7 @@ __global__ void __launch_bounds__(256) k_rhs_plain(StageArgs A) {
     for (int p = threadIdx.x; p < NP; p += blockDim.x) {
       int t[3] = {p % BS, (p / BS) % BS, DIM > 2 ? p / (BS * BS) : 0};
       int i[3] = {t[0] + HW, t[1] + HW, DIM > 2 ? t[2] + HW : 0};
-      const double kv = rhs_adv<DIM, BS, BS, HW, double>(T, i, t, d, r, A);
+      const double kv = rhs_adv<DIM, BS, BS, HW, double>(T, i, t, d, r, A, nullptr, t);
       if (A.stage < 4) {
         ((double*)A.kout)[base + p] = kv;
       } else {
@@ -490,123 +671,71 @@ __global__ void __launch_bounds__(256) k_rhs_plain(StageArgs A) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// multiresolution analysis: details d = u - P(R(u)), per-field max, flag;
-// redundant nodes owned by finer neighbours are written back to the pool
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double nanmax(double a, double b) {
-  if (a != a) return a;
-  if (b != b) return b;
-  return a > b ? a : b;
-}
-
-template <int DIM, int BS, int NF>
-__global__ void __launch_bounds__(256) k_mr(MrArgs A) {
-  constexpr int H = 2, S = BS;
+// details d = u - P(R(u)) at the nodes of one parity class (per-field maxima in m)
+template <int DIM, int BS, int S, int H, int NF>
+struct DetailsBody {
   using G = Geo<DIM, BS, S, H>;
-  constexpr int NP = G::NP, TSZ = G::TSZ;
-  __shared__ GState<DIM, G::TW> g;
-  __shared__ double red[4][4];
-  extern __shared__ __align__(16) char smem[];
-  double* tile = reinterpret_cast<double*>(smem);
-  const int nblk = A.topo.h->n_blocks;
-  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
-    const BlockDesc d = A.topo.blk()[b];
-    int r0[3] = {0, 0, 0}, cnt[3] = {BS, BS, DIM > 2 ? BS : 1};
-    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(), r0);
-    YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
-    gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, 0, H, src);
-    double m[4] = {0.0, 0.0, 0.0, 0.0};
-    const size_t base = (size_t)d.slot * NF * NP;
-    for (int p = threadIdx.x; p < NP; p += blockDim.x) {
-      const int t[3] = {p % BS, (p / BS) % BS, DIM > 2 ? p / (BS * BS) : 0};
-      const int ti = G::idx(t[0] + H, t[1] + H, DIM > 2 ? t[2] + H : 0);
-      bool bnd = false, allEven = true;
-      unsigned long long cand = ~0ull;
-      for (int a = 0; a < DIM; ++a) {
-        if (t[a] == 0 || t[a] == BS - 1) bnd = true;
-        if (t[a] & 1) allEven = false;
-        cand &= g.m[a][t[a] + H];
-      }
-      if (bnd && g.ent[63 - __clzll((long long)cand)].dl > 0) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) A.u[base + (size_t)f * NP + p] = tile[f * TSZ + ti];
-      }
-      if (allEven) continue;   // restriction then prediction returns these nodes unchanged
-      int bb[3] = {0, 0, 0}, stride[3] = {2, 2, 2}, n[3] = {1, 1, 1};
-      for (int a = 0; a < DIM; ++a) {
-        bb[a] = t[a] + H;
-        if (t[a] & 1) { bb[a] -= 3; n[a] = 4; }
-      }
+  const double* tile;
+  const int* r0;
+  const int* cnt;
+  double* m;
+  __device__ __forceinline__ DetailsBody(const double* t_, const int* r_, const int* c_, double* m_)
+      : tile(t_), r0(r_), cnt(c_), m(m_) {}
+  template <int NX, int NY, int NZ>
+  __device__ __forceinline__ void go(int cls) {
+    ParityClass<DIM> pc(cls, r0, cnt);
+    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
+      int t[3];
+      pc.coords(p, t);
+      int i[3] = {t[0] - r0[0] + H, t[1] - r0[1] + H, DIM > 2 ? t[2] - r0[2] + H : 0};
+      const int bb[3] = {NX == 4 ? i[0] - 3 : i[0], NY == 4 ? i[1] - 3 : i[1], NZ == 4 ? i[2] - 3 : i[2]};
+      const int stride[3] = {2, 2, 2};
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         const double* T = tile + f * TSZ;
         auto at = [&](int x, int y, int z) { return T[G::idx(x, y, z)]; };
-        const double pred = tensor_p<DIM, double>(at, bb, stride, n);
-        m[f] = nanmax(m[f], fabs(T[ti] - pred));
+        const double pred = tensor_fixed<NX, NY, NZ, double>(at, bb, stride);
+        m[f] = nanmax(m[f], fabs(T[G::idx(i[0], i[1], i[2])] - pred));
       }
     }
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      double v = m[f];
-      for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][f] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      bool coarse = d.level > 1;
-      for (int f = 0; f < NF; ++f) {
-        double v = red[0][f];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = nanmax(v, red[w][f]);
-        A.maxd[(size_t)b * NF + f] = v;
-        if (!(v < A.thr[f])) coarse = false;
-      }
-      A.flags[b] = coarse ? (int8_t)-1 : (int8_t)0;
-    }
-    __syncthreads();
   }
-}
+  static constexpr int TSZ = Geo<DIM, BS, S, H>::TSZ;
+};
 
-// ---------------------------------------------------------------------------
-// refinement, one workgroup per (parent, child): the child's nodes take the
-// synchronised value at level l+1 -- a finer neighbour's stored value where one
-// holds the node, else the parent's value (even nodes) or its prediction (odd)
-// ---------------------------------------------------------------------------
-template <int DIM, int BS, int NF>
-__global__ void __launch_bounds__(256) k_refine(RefineArgs A) {
-  constexpr int HWR = 2, H = HWR + 3, S = (BS - 1) / 2 + 1;
+// child nodes of one parity class (see k_refine)
+template <int DIM, int BS, int S, int H, int NF>
+struct RefineBody {
   using G = Geo<DIM, BS, S, H>;
-  constexpr int NP = G::NP, TSZ = G::TSZ, NCH = 1 << DIM;
-  __shared__ GState<DIM, G::TW> g;
-  extern __shared__ __align__(16) char smem[];
-  double* tile = reinterpret_cast<double*>(smem);
-  const int nref = A.topo.h->n_ref;
-  for (int w = blockIdx.x; w < nref * NCH; w += gridDim.x) {
-    const int ri = w / NCH, ch = w % NCH;
-    const RefineDesc R = A.topo.ref()[ri];
-    const BlockDesc d = A.topo.pblk()[R.pblk];
-    int r0[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
-    for (int a = 0; a < DIM; ++a) {
-      r0[a] = ((ch >> a) & 1) * ((BS - 1) / 2);
-      cnt[a] = S;
-    }
-    gsetup<DIM, BS, S, H>(g, d, A.topo.pnb(), r0);
-    const int h_even = d.n_coarse > 0 ? H : 0;
-    YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
-    gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, HWR, h_even, src);
-    if (d.n_coarse > 0) gpredict<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, HWR);
-    const size_t cbase = (size_t)R.child[ch] * NF * NP;
-    for (int q = threadIdx.x; q < NP; q += blockDim.x) {
-      int Q[3] = {q % BS, (q / BS) % BS, DIM > 2 ? q / (BS * BS) : 0};
-      bool bnd = false, allEven = true;
+  const double* tile;
+  const GState<DIM, G::TW>& g;
+  const int* q0;
+  const int* qn;
+  const int* r0;
+  const int* cb;
+  int n_ent;
+  size_t cbase;
+  double* u;
+  __device__ __forceinline__ RefineBody(const double* t_, const GState<DIM, G::TW>& g_, const int* q0_, const int* qn_,
+                                 const int* r0_, const int* cb_, int ne, size_t cb0, double* u_)
+      : tile(t_), g(g_), q0(q0_), qn(qn_), r0(r0_), cb(cb_), n_ent(ne), cbase(cb0), u(u_) {}
+  template <int NX, int NY, int NZ>
+  __device__ __forceinline__ void go(int cls) {
+    ParityClass<DIM> pc(cls, q0, qn);
+    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
+      int qq[3];
+      pc.coords(p, qq);
+      int Q[3] = {0, 0, 0};
+      bool bnd = false;
+      int q = 0, mulq = 1;
       for (int a = 0; a < DIM; ++a) {
-        Q[a] += ((ch >> a) & 1) * (BS - 1);
+        q += qq[a] * mulq;
+        mulq *= BS;
+        Q[a] = qq[a] + cb[a];
         if (Q[a] == 0 || Q[a] == 2 * (BS - 1)) bnd = true;
-        if (Q[a] & 1) allEven = false;
       }
       int src_slot = -1, sidx = 0;
-      if (bnd && !allEven) {
-        for (int e = 0; e < d.n_ent && src_slot < 0; ++e) {
+      if (cls != 0 && bnd) {
+        for (int e = 0; e < n_ent && src_slot < 0; ++e) {
           const NbEntry& E = g.ent[e];
           if (E.dl <= 0) continue;
           bool in = true;
@@ -622,22 +751,161 @@ __global__ void __launch_bounds__(256) k_refine(RefineArgs A) {
       }
       if (src_slot >= 0) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) A.u[cbase + (size_t)f * NP + q] = A.u[((size_t)src_slot * NF + f) * NP + sidx];
+        for (int f = 0; f < NF; ++f) u[cbase + (size_t)f * NP + q] = u[((size_t)src_slot * NF + f) * NP + sidx];
         continue;
       }
-      int bb[3] = {0, 0, 0}, stride[3] = {1, 1, 1}, n[3] = {1, 1, 1};
-      for (int a = 0; a < DIM; ++a) {
-        // parent-local coordinate -> region-local -> tile coordinate
-        if (Q[a] & 1) { bb[a] = (Q[a] - 3) / 2 - r0[a] + H; n[a] = 4; }
-        else bb[a] = Q[a] / 2 - r0[a] + H;
-      }
+      // parent coordinate -> region-local -> tile coordinate
+      const int bb[3] = {NX == 4 ? (Q[0] - 3) / 2 - r0[0] + H : Q[0] / 2 - r0[0] + H,
+                         NY == 4 ? (Q[1] - 3) / 2 - r0[1] + H : Q[1] / 2 - r0[1] + H,
+                         DIM > 2 ? (NZ == 4 ? (Q[2] - 3) / 2 - r0[2] + H : Q[2] / 2 - r0[2] + H) : 0};
+      const int stride[3] = {1, 1, 1};
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         const double* T = tile + f * TSZ;
         auto at = [&](int x, int y, int z) { return T[G::idx(x, y, z)]; };
-        A.u[cbase + (size_t)f * NP + q] = tensor_p<DIM, double>(at, bb, stride, n);
+        u[cbase + (size_t)f * NP + q] = tensor_fixed<NX, NY, NZ, double>(at, bb, stride);
       }
     }
+  }
+  static constexpr int TSZ = Geo<DIM, BS, S, H>::TSZ;
+  static constexpr int NP = Geo<DIM, BS, S, H>::NP;
+};
+
+// ---------------------------------------------------------------------------
+// multiresolution analysis: details d = u - P(R(u)), per-field max, flag;
+// redundant nodes owned by finer neighbours are written back to the pool
+// ---------------------------------------------------------------------------
+
+template <int DIM, int BS, int NF, int NSUB>
+__global__ void __launch_bounds__(256) k_mr(MrArgs A) {
+  // H = 3: a region may start at an odd node, whose coarse stencil reaches 3 back
+  constexpr int S = (BS + NSUB - 1) / NSUB, H = 3;
+  using G = Geo<DIM, BS, S, H>;
+  constexpr int NP = G::NP, TSZ = G::TSZ;
+  constexpr int NSUBT = Pow<DIM, NSUB>::v;
+  __shared__ GState<DIM, G::TW> g;
+  __shared__ double red[4][4];
+  extern __shared__ __align__(16) char smem[];
+  double* tile = reinterpret_cast<double*>(smem);
+  const int nblk = A.topo.h->n_blocks;
+  for (XcdWork it(nblk * NSUBT); it.ok(); it.next()) {
+    const int w = it.w;
+    const int b = w / NSUBT;
+    const BlockDesc d = A.topo.blk()[b];
+    int r0[3], cnt[3];
+    subregion<DIM>(w % NSUBT, NSUB, S, BS, r0, cnt);
+    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(), r0);
+    YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
+    gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, 0, H, src);
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    const size_t base = (size_t)d.slot * NF * NP;
+    const int nn = cnt[0] * cnt[1] * (DIM > 2 ? cnt[2] : 1);
+    // redundant nodes owned by a finer neighbour: store the synchronised value
+    for (int p = threadIdx.x; p < nn; p += blockDim.x) {
+      const int l[3] = {p % cnt[0], DIM > 2 ? (p / cnt[0]) % cnt[1] : p / cnt[0], DIM > 2 ? p / (cnt[0] * cnt[1]) : 0};
+      const int t[3] = {r0[0] + l[0], r0[1] + l[1], DIM > 2 ? r0[2] + l[2] : 0};
+      bool bnd = false;
+      unsigned long long cand = ~0ull;
+      for (int a = 0; a < DIM; ++a) {
+        if (t[a] == 0 || t[a] == BS - 1) bnd = true;
+        cand &= g.m[a][l[a] + H];
+      }
+      if (bnd && g.ent[63 - __clzll((long long)cand)].dl > 0) {
+        const int ti = G::idx(l[0] + H, l[1] + H, DIM > 2 ? l[2] + H : 0);
+        const int node = t[0] + BS * t[1] + (DIM > 2 ? BS * BS * t[2] : 0);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) A.u[base + (size_t)f * NP + node] = tile[f * TSZ + ti];
+      }
+    }
+    // details d = u - P(R(u)) at nodes with an odd coordinate (zero at all-even nodes),
+    // one parity class at a time so that every lane runs the same unrolled stencil
+    DetailsBody<DIM, BS, S, H, NF> det(tile, r0, cnt, m);
+    for_odd_classes<DIM>(det);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      double v = m[f];
+      for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][f] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double v[4];
+      for (int f = 0; f < NF; ++f) {
+        v[f] = red[0][f];
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) v[f] = nanmax(v[f], red[q][f]);
+      }
+      bool last = true;
+      if constexpr (NSUBT > 1) {
+        // combine sub-tiles: |d| >= 0 (or NaN, whose bit pattern is larger than +Inf), so
+        // the unsigned maximum of the bit patterns is the maximum; the last sub-tile to
+        // finish reads and clears the partials
+        for (int f = 0; f < NF; ++f) atomicMax(&A.acc[(size_t)b * NF + f], (unsigned long long)__double_as_longlong(v[f]));
+        __threadfence();
+        last = atomicAdd(&A.done[b], 1) == NSUBT - 1;
+        if (last) {
+          __threadfence();
+          for (int f = 0; f < NF; ++f) v[f] = __longlong_as_double((long long)atomicExch(&A.acc[(size_t)b * NF + f], 0ull));
+          atomicExch(&A.done[b], 0);
+        }
+      }
+      if (last) {
+        bool coarse = d.level > 1;
+        for (int f = 0; f < NF; ++f) {
+          A.maxd[(size_t)b * NF + f] = v[f];
+          if (!(v[f] < A.thr[f])) coarse = false;
+        }
+        A.flags[b] = coarse ? (int8_t)-1 : (int8_t)0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// refinement, one workgroup per (parent, child, sub-tile of the child): the
+// child's nodes take the synchronised value at level l+1 -- a finer neighbour's
+// stored value where one holds the node, else the parent's value (even nodes)
+// or its prediction (odd nodes)
+// ---------------------------------------------------------------------------
+template <int DIM, int BS, int NF, int NSUB>
+__global__ void __launch_bounds__(256) k_refine(RefineArgs A) {
+  constexpr int SQ = (BS + NSUB - 1) / NSUB;       // child nodes per axis and sub-tile
+  constexpr int HWR = 2, H = HWR + 3, S = SQ / 2 + 2;
+  using G = Geo<DIM, BS, S, H>;
+  constexpr int NP = G::NP, TSZ = G::TSZ, NCH = 1 << DIM;
+  constexpr int NSUBT = Pow<DIM, NSUB>::v;
+  __shared__ GState<DIM, G::TW> g;
+  extern __shared__ __align__(16) char smem[];
+  double* tile = reinterpret_cast<double*>(smem);
+  const int nref = A.topo.h->n_ref;
+  for (XcdWork it(nref * NCH * NSUBT); it.ok(); it.next()) {
+    const int w = it.w;
+    const int ri = w / (NCH * NSUBT), ch = (w / NSUBT) % NCH;
+    const RefineDesc R = A.topo.ref()[ri];
+    const BlockDesc d = A.topo.pblk()[R.pblk];
+    int q0[3], qn[3];
+    subregion<DIM>(w % NSUBT, NSUB, SQ, BS, q0, qn);
+    // parent region holding the sub-tile's fine nodes Q = cb (bs-1) + q (parent coords Q/2)
+    int r0[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+    for (int a = 0; a < DIM; ++a) {
+      const int off = ((ch >> a) & 1) * (BS - 1);
+      r0[a] = (off + q0[a]) >> 1;
+      cnt[a] = ((off + q0[a] + qn[a]) >> 1) - r0[a] + 1;
+    }
+    gsetup<DIM, BS, S, H>(g, d, A.topo.pnb(), r0);
+    const int h_even = d.n_coarse > 0 ? H : 0;
+    YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
+    gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, HWR, h_even, src);
+    if (d.n_coarse > 0) gpredict<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, HWR);
+    const size_t cbase = (size_t)R.child[ch] * NF * NP;
+    int cb[3] = {0, 0, 0};
+    for (int a = 0; a < DIM; ++a) cb[a] = ((ch >> a) & 1) * (BS - 1);
+    // one parity class of child nodes at a time (fine parity = parity of q, since
+    // bs-1 is even): even nodes copy the parent, odd ones are predicted, and nodes on
+    // the parent's boundary held by a finer neighbour take that neighbour's value
+    RefineBody<DIM, BS, S, H, NF> rf(tile, g, q0, qn, r0, cb, d.n_ent, cbase, A.u);
+    rf.template go<1, 1, 1>(0);
+    for_odd_classes<DIM>(rf);
     __syncthreads();
   }
 }
@@ -677,7 +945,8 @@ __global__ void __launch_bounds__(256) k_read(ReadArgs A) {
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
   const int nblk = A.topo.h->n_blocks;
-  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+  for (XcdWork it(nblk); it.ok(); it.next()) {
+    const int b = it.w;
     const BlockDesc d = A.topo.blk()[b];
     int r0[3] = {0, 0, 0}, cnt[3] = {BS, BS, DIM > 2 ? BS : 1};
     gsetup<DIM, BS, S, H>(g, d, A.topo.nb(), r0);
@@ -706,7 +975,8 @@ static hipError_t go(K kern, int grid, size_t lds, hipStream_t st, const Arg& a)
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(grid > 0 ? grid : 1), dim3(256), lds, st, a);
+  grid = ((grid > 0 ? grid : 1) + 7) & ~7;  // XcdWork needs a multiple of 8
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
@@ -798,20 +1068,51 @@ hipError_t launch_plain(const Shape& s, int grid, const StageArgs& a, hipStream_
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mr(const Shape& s, int grid, const MrArgs& a, hipStream_t st) {
-#define X(D, B, W, F)                                                               \
-  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F)                            \
-    return go(k_mr<D, B, F>, grid, sizeof(double) * F * Geo<D, B, B, 2>::TSZ, st, a);
-  MRB_SHAPES(X)
+// analysis (kind 0) and refinement (kind 1) tilings per shape
+#define MRB_AUX_VARIANTS(X) \
+  X(2, 17, 2, 1, 1)         \
+  X(2, 17, 2, 1, 2)         \
+  X(2, 33, 2, 1, 1)         \
+  X(2, 33, 2, 1, 2)         \
+  X(2, 33, 2, 1, 4)         \
+  X(2, 33, 4, 4, 1)         \
+  X(2, 33, 4, 4, 2)         \
+  X(3, 17, 2, 1, 1)         \
+  X(3, 17, 2, 1, 2)
+
+int aux_variants(const Shape& s, int kind, int* nsub, int cap) {
+  int n = 0;
+  (void)kind;
+#define X(D, B, W, F, NS) if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && n < cap) nsub[n++] = NS;
+  MRB_AUX_VARIANTS(X)
+#undef X
+  return n;
+}
+
+template <int D, int B, int F, int NS>
+static hipError_t mr_go(int grid, const MrArgs& a, hipStream_t st) {
+  constexpr int S = (B + NS - 1) / NS;
+  return go(k_mr<D, B, F, NS>, grid, sizeof(double) * F * Geo<D, B, S, 3>::TSZ, st, a);
+}
+
+template <int D, int B, int F, int NS>
+static hipError_t refine_go(int grid, const RefineArgs& a, hipStream_t st) {
+  constexpr int SQ = (B + NS - 1) / NS;
+  return go(k_refine<D, B, F, NS>, grid, sizeof(double) * F * Geo<D, B, SQ / 2 + 2, 5>::TSZ, st, a);
+}
+
+hipError_t launch_mr(const Shape& s, int nsub, int grid, const MrArgs& a, hipStream_t st) {
+#define X(D, B, W, F, NS) \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && nsub == NS) return mr_go<D, B, F, NS>(grid, a, st);
+  MRB_AUX_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_refine(const Shape& s, int grid, const RefineArgs& a, hipStream_t st) {
-#define X(D, B, W, F)                                                                                \
-  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F)                                             \
-    return go(k_refine<D, B, F>, grid, sizeof(double) * F * Geo<D, B, (B - 1) / 2 + 1, 5>::TSZ, st, a);
-  MRB_SHAPES(X)
+hipError_t launch_refine(const Shape& s, int nsub, int grid, const RefineArgs& a, hipStream_t st) {
+#define X(D, B, W, F, NS) \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && nsub == NS) return refine_go<D, B, F, NS>(grid, a, st);
+  MRB_AUX_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
 }

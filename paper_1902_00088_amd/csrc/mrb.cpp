@@ -72,6 +72,8 @@ struct mrb_ctx {
   size_t arena_cap = 0;
   int8_t* dflags = nullptr;
   double* dmaxd = nullptr;
+  unsigned long long* dacc = nullptr;   // analysis partial maxima (zero between passes)
+  int* ddone = nullptr;                 // analysis sub-tiles finished (zero between passes)
   double* ds2 = nullptr;
   double* ds = nullptr;
   double* dghost = nullptr;
@@ -85,7 +87,17 @@ struct mrb_ctx {
   double* h_maxd = nullptr;    // pinned
   int ncu = 256;
   int nsub = 0;                // stage sub-tiles per axis (0 = choose by block count)
+  int nsub_mr = -1;            // analysis sub-tiles per axis (-1 = whole blocks, measured best)
   std::string tune_log;
+  // captured step graphs (refine, four stages, first analysis), keyed by launch parameters
+  bool use_graph = true;
+  struct GraphEntry { uint64_t key[6]; hipGraphExec_t exec; };
+  std::vector<GraphEntry> graphs;
+  long n_graph_launches = 0;
+  // host-side time (microseconds) by phase
+  double hus_refine_plan = 0, hus_coarsen_plan = 0, hus_upload = 0, hus_wait = 0, hus_launch = 0;
+  int pending_ref = 0;          // parents in the last uploaded refinement plan
+  bool hcount_ref_zero = true;  // the uploaded header has no refinement plan
 
   LevelTab lt;
   Physics ph;
@@ -109,6 +121,18 @@ struct mrb_ctx {
 };
 
 namespace {
+
+double now_us() {
+  return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// adds the elapsed host time of a scope to an accumulator
+struct HostTimer {
+  double* acc;
+  double t0;
+  explicit HostTimer(double* a) : acc(a), t0(now_us()) {}
+  ~HostTimer() { *acc += now_us() - t0; }
+};
 
 mrb_status fail(mrb_ctx* c, mrb_status s, const std::string& m) {
   c->err = m;
@@ -323,6 +347,7 @@ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
                        const std::vector<NbEntry>* pnb = nullptr, const std::vector<RefineDesc>* ref = nullptr,
                        const std::vector<FamilyDesc>* fam = nullptr) {
+  HostTimer ht(&c->hus_upload);
   TopoHeader h;
   std::memset(&h, 0, sizeof h);
   h.n_blocks = (int)c->hblk.size();
@@ -434,8 +459,25 @@ int pick_nsub(const mrb_ctx* c) {
   return v[nv - 1];
 }
 
+// sub-tiles per axis for the analysis / refinement kernels: the smallest count whose
+// workgroups (n_items each) cover the chip twice
+int pick_aux(const mrb_ctx* c, long n_items, int forced = 0) {
+  int v[8];
+  const int nv = aux_variants(c->shape, 0, v, 8);
+  for (int i = 0; i < nv; ++i)
+    if (forced && v[i] == forced) return forced;
+  if (forced < 0) return 1;  // whole blocks
+  std::sort(v, v + nv);
+  for (int i = 0; i < nv; ++i) {
+    long w = n_items;
+    for (int a = 0; a < c->cfg.dim; ++a) w *= v[i];
+    if (w >= 2L * c->ncu) return v[i];
+  }
+  return v[nv - 1];
+}
+
 // launch one RK stage (fused) or ghost + RHS per level (plain)
-mrb_status run_stage(mrb_ctx* c, int s, const StageArgs& a0) {
+mrb_status run_stage(mrb_ctx* c, int s, const StageArgs& a0, bool fixed_grid = false) {
   StageArgs a = a0;
   const int n = (int)c->hblk.size();
   if (c->cfg.form == MRB_FORM_PLAIN) {
@@ -453,7 +495,8 @@ mrb_status run_stage(mrb_ctx* c, int s, const StageArgs& a0) {
   long work = n;
   for (int d = 0; d < c->cfg.dim; ++d) work *= nsub;
   TimeScope ts(c, T_STAGE, (double)n * c->bsz * stage_bytes(c, s));
-  HIPCHK(c, launch_stage(c->shape, c->cfg.precision, Variant{nsub}, grid_for(c, work), a, c->stream));
+  HIPCHK(c, launch_stage(c->shape, c->cfg.precision, Variant{nsub}, fixed_grid ? c->grid : grid_for(c, work), a,
+                         c->stream));
   return MRB_OK;
 }
 
@@ -476,7 +519,7 @@ StageArgs stage_args(mrb_ctx* c) {
 }
 
 // the four stages of one RK4 step; results go to k1..k3 and u_new (u is read only)
-mrb_status sweep(mrb_ctx* c, double t, double dt) {
+mrb_status sweep(mrb_ctx* c, double t, double dt, bool fixed_grid = false) {
   const double h2 = dt * 0.5, h6 = dt / 6.0;
   const double ts[4] = {t, t + h2, t + h2, t + dt};
   StageArgs a = stage_args(c);
@@ -489,7 +532,7 @@ mrb_status sweep(mrb_ctx* c, double t, double dt) {
     a.kout = s < 4 ? c->k[s - 1] : nullptr;
     a.cfac = 1.0;
     if (c->cfg.physics == MRB_ADV_SWIRL && c->cfg.phys[0] > 0.0) a.cfac = std::cos(M_PI * ts[s - 1] / c->cfg.phys[0]);
-    mrb_status r = run_stage(c, s, a);
+    mrb_status r = run_stage(c, s, a, fixed_grid);
     if (r) return r;
   }
   return MRB_OK;
@@ -504,12 +547,32 @@ mrb_status do_rk4(mrb_ctx* c, double t, double dt) {
   return MRB_OK;
 }
 
-mrb_status do_refine_all(mrb_ctx* c) {
+// refinement kernel over the uploaded plan (nref parents); fixed_grid for graph capture
+mrb_status launch_refine_kernel(mrb_ctx* c, int nref, bool fixed_grid) {
+  const int nch = 1 << c->cfg.dim;
+  RefineArgs a{topo(c), c->u};
+  const int ns = pick_aux(c, (long)nref * nch);
+  long work = (long)nref * nch;
+  for (int q = 0; q < c->cfg.dim; ++q) work *= ns;
+  TimeScope ts(c, T_REFINE, (double)nref * c->bsz * 8.0 * (1 + nch));
+  HIPCHK(c, launch_refine(c->shape, ns, fixed_grid ? c->grid : grid_for(c, work), a, c->stream));
+  return MRB_OK;
+}
+
+// Plan the safety-zone refinement (new forest, descriptors, one upload) and, if
+// launch is set, run the refinement kernel.
+mrb_status do_refine_all(mrb_ctx* c, bool launch = true) {
+  HostTimer ht(&c->hus_refine_plan);
   const int d = c->cfg.dim, nch = 1 << d;
+  c->pending_ref = 0;
   std::vector<int> par;
   for (int i = 0; i < (int)c->leaves.size(); ++i)
     if (c->leaves[i].level < c->cfg.jmax) par.push_back(i);
-  if (par.empty()) return MRB_OK;
+  if (par.empty()) {
+    // the upload still clears the previous refinement plan of the header
+    return c->hcount_ref_zero ? MRB_OK : (c->hcount_ref_zero = true, upload_topo(c));
+  }
+  c->hcount_ref_zero = false;
   if (c->free_slots.size() < par.size() * nch) return fail(c, MRB_E_CAPACITY, "refine_all: pool too small");
   // parents' descriptors and entries on the grid before refinement
   std::vector<BlockDesc> pblk(par.size());
@@ -563,31 +626,44 @@ mrb_status do_refine_all(mrb_ctx* c) {
     return s;
   }
   for (int sl : freed) c->free_slots.push_back(sl);
-  RefineArgs a{topo(c), c->u};
-  {
-    TimeScope ts(c, T_REFINE, (double)ref.size() * c->bsz * 8.0 * (1 + nch));
-    HIPCHK(c, launch_refine(c->shape, grid_for(c, (long)ref.size() * nch), a, c->stream));
-  }
   c->n_refined += (long)par.size();
   c->have_flags = false;
-  return MRB_OK;
+  c->pending_ref = (int)ref.size();
+  if (!launch) return MRB_OK;
+  return launch_refine_kernel(c, c->pending_ref, false);
 }
 
-mrb_status do_mr_pass(mrb_ctx* c) {
-  const int n = (int)c->hblk.size();
+MrArgs mr_args(mrb_ctx* c) {
   MrArgs a;
   a.topo = topo(c);
   a.u = c->u;
   a.flags = c->dflags;
   a.maxd = c->dmaxd;
+  a.acc = c->dacc;
+  a.done = c->ddone;
   for (int f = 0; f < 4; ++f) a.thr[f] = f < (int)c->thr.size() ? c->thr[f] : 0.0;
-  {
-    TimeScope ts(c, T_MR, (double)n * c->bsz * 8.0);
-    HIPCHK(c, launch_mr(c->shape, grid_for(c, n), a, c->stream));
-  }
+  return a;
+}
+
+mrb_status launch_mr_kernel(mrb_ctx* c, bool fixed_grid) {
+  const int n = (int)c->hblk.size();
+  MrArgs a = mr_args(c);
+  const int ns = pick_aux(c, n, c->nsub_mr);
+  long work = n;
+  for (int q = 0; q < c->cfg.dim; ++q) work *= ns;
+  TimeScope ts(c, T_MR, (double)n * c->bsz * 8.0);
+  HIPCHK(c, launch_mr(c->shape, ns, fixed_grid ? c->grid : grid_for(c, work), a, c->stream));
+  return MRB_OK;
+}
+
+mrb_status mr_readback(mrb_ctx* c) {
+  const int n = (int)c->hblk.size();
   HIPCHK(c, hipMemcpyAsync(c->h_flags, c->dflags, n, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->h_maxd, c->dmaxd, sizeof(double) * n * c->cfg.nfields, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  {
+    HostTimer ht(&c->hus_wait);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
   c->last_flags.assign(c->h_flags, c->h_flags + n);
   c->last_maxd.assign(c->h_maxd, c->h_maxd + (size_t)n * c->cfg.nfields);
   c->have_flags = true;
@@ -595,6 +671,12 @@ mrb_status do_mr_pass(mrb_ctx* c) {
   for (double v : c->last_maxd)
     if (!std::isfinite(v)) return fail(c, MRB_E_NONFINITE, "detail norm is not finite");
   return MRB_OK;
+}
+
+mrb_status do_mr_pass(mrb_ctx* c) {
+  mrb_status r = launch_mr_kernel(c, false);
+  if (r) return r;
+  return mr_readback(c);
 }
 
 // largest set of complete, flagged families whose merge keeps the grid graded
@@ -655,6 +737,7 @@ std::vector<uint64_t> coarsenable(mrb_ctx* c, const int8_t* flags) {
 }
 
 mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
+  HostTimer ht(&c->hus_coarsen_plan);
   const int d = c->cfg.dim, nch = 1 << d;
   std::vector<uint64_t> fams = coarsenable(c, flags);
   if (ncoarse) *ncoarse = (int)fams.size();
@@ -714,10 +797,10 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
   return MRB_OK;
 }
 
-mrb_status do_adapt(mrb_ctx* c, int* npass) {
+mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false) {
   int passes = 0;
   for (;;) {
-    mrb_status s = do_mr_pass(c);
+    mrb_status s = (first_launched && passes == 0) ? mr_readback(c) : do_mr_pass(c);
     ++passes;
     if (s) return s;
     int nc = 0;
@@ -754,6 +837,69 @@ bool check_state(mrb_ctx* c, bool need_data) {
 namespace mrb {
 hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst, hipStream_t st);
 }
+
+namespace {
+
+// One MR step with the refinement, the four stages and the first analysis replayed
+// from a captured graph (launch parameters are fixed; block counts and
+// descriptors come from the device topology header).
+mrb_status step_graph(mrb_ctx* c, double t, double dt) {
+  mrb_status r = do_refine_all(c, false);
+  if (r) return r;
+  uint64_t dtb;
+  std::memcpy(&dtb, &dt, sizeof dtb);
+  const int ns = pick_nsub(c);
+  const int nsm = pick_aux(c, (long)c->hblk.size(), c->nsub_mr);
+  const int nsr = pick_aux(c, (long)std::max(1, c->pending_ref) << c->cfg.dim);
+  const uint64_t key[6] = {(uint64_t)(uintptr_t)c->u, (uint64_t)ns, (uint64_t)nsm, (uint64_t)nsr, dtb,
+                           (uint64_t)(uintptr_t)c->arena};
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : c->graphs)
+    if (std::memcmp(g.key, key, sizeof key) == 0) exec = g.exec;
+  if (!exec) {
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    mrb_status e = launch_refine_kernel(c, std::max(1, c->pending_ref), true);
+    if (!e) e = sweep(c, t, dt, true);
+    double* u0 = c->u;
+    if (!e) {
+      std::swap(c->u, c->unew);
+      e = launch_mr_kernel(c, true);
+      std::swap(c->u, c->unew);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(c->stream, &graph);
+    if (e) { if (graph) (void)hipGraphDestroy(graph); return e; }
+    if (ec != hipSuccess) return fail(c, MRB_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ec != hipSuccess) return fail(c, MRB_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
+    (void)u0;
+    if (c->graphs.size() >= 4) {
+      (void)hipGraphExecDestroy(c->graphs.front().exec);
+      c->graphs.erase(c->graphs.begin());
+    }
+    mrb_ctx::GraphEntry ge;
+    std::memcpy(ge.key, key, sizeof key);
+    ge.exec = exec;
+    c->graphs.push_back(ge);
+  }
+  {
+    HostTimer ht(&c->hus_launch);
+    HIPCHK(c, hipGraphLaunch(exec, c->stream));
+  }
+  c->n_graph_launches++;
+  std::swap(c->u, c->unew);
+  c->n_rk4++;
+  c->n_block_updates += (long)c->hblk.size();
+  return do_adapt(c, nullptr, true);
+}
+
+bool graph_ok(const mrb_ctx* c) {
+  return c->use_graph && !c->timing && c->cfg.form == MRB_FORM_FUSED &&
+         !(c->cfg.physics == MRB_ADV_SWIRL && c->cfg.phys[0] > 0.0) && c->stream != nullptr;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -827,7 +973,10 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
     return true;
   };
   const size_t mb = cfg->max_blocks;
-  bool ok = dev((void**)&c->dflags, mb) && dev((void**)&c->dmaxd, mb * cfg->nfields * sizeof(double)) &&
+  bool ok = dev((void**)&c->dflags, mb) && dev((void**)&c->dacc, mb * cfg->nfields * 8) &&
+            dev((void**)&c->ddone, mb * sizeof(int)) &&
+            hipMemset(c->dacc, 0, mb * cfg->nfields * 8) == hipSuccess &&
+            hipMemset(c->ddone, 0, mb * sizeof(int)) == hipSuccess && dev((void**)&c->dmaxd, mb * cfg->nfields * sizeof(double)) &&
             dev((void**)&c->dslots, mb * sizeof(int));
   if (ok && cfg->physics == MRB_ADV_SWIRL) {
     const size_t n = (size_t)(1L << cfg->jmax) * (cfg->bs - 1);
@@ -869,8 +1018,9 @@ mrb_status mrb_destroy(mrb_ctx* c) {
   Staging* sts[] = {&c->st_topo[0], &c->st_topo[1], &c->st_slots};
   for (Staging* s : sts) release_staging(*s);
   for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
-  void* ptrs[] = {c->arena, c->dflags, c->dmaxd,
+  void* ptrs[] = {c->arena, c->dflags, c->dmaxd, c->dacc, c->ddone,
                   c->ds2, c->ds, c->dghost, c->dscratch, c->dslots};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -986,9 +1136,13 @@ mrb_status mrb_step(mrb_ctx* c, double t0, double dt, int nsteps) {
   if (nsteps < 0 || !(dt > 0.0)) return fail(c, MRB_E_ARG, "step: bad dt or nsteps");
   for (int s = 0; s < nsteps; ++s) {
     mrb_status r;
-    if ((r = do_refine_all(c))) return r;
-    if ((r = do_rk4(c, t0 + s * dt, dt))) return r;
-    if ((r = do_adapt(c, nullptr))) return r;
+    if (graph_ok(c)) {
+      if ((r = step_graph(c, t0 + s * dt, dt))) return r;
+    } else {
+      if ((r = do_refine_all(c))) return r;
+      if ((r = do_rk4(c, t0 + s * dt, dt))) return r;
+      if ((r = do_adapt(c, nullptr))) return r;
+    }
     c->n_steps++;
   }
   return MRB_OK;
@@ -1052,10 +1206,13 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"tune_ms\": {%s}, \"kernels\": %s}",
+                "\"stage_tiles\": %d, \"graph_launches\": %ld, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f}, "
+                "\"tune_ms\": {%s}, \"kernels\": %s}",
                 c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
                 c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
-                c->tune_log.c_str(), kern.c_str());
+                c->n_graph_launches, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
+                c->hus_launch, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
   return MRB_OK;
 }
@@ -1097,14 +1254,50 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
       c->tune_log += buf;
       if (ms < best) { best = ms; best_v = v[i]; }
     }
+    c->nsub = best_v;
+    // analysis tilings: a pass only synchronises redundant nodes (idempotent) and
+    // rewrites flags and maxima
+    int va[8];
+    const int na = aux_variants(c->shape, 0, va, 8);
+    float best_a = 1e30f;
+    int best_va = 0;
+    c->tune_log += ", \"mr\": {";
+    for (int i = 0; i < na; ++i) {
+      c->nsub_mr = va[i];
+      mrb_status r = do_mr_pass(c);
+      if (r && r != MRB_E_NONFINITE) return r;
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      MrArgs a = mr_args(c);
+      const int n = (int)c->hblk.size();
+      long work = n;
+      for (int q = 0; q < c->cfg.dim; ++q) work *= va[i];
+      for (int k = 0; k < reps; ++k) HIPCHK(c, launch_mr(c->shape, va[i], grid_for(c, work), a, c->stream));
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      char buf[64];
+      std::snprintf(buf, sizeof buf, "%s\"%d\": %.4f", i ? ", " : "", va[i], ms / reps);
+      c->tune_log += buf;
+      if (ms < best_a) { best_a = ms; best_va = va[i]; }
+    }
+    c->tune_log += "}";
+    c->nsub_mr = best_va;
+    c->have_flags = false;
     c->timing = was_timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    c->nsub = best_v;
   } else {
     c->nsub = 0;
+    c->nsub_mr = -1;
   }
   if (chosen) *chosen = c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1;
+  return MRB_OK;
+}
+
+mrb_status mrb_set_graph(mrb_ctx* c, int enable) {
+  if (!c) return MRB_E_ARG;
+  c->use_graph = enable != 0;
   return MRB_OK;
 }
 
