@@ -69,6 +69,7 @@ def lib():
             ("orc_rhs", [ctypes.c_void_p, ctypes.c_double, _dp]),
             ("orc_rk4", [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]),
             ("orc_refine_all", [ctypes.c_void_p]),
+            ("orc_refine_marked", [ctypes.c_void_p, _i8p]),
             ("orc_mr_pass", [ctypes.c_void_p, _i8p, _dp]),
             ("orc_coarsen", [ctypes.c_void_p, _i8p]),
             ("orc_coarsenable", [ctypes.c_void_p, _i8p, _i8p, _i32p]),
@@ -175,6 +176,13 @@ class Oracle:
     # ---- the method ------------------------------------------------------------------
     def refine_all(self):
         self._chk(lib().orc_refine_all(self.h))
+
+    def refine_marked(self, mask) -> int:
+        """Refine the marked leaves (forest order) and every coarser leaf that must
+        follow for the grid to stay graded; returns the number refined."""
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.int8))
+        assert len(m) == self.num_blocks()
+        return self._chk(lib().orc_refine_marked(self.h, _ptr(m, _i8p)))
 
     def rk4(self, t: float, dt: float):
         self._chk(lib().orc_rk4(self.h, t, dt))

@@ -550,15 +550,11 @@ struct Oracle {
     }
   }
 
-  // safety zone: every leaf below jmax is replaced by its 2^d children, whose
-  // nodes take the synchronised value at level l+1 (prediction where needed)
-  void refine_all() {
+  // replace every leaf of R by its 2^d children, whose nodes take the synchronised
+  // value at level l+1 on the grid before any replacement (prediction where needed)
+  void refine_set(const std::set<Key>& R) {
     std::vector<std::pair<Key, std::vector<double>>> made;
-    std::vector<Key> gone;
-    for (auto& kv : F) {
-      const Key& k = kv.first;
-      if (k.l >= jmax) continue;
-      gone.push_back(k);
+    for (auto& k : R) {
       for (auto& c : children(k)) {
         std::vector<double> v((size_t)nf * np);
         int hi1 = dim > 1 ? bs : 1, hi2 = dim > 2 ? bs : 1;
@@ -574,12 +570,62 @@ struct Oracle {
         made.push_back({c, v});
       }
     }
-    for (auto& k : gone) F.erase(k);
+    for (auto& k : R) F.erase(k);
     for (auto& pr : made) {
       Leaf lf;
       lf.u = pr.second;
       F[pr.first] = lf;
     }
+  }
+
+  // safety zone (Sec. 2.1 item 1): every leaf below jmax is refined
+  void refine_all() {
+    std::set<Key> R;
+    for (auto& kv : F)
+      if (kv.first.l < jmax) R.insert(kv.first);
+    refine_set(R);
+  }
+
+  // leaves one level coarser than m whose closed region touches m's closed region
+  // (periodic); found by testing every leaf of that level
+  std::vector<Key> coarser_touching(const Key& m) const {
+    std::vector<Key> r;
+    const long nb = 1L << m.l;   // level-l blocks per direction
+    for (auto& kv : F) {
+      const Key& k = kv.first;
+      if (k.l != m.l - 1) continue;
+      bool touch = true;
+      for (int a = 0; a < dim; ++a) {
+        // in level-l block units m spans [c, c+1] and k spans [2c', 2c'+2]
+        bool any = false;
+        for (long s = -nb; s <= nb; s += nb) {
+          long lo = std::max<long>(m.c[a], 2L * k.c[a] + s);
+          long hi = std::min<long>(m.c[a] + 1, 2L * k.c[a] + 2 + s);
+          if (lo <= hi) any = true;
+        }
+        if (!any) touch = false;
+      }
+      if (touch) r.push_back(k);
+    }
+    return r;
+  }
+
+  // refine the marked leaves (those below jmax) and, so that the grid stays graded
+  // (Sec. 2.2), every coarser leaf touching a leaf that refines, recursively.
+  // Returns the number of leaves refined.
+  int refine_marked(const std::set<Key>& marked) {
+    std::set<Key> R;
+    std::vector<Key> work;
+    for (auto& k : marked)
+      if (k.l < jmax && F.count(k) && R.insert(k).second) work.push_back(k);
+    while (!work.empty()) {
+      Key m = work.back();
+      work.pop_back();
+      for (auto& k : coarser_touching(m))
+        if (R.insert(k).second) work.push_back(k);
+    }
+    refine_set(R);
+    return (int)R.size();
   }
 };
 
@@ -763,6 +809,18 @@ int orc_rk4(void* h, double t, double dt) {
 
 int orc_refine_all(void* h) {
   ORC_TRY({ O->refine_all(); return 0; })
+}
+
+// refine the leaves with mask[i] != 0 (forest order) plus the gradedness closure;
+// returns the number of leaves refined
+int orc_refine_marked(void* h, const int8_t* mask) {
+  ORC_TRY({
+    std::set<Key> m;
+    auto ord = O->order();
+    for (size_t i = 0; i < ord.size(); ++i)
+      if (mask[i]) m.insert(ord[i]);
+    return O->refine_marked(m);
+  })
 }
 
 // one MR analysis: synchronise, details, flags.  flags [n], maxd [n][nf], forest order

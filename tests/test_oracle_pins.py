@@ -630,3 +630,71 @@ def test_ns_rhs_single_mode_closed_forms():
     assert np.max(np.abs(r[:, 2])) < tol
     want_p = -g * p0 * K * A * c + (g - 1) * (4.0 / 3.0) * mu * (K * A * c) ** 2
     assert np.max(np.abs(r[:, 3] - want_p)) < tol
+
+
+def _touch(a, b, dim):
+    """Closed regions of leaves a=(l, c...) and b touch (periodic unit domain)."""
+    la, lb = a[0], b[0]
+    L = max(la, lb)
+    n = 1 << L
+    for ax in range(dim):
+        sa, sb = 1 << (L - la), 1 << (L - lb)
+        lo_a, lo_b = a[1 + ax] * sa, b[1 + ax] * sb
+        ok = False
+        for s in (-n, 0, n):
+            if max(lo_a, lo_b + s) <= min(lo_a + sa, lo_b + s + sb):
+                ok = True
+        if not ok:
+            return False
+    return True
+
+
+@pytest.mark.parametrize("dim,seed", [(2, 0), (2, 1), (2, 2), (3, 3)])
+def test_refine_marked_is_graded_minimal_and_matches_refine_all(dim, seed):
+    """Partial refinement (the 'arbitrary indicator' refinement of Sec. 2.3 under the
+    gradedness of Sec. 2.2): every marked leaf below jmax refines; every other leaf that
+    refines touches a finer refining leaf (minimal closure); the result is a valid
+    graded forest; children values equal those refine-all computes from the same grid."""
+    jmax = 4 if dim == 2 else 3
+    cfg = W.Config(name="t", dim=dim, bs=9, hw=2, nf=1, jmax=jmax, eps=1e-3, physics=W.ADV_CONST,
+                   phys=(1.0, 0.5, 0.25), dt=1e-3, steps=1, max_blocks=4 * 4 ** jmax if dim == 2 else 8 ** jmax)
+    lv, co = W.random_graded_forest(dim, jmax - 1, seed)
+    a = oracle.Oracle(cfg)
+    a.init_forest(lv, co)
+    lv, co = a.read_forest()             # forest order
+    data = W.sample(cfg, lv, co, fn=lambda *x: np.cos(2 * np.pi * x[0]) * np.sin(2 * np.pi * x[1])
+                    + 0.3 * np.sin(4 * np.pi * x[-1]))
+    rng = np.random.default_rng(100 + seed)
+    mask = (rng.random(len(lv)) < 0.15).astype(np.int8)
+    a.load_blocks(data)
+    k = a.refine_marked(mask)
+    lv2, co2 = a.read_forest()
+    oracle.Oracle(cfg).init_forest(lv2, co2)   # raises unless the result tiles and is graded
+    before = {(int(l),) + tuple(int(v) for v in c) for l, c in zip(lv, co)}
+    after = {(int(l),) + tuple(int(v) for v in c) for l, c in zip(lv2, co2)}
+    refined = before - after
+    assert len(refined) == k
+    marked = {(int(lv[i]),) + tuple(int(v) for v in co[i]) for i in range(len(lv)) if mask[i] and lv[i] < jmax}
+    assert marked <= refined
+    for r in refined - marked:
+        assert any(q[0] == r[0] + 1 and _touch(q, r, dim) for q in refined), r
+    # children of each refined leaf exist and hold the refine-all values
+    b = oracle.Oracle(cfg)
+    b.init_forest(lv, co)
+    b.load_blocks(data)
+    b.refine_all()
+    lv3, co3 = b.read_forest()
+    full = {(int(l),) + tuple(int(v) for v in c): i for i, (l, c) in enumerate(zip(lv3, co3))}
+    da, db = a.read_stored(), b.read_stored()
+    for i, (l, c) in enumerate(zip(lv2, co2)):
+        key = (int(l),) + tuple(int(v) for v in c)
+        if key not in before:
+            assert np.array_equal(da[i], db[full[key]])
+    # all-ones mask is refine-all
+    c_ = oracle.Oracle(cfg)
+    c_.init_forest(lv, co)
+    c_.load_blocks(data)
+    c_.refine_marked(np.ones(len(lv), np.int8))
+    l4, c4 = c_.read_forest()
+    assert np.array_equal(l4, lv3) and np.array_equal(c4, co3)
+    assert np.array_equal(c_.read_stored(), db)

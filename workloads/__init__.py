@@ -253,3 +253,39 @@ def random_graded_forest(dim: int, jmax: int, seed: int, p_refine: float = 0.45,
     levels = np.array([k[0] for k in lst], dtype=np.int8)
     coords = np.array([k[1:] for k in lst], dtype=np.int32).reshape(len(lst), dim)
     return levels, coords
+
+
+# --------------------------------------------------------------------------------------
+# learned predictor: seeded inputs (initial weights, class weights, batch order)
+# --------------------------------------------------------------------------------------
+
+MLP_HIDDEN = 64
+MLP_OUT = 3
+
+
+def mlp_init_params(nin: int, seed: int) -> np.ndarray:
+    """Initial parameters of the nin -> 64 -> 64 -> 3 MLP, uniform in +-1/sqrt(fan_in),
+    packed W1[nin][64], b1, W2[64][64], b2, W3[64][3], b3 (float32)."""
+    rng = np.random.default_rng(seed)
+    h, o = MLP_HIDDEN, MLP_OUT
+    parts = [rng.uniform(-1, 1, (nin, h)) / math.sqrt(nin), rng.uniform(-1, 1, h) / math.sqrt(nin),
+             rng.uniform(-1, 1, (h, h)) / math.sqrt(h), rng.uniform(-1, 1, h) / math.sqrt(h),
+             rng.uniform(-1, 1, (h, o)) / math.sqrt(h), rng.uniform(-1, 1, o) / math.sqrt(h)]
+    return np.concatenate([q.ravel() for q in parts]).astype(np.float32)
+
+
+def class_weights(labels, ncls: int = 3) -> np.ndarray:
+    """Inverse-frequency weights n / (ncls * n_c) (1 for absent classes)."""
+    labels = np.asarray(labels)
+    n = len(labels)
+    w = np.ones(ncls, dtype=np.float32)
+    for c in range(ncls):
+        k = int(np.sum(labels == c))
+        if k:
+            w[c] = n / (ncls * k)
+    return w
+
+
+def epoch_order(n: int, seed: int, epoch: int) -> np.ndarray:
+    """Seeded permutation of the training samples for one epoch."""
+    return np.random.default_rng([seed, epoch]).permutation(n)
