@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="fp64_plain,fp64_fused,mixed_fused")
     ap.add_argument("--c4-steps", type=int, default=20, help="steps of the 3D workload (0 = skip)")
+    ap.add_argument("--c5-steps", type=int, default=2000,
+                    help="recorded steps of the learned-predictor study (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the multi-GPU path (sharding the block forest along the "
@@ -172,6 +174,16 @@ def main():
                      "forms": c4,
                      "roofline_stage_mixed": {"bound": "hbm", "achieved": ach4, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                               "frac": ach4 / PEAK_HBM_GBS}}
+    if args.c5_steps > 0:
+        from paper_1902_00088_amd import predictor as P
+        c5 = {}
+        for name, cfg in (("C5_mixing_layer", W.C3(precision=W.MIXED)), ("swirl_moving_fronts", base.replace(precision=W.MIXED))):
+            print(f"bench: predictor study {name} steps={args.c5_steps}", file=sys.stderr, flush=True)
+            s = M.Solver(cfg)
+            s.init_grid()
+            c5[name] = P.gain_study(s, W.mlp_init_params(64 * cfg.nf, 5), nsteps=args.c5_steps)
+            s.close()
+        out["predictor"] = c5
     if not args.no_cpu:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W, base, args.cpu_seconds)

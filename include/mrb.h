@@ -158,6 +158,50 @@ mrb_status mrb_tune(mrb_ctx *ctx, int nsub, int reps, double dt, int *chosen);
  * identical with the graph on or off. */
 mrb_status mrb_set_graph(mrb_ctx *ctx, int enable);
 
+/* ---------------------------------------------------------------------------
+ * Learned refinement predictor.  The paper's refinement flag admits "+1 for
+ * refinement" from arbitrary indicators besides the detail test (Sec. 2.3, after the
+ * flag rule); here a per-block MLP predicts which blocks the safety zone (Sec. 2.1
+ * item 1) needs to refine, and the exact detail threshold still decides every
+ * coarsening.  2D only.  Features: per field, the 8 x 8 averages of the synchronised
+ * block over bins of (bs-1)/8 nodes (last node row/column unused), x-fastest bins,
+ * fields outer (nin = 64 * nfields).  Network: nin -> 64 -> 64 -> 3, GELU, FP32;
+ * parameters packed W1[nin][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3]
+ * (row-major).  Classes: 0 refine, 1 keep, 2 coarsen.  All arrays are host memory.
+ * --------------------------------------------------------------------------- */
+
+/* Set the model: parameters (see layout), per-field normalisation mean[nf], std[nf]
+ * applied to the features (x - mean)/std; resets the Adam state. */
+mrb_status mrb_mlp_init(mrb_ctx *ctx, int nin, const float *params, const float *mean, const float *std);
+mrb_status mrb_mlp_get_params(mrb_ctx *ctx, float *params);
+/* Raw features of the current forest: feat[n][nin], forest order. */
+mrb_status mrb_mlp_features(mrb_ctx *ctx, float *feat);
+/* Logits for n given feature rows: logits[n][3]. */
+mrb_status mrb_mlp_forward(mrb_ctx *ctx, const float *x, int n, float *logits);
+/* Gradient of the class-weighted softmax cross-entropy (weights classw[3]; the loss
+ * is divided by the sum of the weights of the labels y[n]) w.r.t. the parameters:
+ * grads[n_params] (may be NULL), *loss (may be NULL). */
+mrb_status mrb_mlp_grad(mrb_ctx *ctx, const float *x, const int8_t *y, const float *classw, int n,
+                        float *grads, float *loss);
+/* One epoch over the n samples in the given order: batches of `batch`, one Adam step
+ * (lr, beta 0.9/0.999, eps 1e-8) per batch; *mean_loss (may be NULL) = mean batch loss. */
+mrb_status mrb_mlp_train(mrb_ctx *ctx, const float *x, const int8_t *y, const float *classw, int n, int batch,
+                         float lr, float *mean_loss);
+/* Prediction on the current forest: pred[n] (class), prob[n] (its softmax probability, may be NULL). */
+mrb_status mrb_mlp_predict(mrb_ctx *ctx, int8_t *pred, float *prob);
+/* Refine the blocks with mask[i] != 0 (forest order) and every coarser neighbour that
+ * must follow to keep the grid graded; children take the synchronised finer values
+ * as in mrb_refine_all.  *n_refined (may be NULL) receives the number refined. */
+mrb_status mrb_refine_marked(mrb_ctx *ctx, const int8_t *mask, int *n_refined);
+/* One predictor-guided MR step: refine the blocks predicted 'refine' or predicted with
+ * probability < tau (graded closure), RK4, then adapt by the exact detail threshold. */
+mrb_status mrb_step_predicted(mrb_ctx *ctx, double t, double dt, float tau, int *n_refined);
+/* Training labels at a horizon (no context): block i of the grid "now" is 0 (refine)
+ * if a finer block of the later grid overlaps it, 2 (coarsen) if it lies inside a
+ * coarser block of the later grid, else 1 (keep). */
+mrb_status mrb_horizon_labels(int dim, int n_now, const int8_t *lv_now, const int32_t *co_now, int n_later,
+                              const int8_t *lv_later, const int32_t *co_later, int8_t *labels);
+
 #ifdef __cplusplus
 }
 #endif

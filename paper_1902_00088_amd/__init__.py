@@ -28,7 +28,9 @@ STATUS = {0: "MRB_OK", -1: "MRB_E_ARG", -2: "MRB_E_CAPACITY", -3: "MRB_E_TOPOLOG
 EXPORTS = ("mrb_create", "mrb_destroy", "mrb_last_error", "mrb_init_forest", "mrb_load_blocks",
            "mrb_refine_all", "mrb_rk4", "mrb_mr_pass", "mrb_coarsen", "mrb_adapt", "mrb_step",
            "mrb_num_blocks", "mrb_read_forest", "mrb_read_blocks", "mrb_get_flags", "mrb_stats",
-           "mrb_timing", "mrb_tune", "mrb_set_graph")
+           "mrb_timing", "mrb_tune", "mrb_set_graph", "mrb_mlp_init", "mrb_mlp_get_params", "mrb_mlp_features",
+           "mrb_mlp_forward", "mrb_mlp_grad", "mrb_mlp_train", "mrb_mlp_predict", "mrb_refine_marked",
+           "mrb_step_predicted", "mrb_horizon_labels")
 
 
 class MrbError(RuntimeError):
@@ -47,6 +49,7 @@ class mrb_config(ctypes.Structure):
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
 _i8p = ctypes.POINTER(ctypes.c_int8)
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _vp = ctypes.c_void_p
@@ -84,6 +87,16 @@ def lib():
             "mrb_timing": [_vp, ctypes.c_int],
             "mrb_tune": [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int)],
             "mrb_set_graph": [_vp, ctypes.c_int],
+            "mrb_mlp_init": [_vp, ctypes.c_int, _fp, _fp, _fp],
+            "mrb_mlp_get_params": [_vp, _fp],
+            "mrb_mlp_features": [_vp, _fp],
+            "mrb_mlp_forward": [_vp, _fp, ctypes.c_int, _fp],
+            "mrb_mlp_grad": [_vp, _fp, _i8p, _fp, ctypes.c_int, _fp, _fp],
+            "mrb_mlp_train": [_vp, _fp, _i8p, _fp, ctypes.c_int, ctypes.c_int, ctypes.c_float, _fp],
+            "mrb_mlp_predict": [_vp, _i8p, _fp],
+            "mrb_refine_marked": [_vp, _i8p, ctypes.POINTER(ctypes.c_int)],
+            "mrb_step_predicted": [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.POINTER(ctypes.c_int)],
+            "mrb_horizon_labels": [ctypes.c_int, ctypes.c_int, _i8p, _i32p, ctypes.c_int, _i8p, _i32p, _i8p],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -259,6 +272,69 @@ class Solver:
         self._chk(lib().mrb_stats(self.h, buf, len(buf)))
         return json.loads(buf.value.decode())
 
+    # ---- learned predictor -------------------------------------------------------------
+    def mlp_init(self, params, mean, std):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        m = np.ascontiguousarray(np.asarray(mean, dtype=np.float32))
+        s = np.ascontiguousarray(np.asarray(std, dtype=np.float32))
+        self.mlp_nin = self.cfg.nf * 64
+        self._chk(lib().mrb_mlp_init(self.h, self.mlp_nin, _ptr(p, _fp), _ptr(m, _fp), _ptr(s, _fp)))
+        self.mlp_np = len(p)
+
+    def mlp_params(self):
+        out = np.zeros(self.mlp_np, dtype=np.float32)
+        self._chk(lib().mrb_mlp_get_params(self.h, _ptr(out, _fp)))
+        return out
+
+    def mlp_features(self):
+        out = np.zeros((self.num_blocks(), self.cfg.nf * 64), dtype=np.float32)
+        self._chk(lib().mrb_mlp_features(self.h, _ptr(out, _fp)))
+        return out
+
+    def mlp_forward(self, x):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+        out = np.zeros((len(x), 3), dtype=np.float32)
+        self._chk(lib().mrb_mlp_forward(self.h, _ptr(x, _fp), len(x), _ptr(out, _fp)))
+        return out
+
+    def mlp_grad(self, x, y, classw):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.int8))
+        cw = np.ascontiguousarray(np.asarray(classw, dtype=np.float32))
+        g = np.zeros(self.mlp_np, dtype=np.float32)
+        loss = ctypes.c_float()
+        self._chk(lib().mrb_mlp_grad(self.h, _ptr(x, _fp), _ptr(y, _i8p), _ptr(cw, _fp), len(x), _ptr(g, _fp),
+                                     ctypes.byref(loss)))
+        return loss.value, g
+
+    def mlp_train_epoch(self, x, y, classw, batch=1024, lr=1e-3):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.int8))
+        cw = np.ascontiguousarray(np.asarray(classw, dtype=np.float32))
+        loss = ctypes.c_float()
+        self._chk(lib().mrb_mlp_train(self.h, _ptr(x, _fp), _ptr(y, _i8p), _ptr(cw, _fp), len(x), batch, lr,
+                                      ctypes.byref(loss)))
+        return loss.value
+
+    def mlp_predict(self):
+        n = self.num_blocks()
+        pred = np.zeros(n, dtype=np.int8)
+        prob = np.zeros(n, dtype=np.float32)
+        self._chk(lib().mrb_mlp_predict(self.h, _ptr(pred, _i8p), _ptr(prob, _fp)))
+        return pred, prob
+
+    def refine_marked(self, mask) -> int:
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.int8))
+        assert len(m) == self.num_blocks()
+        k = ctypes.c_int()
+        self._chk(lib().mrb_refine_marked(self.h, _ptr(m, _i8p), ctypes.byref(k)))
+        return k.value
+
+    def step_predicted(self, t, dt, tau=0.9) -> int:
+        k = ctypes.c_int()
+        self._chk(lib().mrb_step_predicted(self.h, t, dt, tau, ctypes.byref(k)))
+        return k.value
+
     def init_grid(self, fn=None, max_iter: int = 0):
         """Initial adaptive grid: uniform level 1, then {refine all, resample the
         analytic initial condition, adapt, resample} until the forest is unchanged."""
@@ -277,3 +353,18 @@ class Solver:
             if key == prev:
                 break
             prev = key
+
+
+def horizon_labels(dim, lv_now, co_now, lv_later, co_later):
+    """Labels (0 refine, 1 keep, 2 coarsen) of the blocks of one grid from a later grid."""
+    a = np.ascontiguousarray(np.asarray(lv_now, dtype=np.int8))
+    ca = np.ascontiguousarray(np.asarray(co_now, dtype=np.int32).reshape(len(a), dim))
+    b = np.ascontiguousarray(np.asarray(lv_later, dtype=np.int8))
+    cb = np.ascontiguousarray(np.asarray(co_later, dtype=np.int32).reshape(len(b), dim))
+    out = np.zeros(len(a), dtype=np.int8)
+    rc = lib().mrb_horizon_labels(dim, len(a), _ptr(a, _i8p), _ptr(ca, _i32p), len(b), _ptr(b, _i8p), _ptr(cb, _i32p),
+                                  _ptr(out, _i8p))
+    if rc != MRB_OK:
+        raise MrbError(rc, "mrb_horizon_labels")
+    return out
+

@@ -4,6 +4,7 @@
 // C ABI declared in include/mrb.h.
 #include "../../include/mrb.h"
 #include "internal.hpp"
+#include "mlp.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -96,6 +97,13 @@ struct mrb_ctx {
   long n_graph_launches = 0;
   // host-side time (microseconds) by phase
   double hus_refine_plan = 0, hus_coarsen_plan = 0, hus_upload = 0, hus_wait = 0, hus_launch = 0;
+  // learned predictor: model, Adam state and batch workspace (device)
+  int mlp_nin = 0, mlp_np = 0, mlp_t = 0, mlp_cap = 0;
+  float *mp = nullptr, *mgrad = nullptr, *mm = nullptr, *mv = nullptr, *mnorm = nullptr;
+  float *mx = nullptr, *mxn = nullptr, *mz1 = nullptr, *ma1 = nullptr, *mz2 = nullptr, *ma2 = nullptr;
+  float *mlog = nullptr, *mloss = nullptr, *mdl = nullptr, *mdz1 = nullptr, *mdz2 = nullptr, *mcw = nullptr;
+  float* mpmax = nullptr;
+  int8_t *my = nullptr, *mpred = nullptr;
   int pending_ref = 0;          // parents in the last uploaded refinement plan
   bool hcount_ref_zero = true;  // the uploaded header has no refinement plan
 
@@ -561,13 +569,21 @@ mrb_status launch_refine_kernel(mrb_ctx* c, int nref, bool fixed_grid) {
 
 // Plan the safety-zone refinement (new forest, descriptors, one upload) and, if
 // launch is set, run the refinement kernel.
+mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch);
+
 mrb_status do_refine_all(mrb_ctx* c, bool launch = true) {
-  HostTimer ht(&c->hus_refine_plan);
-  const int d = c->cfg.dim, nch = 1 << d;
-  c->pending_ref = 0;
   std::vector<int> par;
   for (int i = 0; i < (int)c->leaves.size(); ++i)
     if (c->leaves[i].level < c->cfg.jmax) par.push_back(i);
+  return do_refine(c, par, launch);
+}
+
+// refine the listed blocks (forest positions, all below jmax; the caller keeps the
+// grid graded)
+mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch) {
+  HostTimer ht(&c->hus_refine_plan);
+  const int d = c->cfg.dim, nch = 1 << d;
+  c->pending_ref = 0;
   if (par.empty()) {
     // the upload still clears the previous refinement plan of the header
     return c->hcount_ref_zero ? MRB_OK : (c->hcount_ref_zero = true, upload_topo(c));
@@ -602,7 +618,7 @@ mrb_status do_refine_all(mrb_ctx* c, bool launch = true) {
       kids.push_back(K);
     }
   }
-  // new forest: parents leave, children join; parent slots return to the pool
+  // new forest: refined parents leave, children join; parent slots return to the pool
   std::vector<Leaf> old = c->leaves;
   std::vector<char> gone(c->leaves.size(), 0);
   for (int i : par) gone[i] = 1;
@@ -1020,6 +1036,10 @@ mrb_status mrb_destroy(mrb_ctx* c) {
   for (auto& t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  void* mlpbufs[] = {c->mp, c->mgrad, c->mm, c->mv, c->mnorm, c->mx, c->mxn, c->mz1, c->ma1, c->mz2, c->ma2,
+                     c->mlog, c->mloss, c->mdl, c->mdz1, c->mdz2, c->mcw, c->mpmax, c->my, c->mpred};
+  for (void* p : mlpbufs)
+    if (p) (void)hipFree(p);
   void* ptrs[] = {c->arena, c->dflags, c->dmaxd, c->dacc, c->ddone,
                   c->ds2, c->ds, c->dghost, c->dscratch, c->dslots};
   for (void* p : ptrs)
@@ -1292,6 +1312,327 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->nsub_mr = -1;
   }
   if (chosen) *chosen = c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1;
+  return MRB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned predictor
+// ---------------------------------------------------------------------------
+namespace {
+
+mrb_status mlp_ready(mrb_ctx* c) {
+  if (!c->mp) return fail(c, MRB_E_STATE, "predictor not initialised (mrb_mlp_init)");
+  return MRB_OK;
+}
+
+mrb_status mlp_workspace(mrb_ctx* c, int n) {
+  if (n <= c->mlp_cap) return MRB_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float** fl[] = {&c->mx, &c->mxn, &c->mz1, &c->ma1, &c->mz2, &c->ma2, &c->mlog, &c->mloss, &c->mdl, &c->mdz1,
+                  &c->mdz2, &c->mpmax};
+  for (float** p : fl)
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
+  if (c->my) { (void)hipFree(c->my); c->my = nullptr; }
+  if (c->mpred) { (void)hipFree(c->mpred); c->mpred = nullptr; }
+  const size_t N = (size_t)n;
+  HIPCHK(c, hipMalloc(&c->mx, N * c->mlp_nin * 4));
+  HIPCHK(c, hipMalloc(&c->mxn, N * c->mlp_nin * 4));
+  HIPCHK(c, hipMalloc(&c->mz1, N * 64 * 4));
+  HIPCHK(c, hipMalloc(&c->ma1, N * 64 * 4));
+  HIPCHK(c, hipMalloc(&c->mz2, N * 64 * 4));
+  HIPCHK(c, hipMalloc(&c->ma2, N * 64 * 4));
+  HIPCHK(c, hipMalloc(&c->mlog, N * 3 * 4));
+  HIPCHK(c, hipMalloc(&c->mloss, N * 4));
+  HIPCHK(c, hipMalloc(&c->mdl, N * 3 * 4));
+  HIPCHK(c, hipMalloc(&c->mdz1, N * 64 * 4));
+  HIPCHK(c, hipMalloc(&c->mdz2, N * 64 * 4));
+  HIPCHK(c, hipMalloc(&c->mpmax, N * 4));
+  HIPCHK(c, hipMalloc(&c->my, N));
+  HIPCHK(c, hipMalloc(&c->mpred, N));
+  c->mlp_cap = n;
+  return MRB_OK;
+}
+
+MlpArgs mlp_args(mrb_ctx* c, int off, int n) {
+  MlpArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.p = c->mp;
+  a.nin = c->mlp_nin;
+  a.n = n;
+  const size_t o = (size_t)off;
+  a.x = c->mx + o * c->mlp_nin;
+  a.mean = c->mnorm;
+  a.std = c->mnorm + 4;
+  a.xn = c->mxn + o * c->mlp_nin;
+  a.z1 = c->mz1 + o * 64;
+  a.a1 = c->ma1 + o * 64;
+  a.z2 = c->mz2 + o * 64;
+  a.a2 = c->ma2 + o * 64;
+  a.logits = c->mlog + o * 3;
+  a.y = c->my + o;
+  a.classw = c->mcw;
+  a.loss = c->mloss + o;
+  a.dl = c->mdl + o * 3;
+  a.dz1 = c->mdz1 + o * 64;
+  a.dz2 = c->mdz2 + o * 64;
+  a.g = c->mgrad;
+  return a;
+}
+
+// features of the current forest into the workspace (device)
+mrb_status mlp_features_dev(mrb_ctx* c) {
+  const int n = (int)c->hblk.size();
+  mrb_status r = mlp_workspace(c, n);
+  if (r) return r;
+  MlpPoolArgs a{topo(c), c->u, c->cfg.nfields, c->mx};
+  HIPCHK(c, launch_pool(c->cfg.bs, grid_for(c, n), a, c->stream));
+  return MRB_OK;
+}
+
+double batch_inv_wsum(const int8_t* y, int n, const float* cw) {
+  double W = 0.0;
+  for (int i = 0; i < n; ++i) W += cw[y[i]];
+  return W > 0.0 ? 1.0 / W : 0.0;
+}
+
+}  // namespace
+
+mrb_status mrb_mlp_init(mrb_ctx* c, int nin, const float* params, const float* mean, const float* std) {
+  if (!c) return MRB_E_ARG;
+  if (c->cfg.dim != 2 || (c->cfg.bs != 17 && c->cfg.bs != 33))
+    return fail(c, MRB_E_ARG, "mlp: 2D blocks of 17 or 33 points only");
+  if (nin != c->cfg.nfields * 64) return fail(c, MRB_E_ARG, "mlp: nin must be 64 per field");
+  if (!params || !mean || !std) return fail(c, MRB_E_ARG, "mlp: null parameters or normalisation");
+  for (int f = 0; f < c->cfg.nfields; ++f)
+    if (!(std[f] > 0.0f)) return fail(c, MRB_E_ARG, "mlp: std must be positive");
+  const int np = mlp_param_count(nin);
+  if (!c->mp || c->mlp_np != np) {
+    float** bufs[] = {&c->mp, &c->mgrad, &c->mm, &c->mv};
+    for (float** b : bufs) {
+      if (*b) (void)hipFree(*b);
+      *b = nullptr;
+      HIPCHK(c, hipMalloc(b, (size_t)np * 4));
+    }
+    if (!c->mnorm) HIPCHK(c, hipMalloc(&c->mnorm, 8 * 4));
+    if (!c->mcw) HIPCHK(c, hipMalloc(&c->mcw, 4 * 4));
+  }
+  c->mlp_nin = nin;
+  c->mlp_np = np;
+  c->mlp_t = 0;
+  float norm[8] = {0, 0, 0, 0, 1, 1, 1, 1};
+  for (int f = 0; f < c->cfg.nfields; ++f) {
+    norm[f] = mean[f];
+    norm[4 + f] = std[f];
+  }
+  HIPCHK(c, hipMemcpyAsync(c->mp, params, (size_t)np * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->mnorm, norm, sizeof norm, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->mm, 0, (size_t)np * 4, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->mv, 0, (size_t)np * 4, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MRB_OK;
+}
+
+mrb_status mrb_mlp_get_params(mrb_ctx* c, float* params) {
+  if (!c || !params) return MRB_E_ARG;
+  if (mlp_ready(c)) return MRB_E_STATE;
+  HIPCHK(c, hipMemcpyAsync(params, c->mp, (size_t)c->mlp_np * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MRB_OK;
+}
+
+mrb_status mrb_mlp_features(mrb_ctx* c, float* feat) {
+  if (!c || !feat) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  if (c->cfg.dim != 2 || (c->cfg.bs != 17 && c->cfg.bs != 33)) return fail(c, MRB_E_ARG, "features: 2D only");
+  if (!c->mlp_nin) c->mlp_nin = c->cfg.nfields * 64;
+  mrb_status r = mlp_features_dev(c);
+  if (r) return r;
+  HIPCHK(c, hipMemcpyAsync(feat, c->mx, c->hblk.size() * c->cfg.nfields * 64 * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MRB_OK;
+}
+
+mrb_status mrb_mlp_forward(mrb_ctx* c, const float* x, int n, float* logits) {
+  if (!c || !x || !logits || n <= 0) return MRB_E_ARG;
+  if (mlp_ready(c)) return MRB_E_STATE;
+  mrb_status r = mlp_workspace(c, n);
+  if (r) return r;
+  HIPCHK(c, hipMemcpyAsync(c->mx, x, (size_t)n * c->mlp_nin * 4, hipMemcpyHostToDevice, c->stream));
+  MlpArgs a = mlp_args(c, 0, n);
+  HIPCHK(c, launch_mlp_forward(a, c->stream));
+  HIPCHK(c, hipMemcpyAsync(logits, c->mlog, (size_t)n * 3 * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MRB_OK;
+}
+
+mrb_status mrb_mlp_grad(mrb_ctx* c, const float* x, const int8_t* y, const float* classw, int n, float* grads,
+                        float* loss) {
+  if (!c || !x || !y || !classw || n <= 0) return MRB_E_ARG;
+  if (mlp_ready(c)) return MRB_E_STATE;
+  for (int i = 0; i < n; ++i)
+    if (y[i] < 0 || y[i] > 2) return fail(c, MRB_E_ARG, "mlp: labels must be 0, 1 or 2");
+  mrb_status r = mlp_workspace(c, n);
+  if (r) return r;
+  HIPCHK(c, hipMemcpyAsync(c->mx, x, (size_t)n * c->mlp_nin * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->my, y, (size_t)n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->mcw, classw, 3 * 4, hipMemcpyHostToDevice, c->stream));
+  MlpArgs a = mlp_args(c, 0, n);
+  a.inv_wsum = (float)batch_inv_wsum(y, n, classw);
+  HIPCHK(c, launch_mlp_forward(a, c->stream));
+  HIPCHK(c, launch_mlp_backward(a, c->stream));
+  std::vector<float> ls(n);
+  if (grads) HIPCHK(c, hipMemcpyAsync(grads, c->mgrad, (size_t)c->mlp_np * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(ls.data(), c->mloss, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (loss) {
+    double s = 0.0;
+    for (float v : ls) s += v;
+    *loss = (float)s;
+  }
+  return MRB_OK;
+}
+
+mrb_status mrb_mlp_train(mrb_ctx* c, const float* x, const int8_t* y, const float* classw, int n, int batch, float lr,
+                         float* mean_loss) {
+  if (!c || !x || !y || !classw || n <= 0 || batch <= 0 || !(lr > 0.0f)) return MRB_E_ARG;
+  if (mlp_ready(c)) return MRB_E_STATE;
+  for (int i = 0; i < n; ++i)
+    if (y[i] < 0 || y[i] > 2) return fail(c, MRB_E_ARG, "mlp: labels must be 0, 1 or 2");
+  mrb_status r = mlp_workspace(c, n);
+  if (r) return r;
+  HIPCHK(c, hipMemcpyAsync(c->mx, x, (size_t)n * c->mlp_nin * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->my, y, (size_t)n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->mcw, classw, 3 * 4, hipMemcpyHostToDevice, c->stream));
+  const double b1 = 0.9, b2 = 0.999;
+  int nb = 0;
+  for (int off = 0; off < n; off += batch, ++nb) {
+    const int m = std::min(batch, n - off);
+    MlpArgs a = mlp_args(c, off, m);
+    a.inv_wsum = (float)batch_inv_wsum(y + off, m, classw);
+    HIPCHK(c, launch_mlp_forward(a, c->stream));
+    HIPCHK(c, launch_mlp_backward(a, c->stream));
+    c->mlp_t++;
+    MlpAdamArgs ad{c->mp, c->mgrad, c->mm, c->mv, c->mlp_np, lr, (float)b1, (float)b2, 1e-8f,
+                   (float)(1.0 - std::pow(b1, c->mlp_t)), (float)(1.0 - std::pow(b2, c->mlp_t))};
+    HIPCHK(c, launch_adam(ad, c->stream));
+  }
+  std::vector<float> ls(n);
+  HIPCHK(c, hipMemcpyAsync(ls.data(), c->mloss, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (mean_loss) {
+    double s = 0.0;
+    for (float v : ls) s += v;
+    *mean_loss = (float)(s / nb);
+  }
+  return MRB_OK;
+}
+
+mrb_status mrb_mlp_predict(mrb_ctx* c, int8_t* pred, float* prob) {
+  if (!c || !pred) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  if (mlp_ready(c)) return MRB_E_STATE;
+  const int n = (int)c->hblk.size();
+  mrb_status r = mlp_features_dev(c);
+  if (r) return r;
+  MlpArgs a = mlp_args(c, 0, n);
+  HIPCHK(c, launch_mlp_forward(a, c->stream));
+  HIPCHK(c, launch_pred(c->mlog, n, c->mpred, c->mpmax, c->stream));
+  HIPCHK(c, hipMemcpyAsync(pred, c->mpred, (size_t)n, hipMemcpyDeviceToHost, c->stream));
+  if (prob) HIPCHK(c, hipMemcpyAsync(prob, c->mpmax, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MRB_OK;
+}
+
+namespace {
+// marked blocks plus every coarser leaf that must refine with them to keep the grid graded
+std::vector<int> graded_closure(mrb_ctx* c, const int8_t* mask) {
+  const int n = (int)c->leaves.size();
+  std::vector<char> mk(n, 0);
+  std::unordered_map<int, int> by_slot;
+  by_slot.reserve(n * 2);
+  for (int i = 0; i < n; ++i) by_slot[c->leaves[i].slot] = i;
+  std::vector<int> work;
+  for (int i = 0; i < n; ++i)
+    if (mask[i] && c->leaves[i].level < c->cfg.jmax) { mk[i] = 1; work.push_back(i); }
+  while (!work.empty()) {
+    const int i = work.back();
+    work.pop_back();
+    const BlockDesc& B = c->hblk[i];
+    for (int e = B.nb_begin; e < B.nb_begin + B.n_ent; ++e) {
+      const NbEntry& E = c->hnb[e];
+      if (E.dl >= 0) continue;
+      const int j = by_slot.at(E.slot);
+      if (!mk[j]) { mk[j] = 1; work.push_back(j); }
+    }
+  }
+  std::vector<int> par;
+  for (int i = 0; i < n; ++i)
+    if (mk[i]) par.push_back(i);
+  return par;
+}
+}  // namespace
+
+mrb_status mrb_refine_marked(mrb_ctx* c, const int8_t* mask, int* n_refined) {
+  if (!c || !mask) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  std::vector<int> par = graded_closure(c, mask);
+  if (n_refined) *n_refined = (int)par.size();
+  return do_refine(c, par, true);
+}
+
+mrb_status mrb_step_predicted(mrb_ctx* c, double t, double dt, float tau, int* n_refined) {
+  if (!c) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  if (mlp_ready(c)) return MRB_E_STATE;
+  if (!(dt > 0.0)) return fail(c, MRB_E_ARG, "step_predicted: dt must be positive");
+  const int n = (int)c->hblk.size();
+  std::vector<int8_t> pred(n), mask(n);
+  std::vector<float> prob(n);
+  mrb_status r = mrb_mlp_predict(c, pred.data(), prob.data());
+  if (r) return r;
+  // refine what the predictor calls 'refine' and everything it is unsure about
+  for (int i = 0; i < n; ++i) mask[i] = (pred[i] == 0 || prob[i] < tau) ? 1 : 0;
+  if ((r = mrb_refine_marked(c, mask.data(), n_refined))) return r;
+  if ((r = do_rk4(c, t, dt))) return r;
+  if ((r = do_adapt(c, nullptr))) return r;
+  c->n_steps++;
+  return MRB_OK;
+}
+
+mrb_status mrb_horizon_labels(int dim, int n_now, const int8_t* lv_now, const int32_t* co_now, int n_later,
+                              const int8_t* lv_later, const int32_t* co_later, int8_t* labels) {
+  if (dim < 2 || dim > 3 || n_now < 0 || n_later < 0 || !labels) return MRB_E_ARG;
+  std::unordered_map<uint64_t, int> later;
+  int jmax = 1;
+  for (int i = 0; i < n_later; ++i) {
+    int c[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) c[a] = co_later[(size_t)i * dim + a];
+    later[pack_key(lv_later[i], c)] = lv_later[i];
+    jmax = std::max(jmax, (int)lv_later[i]);
+  }
+  for (int i = 0; i < n_now; ++i) {
+    const int l = lv_now[i];
+    int c[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) c[a] = co_now[(size_t)i * dim + a];
+    bool coarser = false, finer = false;
+    for (int L = 1; L < l && !coarser; ++L) {
+      int p[3] = {0, 0, 0};
+      for (int a = 0; a < dim; ++a) p[a] = c[a] >> (l - L);
+      coarser = later.count(pack_key(L, p)) > 0;
+    }
+    for (int L = l + 1; L <= jmax && !finer; ++L) {
+      const int s = L - l, side = 1 << s;
+      const long cnt = dim == 2 ? (long)side * side : (long)side * side * side;
+      for (long q = 0; q < cnt && !finer; ++q) {
+        int cc[3] = {0, 0, 0};
+        cc[0] = (c[0] << s) + (int)(q % side);
+        cc[1] = (c[1] << s) + (int)((q / side) % side);
+        if (dim > 2) cc[2] = (c[2] << s) + (int)(q / ((long)side * side));
+        finer = later.count(pack_key(L, cc)) > 0;
+      }
+    }
+    labels[i] = finer ? 0 : (coarser ? 2 : 1);
+  }
   return MRB_OK;
 }
 
