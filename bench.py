@@ -103,35 +103,8 @@ def cpu_baseline(W, cfg, budget_s):
                       f"({nbu} block-updates in {elapsed:.1f} s)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="fp64_plain,fp64_fused,mixed_fused")
-    ap.add_argument("--c4-steps", type=int, default=20, help="steps of the 3D workload (0 = skip)")
-    ap.add_argument("--c5-steps", type=int, default=2000,
-                    help="recorded steps of the learned-predictor study (0 = skip)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: the multi-GPU path (sharding the block forest along the "
-              f"space-filling curve) is not built, so --gpus {args.gpus} is not supported.", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import workloads as W
-    import paper_1902_00088_amd as M
-
-    base = W.C2()
-    forms = {"fp64_plain": (W.FP64, W.FORM_PLAIN), "fp64_fused": (W.FP64, W.FORM_FUSED),
-             "mixed_fused": (W.MIXED, W.FORM_FUSED)}
-    res = {}
-    for name in args.forms.split(","):
-        prec, form = forms[name]
-        print(f"bench: {name} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
-        res[name] = run_form(M, W, torch, base.replace(precision=prec, form=form), args.steps, args.warmup)
+def headline(args, res):
+    """The JSON line's headline fields from the 2D swirl forms."""
     head = res.get("mixed_fused") or next(iter(res.values()))
     head_name = "mixed_fused" if "mixed_fused" in res else next(iter(res))
     ks = head["kernels"]
@@ -140,7 +113,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
                 "launches": ks[dom]["launches"], "avg_launch_us": 1e3 * ks[dom]["ms"] / max(1, ks[dom]["launches"])}
-    out = {
+    return {
         "metric": METRIC,
         "value": head["value"],
         "unit": "block-updates/s",
@@ -158,22 +131,71 @@ def main():
                    "blocks_initial": head["blocks_initial"], "parallelism": "single GPU"},
         "roofline": roofline,
         "forms": res,
+        "speedup_mixed_fused_vs_fp64_plain": (res["mixed_fused"]["value"] / res["fp64_plain"]["value"]
+                                              if "fp64_plain" in res and "mixed_fused" in res else None),
     }
-    if "fp64_plain" in res and "mixed_fused" in res:
-        out["speedup_mixed_fused_vs_fp64_plain"] = res["mixed_fused"]["value"] / res["fp64_plain"]["value"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB five times (counter calibration)")
+    ap.add_argument("--forms", default="fp64_plain,fp64_fused,mixed_fused")
+    ap.add_argument("--c4-steps", type=int, default=20, help="steps of the 3D workload (0 = skip)")
+    ap.add_argument("--c4-forms", default="fp64_fused,mixed_fused")
+    ap.add_argument("--no-tune", action="store_true", help="3D workload: default tilings instead of the autotuner")
+    ap.add_argument("--c5-steps", type=int, default=2000,
+                    help="recorded steps of the learned-predictor study (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the multi-GPU path (sharding the block forest along the "
+              f"space-filling curve) is not built, so --gpus {args.gpus} is not supported.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_1902_00088_amd as M
+
+    if args.copy_calib > 0:
+        n = args.copy_calib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    base = W.C2()
+    forms = {"fp64_plain": (W.FP64, W.FORM_PLAIN), "fp64_fused": (W.FP64, W.FORM_FUSED),
+             "mixed_fused": (W.MIXED, W.FORM_FUSED)}
+    res = {}
+    for name in [f for f in args.forms.split(",") if f and f != "none"]:
+        prec, form = forms[name]
+        print(f"bench: {name} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+        res[name] = run_form(M, W, torch, base.replace(precision=prec, form=form), args.steps, args.warmup)
+    out = {}
+    if res:
+        out = headline(args, res)
     if args.c4_steps > 0:
         # the 3D set-up: a ragged forest of ~3,000 blocks of 17^3 after refine-all, HBM bound
         c4 = {}
-        for name in ("fp64_fused", "mixed_fused"):
+        for name in [f for f in args.c4_forms.split(",") if f]:
             prec, form = forms[name]
             print(f"bench: C4 {name} steps={args.c4_steps}", file=sys.stderr, flush=True)
-            c4[name] = run_form(M, W, torch, W.C4().replace(precision=prec, form=form), args.c4_steps, 2, tune=True)
-        ks4 = c4["mixed_fused"]["kernels"]["stage"]
-        ach4 = ks4["bytes"] / (ks4["ms"] * 1e-3) / 1e9 if ks4["ms"] > 0 else 0.0
+            c4[name] = run_form(M, W, torch, W.C4().replace(precision=prec, form=form), args.c4_steps, 2,
+                                tune=not args.no_tune)
         out["c4"] = {"workload": "C4 3D advection: 4 seeded blobs sigma=0.04, Bs=17^3, Jmax=6, eps=1e-4, dt=2^-11",
-                     "forms": c4,
-                     "roofline_stage_mixed": {"bound": "hbm", "achieved": ach4, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                              "frac": ach4 / PEAK_HBM_GBS}}
+                     "forms": c4}
+        if "mixed_fused" in c4:
+            ks4 = c4["mixed_fused"]["kernels"]["stage"]
+            ach4 = ks4["bytes"] / (ks4["ms"] * 1e-3) / 1e9 if ks4["ms"] > 0 else 0.0
+            out["c4"]["roofline_stage_mixed"] = {"bound": "hbm", "achieved": ach4, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                                 "frac": ach4 / PEAK_HBM_GBS}
+
     if args.c5_steps > 0:
         from paper_1902_00088_amd import predictor as P
         c5 = {}

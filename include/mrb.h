@@ -66,7 +66,8 @@ typedef struct {
   int hw;              /* ghost width of the RHS stencil: 2 (advection) or 4 (NS)            */
   int nfields;         /* 1 (advection) or 4 (NS)                                            */
   int jmax;            /* finest level, 2..12                                                */
-  int max_blocks;      /* pool capacity in blocks (N_max of Sec. 2.4)                         */
+  int max_blocks;      /* pool capacity in blocks (N_max of Sec. 2.4); max_blocks * nfields *
+                          bs^dim must stay below 2^31 (32-bit offsets in the kernels)      */
   double eps;          /* detail threshold (Sec. 2.3)                                        */
   int physics;         /* MRB_ADV_CONST / MRB_ADV_SWIRL / MRB_NS2D                           */
   double phys[8];      /* see physics                                                        */

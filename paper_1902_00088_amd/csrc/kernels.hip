@@ -358,6 +358,209 @@ __device__ void gpredict(TT* tile, const GState<DIM, S + 2 * H>& g, const int* r
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Stage-kernel gather.  The tile holds box A only (the region plus the stencil
+// halo HW); the coarse-lattice values that predictions need (even points up to
+// H = HW + 3 beyond the region) sit in a compact array C of half resolution, so
+// the tile of a block without coarser neighbours carries no prediction margin.
+// ---------------------------------------------------------------------------
+template <int DIM, int BS, int S, int HW>
+struct SGeo {
+  static constexpr int H = HW + 3;
+  static constexpr int TW = S + 2 * HW;           // tile (box A) width
+  static constexpr int TSZ = Pow<DIM, TW>::v;
+  static constexpr int CW = (S + 2 * H + 1) / 2;  // coarse-lattice array width
+  static constexpr int CSZ = Pow<DIM, CW>::v;
+  static constexpr int NP = Pow<DIM, BS>::v;
+  __device__ static __forceinline__ int idx(int ix, int iy, int iz) {
+    return ix + TW * iy + (DIM > 2 ? TW * TW * iz : 0);
+  }
+  __device__ static __forceinline__ int cidx(int ix, int iy, int iz) {
+    return ix + CW * iy + (DIM > 2 ? CW * CW * iz : 0);
+  }
+};
+
+// Source address of a held point as base + sum_a f(t_a) BS^a, with f(t) = 2t for a
+// finer holder, t for a same-level one and t/2 for a coarser one (its points are even);
+// the holder's origin is folded into base.
+struct SEnt {
+  int base;
+  int mode;   // 0 coarser, 1 same level, 2 finer
+};
+
+template <int DIM, int BS, int NF>
+__device__ __forceinline__ void sent_setup(SEnt* se, const NbEntry* ent, int ne) {
+  constexpr int NP = Pow<DIM, BS>::v;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const NbEntry E = ent[e];
+    const int mode = E.dl + 1;
+    int b = E.slot * NF * NP, mul = 1;
+    for (int a = 0; a < DIM; ++a) {
+      const int o = E.o[a];
+      b -= (mode == 2 ? 2 * o : (mode == 1 ? o : (o >> 1))) * mul;
+      mul *= BS;
+    }
+    se[e] = SEnt{b, mode};
+  }
+}
+
+__device__ __forceinline__ int sf(int t, int mode) { return mode == 2 ? 2 * t : (mode == 1 ? t : (t >> 1)); }
+
+// Fill box A (and, for blocks with coarser neighbours, the coarse-lattice array).
+// Points strictly inside the block are the block's own; the others take their
+// owner's value (highest set bit of the candidate mask).  Unowned points of box A
+// are left for spredict.  Box A goes row by row: a lane keeps one x position (its
+// mask word and x-dependent terms stay in registers) and walks rows of its row
+// group; B rows per round, loads issued unconditionally (a lane with no point
+// loads the block's first node and discards it).
+template <int DIM, int BS, int S, int HW, int NF, bool HASC, typename TT, typename SRC>
+__device__ void sgather(TT* tile, TT* carr, const GState<DIM, S + 2 * (HW + 3)>& g, const SEnt* se, int slot,
+                        const int* r0, const int* cnt, const SRC& src) {
+  using G = SGeo<DIM, BS, S, HW>;
+  constexpr int TW = G::TW, TSZ = G::TSZ, CW = G::CW, CSZ = G::CSZ, NP = G::NP, H = G::H;
+  constexpr int NT = 256, RG = NT / TW, NROW = Pow<DIM - 1, TW>::v;
+  constexpr int B = 8;
+  static_assert(RG >= 1, "tile row wider than the workgroup");
+  const int self = slot * NF * NP;
+  int cb0[3] = {0, 0, 0};
+  for (int a = 0; a < DIM; ++a) cb0[a] = (r0[a] - H + 1) & ~1;
+  const int tid = threadIdx.x;
+  const int x = tid % TW, rg = tid / TW;
+  const bool lane_ok = rg < RG && x < cnt[0] + 2 * HW;
+  const int tx = r0[0] + x - HW;
+  const unsigned long long mx = g.m[0][x + 3];
+  const bool xint = tx >= 1 && tx <= BS - 2;
+  const bool xeven = (tx & 1) == 0;
+  const int cx = (tx - cb0[0]) >> 1;
+  for (int rb = rg; rb < NROW; rb += B * RG) {
+    int addr[B], pos[B], cpos[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int r = rb + q * RG;
+      addr[q] = self;
+      pos[q] = -1;
+      cpos[q] = -1;
+      const int iy = DIM > 2 ? r % TW : r, iz = DIM > 2 ? r / TW : 0;
+      const bool ok = lane_ok && r < NROW && iy < cnt[1] + 2 * HW && (DIM < 3 || iz < cnt[2] + 2 * HW);
+      if (!ok) continue;
+      const int ty = r0[1] + iy - HW, tz = DIM > 2 ? r0[2] + iz - HW : 0;
+      pos[q] = G::idx(x, iy, iz);
+      if (HASC && xeven && (ty & 1) == 0 && (tz & 1) == 0)
+        cpos[q] = G::cidx(cx, (ty - cb0[1]) >> 1, DIM > 2 ? (tz - cb0[2]) >> 1 : 0);
+      const bool inner = xint && ty >= 1 && ty <= BS - 2 && (DIM < 3 || (tz >= 1 && tz <= BS - 2));
+      if (inner) {
+        addr[q] = self + tx + BS * ty + (DIM > 2 ? BS * BS * tz : 0);
+        continue;
+      }
+      unsigned long long cand = mx & g.m[1][iy + 3];
+      if (DIM > 2) cand &= g.m[2][iz + 3];
+      if (cand == 0) {  // no holder: predicted later
+        pos[q] = -1;
+        cpos[q] = -1;
+        continue;
+      }
+      const SEnt E = se[63 - __clzll((long long)cand)];
+      addr[q] = E.base + sf(tx, E.mode) + BS * sf(ty, E.mode) + (DIM > 2 ? BS * BS * sf(tz, E.mode) : 0);
+    }
+    TT v[B][NF];
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) v[q][f] = src((size_t)addr[q] + (size_t)f * NP, f);
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      if (pos[q] >= 0) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) tile[f * TSZ + pos[q]] = v[q][f];
+      }
+      if (HASC && cpos[q] >= 0) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) carr[f * CSZ + cpos[q]] = v[q][f];
+      }
+    }
+  }
+  if constexpr (HASC) {
+    // coarse-lattice points outside box A, row by row like box A
+    constexpr int RGC = NT / CW, NRC = Pow<DIM - 1, CW>::v;
+    const int cxl = tid % CW, rgc = tid / CW;
+    const int tcx = cb0[0] + 2 * cxl;
+    const bool xin = rgc < RGC && tcx <= r0[0] + cnt[0] - 1 + H;
+    const bool xa = tcx >= r0[0] - HW && tcx <= r0[0] + cnt[0] - 1 + HW;
+    const unsigned long long mcx = xin ? g.m[0][tcx - r0[0] + H] : 0ull;
+    for (int rb = rgc; rb < NRC; rb += B * RGC) {
+      int addr[B], cpos[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        const int r = rb + q * RGC;
+        addr[q] = self;
+        cpos[q] = -1;
+        const int cy = DIM > 2 ? r % CW : r, cz = DIM > 2 ? r / CW : 0;
+        const int tcy = cb0[1] + 2 * cy, tcz = DIM > 2 ? cb0[2] + 2 * cz : 0;
+        const bool ok = xin && r < NRC && tcy <= r0[1] + cnt[1] - 1 + H &&
+                        (DIM < 3 || tcz <= r0[2] + cnt[2] - 1 + H);
+        const bool in_a = xa && tcy >= r0[1] - HW && tcy <= r0[1] + cnt[1] - 1 + HW &&
+                          (DIM < 3 || (tcz >= r0[2] - HW && tcz <= r0[2] + cnt[2] - 1 + HW));
+        if (!ok || in_a) continue;
+        unsigned long long cand = mcx & g.m[1][tcy - r0[1] + H];
+        if (DIM > 2) cand &= g.m[2][tcz - r0[2] + H];
+        if (cand == 0) continue;
+        const SEnt E = se[63 - __clzll((long long)cand)];
+        addr[q] = E.base + sf(tcx, E.mode) + BS * sf(tcy, E.mode) + (DIM > 2 ? BS * BS * sf(tcz, E.mode) : 0);
+        cpos[q] = G::cidx(cxl, cy, cz);
+      }
+      TT v[B][NF];
+#pragma unroll
+      for (int q = 0; q < B; ++q)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[q][f] = src((size_t)addr[q] + (size_t)f * NP, f);
+#pragma unroll
+      for (int q = 0; q < B; ++q)
+        if (cpos[q] >= 0) {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) carr[f * CSZ + cpos[q]] = v[q][f];
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// Predict the unowned points of box A from the coarse-lattice array.
+template <int DIM, int BS, int S, int HW, int NF, typename TT>
+__device__ void spredict(TT* tile, const TT* carr, const GState<DIM, S + 2 * (HW + 3)>& g, const int* r0,
+                         const int* cnt) {
+  using G = SGeo<DIM, BS, S, HW>;
+  constexpr int TW = G::TW, TSZ = G::TSZ, CSZ = G::CSZ, H = G::H;
+  int cb0[3] = {0, 0, 0};
+  for (int a = 0; a < DIM; ++a) cb0[a] = (r0[a] - H + 1) & ~1;
+  for (int p = threadIdx.x; p < TSZ; p += blockDim.x) {
+    const int ix = p % TW, iy = DIM > 2 ? (p / TW) % TW : p / TW, iz = DIM > 2 ? p / (TW * TW) : 0;
+    const int ia[3] = {ix, iy, iz};
+    int t[3] = {0, 0, 0};
+    bool ok = true, outside = false;
+    unsigned long long cand = ~0ull;
+    for (int a = 0; a < DIM; ++a) {
+      if (ia[a] >= cnt[a] + 2 * HW) ok = false;
+      t[a] = r0[a] + ia[a] - HW;
+      if (t[a] < 0 || t[a] > BS - 1) outside = true;
+    }
+    if (!ok || !outside) continue;
+    for (int a = 0; a < DIM; ++a) cand &= g.m[a][ia[a] + 3];
+    if (cand != 0) continue;
+    int base[3] = {0, 0, 0}, stride[3] = {1, 1, 1}, n[3] = {1, 1, 1};
+    for (int a = 0; a < DIM; ++a) {
+      if (t[a] & 1) { base[a] = (t[a] - 3 - cb0[a]) >> 1; n[a] = 4; }
+      else base[a] = (t[a] - cb0[a]) >> 1;
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const TT* C = carr + f * CSZ;
+      auto at = [&](int x, int y, int z) { return C[G::cidx(x, y, z)]; };
+      tile[f * TSZ + G::idx(ix, iy, iz)] = tensor_p<DIM, TT>(at, base, stride, n);
+    }
+  }
+  __syncthreads();
+}
+
 template <int DIM>
 __device__ __forceinline__ void subregion(int sub, int nsub, int S, int BS, int* r0, int* cnt) {
   r0[0] = r0[1] = r0[2] = 0;
@@ -521,18 +724,27 @@ __device__ __forceinline__ void ns_rhs(const double* T, const CT* W, int ux0, in
 // ---------------------------------------------------------------------------
 // fused stage kernel: gather y_s, predict missing ghosts, RHS, store
 // ---------------------------------------------------------------------------
+// threads per workgroup of the stage kernel (the gather and RHS loops lay lanes
+// out along x for 256; 1024 measured slower on 3D blocks)
+template <int DIM>
+struct StageThreads { static constexpr int v = 256; };
+
 template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
-__global__ void __launch_bounds__(256) k_stage(StageArgs A) {
+__global__ void __launch_bounds__(StageThreads<DIM>::v) k_stage(StageArgs A) {
   constexpr int S = (BS + NSUB - 1) / NSUB, H = HW + 3;
-  using G = Geo<DIM, BS, S, H>;
+  using SG = SGeo<DIM, BS, S, HW>;
+  using G = Geo<DIM, BS, S, HW>;  // tile indexing of the right-hand sides
   constexpr int NP = G::NP, TSZ = G::TSZ;
   constexpr int NSUBT = Pow<DIM, NSUB>::v;
   constexpr bool NS = NF == 4;
-  __shared__ GState<DIM, G::TW> g;
+  static_assert(SG::TSZ == G::TSZ, "tile geometry");
+  __shared__ GState<DIM, S + 2 * H> g;
+  __shared__ SEnt se[kMaxEnt];
   __shared__ double swirl[DIM == 2 && NF == 1 ? 4 * S : 1];
   extern __shared__ __align__(16) char smem[];
   TT* tile = reinterpret_cast<TT*>(smem);
-  CT* W = reinterpret_cast<CT*>(tile + NF * TSZ);  // NS stresses / fluxes
+  TT* carr = tile + NF * TSZ;
+  CT* W = reinterpret_cast<CT*>(carr + NF * SG::CSZ);  // NS stresses / fluxes
   const int nblk = A.topo.h->n_blocks;
   const BlockDesc* blk = A.topo.blk();
   const NbEntry* nb = A.topo.nb();
@@ -543,17 +755,21 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs A) {
     int r0[3], cnt[3];
     subregion<DIM>(w % NSUBT, NSUB, S, BS, r0, cnt);
     gsetup<DIM, BS, S, H>(g, d, nb, r0);
+    sent_setup<DIM, BS, NF>(se, g.ent, d.n_ent);
     const bool sw_lds = DIM == 2 && NF == 1 && A.ph.kind == 1;
     if (sw_lds) load_swirl<BS, S>(swirl, d, r0, cnt, A);
-    const int h_even = d.n_coarse > 0 ? H : 0;
+    __syncthreads();
+    const bool hasc = d.n_coarse > 0;
     if (A.stage == 1) {
       YSrc<TT, KT, false> src{A.u, nullptr, 0.0, A.off};
-      gfill<DIM, BS, S, H, NF, TT>(tile, g, r0, cnt, HW, h_even, src);
+      if (hasc) sgather<DIM, BS, S, HW, NF, true, TT>(tile, carr, g, se, d.slot, r0, cnt, src);
+      else sgather<DIM, BS, S, HW, NF, false, TT>(tile, carr, g, se, d.slot, r0, cnt, src);
     } else {
       YSrc<TT, KT, true> src{A.u, (const KT*)A.kprev, A.alpha, A.off};
-      gfill<DIM, BS, S, H, NF, TT>(tile, g, r0, cnt, HW, h_even, src);
+      if (hasc) sgather<DIM, BS, S, HW, NF, true, TT>(tile, carr, g, se, d.slot, r0, cnt, src);
+      else sgather<DIM, BS, S, HW, NF, false, TT>(tile, carr, g, se, d.slot, r0, cnt, src);
     }
-    if (d.n_coarse > 0) gpredict<DIM, BS, S, H, NF, TT>(tile, g, r0, cnt, HW);
+    if (hasc) spredict<DIM, BS, S, HW, NF, TT>(tile, carr, g, r0, cnt);
     TT r;
     if constexpr (sizeof(TT) == 8) r = A.lt.r[d.level];
     else r = A.lt.rf[d.level];
@@ -568,11 +784,11 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs A) {
       K.c23 = (CT)(2.0 / 3.0);
       if constexpr (sizeof(CT) == 8) K.r = A.lt.r[d.level];
       else K.r = A.lt.rf[d.level];
-      ns_fluxes<BS, S, H, CT>(tile, W, cnt, K);
+      ns_fluxes<BS, S, HW, CT>(tile, W, cnt, K);
       for (int p = threadIdx.x; p < nn; p += blockDim.x) {
         const int lx = p % cnt[0], ly = p / cnt[0];
         CT kv[4];
-        ns_rhs<BS, S, H, CT>(tile, W, lx, ly, K, kv);
+        ns_rhs<BS, S, HW, CT>(tile, W, lx, ly, K, kv);
         const int node = (r0[0] + lx) + BS * (r0[1] + ly);
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
@@ -587,11 +803,16 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs A) {
         }
       }
     } else {
-      for (int p = threadIdx.x; p < nn; p += blockDim.x) {
-        int l[3] = {p % cnt[0], DIM > 2 ? (p / cnt[0]) % cnt[1] : p / cnt[0], DIM > 2 ? p / (cnt[0] * cnt[1]) : 0};
+      // lanes along x, rows of the region walked by row groups
+      constexpr int RGS = 256 / S, NR = Pow<DIM - 1, S>::v;
+      const int lx = (int)threadIdx.x % S, rgs = (int)threadIdx.x / S;
+      for (int row = rgs; rgs < RGS && lx < cnt[0] && row < NR; row += RGS) {
+        const int ly = DIM > 2 ? row % S : row, lz = DIM > 2 ? row / S : 0;
+        if (ly >= cnt[1] || (DIM > 2 && lz >= cnt[2])) continue;
+        int l[3] = {lx, ly, lz};
         int t[3] = {r0[0] + l[0], r0[1] + l[1], r0[2] + l[2]};
-        int i[3] = {l[0] + H, l[1] + H, DIM > 2 ? l[2] + H : 0};
-        const TT kv = rhs_adv<DIM, BS, S, H, TT>(tile, i, t, d, r, A, sw_lds ? swirl : nullptr, l);
+        int i[3] = {l[0] + HW, l[1] + HW, DIM > 2 ? l[2] + HW : 0};
+        const TT kv = rhs_adv<DIM, BS, S, HW, TT>(tile, i, t, d, r, A, sw_lds ? swirl : nullptr, l);
         const size_t q = base + t[0] + BS * t[1] + (DIM > 2 ? BS * BS * t[2] : 0);
         if (A.stage < 4) {
           ((KT*)A.kout)[q] = (KT)kv;
@@ -970,24 +1191,24 @@ __global__ void __launch_bounds__(256) k_scatter(const double* src, const int* s
 // launchers
 // ---------------------------------------------------------------------------
 template <typename K, typename Arg>
-static hipError_t go(K kern, int grid, size_t lds, hipStream_t st, const Arg& a) {
+static hipError_t go(K kern, int grid, size_t lds, hipStream_t st, const Arg& a, int threads = 256) {
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   grid = ((grid > 0 ? grid : 1) + 7) & ~7;  // XcdWork needs a multiple of 8
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
 // TT: tile type, KT: slope storage type, CT: arithmetic type
 template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
 static hipError_t stage_go(int grid, const StageArgs& a, hipStream_t st) {
-  constexpr int S = (BS + NSUB - 1) / NSUB, H = HW + 3;
-  using G = Geo<DIM, BS, S, H>;
-  size_t lds = sizeof(TT) * NF * G::TSZ;
+  constexpr int S = (BS + NSUB - 1) / NSUB;
+  using SG = SGeo<DIM, BS, S, HW>;
+  size_t lds = sizeof(TT) * NF * (SG::TSZ + SG::CSZ);
   if (NF == 4) lds += sizeof(CT) * 5 * (S + 4) * (S + 4);
-  return go(k_stage<DIM, BS, HW, NF, NSUB, TT, KT, CT>, grid, lds, st, a);
+  return go(k_stage<DIM, BS, HW, NF, NSUB, TT, KT, CT>, grid, lds, st, a, StageThreads<DIM>::v);
 }
 
 // FP64: FP64 tile, slopes and arithmetic.  Mixed: FP32 slopes and arithmetic; the

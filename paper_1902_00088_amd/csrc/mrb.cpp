@@ -941,6 +941,13 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
   if (cfg->nfields < 1 || cfg->nfields > 4) return bad("nfields must be 1..4");
   if (cfg->jmax < 2 || cfg->jmax >= kMaxLevels - 1) return bad("jmax out of range");
   if (cfg->max_blocks < (1 << cfg->dim)) return bad("max_blocks too small");
+  {
+    size_t npt = 1;
+    for (int a = 0; a < cfg->dim; ++a) npt *= (size_t)cfg->bs;
+    // the kernels address the pool with 32-bit offsets
+    if ((size_t)cfg->max_blocks * (size_t)cfg->nfields * npt >= ((size_t)1 << 31))
+      return bad("max_blocks * nfields * bs^dim must stay below 2^31");
+  }
   if (cfg->precision != MRB_FP64 && cfg->precision != MRB_MIXED) return bad("precision");
   if (cfg->form != MRB_FORM_PLAIN && cfg->form != MRB_FORM_FUSED) return bad("form");
   if (cfg->form == MRB_FORM_PLAIN && cfg->precision != MRB_FP64) return bad("the plain form is FP64 only");
