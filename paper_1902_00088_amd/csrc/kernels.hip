@@ -524,40 +524,62 @@ __device__ void sgather(TT* tile, TT* carr, const GState<DIM, S + 2 * (HW + 3)>&
   __syncthreads();
 }
 
-// Predict the unowned points of box A from the coarse-lattice array.
+// Predict the unowned points of box A from the coarse-lattice array, one parity
+// class at a time so that a wave's lanes share one unrolled stencil shape.
+template <int DIM, int BS, int S, int HW, int NF, typename TT>
+struct SPredictBody {
+  using G = SGeo<DIM, BS, S, HW>;
+  TT* tile;
+  const TT* carr;
+  const GState<DIM, S + 2 * (HW + 3)>& g;
+  const int* r0;
+  int a0[3], an[3], cb0[3];
+  __device__ __forceinline__ SPredictBody(TT* t_, const TT* c_, const GState<DIM, S + 2 * (HW + 3)>& g_,
+                                          const int* r0_, const int* cnt)
+      : tile(t_), carr(c_), g(g_), r0(r0_) {
+    for (int a = 0; a < 3; ++a) { a0[a] = 0; an[a] = 1; cb0[a] = 0; }
+    for (int a = 0; a < DIM; ++a) {
+      a0[a] = r0[a] - HW;
+      an[a] = cnt[a] + 2 * HW;
+      cb0[a] = (r0[a] - G::H + 1) & ~1;
+    }
+  }
+  template <int NX, int NY, int NZ>
+  __device__ __forceinline__ void go(int cls) {
+    ParityClass<DIM> pc(cls, a0, an);
+    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
+      int t[3];
+      pc.coords(p, t);
+      bool outside = false;
+      for (int a = 0; a < DIM; ++a)
+        if (t[a] < 0 || t[a] > BS - 1) outside = true;
+      if (!outside) continue;  // the block holds its own points
+      int ia[3] = {0, 0, 0};
+      unsigned long long cand = ~0ull;
+      for (int a = 0; a < DIM; ++a) {
+        ia[a] = t[a] - r0[a] + HW;
+        cand &= g.m[a][ia[a] + 3];
+      }
+      if (cand != 0) continue;
+      const int bb[3] = {NX == 4 ? (t[0] - 3 - cb0[0]) >> 1 : (t[0] - cb0[0]) >> 1,
+                         NY == 4 ? (t[1] - 3 - cb0[1]) >> 1 : (t[1] - cb0[1]) >> 1,
+                         DIM > 2 ? (NZ == 4 ? (t[2] - 3 - cb0[2]) >> 1 : (t[2] - cb0[2]) >> 1) : 0};
+      const int stride[3] = {1, 1, 1};
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const TT* C = carr + f * G::CSZ;
+        auto at = [&](int x, int y, int z) { return C[G::cidx(x, y, z)]; };
+        tile[f * G::TSZ + G::idx(ia[0], ia[1], ia[2])] = tensor_fixed<NX, NY, NZ, TT>(at, bb, stride);
+      }
+    }
+  }
+};
+
 template <int DIM, int BS, int S, int HW, int NF, typename TT>
 __device__ void spredict(TT* tile, const TT* carr, const GState<DIM, S + 2 * (HW + 3)>& g, const int* r0,
                          const int* cnt) {
-  using G = SGeo<DIM, BS, S, HW>;
-  constexpr int TW = G::TW, TSZ = G::TSZ, CSZ = G::CSZ, H = G::H;
-  int cb0[3] = {0, 0, 0};
-  for (int a = 0; a < DIM; ++a) cb0[a] = (r0[a] - H + 1) & ~1;
-  for (int p = threadIdx.x; p < TSZ; p += blockDim.x) {
-    const int ix = p % TW, iy = DIM > 2 ? (p / TW) % TW : p / TW, iz = DIM > 2 ? p / (TW * TW) : 0;
-    const int ia[3] = {ix, iy, iz};
-    int t[3] = {0, 0, 0};
-    bool ok = true, outside = false;
-    unsigned long long cand = ~0ull;
-    for (int a = 0; a < DIM; ++a) {
-      if (ia[a] >= cnt[a] + 2 * HW) ok = false;
-      t[a] = r0[a] + ia[a] - HW;
-      if (t[a] < 0 || t[a] > BS - 1) outside = true;
-    }
-    if (!ok || !outside) continue;
-    for (int a = 0; a < DIM; ++a) cand &= g.m[a][ia[a] + 3];
-    if (cand != 0) continue;
-    int base[3] = {0, 0, 0}, stride[3] = {1, 1, 1}, n[3] = {1, 1, 1};
-    for (int a = 0; a < DIM; ++a) {
-      if (t[a] & 1) { base[a] = (t[a] - 3 - cb0[a]) >> 1; n[a] = 4; }
-      else base[a] = (t[a] - cb0[a]) >> 1;
-    }
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const TT* C = carr + f * CSZ;
-      auto at = [&](int x, int y, int z) { return C[G::cidx(x, y, z)]; };
-      tile[f * TSZ + G::idx(ix, iy, iz)] = tensor_p<DIM, TT>(at, base, stride, n);
-    }
-  }
+  SPredictBody<DIM, BS, S, HW, NF, TT> body(tile, carr, g, r0, cnt);
+  for_odd_classes<DIM>(body);
   __syncthreads();
 }
 
