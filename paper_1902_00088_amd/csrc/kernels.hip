@@ -324,37 +324,50 @@ __device__ void gfill(TT* tile, const GState<DIM, S + 2 * H>& g, const int* r0, 
   __syncthreads();
 }
 
-// Predict the points within hw_all of the region that no leaf holds on its lattice.
+// Predict the points within hw_all of the region that no leaf holds on its lattice,
+// one parity class at a time (one unrolled stencil shape per wave).
+template <int DIM, int BS, int S, int H, int NF, typename TT>
+struct GPredictBody {
+  using G = Geo<DIM, BS, S, H>;
+  TT* tile;
+  const GState<DIM, S + 2 * H>& g;
+  const int* r0;
+  int a0[3], an[3];
+  __device__ __forceinline__ GPredictBody(TT* t_, const GState<DIM, S + 2 * H>& g_, const int* r0_, const int* cnt,
+                                          int hw_all)
+      : tile(t_), g(g_), r0(r0_) {
+    for (int a = 0; a < 3; ++a) { a0[a] = 0; an[a] = 1; }
+    for (int a = 0; a < DIM; ++a) {
+      a0[a] = r0[a] - hw_all;
+      an[a] = cnt[a] + 2 * hw_all;
+    }
+  }
+  template <int NX, int NY, int NZ>
+  __device__ __forceinline__ void go(int cls) {
+    ParityClass<DIM> pc(cls, a0, an);
+    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
+      int t[3];
+      pc.coords(p, t);
+      int i[3] = {0, 0, 0};
+      for (int a = 0; a < DIM; ++a) i[a] = t[a] - r0[a] + H;
+      if (cand_at<DIM, S + 2 * H>(g, i) != 0) continue;
+      const int bb[3] = {NX == 4 ? i[0] - 3 : i[0], NY == 4 ? i[1] - 3 : i[1],
+                         DIM > 2 ? (NZ == 4 ? i[2] - 3 : i[2]) : 0};
+      const int stride[3] = {2, 2, 2};
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const TT* T = tile + f * G::TSZ;
+        auto at = [&](int x, int y, int z) { return T[G::idx(x, y, z)]; };
+        tile[f * G::TSZ + G::idx(i[0], i[1], i[2])] = tensor_fixed<NX, NY, NZ, TT>(at, bb, stride);
+      }
+    }
+  }
+};
+
 template <int DIM, int BS, int S, int H, int NF, typename TT>
 __device__ void gpredict(TT* tile, const GState<DIM, S + 2 * H>& g, const int* r0, const int* cnt, int hw_all) {
-  using G = Geo<DIM, BS, S, H>;
-  constexpr int TSZ = G::TSZ;
-  int an[3] = {1, 1, 1}, nA = 1;
-  for (int a = 0; a < DIM; ++a) {
-    an[a] = cnt[a] + 2 * hw_all;
-    nA *= an[a];
-  }
-  for (int p = threadIdx.x; p < nA; p += blockDim.x) {
-    int i[3] = {0, 0, 0};
-    i[0] = H - hw_all + p % an[0];
-    if (DIM > 2) {
-      i[1] = H - hw_all + (p / an[0]) % an[1];
-      i[2] = H - hw_all + p / (an[0] * an[1]);
-    } else {
-      i[1] = H - hw_all + p / an[0];
-    }
-    if (cand_at<DIM, S + 2 * H>(g, i) != 0) continue;
-    int base[3] = {i[0], i[1], i[2]}, stride[3] = {2, 2, 2}, n[3] = {1, 1, 1};
-    for (int a = 0; a < DIM; ++a)
-      if ((r0[a] + i[a] - H) & 1) { base[a] = i[a] - 3; n[a] = 4; }
-    const int ti = G::idx(i[0], i[1], i[2]);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const TT* T = tile + f * TSZ;
-      auto at = [&](int x, int y, int z) { return T[G::idx(x, y, z)]; };
-      tile[f * TSZ + ti] = tensor_p<DIM, TT>(at, base, stride, n);
-    }
-  }
+  GPredictBody<DIM, BS, S, H, NF, TT> body(tile, g, r0, cnt, hw_all);
+  for_odd_classes<DIM>(body);
   __syncthreads();
 }
 

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <unordered_set>
 #include <vector>
@@ -259,80 +260,117 @@ const Leaf* find_leaf(const mrb_ctx* c, int l, const int* co) {
   return it == c->index.end() ? nullptr : &c->leaves[it->second];
 }
 
-// Neighbour entries of every leaf; fails with MRB_E_TOPOLOGY if the forest is not graded.
-mrb_status build_descriptors(mrb_ctx* c) {
+// Neighbour entries of leaf i appended to out (nb_begin relative to out's start);
+// returns an error message, or nullptr, if the forest is not graded around it.
+const char* block_entries(const mrb_ctx* c, int i, std::vector<NbEntry>& out, BlockDesc& B,
+                          std::vector<NbEntry>& co, std::vector<NbEntry>& sa, std::vector<NbEntry>& fi) {
   const int d = c->cfg.dim, bs = c->cfg.bs, jmax = c->cfg.jmax;
-  const int n = (int)c->leaves.size();
-  std::vector<BlockDesc> hblk(n);
-  std::vector<NbEntry> hnb;
-  hnb.reserve((size_t)n * (d == 2 ? 13 : 57));
-  std::vector<NbEntry> co, sa, fi;
-  for (int i = 0; i < n; ++i) {
-    const Leaf& L = c->leaves[i];
-    co.clear();
-    sa.clear();
-    fi.clear();
-    sa.push_back(NbEntry{L.slot, 0, {0, 0, 0}});
-    auto add = [](std::vector<NbEntry>& v, const NbEntry& e) {
-      for (auto& x : v)
-        if (x.slot == e.slot && x.o[0] == e.o[0] && x.o[1] == e.o[1] && x.o[2] == e.o[2]) return;
-      v.push_back(e);
-    };
-    const int nd = d == 2 ? 9 : 27;
-    for (int q = 0; q < nd; ++q) {
-      int dlt[3] = {q % 3 - 1, (q / 3) % 3 - 1, d > 2 ? q / 9 - 1 : 0};
-      if (dlt[0] == 0 && dlt[1] == 0 && dlt[2] == 0) continue;
-      int cn[3] = {0, 0, 0};
-      for (int a = 0; a < d; ++a) cn[a] = L.c[a] + dlt[a];
-      if (const Leaf* s = find_leaf(c, L.level, cn)) {
-        NbEntry e{s->slot, 0, {0, 0, 0}};
-        for (int a = 0; a < d; ++a) e.o[a] = dlt[a] * (bs - 1);
-        add(sa, e);
+  const Leaf& L = c->leaves[i];
+  co.clear();
+  sa.clear();
+  fi.clear();
+  sa.push_back(NbEntry{L.slot, 0, {0, 0, 0}});
+  auto add = [](std::vector<NbEntry>& v, const NbEntry& e) {
+    for (auto& x : v)
+      if (x.slot == e.slot && x.o[0] == e.o[0] && x.o[1] == e.o[1] && x.o[2] == e.o[2]) return;
+    v.push_back(e);
+  };
+  const int nd = d == 2 ? 9 : 27;
+  for (int q = 0; q < nd; ++q) {
+    int dlt[3] = {q % 3 - 1, (q / 3) % 3 - 1, d > 2 ? q / 9 - 1 : 0};
+    if (dlt[0] == 0 && dlt[1] == 0 && dlt[2] == 0) continue;
+    int cn[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) cn[a] = L.c[a] + dlt[a];
+    if (const Leaf* s = find_leaf(c, L.level, cn)) {
+      NbEntry e{s->slot, 0, {0, 0, 0}};
+      for (int a = 0; a < d; ++a) e.o[a] = dlt[a] * (bs - 1);
+      add(sa, e);
+      continue;
+    }
+    int pc[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) pc[a] = cn[a] >> 1;  // floor division
+    if (L.level > 1) {
+      if (const Leaf* s = find_leaf(c, L.level - 1, pc)) {
+        NbEntry e{s->slot, -1, {0, 0, 0}};
+        for (int a = 0; a < d; ++a) e.o[a] = (2 * pc[a] - L.c[a]) * (bs - 1);
+        add(co, e);
         continue;
       }
-      int pc[3] = {0, 0, 0};
-      for (int a = 0; a < d; ++a) pc[a] = cn[a] >> 1;  // floor division
-      if (L.level > 1) {
-        if (const Leaf* s = find_leaf(c, L.level - 1, pc)) {
-          NbEntry e{s->slot, -1, {0, 0, 0}};
-          for (int a = 0; a < d; ++a) e.o[a] = (2 * pc[a] - L.c[a]) * (bs - 1);
-          add(co, e);
-          continue;
-        }
-      }
-      if (L.level >= jmax)
-        return fail(c, MRB_E_TOPOLOGY, "forest is not graded or leaves a hole next to a level-jmax block");
-      // the region is split: its children touching this block must all be leaves
-      int nb = 1 << d;
-      for (int b = 0; b < nb; ++b) {
-        int beta[3] = {0, 0, 0};
-        bool ok = true;
-        for (int a = 0; a < d; ++a) {
-          beta[a] = (b >> a) & 1;
-          if (dlt[a] == 1 && beta[a] != 0) ok = false;
-          if (dlt[a] == -1 && beta[a] != 1) ok = false;
-        }
-        if (!ok) continue;
-        int ch[3] = {0, 0, 0};
-        for (int a = 0; a < d; ++a) ch[a] = 2 * wrapi(cn[a], 1 << L.level) + beta[a];
-        const Leaf* s = find_leaf(c, L.level + 1, ch);
-        if (!s) return fail(c, MRB_E_TOPOLOGY, "forest is not graded (a neighbour differs by two or more levels)");
-        NbEntry e{s->slot, 1, {0, 0, 0}};
-        for (int a = 0; a < d; ++a) e.o[a] = dlt[a] * (bs - 1) + beta[a] * ((bs - 1) / 2);
-        add(fi, e);
-      }
     }
-    BlockDesc& B = hblk[i];
-    B.slot = L.slot;
-    B.level = L.level;
-    for (int a = 0; a < 3; ++a) B.c[a] = L.c[a];
-    B.nb_begin = (int)hnb.size();
-    B.n_ent = (int)(co.size() + sa.size() + fi.size());
-    B.n_coarse = (int)co.size();
-    if (B.n_ent > kMaxEnt) return fail(c, MRB_E_TOPOLOGY, "too many neighbour entries");
-    hnb.insert(hnb.end(), co.begin(), co.end());
-    hnb.insert(hnb.end(), sa.begin(), sa.end());
-    hnb.insert(hnb.end(), fi.begin(), fi.end());
+    if (L.level >= jmax) return "forest is not graded or leaves a hole next to a level-jmax block";
+    // the region is split: its children touching this block must all be leaves
+    int nb = 1 << d;
+    for (int b = 0; b < nb; ++b) {
+      int beta[3] = {0, 0, 0};
+      bool ok = true;
+      for (int a = 0; a < d; ++a) {
+        beta[a] = (b >> a) & 1;
+        if (dlt[a] == 1 && beta[a] != 0) ok = false;
+        if (dlt[a] == -1 && beta[a] != 1) ok = false;
+      }
+      if (!ok) continue;
+      int ch[3] = {0, 0, 0};
+      for (int a = 0; a < d; ++a) ch[a] = 2 * wrapi(cn[a], 1 << L.level) + beta[a];
+      const Leaf* s = find_leaf(c, L.level + 1, ch);
+      if (!s) return "forest is not graded (a neighbour differs by two or more levels)";
+      NbEntry e{s->slot, 1, {0, 0, 0}};
+      for (int a = 0; a < d; ++a) e.o[a] = dlt[a] * (bs - 1) + beta[a] * ((bs - 1) / 2);
+      add(fi, e);
+    }
+  }
+  B.slot = L.slot;
+  B.level = L.level;
+  for (int a = 0; a < 3; ++a) B.c[a] = L.c[a];
+  B.nb_begin = (int)out.size();
+  B.n_ent = (int)(co.size() + sa.size() + fi.size());
+  B.n_coarse = (int)co.size();
+  if (B.n_ent > kMaxEnt) return "too many neighbour entries";
+  out.insert(out.end(), co.begin(), co.end());
+  out.insert(out.end(), sa.begin(), sa.end());
+  out.insert(out.end(), fi.begin(), fi.end());
+  return nullptr;
+}
+
+// Neighbour entries of every leaf; fails with MRB_E_TOPOLOGY if the forest is not
+// graded.  Large forests are split over host threads (read-only lookups), each
+// filling its own entry list; the lists are then concatenated in forest order.
+mrb_status build_descriptors(mrb_ctx* c) {
+  const int d = c->cfg.dim, jmax = c->cfg.jmax;
+  const int n = (int)c->leaves.size();
+  std::vector<BlockDesc> hblk(n);
+  int nt = 1;
+  if (n >= 1024) {
+    const int hc = (int)std::max(1u, std::thread::hardware_concurrency());
+    nt = std::max(1, std::min({16, hc, n / 256}));
+  }
+  std::vector<std::vector<NbEntry>> part(nt);
+  std::vector<const char*> err(nt, nullptr);
+  auto work = [&](int t) {
+    const int lo = (int)((long)n * t / nt), hi = (int)((long)n * (t + 1) / nt);
+    std::vector<NbEntry> co, sa, fi;
+    part[t].reserve((size_t)(hi - lo) * (d == 2 ? 13 : 57));
+    for (int i = lo; i < hi && !err[t]; ++i) err[t] = block_entries(c, i, part[t], hblk[i], co, sa, fi);
+  };
+  if (nt == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto& x : th) x.join();
+  }
+  for (int t = 0; t < nt; ++t)
+    if (err[t]) return fail(c, MRB_E_TOPOLOGY, err[t]);
+  std::vector<NbEntry> hnb;
+  size_t total = 0;
+  for (auto& v : part) total += v.size();
+  hnb.reserve(total);
+  for (int t = 0; t < nt; ++t) {
+    const int lo = (int)((long)n * t / nt), hi = (int)((long)n * (t + 1) / nt);
+    const int off = (int)hnb.size();
+    for (int i = lo; i < hi; ++i) hblk[i].nb_begin += off;
+    hnb.insert(hnb.end(), part[t].begin(), part[t].end());
   }
   // blocks grouped by level (plain form launches one sweep per level)
   std::vector<int> level_off(jmax + 2, 0), hlist(n, 0);
