@@ -27,6 +27,29 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "block-updates/s (RK4 step, all blocks) FP64 vs mixed; % HBM roofline"
 
 
+def counter_traffic(key):
+    """HBM bytes per stage launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE runs, scaled by a copy calibration), or None if the kernel source
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "stage_traffic_counters.md")
+    src = os.path.join(ROOT, "paper_1902_00088_amd", "csrc", "kernels.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("traffic_sha256:"):
+            vals["sha"] = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes_per_launch " + key + ":"):
+            vals["bytes"] = float(line.split(":", 1)[1])
+    if vals.get("sha") != sha or "bytes" not in vals:
+        return None
+    return vals["bytes"]
+
+
 def run_form(M, W, torch, cfg, steps, warmup, tune=False):
     s = M.Solver(cfg)
     s.init_grid()
@@ -111,7 +134,9 @@ def headline(args, res):
     dom = max(ks, key=lambda k: ks[k]["ms"])
     ach = ks[dom]["bytes"] / (ks[dom]["ms"] * 1e-3) / 1e9 if ks[dom]["ms"] > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
+                "frac": ach / PEAK_HBM_GBS, "traffic": counter_traffic("c2") if dom == "stage" else None,
+                "traffic_unit": "bytes per launch", "kernel": dom,
+                "algorithmic_bytes_per_launch": ks[dom]["bytes"] / max(1, ks[dom]["launches"]),
                 "launches": ks[dom]["launches"], "avg_launch_us": 1e3 * ks[dom]["ms"] / max(1, ks[dom]["launches"])}
     return {
         "metric": METRIC,
@@ -193,8 +218,11 @@ def main():
         if "mixed_fused" in c4:
             ks4 = c4["mixed_fused"]["kernels"]["stage"]
             ach4 = ks4["bytes"] / (ks4["ms"] * 1e-3) / 1e9 if ks4["ms"] > 0 else 0.0
-            out["c4"]["roofline_stage_mixed"] = {"bound": "hbm", "achieved": ach4, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                                 "frac": ach4 / PEAK_HBM_GBS}
+            out["c4"]["roofline_stage_mixed"] = {
+                "bound": "hbm", "achieved": ach4, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach4 / PEAK_HBM_GBS,
+                "traffic": counter_traffic("c4"), "traffic_unit": "bytes per launch",
+                "algorithmic_bytes_per_launch": ks4["bytes"] / max(1, ks4["launches"]),
+                "avg_launch_us": 1e3 * ks4["ms"] / max(1, ks4["launches"])}
 
     if args.c5_steps > 0:
         from paper_1902_00088_amd import predictor as P
