@@ -70,8 +70,29 @@ struct mrb_ctx {
   std::vector<NbEntry> hnb;
   std::vector<int> hlist, level_off;         // blocks grouped by level (plain form)
 
-  char* arena = nullptr;        // packed topology: header, blocks, entries, lists, plans
-  size_t arena_cap = 0;
+  char* arena = nullptr;        // packed topology in use: header, blocks, entries, lists, plans
+  char* work_arena = nullptr;   // the arena uploads go to (owned)
+  size_t arena_cap = 0, arena_bytes = 0;
+  // memo of topology transitions on small forests: a refine-all or a coarsening from a
+  // state seen before (same leaves, slots, free-list tail and flags) reuses the host
+  // plan and a device copy of its packed topology instead of planning and uploading
+  struct Memo {
+    int kind = 0;                       // 0 refine-all, 1 coarsen
+    std::vector<int> material;          // leaves, free-list tail and flags the plan came from
+    long last_use = 0;
+    std::vector<Leaf> leaves;
+    std::unordered_map<uint64_t, int> index;
+    std::vector<BlockDesc> hblk;
+    std::vector<NbEntry> hnb;
+    std::vector<int> hlist, level_off;
+    size_t pop = 0;                     // free slots taken from the back
+    std::vector<int> pushed;            // slots returned, in order
+    int pending_ref = 0, nfam = 0, npar = 0;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+  };
+  std::vector<Memo> memo;
+  long memo_clock = 0, memo_hits = 0;
   int8_t* dflags = nullptr;
   double* dmaxd = nullptr;
   unsigned long long* dacc = nullptr;   // analysis partial maxima (zero between passes)
@@ -417,12 +438,14 @@ mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
   if (total > (size_t)0x7fffffff) return fail(c, MRB_E_CAPACITY, "topology buffer exceeds 2 GiB");
   if (total > c->arena_cap) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (c->arena) HIPCHK(c, hipFree(c->arena));
-    c->arena = nullptr;
+    if (c->work_arena) HIPCHK(c, hipFree(c->work_arena));
+    c->work_arena = nullptr;
     const size_t cap = total + total / 2 + 4096;
-    HIPCHK(c, hipMalloc((void**)&c->arena, cap));
+    HIPCHK(c, hipMalloc((void**)&c->work_arena, cap));
     c->arena_cap = cap;
   }
+  c->arena = c->work_arena;
+  c->arena_bytes = total;
   Staging& S = c->st_topo[c->st_cur];
   c->st_cur ^= 1;
   if (S.pending) {
@@ -454,6 +477,91 @@ mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
 }
 
 Topo topo(const mrb_ctx* c) { return Topo{(const TopoHeader*)c->arena}; }
+
+// ---- memo of topology transitions (small forests) ----------------------------------
+constexpr size_t kMemoMaxLeaves = 1024;
+constexpr size_t kMemoEntries = 8;
+
+// everything a refine-all (kind 0) or a coarsening (kind 1) plan depends on: the
+// leaves with their slots, the free-list tail the plan can consume, and the flags
+void memo_material(const mrb_ctx* c, int kind, const int8_t* flags, std::vector<int>& m) {
+  const size_t n = c->leaves.size(), nch = (size_t)1 << c->cfg.dim;
+  m.clear();
+  m.reserve(n * 6 + 8);
+  m.push_back(kind);
+  m.push_back((int)n);
+  for (const Leaf& L : c->leaves) {
+    m.push_back(L.level);
+    m.push_back(L.c[0]);
+    m.push_back(L.c[1]);
+    m.push_back(L.c[2]);
+    m.push_back(L.slot);
+  }
+  const size_t k = std::min(c->free_slots.size(), kind == 0 ? n * nch : n / nch + 1);
+  m.push_back((int)c->free_slots.size());
+  m.insert(m.end(), c->free_slots.end() - (long)k, c->free_slots.end());
+  if (kind == 1)
+    for (size_t i = 0; i < n; ++i) m.push_back(flags[i]);
+}
+
+mrb_ctx::Memo* memo_find(mrb_ctx* c, int kind, const std::vector<int>& m) {
+  for (auto& e : c->memo)
+    if (e.kind == kind && e.material == m) return &e;
+  return nullptr;
+}
+
+void memo_apply(mrb_ctx* c, mrb_ctx::Memo& e) {
+  c->leaves = e.leaves;
+  c->index = e.index;
+  c->hblk = e.hblk;
+  c->hnb = e.hnb;
+  c->hlist = e.hlist;
+  c->level_off = e.level_off;
+  c->free_slots.resize(c->free_slots.size() - e.pop);
+  c->free_slots.insert(c->free_slots.end(), e.pushed.begin(), e.pushed.end());
+  c->arena = e.arena;
+  c->arena_bytes = e.arena_bytes;
+  e.last_use = ++c->memo_clock;
+  ++c->memo_hits;
+}
+
+// Remember the transition just planned and uploaded (the current state is its result).
+mrb_status memo_record(mrb_ctx* c, int kind, std::vector<int>& material, size_t pop, const std::vector<int>& pushed,
+                       int pending_ref, int nfam, int npar) {
+  if (material.empty() || c->leaves.size() > kMemoMaxLeaves) return MRB_OK;
+  mrb_ctx::Memo* e = nullptr;
+  if (c->memo.size() < kMemoEntries) {
+    c->memo.emplace_back();
+    e = &c->memo.back();
+  } else {
+    e = &c->memo[0];
+    for (auto& x : c->memo)
+      if (x.last_use < e->last_use) e = &x;
+  }
+  if (e->arena && e->arena_bytes < c->arena_bytes) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // queued kernels may still read it
+    HIPCHK(c, hipFree(e->arena));
+    e->arena = nullptr;
+  }
+  if (!e->arena) HIPCHK(c, hipMalloc((void**)&e->arena, c->arena_bytes));
+  e->arena_bytes = c->arena_bytes;
+  e->kind = kind;
+  e->material.swap(material);
+  e->last_use = ++c->memo_clock;
+  e->leaves = c->leaves;
+  e->index = c->index;
+  e->hblk = c->hblk;
+  e->hnb = c->hnb;
+  e->hlist = c->hlist;
+  e->level_off = c->level_off;
+  e->pop = pop;
+  e->pushed = pushed;
+  e->pending_ref = pending_ref;
+  e->nfam = nfam;
+  e->npar = npar;
+  HIPCHK(c, hipMemcpyAsync(e->arena, c->arena, c->arena_bytes, hipMemcpyDeviceToDevice, c->stream));
+  return MRB_OK;
+}
 
 int grid_for(const mrb_ctx* c, long n) { return (int)std::max(1L, std::min((long)c->grid, n)); }
 
@@ -607,24 +715,37 @@ mrb_status launch_refine_kernel(mrb_ctx* c, int nref, bool fixed_grid) {
 
 // Plan the safety-zone refinement (new forest, descriptors, one upload) and, if
 // launch is set, run the refinement kernel.
-mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch);
+mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch, bool memoize = false);
 
 mrb_status do_refine_all(mrb_ctx* c, bool launch = true) {
   std::vector<int> par;
   for (int i = 0; i < (int)c->leaves.size(); ++i)
     if (c->leaves[i].level < c->cfg.jmax) par.push_back(i);
-  return do_refine(c, par, launch);
+  return do_refine(c, par, launch, true);
 }
 
 // refine the listed blocks (forest positions, all below jmax; the caller keeps the
 // grid graded)
-mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch) {
+mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch, bool memoize) {
   HostTimer ht(&c->hus_refine_plan);
   const int d = c->cfg.dim, nch = 1 << d;
   c->pending_ref = 0;
   if (par.empty()) {
     // the upload still clears the previous refinement plan of the header
     return c->hcount_ref_zero ? MRB_OK : (c->hcount_ref_zero = true, upload_topo(c));
+  }
+  std::vector<int> material;
+  if (memoize && c->leaves.size() <= kMemoMaxLeaves) {
+    memo_material(c, 0, nullptr, material);
+    if (mrb_ctx::Memo* e = memo_find(c, 0, material)) {
+      memo_apply(c, *e);
+      c->hcount_ref_zero = false;
+      c->n_refined += e->npar;
+      c->have_flags = false;
+      c->pending_ref = e->pending_ref;
+      if (!launch) return MRB_OK;
+      return launch_refine_kernel(c, c->pending_ref, false);
+    }
   }
   c->hcount_ref_zero = false;
   if (c->free_slots.size() < par.size() * nch) return fail(c, MRB_E_CAPACITY, "refine_all: pool too small");
@@ -683,6 +804,8 @@ mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch) {
   c->n_refined += (long)par.size();
   c->have_flags = false;
   c->pending_ref = (int)ref.size();
+  if (!material.empty() && (s = memo_record(c, 0, material, taken.size(), freed, c->pending_ref, 0, (int)par.size())))
+    return s;
   if (!launch) return MRB_OK;
   return launch_refine_kernel(c, c->pending_ref, false);
 }
@@ -793,9 +916,39 @@ std::vector<uint64_t> coarsenable(mrb_ctx* c, const int8_t* flags) {
 mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
   HostTimer ht(&c->hus_coarsen_plan);
   const int d = c->cfg.dim, nch = 1 << d;
+  std::vector<int> material;
+  if (c->leaves.size() <= kMemoMaxLeaves) {
+    memo_material(c, 1, flags, material);
+    if (mrb_ctx::Memo* e = memo_find(c, 1, material)) {
+      if (ncoarse) *ncoarse = e->nfam;
+      if (e->nfam == 0) {  // nothing merges: the state stays as it is
+        e->last_use = ++c->memo_clock;
+        ++c->memo_hits;
+        return MRB_OK;
+      }
+      memo_apply(c, *e);
+      c->hcount_ref_zero = true;
+      CoarsenArgs a{topo(c), c->u};
+      const long total = (long)e->nfam * c->np;
+      {
+        TimeScope ts(c, T_COARSEN, (double)total * c->cfg.nfields * 16.0);
+        HIPCHK(c, launch_coarsen(c->shape, (int)std::min(4096L, (total + 255) / 256), a, c->stream));
+      }
+      c->n_fam += e->nfam;
+      c->have_flags = false;
+      return MRB_OK;
+    }
+  }
   std::vector<uint64_t> fams = coarsenable(c, flags);
   if (ncoarse) *ncoarse = (int)fams.size();
-  if (fams.empty()) return MRB_OK;
+  if (fams.empty()) {
+    if (!material.empty()) {
+      // remember that nothing merges here (no device copy needed: state unchanged)
+      mrb_status r = memo_record(c, 1, material, 0, std::vector<int>(), 0, 0, 0);
+      if (r) return r;
+    }
+    return MRB_OK;
+  }
   if (c->free_slots.size() < fams.size()) return fail(c, MRB_E_CAPACITY, "coarsen: pool too small");
   std::vector<FamilyDesc> fd(fams.size());
   std::vector<char> gone(c->leaves.size(), 0);
@@ -840,6 +993,8 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
     return s;
   }
   for (int sl : freed) c->free_slots.push_back(sl);
+  c->hcount_ref_zero = true;
+  if (!material.empty() && (s = memo_record(c, 1, material, fams.size(), freed, 0, (int)fams.size(), 0))) return s;
   CoarsenArgs a{topo(c), c->u};
   const long total = (long)fd.size() * c->np;
   {
@@ -1085,7 +1240,9 @@ mrb_status mrb_destroy(mrb_ctx* c) {
                      c->mlog, c->mloss, c->mdl, c->mdz1, c->mdz2, c->mcw, c->mpmax, c->my, c->mpred};
   for (void* p : mlpbufs)
     if (p) (void)hipFree(p);
-  void* ptrs[] = {c->arena, c->dflags, c->dmaxd, c->dacc, c->ddone,
+  for (auto& e : c->memo)
+    if (e.arena) (void)hipFree(e.arena);
+  void* ptrs[] = {c->work_arena, c->dflags, c->dmaxd, c->dacc, c->ddone,
                   c->ds2, c->ds, c->dghost, c->dscratch, c->dslots};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -1271,12 +1428,12 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"graph_launches\": %ld, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"graph_launches\": %ld, \"memo_hits\": %ld, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
                 c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
                 c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
-                c->n_graph_launches, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
+                c->n_graph_launches, c->memo_hits, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
                 c->hus_launch, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
   return MRB_OK;

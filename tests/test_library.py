@@ -151,6 +151,9 @@ def test_c2_full_size_sampled_steps():
         t += cfg.dt
         if n % 10 == 9:
             assert_same(s, o, f"step {n + 1}")
+    # the forest cycles through the same refine / coarsen transitions every step:
+    # from the second step on the library replays memoised plans
+    assert s.stats()["memo_hits"] >= 2 * 38
 
 
 @pytest.mark.gpu
