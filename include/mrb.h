@@ -151,12 +151,14 @@ mrb_status mrb_timing(mrb_ctx *ctx, int enable);
  * reps = 0 returns to the built-in choice by block count.  *chosen (may be NULL)
  * receives the tiling in use.  Not a step of the method: a schedule choice. */
 mrb_status mrb_tune(mrb_ctx *ctx, int nsub, int reps, double dt, int *chosen);
-/* Graph replay in mrb_step (default on): the refinement, the four RK stages and the
- * first analysis of a step are captured once into a HIP graph and replayed; the
- * kernels read block counts and descriptors from device memory, so the graph stays
- * valid when the forest changes.  Used only for the fused form, with kernel timing
- * off, a non-default stream and a time-independent right-hand side.  Results are
- * identical with the graph on or off. */
+/* Graph replay in mrb_step: the refinement, the four RK stages and the first analysis
+ * of a step are captured once into a HIP graph and replayed; the kernels read block
+ * counts and descriptors from device memory, so the graph stays valid when the forest
+ * changes.  enable: 0 off, 1 on, 2 automatic (default: the first steps alternate
+ * between graph replay and direct launches, ten each, and the faster median step wall
+ * time decides).  Used only for the fused form, with kernel timing off, a non-default
+ * stream and a time-independent right-hand side.  Results are identical either way.
+ * MRB_E_ARG for other values. */
 mrb_status mrb_set_graph(mrb_ctx *ctx, int enable);
 
 /* ---------------------------------------------------------------------------

@@ -261,8 +261,10 @@ class Solver:
         self._chk(lib().mrb_tune(self.h, nsub, reps, self.cfg.dt, ctypes.byref(ch)))
         return ch.value
 
-    def set_graph(self, enable: bool):
-        self._chk(lib().mrb_set_graph(self.h, 1 if enable else 0))
+    def set_graph(self, mode):
+        """Graph replay in step(): False/0 off, True/1 on, 2 automatic (the default)."""
+        m = int(mode) if not isinstance(mode, bool) else (1 if mode else 0)
+        self._chk(lib().mrb_set_graph(self.h, m))
 
     def timing(self, enable: bool):
         self._chk(lib().mrb_timing(self.h, 1 if enable else 0))

@@ -93,7 +93,7 @@ struct mrb_ctx {
   };
   std::vector<Memo> memo;
   long memo_clock = 0, memo_hits = 0;
-  int8_t* dflags = nullptr;
+  int8_t* dflags = nullptr;     // device views of h_flags / h_maxd (mapped host memory)
   double* dmaxd = nullptr;
   unsigned long long* dacc = nullptr;   // analysis partial maxima (zero between passes)
   int* ddone = nullptr;                 // analysis sub-tiles finished (zero between passes)
@@ -106,14 +106,18 @@ struct mrb_ctx {
 
   Staging st_topo[2], st_slots;
   int st_cur = 0;
-  int8_t* h_flags = nullptr;   // pinned
-  double* h_maxd = nullptr;    // pinned
+  int8_t* h_flags = nullptr;   // pinned, mapped
+  double* h_maxd = nullptr;    // pinned, mapped
   int ncu = 256;
   int nsub = 0;                // stage sub-tiles per axis (0 = choose by block count)
   int nsub_mr = -1;            // analysis sub-tiles per axis (-1 = whole blocks, measured best)
   std::string tune_log;
   // captured step graphs (refine, four stages, first analysis), keyed by launch parameters
   bool use_graph = true;
+  // graph mode: 0 off, 1 on, 2 automatic (steps alternate between the two launch
+  // paths until each has ten samples, then the faster median wall time wins)
+  int graph_mode = 2;
+  std::vector<double> probe_us[2];
   struct GraphEntry { uint64_t key[6]; hipGraphExec_t exec; };
   std::vector<GraphEntry> graphs;
   long n_graph_launches = 0;
@@ -835,8 +839,6 @@ mrb_status launch_mr_kernel(mrb_ctx* c, bool fixed_grid) {
 
 mrb_status mr_readback(mrb_ctx* c) {
   const int n = (int)c->hblk.size();
-  HIPCHK(c, hipMemcpyAsync(c->h_flags, c->dflags, n, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->h_maxd, c->dmaxd, sizeof(double) * n * c->cfg.nfields, hipMemcpyDeviceToHost, c->stream));
   {
     HostTimer ht(&c->hus_wait);
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1189,11 +1191,9 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
     return true;
   };
   const size_t mb = cfg->max_blocks;
-  bool ok = dev((void**)&c->dflags, mb) && dev((void**)&c->dacc, mb * cfg->nfields * 8) &&
-            dev((void**)&c->ddone, mb * sizeof(int)) &&
+  bool ok = dev((void**)&c->dacc, mb * cfg->nfields * 8) && dev((void**)&c->ddone, mb * sizeof(int)) &&
             hipMemset(c->dacc, 0, mb * cfg->nfields * 8) == hipSuccess &&
-            hipMemset(c->ddone, 0, mb * sizeof(int)) == hipSuccess && dev((void**)&c->dmaxd, mb * cfg->nfields * sizeof(double)) &&
-            dev((void**)&c->dslots, mb * sizeof(int));
+            hipMemset(c->ddone, 0, mb * sizeof(int)) == hipSuccess && dev((void**)&c->dslots, mb * sizeof(int));
   if (ok && cfg->physics == MRB_ADV_SWIRL) {
     const size_t n = (size_t)(1L << cfg->jmax) * (cfg->bs - 1);
     ok = dev((void**)&c->ds2, n * sizeof(double)) && dev((void**)&c->ds, n * sizeof(double));
@@ -1211,9 +1211,14 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
     ok = dev((void**)&c->dghost, mb * cfg->nfields * g * sizeof(double));
   }
   if (ok) {
-    ok = hipHostMalloc((void**)&c->h_flags, mb, hipHostMallocDefault) == hipSuccess &&
-         hipHostMalloc((void**)&c->h_maxd, mb * cfg->nfields * sizeof(double), hipHostMallocDefault) == hipSuccess;
-    if (!ok) c->err = "hipHostMalloc failed";
+    // flags and detail maxima go straight from the analysis kernel into mapped,
+    // coherent host memory: reading them back is one stream synchronisation
+    const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
+    ok = hipHostMalloc((void**)&c->h_flags, mb, fl) == hipSuccess &&
+         hipHostMalloc((void**)&c->h_maxd, mb * cfg->nfields * sizeof(double), fl) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&c->dflags, c->h_flags, 0) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&c->dmaxd, c->h_maxd, 0) == hipSuccess;
+    if (!ok) c->err = "hipHostMalloc (mapped) failed";
   }
   if (ok) {
     int dev_id = 0, ncu = 0;
@@ -1242,7 +1247,7 @@ mrb_status mrb_destroy(mrb_ctx* c) {
     if (p) (void)hipFree(p);
   for (auto& e : c->memo)
     if (e.arena) (void)hipFree(e.arena);
-  void* ptrs[] = {c->work_arena, c->dflags, c->dmaxd, c->dacc, c->ddone,
+  void* ptrs[] = {c->work_arena, c->dacc, c->ddone,
                   c->ds2, c->ds, c->dghost, c->dscratch, c->dslots};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -1356,14 +1361,35 @@ mrb_status mrb_step(mrb_ctx* c, double t0, double dt, int nsteps) {
   if (!c) return MRB_E_ARG;
   if (!check_state(c, true)) return MRB_E_STATE;
   if (nsteps < 0 || !(dt > 0.0)) return fail(c, MRB_E_ARG, "step: bad dt or nsteps");
+  constexpr size_t kGraphProbe = 10;
   for (int s = 0; s < nsteps; ++s) {
     mrb_status r;
+    bool probing = false;
+    if (c->graph_mode == 2) {
+      const size_t n0 = c->probe_us[0].size(), n1 = c->probe_us[1].size();
+      if (n0 < kGraphProbe || n1 < kGraphProbe) {
+        probing = true;
+        c->use_graph = n1 <= n0;   // alternate, graph first
+      }
+    }
+    const double w0 = probing ? now_us() : 0.0;
     if (graph_ok(c)) {
       if ((r = step_graph(c, t0 + s * dt, dt))) return r;
     } else {
       if ((r = do_refine_all(c))) return r;
       if ((r = do_rk4(c, t0 + s * dt, dt))) return r;
       if ((r = do_adapt(c, nullptr))) return r;
+    }
+    if (probing) {
+      c->probe_us[c->use_graph ? 1 : 0].push_back(now_us() - w0);
+      if (c->probe_us[0].size() >= kGraphProbe && c->probe_us[1].size() >= kGraphProbe) {
+        auto med = [](std::vector<double> v) {
+          std::sort(v.begin(), v.end());
+          return v[v.size() / 2];
+        };
+        // the first graph step pays for the capture: medians ignore it
+        c->use_graph = med(c->probe_us[1]) < med(c->probe_us[0]);
+      }
     }
     c->n_steps++;
   }
@@ -1428,12 +1454,12 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"graph_launches\": %ld, \"memo_hits\": %ld, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
                 c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
                 c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
-                c->n_graph_launches, c->memo_hits, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
+                c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
                 c->hus_launch, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
   return MRB_OK;
@@ -1840,6 +1866,10 @@ mrb_status mrb_horizon_labels(int dim, int n_now, const int8_t* lv_now, const in
 
 mrb_status mrb_set_graph(mrb_ctx* c, int enable) {
   if (!c) return MRB_E_ARG;
+  if (enable < 0 || enable > 2) return fail(c, MRB_E_ARG, "set_graph: 0 off, 1 on, 2 automatic");
+  c->graph_mode = enable;
+  c->probe_us[0].clear();
+  c->probe_us[1].clear();
   c->use_graph = enable != 0;
   return MRB_OK;
 }

@@ -352,14 +352,19 @@ def test_graph_replay_matches_direct_launches():
     across topology changes (narrow blobs: the forest changes every few steps)."""
     cfg = W.C2(jmax=6, eps=1e-4, blob_beta=4e-4, form=W.FORM_FUSED)
     outs = []
-    for graph in (True, False):
+    for graph in (1, 0, 2):
         s = M.Solver(cfg)
         s.set_graph(graph)
         s.init_grid()
-        s.step(0.0, cfg.dt, 8)
+        s.step(0.0, cfg.dt, 24)
         st = s.stats()
-        assert (st["graph_launches"] > 0) == graph
+        assert (st["graph_launches"] > 0) == (graph != 0)
+        if graph == 2:   # automatic: ten steps each way, then the faster one
+            assert st["graph_launches"] >= 10 and st["graph_mode"] == 2
         outs.append((s.read_forest(), s.read_blocks()))
         s.close()
-    assert np.array_equal(outs[0][0][0], outs[1][0][0]) and np.array_equal(outs[0][0][1], outs[1][0][1])
-    assert np.array_equal(_bits(outs[0][1]), _bits(outs[1][1]))
+    for o in outs[1:]:
+        assert np.array_equal(outs[0][0][0], o[0][0]) and np.array_equal(outs[0][0][1], o[0][1])
+        assert np.array_equal(_bits(outs[0][1]), _bits(o[1]))
+    with pytest.raises(M.MrbError):
+        M.Solver(cfg).set_graph(3)
