@@ -173,7 +173,7 @@ def main():
     ap.add_argument("--forms", default="fp64_plain,fp64_fused,mixed_fused")
     ap.add_argument("--c4-steps", type=int, default=20, help="steps of the 3D workload (0 = skip)")
     ap.add_argument("--c4-forms", default="fp64_fused,mixed_fused")
-    ap.add_argument("--no-tune", action="store_true", help="3D workload: default tilings instead of the autotuner")
+    ap.add_argument("--no-tune", action="store_true", help="default tilings instead of the autotuner")
     ap.add_argument("--c5-steps", type=int, default=2000,
                     help="recorded steps of the learned-predictor study (0 = skip)")
     args = ap.parse_args()
@@ -201,7 +201,8 @@ def main():
     for name in [f for f in args.forms.split(",") if f and f != "none"]:
         prec, form = forms[name]
         print(f"bench: {name} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
-        res[name] = run_form(M, W, torch, base.replace(precision=prec, form=form), args.steps, args.warmup)
+        res[name] = run_form(M, W, torch, base.replace(precision=prec, form=form), args.steps, args.warmup,
+                             tune=form == W.FORM_FUSED and not args.no_tune)
     out = {}
     if res:
         out = headline(args, res)

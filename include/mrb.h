@@ -144,12 +144,15 @@ mrb_status mrb_stats(mrb_ctx *ctx, char *json, int cap);
  * events on the solver's stream and mrb_stats reports the accumulated device
  * time and algorithmic bytes per kernel kind; enable = 0 stops and clears. */
 mrb_status mrb_timing(mrb_ctx *ctx, int enable);
-/* Block tiling of the fused stage sweep (the autotuner).  nsub > 0 forces nsub
- * sub-tiles per axis (one workgroup each); nsub = 0 with reps > 0 times reps dry
+/* Block tilings (the autotuner).  nsub > 0 forces nsub sub-tiles per axis (one
+ * workgroup each) for the fused stage sweep; nsub = 0 with reps > 0 times reps dry
  * sweeps (four stages into k1..k3/u_new, the state u is not advanced) of every
- * compiled tiling on the current forest and keeps the fastest; nsub = 0 with
- * reps = 0 returns to the built-in choice by block count.  *chosen (may be NULL)
- * receives the tiling in use.  Not a step of the method: a schedule choice. */
+ * compiled stage tiling on the current forest and keeps the fastest, then does the
+ * same for the analysis kernel (one pass; flags are recomputed) and, if the last
+ * refinement plan is still the uploaded one (right after mrb_refine_all), for the
+ * refinement kernel (re-run on the same parents); nsub = 0 with reps = 0 returns to
+ * the built-in choices.  *chosen (may be NULL) receives the stage tiling in use.
+ * Not a step of the method: a schedule choice. */
 mrb_status mrb_tune(mrb_ctx *ctx, int nsub, int reps, double dt, int *chosen);
 /* Graph replay in mrb_step: the refinement, the four RK stages and the first analysis
  * of a step are captured once into a HIP graph and replayed; the kernels read block

@@ -111,6 +111,7 @@ struct mrb_ctx {
   int ncu = 256;
   int nsub = 0;                // stage sub-tiles per axis (0 = choose by block count)
   int nsub_mr = -1;            // analysis sub-tiles per axis (-1 = whole blocks, measured best)
+  int nsub_ref = 0;            // refinement sub-tiles per axis (0 = choose by work count)
   std::string tune_log;
   // captured step graphs (refine, four stages, first analysis), keyed by launch parameters
   bool use_graph = true;
@@ -709,7 +710,7 @@ mrb_status do_rk4(mrb_ctx* c, double t, double dt) {
 mrb_status launch_refine_kernel(mrb_ctx* c, int nref, bool fixed_grid) {
   const int nch = 1 << c->cfg.dim;
   RefineArgs a{topo(c), c->u};
-  const int ns = pick_aux(c, (long)nref * nch);
+  const int ns = pick_aux(c, (long)nref * nch, c->nsub_ref);
   long work = (long)nref * nch;
   for (int q = 0; q < c->cfg.dim; ++q) work *= ns;
   TimeScope ts(c, T_REFINE, (double)nref * c->bsz * 8.0 * (1 + nch));
@@ -1061,7 +1062,7 @@ mrb_status step_graph(mrb_ctx* c, double t, double dt) {
   std::memcpy(&dtb, &dt, sizeof dtb);
   const int ns = pick_nsub(c);
   const int nsm = pick_aux(c, (long)c->hblk.size(), c->nsub_mr);
-  const int nsr = pick_aux(c, (long)std::max(1, c->pending_ref) << c->cfg.dim);
+  const int nsr = pick_aux(c, (long)std::max(1, c->pending_ref) << c->cfg.dim, c->nsub_ref);
   const uint64_t key[6] = {(uint64_t)(uintptr_t)c->u, (uint64_t)ns, (uint64_t)nsm, (uint64_t)nsr, dtb,
                            (uint64_t)(uintptr_t)c->arena};
   hipGraphExec_t exec = nullptr;
@@ -1531,6 +1532,31 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     }
     c->tune_log += "}";
     c->nsub_mr = best_va;
+    // refinement tilings, while the last refinement plan is still the uploaded one:
+    // re-running it rewrites the same children from the untouched parents
+    if (c->pending_ref > 0) {
+      float best_r = 1e30f;
+      int best_vr = 0;
+      c->tune_log += ", \"refine\": {";
+      for (int i = 0; i < na; ++i) {
+        c->nsub_ref = va[i];
+        mrb_status r = launch_refine_kernel(c, c->pending_ref, false);  // warm-up
+        if (r) return r;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int k = 0; k < reps; ++k)
+          if ((r = launch_refine_kernel(c, c->pending_ref, false))) return r;
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        char buf[64];
+        std::snprintf(buf, sizeof buf, "%s\"%d\": %.4f", i ? ", " : "", va[i], ms / reps);
+        c->tune_log += buf;
+        if (ms < best_r) { best_r = ms; best_vr = va[i]; }
+      }
+      c->tune_log += "}";
+      c->nsub_ref = best_vr;
+    }
     c->have_flags = false;
     c->timing = was_timing;
     (void)hipEventDestroy(e0);
@@ -1538,6 +1564,7 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
   } else {
     c->nsub = 0;
     c->nsub_mr = -1;
+    c->nsub_ref = 0;
   }
   if (chosen) *chosen = c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1;
   return MRB_OK;
