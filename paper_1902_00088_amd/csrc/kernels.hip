@@ -927,37 +927,6 @@ __global__ void __launch_bounds__(256) k_rhs_plain(StageArgs A) {
   }
 }
 
-// details d = u - P(R(u)) at the nodes of one parity class (per-field maxima in m)
-template <int DIM, int BS, int S, int H, int NF>
-struct DetailsBody {
-  using G = Geo<DIM, BS, S, H>;
-  const double* tile;
-  const int* r0;
-  const int* cnt;
-  double* m;
-  __device__ __forceinline__ DetailsBody(const double* t_, const int* r_, const int* c_, double* m_)
-      : tile(t_), r0(r_), cnt(c_), m(m_) {}
-  template <int NX, int NY, int NZ>
-  __device__ __forceinline__ void go(int cls) {
-    ParityClass<DIM> pc(cls, r0, cnt);
-    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
-      int t[3];
-      pc.coords(p, t);
-      int i[3] = {t[0] - r0[0] + H, t[1] - r0[1] + H, DIM > 2 ? t[2] - r0[2] + H : 0};
-      const int bb[3] = {NX == 4 ? i[0] - 3 : i[0], NY == 4 ? i[1] - 3 : i[1], NZ == 4 ? i[2] - 3 : i[2]};
-      const int stride[3] = {2, 2, 2};
-#pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        const double* T = tile + f * TSZ;
-        auto at = [&](int x, int y, int z) { return T[G::idx(x, y, z)]; };
-        const double pred = tensor_fixed<NX, NY, NZ, double>(at, bb, stride);
-        m[f] = nanmax(m[f], fabs(T[G::idx(i[0], i[1], i[2])] - pred));
-      }
-    }
-  }
-  static constexpr int TSZ = Geo<DIM, BS, S, H>::TSZ;
-};
-
 // child nodes of one parity class (see k_refine)
 template <int DIM, int BS, int S, int H, int NF>
 struct RefineBody {
@@ -1032,17 +1001,57 @@ struct RefineBody {
 // redundant nodes owned by finer neighbours are written back to the pool
 // ---------------------------------------------------------------------------
 
+// details d = u - P(R(u)) of one parity class, the prediction read from the
+// coarse-lattice array (its points are the even nodes around the region)
+template <int DIM, int BS, int S, int NF>
+struct DetailsBodyC {
+  using G = SGeo<DIM, BS, S, 0>;
+  const double* tile;
+  const double* carr;
+  const int* r0;
+  const int* cnt;
+  double* m;
+  int cb0[3];
+  __device__ __forceinline__ DetailsBodyC(const double* t_, const double* c_, const int* r_, const int* n_, double* m_)
+      : tile(t_), carr(c_), r0(r_), cnt(n_), m(m_) {
+    for (int a = 0; a < 3; ++a) cb0[a] = a < DIM ? (r0[a] - G::H + 1) & ~1 : 0;
+  }
+  template <int NX, int NY, int NZ>
+  __device__ __forceinline__ void go(int cls) {
+    ParityClass<DIM> pc(cls, r0, cnt);
+    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
+      int t[3];
+      pc.coords(p, t);
+      const int bb[3] = {NX == 4 ? (t[0] - 3 - cb0[0]) >> 1 : (t[0] - cb0[0]) >> 1,
+                         NY == 4 ? (t[1] - 3 - cb0[1]) >> 1 : (t[1] - cb0[1]) >> 1,
+                         DIM > 2 ? (NZ == 4 ? (t[2] - 3 - cb0[2]) >> 1 : (t[2] - cb0[2]) >> 1) : 0};
+      const int stride[3] = {1, 1, 1};
+      const int ti = G::idx(t[0] - r0[0], t[1] - r0[1], DIM > 2 ? t[2] - r0[2] : 0);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double* C = carr + f * G::CSZ;
+        auto at = [&](int x, int y, int z) { return C[G::cidx(x, y, z)]; };
+        const double pred = tensor_fixed<NX, NY, NZ, double>(at, bb, stride);
+        m[f] = nanmax(m[f], fabs(tile[f * G::TSZ + ti] - pred));
+      }
+    }
+  }
+};
+
 template <int DIM, int BS, int NF, int NSUB>
 __global__ void __launch_bounds__(256) k_mr(MrArgs A) {
-  // H = 3: a region may start at an odd node, whose coarse stencil reaches 3 back
+  // the region's nodes in the tile; the even nodes up to H = 3 around it (a region may
+  // start at an odd node, whose coarse stencil reaches 3 back) in the coarse array
   constexpr int S = (BS + NSUB - 1) / NSUB, H = 3;
-  using G = Geo<DIM, BS, S, H>;
-  constexpr int NP = G::NP, TSZ = G::TSZ;
+  using SG = SGeo<DIM, BS, S, 0>;
+  constexpr int NP = SG::NP, TSZ = SG::TSZ;
   constexpr int NSUBT = Pow<DIM, NSUB>::v;
-  __shared__ GState<DIM, G::TW> g;
+  __shared__ GState<DIM, S + 2 * H> g;
+  __shared__ SEnt se[kMaxEnt];
   __shared__ double red[4][4];
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
+  double* carr = tile + NF * TSZ;
   const int nblk = A.topo.h->n_blocks;
   for (XcdWork it(nblk * NSUBT); it.ok(); it.next()) {
     const int w = it.w;
@@ -1051,8 +1060,10 @@ __global__ void __launch_bounds__(256) k_mr(MrArgs A) {
     int r0[3], cnt[3];
     subregion<DIM>(w % NSUBT, NSUB, S, BS, r0, cnt);
     gsetup<DIM, BS, S, H>(g, d, A.topo.nb(), r0);
+    sent_setup<DIM, BS, NF>(se, g.ent, d.n_ent);
+    __syncthreads();
     YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
-    gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, 0, H, src);
+    sgather<DIM, BS, S, 0, NF, true, double>(tile, carr, g, se, d.slot, r0, cnt, src);
     double m[4] = {0.0, 0.0, 0.0, 0.0};
     const size_t base = (size_t)d.slot * NF * NP;
     const int nn = cnt[0] * cnt[1] * (DIM > 2 ? cnt[2] : 1);
@@ -1067,7 +1078,7 @@ __global__ void __launch_bounds__(256) k_mr(MrArgs A) {
         cand &= g.m[a][l[a] + H];
       }
       if (bnd && g.ent[63 - __clzll((long long)cand)].dl > 0) {
-        const int ti = G::idx(l[0] + H, l[1] + H, DIM > 2 ? l[2] + H : 0);
+        const int ti = SG::idx(l[0], l[1], DIM > 2 ? l[2] : 0);
         const int node = t[0] + BS * t[1] + (DIM > 2 ? BS * BS * t[2] : 0);
 #pragma unroll
         for (int f = 0; f < NF; ++f) A.u[base + (size_t)f * NP + node] = tile[f * TSZ + ti];
@@ -1075,7 +1086,7 @@ __global__ void __launch_bounds__(256) k_mr(MrArgs A) {
     }
     // details d = u - P(R(u)) at nodes with an odd coordinate (zero at all-even nodes),
     // one parity class at a time so that every lane runs the same unrolled stencil
-    DetailsBody<DIM, BS, S, H, NF> det(tile, r0, cnt, m);
+    DetailsBodyC<DIM, BS, S, NF> det(tile, carr, r0, cnt, m);
     for_odd_classes<DIM>(det);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -1348,7 +1359,8 @@ int aux_variants(const Shape& s, int kind, int* nsub, int cap) {
 template <int D, int B, int F, int NS>
 static hipError_t mr_go(int grid, const MrArgs& a, hipStream_t st) {
   constexpr int S = (B + NS - 1) / NS;
-  return go(k_mr<D, B, F, NS>, grid, sizeof(double) * F * Geo<D, B, S, 3>::TSZ, st, a);
+  using SG = SGeo<D, B, S, 0>;
+  return go(k_mr<D, B, F, NS>, grid, sizeof(double) * F * (SG::TSZ + SG::CSZ), st, a);
 }
 
 template <int D, int B, int F, int NS>
