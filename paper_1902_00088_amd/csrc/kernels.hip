@@ -932,7 +932,7 @@ template <int DIM, int BS, int S, int H, int NF>
 struct RefineBody {
   using G = Geo<DIM, BS, S, H>;
   const double* tile;
-  const GState<DIM, G::TW>& g;
+  const NbEntry* ent;
   const int* q0;
   const int* qn;
   const int* r0;
@@ -940,9 +940,9 @@ struct RefineBody {
   int n_ent;
   size_t cbase;
   double* u;
-  __device__ __forceinline__ RefineBody(const double* t_, const GState<DIM, G::TW>& g_, const int* q0_, const int* qn_,
+  __device__ __forceinline__ RefineBody(const double* t_, const NbEntry* e_, const int* q0_, const int* qn_,
                                  const int* r0_, const int* cb_, int ne, size_t cb0, double* u_)
-      : tile(t_), g(g_), q0(q0_), qn(qn_), r0(r0_), cb(cb_), n_ent(ne), cbase(cb0), u(u_) {}
+      : tile(t_), ent(e_), q0(q0_), qn(qn_), r0(r0_), cb(cb_), n_ent(ne), cbase(cb0), u(u_) {}
   template <int NX, int NY, int NZ>
   __device__ __forceinline__ void go(int cls) {
     ParityClass<DIM> pc(cls, q0, qn);
@@ -961,7 +961,7 @@ struct RefineBody {
       int src_slot = -1, sidx = 0;
       if (cls != 0 && bnd) {
         for (int e = 0; e < n_ent && src_slot < 0; ++e) {
-          const NbEntry& E = g.ent[e];
+          const NbEntry& E = ent[e];
           if (E.dl <= 0) continue;
           bool in = true;
           int s = 0, mul = 1;
@@ -1138,12 +1138,14 @@ template <int DIM, int BS, int NF, int NSUB>
 __global__ void __launch_bounds__(256) k_refine(RefineArgs A) {
   constexpr int SQ = (BS + NSUB - 1) / NSUB;       // child nodes per axis and sub-tile
   constexpr int HWR = 2, H = HWR + 3, S = SQ / 2 + 2;
-  using G = Geo<DIM, BS, S, H>;
-  constexpr int NP = G::NP, TSZ = G::TSZ, NCH = 1 << DIM;
+  using SG = SGeo<DIM, BS, S, HWR>;
+  constexpr int NP = SG::NP, NCH = 1 << DIM;
   constexpr int NSUBT = Pow<DIM, NSUB>::v;
-  __shared__ GState<DIM, G::TW> g;
+  __shared__ GState<DIM, S + 2 * H> g;
+  __shared__ SEnt se[kMaxEnt];
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
+  double* carr = tile + NF * SG::TSZ;
   const int nref = A.topo.h->n_ref;
   for (XcdWork it(nref * NCH * NSUBT); it.ok(); it.next()) {
     const int w = it.w;
@@ -1160,17 +1162,22 @@ __global__ void __launch_bounds__(256) k_refine(RefineArgs A) {
       cnt[a] = ((off + q0[a] + qn[a]) >> 1) - r0[a] + 1;
     }
     gsetup<DIM, BS, S, H>(g, d, A.topo.pnb(), r0);
-    const int h_even = d.n_coarse > 0 ? H : 0;
+    sent_setup<DIM, BS, NF>(se, g.ent, d.n_ent);
+    __syncthreads();
     YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
-    gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, HWR, h_even, src);
-    if (d.n_coarse > 0) gpredict<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, HWR);
+    if (d.n_coarse > 0) {
+      sgather<DIM, BS, S, HWR, NF, true, double>(tile, carr, g, se, d.slot, r0, cnt, src);
+      spredict<DIM, BS, S, HWR, NF, double>(tile, carr, g, r0, cnt);
+    } else {
+      sgather<DIM, BS, S, HWR, NF, false, double>(tile, carr, g, se, d.slot, r0, cnt, src);
+    }
     const size_t cbase = (size_t)R.child[ch] * NF * NP;
     int cb[3] = {0, 0, 0};
     for (int a = 0; a < DIM; ++a) cb[a] = ((ch >> a) & 1) * (BS - 1);
     // one parity class of child nodes at a time (fine parity = parity of q, since
     // bs-1 is even): even nodes copy the parent, odd ones are predicted, and nodes on
     // the parent's boundary held by a finer neighbour take that neighbour's value
-    RefineBody<DIM, BS, S, H, NF> rf(tile, g, q0, qn, r0, cb, d.n_ent, cbase, A.u);
+    RefineBody<DIM, BS, S, HWR, NF> rf(tile, g.ent, q0, qn, r0, cb, d.n_ent, cbase, A.u);
     rf.template go<1, 1, 1>(0);
     for_odd_classes<DIM>(rf);
     __syncthreads();
@@ -1366,7 +1373,8 @@ static hipError_t mr_go(int grid, const MrArgs& a, hipStream_t st) {
 template <int D, int B, int F, int NS>
 static hipError_t refine_go(int grid, const RefineArgs& a, hipStream_t st) {
   constexpr int SQ = (B + NS - 1) / NS;
-  return go(k_refine<D, B, F, NS>, grid, sizeof(double) * F * Geo<D, B, SQ / 2 + 2, 5>::TSZ, st, a);
+  using SG = SGeo<D, B, SQ / 2 + 2, 2>;
+  return go(k_refine<D, B, F, NS>, grid, sizeof(double) * F * (SG::TSZ + SG::CSZ), st, a);
 }
 
 hipError_t launch_mr(const Shape& s, int nsub, int grid, const MrArgs& a, hipStream_t st) {
