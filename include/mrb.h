@@ -135,6 +135,13 @@ mrb_status mrb_read_forest(mrb_ctx *ctx, int8_t *level, int32_t *coords);
 /* Synchronised block values [n][nfields][bs^dim] in forest order (redundant nodes
  * carry the owner's value).  out is host (on_device = 0) or device memory. */
 mrb_status mrb_read_blocks(mrb_ctx *ctx, double *out, int on_device);
+/* The solution on the uniform lattice of `level` (periodic, N = 2^level (bs-1) nodes
+ * per direction): out[nfields][N^dim], x fastest, host (on_device = 0) or device
+ * memory of nfields * N^dim doubles.  Node m takes the synchronised value of the
+ * finest leaf holding it (Sec. 2.2), so level may not exceed the coarsest leaf's
+ * level (every lattice point is then a node of every leaf covering it); MRB_E_ARG
+ * otherwise. */
+mrb_status mrb_read_uniform(mrb_ctx *ctx, int level, double *out, int on_device);
 /* Last analysis: flags[n], maxd[n*nfields] in forest order (host; maxd may be NULL). */
 mrb_status mrb_get_flags(mrb_ctx *ctx, int8_t *flags, double *maxd);
 /* Counters and timings as one JSON object (NUL-terminated, at most cap bytes).

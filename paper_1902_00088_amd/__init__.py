@@ -30,7 +30,7 @@ EXPORTS = ("mrb_create", "mrb_destroy", "mrb_last_error", "mrb_init_forest", "mr
            "mrb_num_blocks", "mrb_read_forest", "mrb_read_blocks", "mrb_get_flags", "mrb_stats",
            "mrb_timing", "mrb_tune", "mrb_set_graph", "mrb_mlp_init", "mrb_mlp_get_params", "mrb_mlp_features",
            "mrb_mlp_forward", "mrb_mlp_grad", "mrb_mlp_train", "mrb_mlp_predict", "mrb_refine_marked",
-           "mrb_step_predicted", "mrb_horizon_labels")
+           "mrb_step_predicted", "mrb_horizon_labels", "mrb_read_uniform")
 
 
 class MrbError(RuntimeError):
@@ -82,6 +82,7 @@ def lib():
             "mrb_num_blocks": [_vp, ctypes.POINTER(ctypes.c_int)],
             "mrb_read_forest": [_vp, _i8p, _i32p],
             "mrb_read_blocks": [_vp, _vp, ctypes.c_int],
+            "mrb_read_uniform": [_vp, ctypes.c_int, _vp, ctypes.c_int],
             "mrb_get_flags": [_vp, _i8p, _dp],
             "mrb_stats": [_vp, ctypes.c_char_p, ctypes.c_int],
             "mrb_timing": [_vp, ctypes.c_int],
@@ -208,6 +209,13 @@ class Solver:
         a = np.ascontiguousarray(np.asarray(data, dtype=np.float64))
         assert a.shape == (self.num_blocks(), self.cfg.nf, self.cfg.npts), a.shape
         self._chk(lib().mrb_load_blocks(self.h, _vp(a.ctypes.data), 0))
+
+    def read_uniform(self, level: int):
+        """Solution on the uniform level-`level` lattice: [nf][N]*dim (x fastest), numpy."""
+        nl = (2 ** level) * (self.cfg.bs - 1)
+        out = np.zeros((self.cfg.nf,) + (nl,) * self.cfg.dim)
+        self._chk(lib().mrb_read_uniform(self.h, level, _vp(out.ctypes.data), 0))
+        return out
 
     def read_blocks(self, on_device: bool = False):
         n = self.num_blocks()

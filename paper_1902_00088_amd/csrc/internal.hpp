@@ -25,9 +25,10 @@ struct BlockDesc {
 // ext = (bs-1) * 2^-dl.  Periodic images are separate entries.
 struct NbEntry {
   int slot;
-  int dl;         // level(neighbour) - level(block): -1, 0 or +1
-  int o[3];
+  int8_t dl;      // level(neighbour) - level(block): -1, 0 or +1
+  int8_t o[3];    // |o| <= 2 (bs-1) <= 124 (bs <= 63)
 };
+static_assert(sizeof(NbEntry) == 8, "NbEntry packs into 8 bytes");
 
 // Refinement work: the parent's descriptor index (parent section) and the slots of
 // its 2^dim children (child bit a = coordinate bit along axis a).
@@ -125,7 +126,8 @@ struct CoarsenArgs {
 struct ReadArgs {
   Topo topo;
   const double* u;
-  double* out;            // [n][nf][bs^dim]
+  double* out;            // level 0: [n][nf][bs^dim]; level L > 0: [nf][N_L^dim], x fastest
+  int level;              // 0: per block; L: uniform lattice of level L (no leaf coarser than L)
 };
 
 struct Shape {

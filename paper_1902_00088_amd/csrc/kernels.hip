@@ -1226,7 +1226,29 @@ __global__ void __launch_bounds__(256) k_read(ReadArgs A) {
     gsetup<DIM, BS, S, H>(g, d, A.topo.nb(), r0);
     YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
     gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, 0, 0, src);
-    for (int p = threadIdx.x; p < NF * NP; p += blockDim.x) A.out[(size_t)b * NF * NP + p] = tile[p];
+    if (A.level == 0) {
+      for (int p = threadIdx.x; p < NF * NP; p += blockDim.x) A.out[(size_t)b * NF * NP + p] = tile[p];
+    } else {
+      // nodes on the level-L lattice go to their place in the uniform array; nodes
+      // shared with neighbours hold the same synchronised value in every holder
+      const int sh = d.level - A.level;
+      const long nl = (long)(1L << A.level) * (BS - 1);
+      const long ntot = DIM > 2 ? nl * nl * nl : nl * nl;
+      for (int p = threadIdx.x; p < NP; p += blockDim.x) {
+        const int t[3] = {p % BS, DIM > 2 ? (p / BS) % BS : p / BS, DIM > 2 ? p / (BS * BS) : 0};
+        long m = 0, mul = 1;
+        bool on = true;
+        for (int a = 0; a < DIM; ++a) {
+          const long gq = (long)d.c[a] * (BS - 1) + t[a];
+          if (gq & ((1L << sh) - 1)) on = false;
+          m += ((gq >> sh) % nl) * mul;
+          mul *= nl;
+        }
+        if (!on) continue;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) A.out[(size_t)f * ntot + m] = tile[f * NP + p];
+      }
+    }
     __syncthreads();
   }
 }

@@ -40,6 +40,78 @@ inline int wrapi(int a, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Leaf position by key (level, coords).  A dense table with one cell per possible
+// block of every level when that fits in 2^24 cells (a lookup is one load; clearing
+// touches only the cells set), else a hash map.
+struct LeafIndex {
+  int dim = 2, jmax = 0;
+  bool dense = false;
+  std::vector<int> cells;
+  std::vector<size_t> off, used;
+  std::unordered_map<uint64_t, int> map;
+  size_t n = 0;
+  void init(int d, int jm) {
+    dim = d;
+    jmax = jm;
+    off.assign(jm + 2, 0);
+    size_t tot = 0;
+    for (int l = 1; l <= jm && tot <= ((size_t)1 << 24); ++l) {
+      off[l] = tot;
+      tot += (size_t)1 << (d * l);
+    }
+    dense = tot <= ((size_t)1 << 24);
+    cells.assign(dense ? tot : 0, -1);
+    used.clear();
+    map.clear();
+    n = 0;
+  }
+  bool valid(uint64_t key) const {
+    const int l = (int)(key >> 60);
+    if (l < 1 || l > jmax) return false;
+    const uint64_t lim = (uint64_t)1 << l;
+    return (key & 0xFFFFF) < lim && ((key >> 20) & 0xFFFFF) < lim && (dim > 2 ? ((key >> 40) & 0xFFFFF) < lim
+                                                                                : ((key >> 40) & 0xFFFFF) == 0);
+  }
+  size_t cell(uint64_t key) const {
+    const int l = (int)(key >> 60);
+    return off[l] + (key & 0xFFFFF) + (((key >> 20) & 0xFFFFF) << l) + (((key >> 40) & 0xFFFFF) << (2 * l));
+  }
+  void clear() {
+    if (dense) {
+      for (size_t u : used) cells[u] = -1;
+      used.clear();
+    } else {
+      map.clear();
+    }
+    n = 0;
+  }
+  void reserve(size_t k) {
+    if (dense) used.reserve(k);
+    else map.reserve(k * 2);
+  }
+  void set(uint64_t key, int i) {
+    if (dense) {
+      const size_t u = cell(key);
+      if (cells[u] < 0) {
+        used.push_back(u);
+        ++n;
+      }
+      cells[u] = i;
+    } else {
+      auto r = map.emplace(key, i);
+      if (r.second) ++n;
+      else r.first->second = i;
+    }
+  }
+  int find(uint64_t key) const {
+    if (!valid(key)) return -1;
+    if (dense) return cells[cell(key)];
+    auto it = map.find(key);
+    return it == map.end() ? -1 : it->second;
+  }
+  size_t size() const { return n; }
+};
+
 // Pinned host staging buffer; an event guards reuse while a copy is in flight.
 struct Staging {
   void* h = nullptr;
@@ -62,13 +134,16 @@ struct mrb_ctx {
   std::vector<double> thr, off;
 
   std::vector<Leaf> leaves;                  // forest order
-  std::unordered_map<uint64_t, int> index;   // key -> position in leaves
+  LeafIndex index;                           // key -> position in leaves
   std::vector<int> free_slots;
   bool have_forest = false, have_data = false;
 
   std::vector<BlockDesc> hblk;
   std::vector<NbEntry> hnb;
   std::vector<int> hlist, level_off;         // blocks grouped by level (plain form)
+  std::vector<NbEntry> hnb_next;             // descriptor build buffers, reused
+  std::vector<std::vector<NbEntry>> desc_parts;
+  long desc_thread_min = 1024;               // forests at least this large use host threads
 
   char* arena = nullptr;        // packed topology in use: header, blocks, entries, lists, plans
   char* work_arena = nullptr;   // the arena uploads go to (owned)
@@ -81,7 +156,6 @@ struct mrb_ctx {
     std::vector<int> material;          // leaves, free-list tail and flags the plan came from
     long last_use = 0;
     std::vector<Leaf> leaves;
-    std::unordered_map<uint64_t, int> index;
     std::vector<BlockDesc> hblk;
     std::vector<NbEntry> hnb;
     std::vector<int> hlist, level_off;
@@ -124,6 +198,7 @@ struct mrb_ctx {
   long n_graph_launches = 0;
   // host-side time (microseconds) by phase
   double hus_refine_plan = 0, hus_coarsen_plan = 0, hus_upload = 0, hus_wait = 0, hus_launch = 0;
+  double hus_index = 0, hus_desc = 0, hus_fixed = 0;   // parts of the plans: ordering, entries, fixed point
   // learned predictor: model, Adam state and batch workspace (device)
   int mlp_nin = 0, mlp_np = 0, mlp_t = 0, mlp_cap = 0;
   float *mp = nullptr, *mgrad = nullptr, *mm = nullptr, *mv = nullptr, *mnorm = nullptr;
@@ -231,15 +306,33 @@ void resolve_timing(mrb_ctx* c) {
       return fail(ctx, MRB_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));           \
   } while (0)
 
+// spread the low 21 bits of v to every third bit (3D) / the low 32 bits to every
+// second bit (2D)
+inline uint64_t spread3(uint64_t v) {
+  v &= 0x1fffff;
+  v = (v | v << 32) & 0x1f00000000ffffULL;
+  v = (v | v << 16) & 0x1f0000ff0000ffULL;
+  v = (v | v << 8) & 0x100f00f00f00f00fULL;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+  v = (v | v << 2) & 0x1249249249249249ULL;
+  return v;
+}
+inline uint64_t spread2(uint64_t v) {
+  v &= 0xffffffffULL;
+  v = (v | v << 16) & 0x0000ffff0000ffffULL;
+  v = (v | v << 8) & 0x00ff00ff00ff00ffULL;
+  v = (v | v << 4) & 0x0f0f0f0f0f0f0f0fULL;
+  v = (v | v << 2) & 0x3333333333333333ULL;
+  v = (v | v << 1) & 0x5555555555555555ULL;
+  return v;
+}
+
+// Morton key of coords << (jmax - l), x least significant
 uint64_t morton_of(const mrb_ctx* c, int l, const int* co) {
-  uint64_t key = 0;
-  const int d = c->cfg.dim, sh = c->cfg.jmax - l;
-  for (int bit = 0; bit < 21; ++bit)
-    for (int a = 0; a < d; ++a) {
-      uint64_t v = (uint64_t)co[a] << sh;
-      key |= ((v >> bit) & 1ULL) << (bit * d + a);
-    }
-  return key;
+  const int sh = c->cfg.jmax - l;
+  if (c->cfg.dim == 2)
+    return spread2((uint64_t)co[0] << sh) | spread2((uint64_t)co[1] << sh) << 1;
+  return spread3((uint64_t)co[0] << sh) | spread3((uint64_t)co[1] << sh) << 1 | spread3((uint64_t)co[2] << sh) << 2;
 }
 
 mrb_status stage_upload(mrb_ctx* c, Staging& s, const void* src, size_t bytes, void* dst) {
@@ -271,19 +364,20 @@ void release_staging(Staging& s) {
 }
 
 void sort_and_index(mrb_ctx* c) {
+  HostTimer ht(&c->hus_index);
   for (auto& L : c->leaves) L.morton = morton_of(c, L.level, L.c);
   std::sort(c->leaves.begin(), c->leaves.end(), [](const Leaf& a, const Leaf& b) { return a.morton < b.morton; });
   c->index.clear();
-  c->index.reserve(c->leaves.size() * 2);
-  for (size_t i = 0; i < c->leaves.size(); ++i) c->index[pack_key(c->leaves[i].level, c->leaves[i].c)] = (int)i;
+  c->index.reserve(c->leaves.size());
+  for (size_t i = 0; i < c->leaves.size(); ++i) c->index.set(pack_key(c->leaves[i].level, c->leaves[i].c), (int)i);
 }
 
 const Leaf* find_leaf(const mrb_ctx* c, int l, const int* co) {
   if (l < 1 || l > c->cfg.jmax) return nullptr;
   int w[3] = {0, 0, 0};
   for (int a = 0; a < c->cfg.dim; ++a) w[a] = wrapi(co[a], 1 << l);
-  auto it = c->index.find(pack_key(l, w));
-  return it == c->index.end() ? nullptr : &c->leaves[it->second];
+  const int i = c->index.find(pack_key(l, w));
+  return i < 0 ? nullptr : &c->leaves[i];
 }
 
 // Neighbour entries of leaf i appended to out (nb_begin relative to out's start);
@@ -308,9 +402,10 @@ const char* block_entries(const mrb_ctx* c, int i, std::vector<NbEntry>& out, Bl
     int cn[3] = {0, 0, 0};
     for (int a = 0; a < d; ++a) cn[a] = L.c[a] + dlt[a];
     if (const Leaf* s = find_leaf(c, L.level, cn)) {
+      // origins differ between directions, so a same-level entry is never repeated
       NbEntry e{s->slot, 0, {0, 0, 0}};
-      for (int a = 0; a < d; ++a) e.o[a] = dlt[a] * (bs - 1);
-      add(sa, e);
+      for (int a = 0; a < d; ++a) e.o[a] = (int8_t)(dlt[a] * (bs - 1));
+      sa.push_back(e);
       continue;
     }
     int pc[3] = {0, 0, 0};
@@ -318,7 +413,7 @@ const char* block_entries(const mrb_ctx* c, int i, std::vector<NbEntry>& out, Bl
     if (L.level > 1) {
       if (const Leaf* s = find_leaf(c, L.level - 1, pc)) {
         NbEntry e{s->slot, -1, {0, 0, 0}};
-        for (int a = 0; a < d; ++a) e.o[a] = (2 * pc[a] - L.c[a]) * (bs - 1);
+        for (int a = 0; a < d; ++a) e.o[a] = (int8_t)((2 * pc[a] - L.c[a]) * (bs - 1));
         add(co, e);
         continue;
       }
@@ -339,9 +434,10 @@ const char* block_entries(const mrb_ctx* c, int i, std::vector<NbEntry>& out, Bl
       for (int a = 0; a < d; ++a) ch[a] = 2 * wrapi(cn[a], 1 << L.level) + beta[a];
       const Leaf* s = find_leaf(c, L.level + 1, ch);
       if (!s) return "forest is not graded (a neighbour differs by two or more levels)";
+      // (direction, child) pairs give distinct origins: no repeats either
       NbEntry e{s->slot, 1, {0, 0, 0}};
-      for (int a = 0; a < d; ++a) e.o[a] = dlt[a] * (bs - 1) + beta[a] * ((bs - 1) / 2);
-      add(fi, e);
+      for (int a = 0; a < d; ++a) e.o[a] = (int8_t)(dlt[a] * (bs - 1) + beta[a] * ((bs - 1) / 2));
+      fi.push_back(e);
     }
   }
   B.slot = L.slot;
@@ -361,19 +457,23 @@ const char* block_entries(const mrb_ctx* c, int i, std::vector<NbEntry>& out, Bl
 // graded.  Large forests are split over host threads (read-only lookups), each
 // filling its own entry list; the lists are then concatenated in forest order.
 mrb_status build_descriptors(mrb_ctx* c) {
+  HostTimer ht(&c->hus_desc);
   const int d = c->cfg.dim, jmax = c->cfg.jmax;
   const int n = (int)c->leaves.size();
   std::vector<BlockDesc> hblk(n);
   int nt = 1;
-  if (n >= 1024) {
+  if (n >= (int)c->desc_thread_min) {
     const int hc = (int)std::max(1u, std::thread::hardware_concurrency());
     nt = std::max(1, std::min({16, hc, n / 256}));
   }
-  std::vector<std::vector<NbEntry>> part(nt);
+  // per-thread entry lists kept between calls (no fresh pages to fault in)
+  if ((int)c->desc_parts.size() < nt) c->desc_parts.resize(nt);
+  auto& part = c->desc_parts;
   std::vector<const char*> err(nt, nullptr);
   auto work = [&](int t) {
     const int lo = (int)((long)n * t / nt), hi = (int)((long)n * (t + 1) / nt);
     std::vector<NbEntry> co, sa, fi;
+    part[t].clear();
     part[t].reserve((size_t)(hi - lo) * (d == 2 ? 13 : 57));
     for (int i = lo; i < hi && !err[t]; ++i) err[t] = block_entries(c, i, part[t], hblk[i], co, sa, fi);
   };
@@ -388,9 +488,10 @@ mrb_status build_descriptors(mrb_ctx* c) {
   }
   for (int t = 0; t < nt; ++t)
     if (err[t]) return fail(c, MRB_E_TOPOLOGY, err[t]);
-  std::vector<NbEntry> hnb;
+  std::vector<NbEntry>& hnb = c->hnb_next;
+  hnb.clear();
   size_t total = 0;
-  for (auto& v : part) total += v.size();
+  for (int t = 0; t < nt; ++t) total += part[t].size();
   hnb.reserve(total);
   for (int t = 0; t < nt; ++t) {
     const int lo = (int)((long)n * t / nt), hi = (int)((long)n * (t + 1) / nt);
@@ -517,7 +618,8 @@ mrb_ctx::Memo* memo_find(mrb_ctx* c, int kind, const std::vector<int>& m) {
 
 void memo_apply(mrb_ctx* c, mrb_ctx::Memo& e) {
   c->leaves = e.leaves;
-  c->index = e.index;
+  c->index.clear();
+  for (size_t i = 0; i < c->leaves.size(); ++i) c->index.set(pack_key(c->leaves[i].level, c->leaves[i].c), (int)i);
   c->hblk = e.hblk;
   c->hnb = e.hnb;
   c->hlist = e.hlist;
@@ -554,7 +656,6 @@ mrb_status memo_record(mrb_ctx* c, int kind, std::vector<int>& material, size_t 
   e->material.swap(material);
   e->last_use = ++c->memo_clock;
   e->leaves = c->leaves;
-  e->index = c->index;
   e->hblk = c->hblk;
   e->hnb = c->hnb;
   e->hlist = c->hlist;
@@ -579,7 +680,7 @@ mrb_status check_forest(mrb_ctx* c) {
     int pc[3] = {L.c[0], L.c[1], L.c[2]};
     for (int l = L.level - 1; l >= 1; --l) {
       for (int a = 0; a < d; ++a) pc[a] >>= 1;
-      if (c->index.count(pack_key(l, pc))) return fail(c, MRB_E_TOPOLOGY, "blocks overlap");
+      if (c->index.find(pack_key(l, pc)) >= 0) return fail(c, MRB_E_TOPOLOGY, "blocks overlap");
     }
   }
   if (vol != total) return fail(c, MRB_E_TOPOLOGY, "forest does not tile the domain");
@@ -861,6 +962,7 @@ mrb_status do_mr_pass(mrb_ctx* c) {
 
 // largest set of complete, flagged families whose merge keeps the grid graded
 std::vector<uint64_t> coarsenable(mrb_ctx* c, const int8_t* flags) {
+  HostTimer ht(&c->hus_fixed);
   const int d = c->cfg.dim, nch = 1 << d;
   std::unordered_set<uint64_t> cand;
   for (size_t i = 0; i < c->leaves.size(); ++i) {
@@ -874,8 +976,8 @@ std::vector<uint64_t> coarsenable(mrb_ctx* c, const int8_t* flags) {
     for (int b = 0; b < nch && all; ++b) {
       int ch[3] = {0, 0, 0};
       for (int a = 0; a < d; ++a) ch[a] = 2 * p[a] + ((b >> a) & 1);
-      auto it = c->index.find(pack_key(L.level, ch));
-      if (it == c->index.end() || flags[it->second] != -1) all = false;
+      const int j = c->index.find(pack_key(L.level, ch));
+      if (j < 0 || flags[j] != -1) all = false;
     }
     if (all) cand.insert(pk);
   }
@@ -891,7 +993,7 @@ std::vector<uint64_t> coarsenable(mrb_ctx* c, const int8_t* flags) {
       for (int b = 0; b < nch && ok; ++b) {
         int ch[3] = {0, 0, 0};
         for (int a = 0; a < d; ++a) ch[a] = 2 * p[a] + ((b >> a) & 1);
-        const int mi = c->index.at(pack_key(l, ch));
+        const int mi = c->index.find(pack_key(l, ch));
         const BlockDesc& B = c->hblk[mi];
         for (int e = B.nb_begin; e < B.nb_begin + B.n_ent && ok; ++e) {
           // the finer neighbour's family (its mother at this member's level)
@@ -970,7 +1072,7 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
     for (int b = 0; b < nch; ++b) {
       int ch[3] = {0, 0, 0};
       for (int a = 0; a < d; ++a) ch[a] = 2 * p[a] + ((b >> a) & 1);
-      const int mi = c->index.at(pack_key(l + 1, ch));
+      const int mi = c->index.find(pack_key(l + 1, ch));
       fd[i].child[b] = c->leaves[mi].slot;
       gone[mi] = 1;
     }
@@ -1131,7 +1233,7 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
   };
   if (!u || !u_new || !k1 || !k2 || !k3) return bad("pool pointers must be non-null");
   if (cfg->dim < 2 || cfg->dim > 3) return bad("dim must be 2 or 3");
-  if (cfg->bs < 5 || cfg->bs % 2 == 0) return bad("bs must be odd");
+  if (cfg->bs < 5 || cfg->bs % 2 == 0 || cfg->bs > 63) return bad("bs must be odd, 5..63");
   if (cfg->hw < 2 || cfg->hw % 2) return bad("hw must be even and >= 2");
   if ((cfg->bs - 1) / 2 < cfg->hw + 2) return bad("need (bs-1)/2 >= hw + 2");
   if (cfg->nfields < 1 || cfg->nfields > 4) return bad("nfields must be 1..4");
@@ -1186,6 +1288,7 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
     c->ph.mu = mu;
     c->ph.kap = mu * gam / ((gam - 1.0) * pr);
   }
+  c->index.init(cfg->dim, cfg->jmax);
   auto dev = [&](void** p, size_t bytes) -> bool {
     hipError_t e = hipMalloc(p, std::max(bytes, (size_t)256));
     if (e != hipSuccess) { c->err = std::string("hipMalloc: ") + hipGetErrorString(e); return false; }
@@ -1426,7 +1529,31 @@ mrb_status mrb_read_blocks(mrb_ctx* c, double* out, int on_device) {
     if ((s = ensure_scratch(c, bytes))) return s;
     dst = c->dscratch;
   }
-  ReadArgs a{topo(c), c->u, dst};
+  ReadArgs a{topo(c), c->u, dst, 0};
+  HIPCHK(c, launch_read(c->shape, grid_for(c, n), a, c->stream));
+  if (!on_device) HIPCHK(c, hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MRB_OK;
+}
+
+mrb_status mrb_read_uniform(mrb_ctx* c, int level, double* out, int on_device) {
+  if (!c || !out) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  int lmin = c->cfg.jmax;
+  for (const Leaf& L : c->leaves) lmin = std::min(lmin, L.level);
+  if (level < 1 || level > lmin)
+    return fail(c, MRB_E_ARG, "read_uniform: level must be between 1 and the coarsest leaf level");
+  size_t pts = 1;
+  for (int a = 0; a < c->cfg.dim; ++a) pts *= (size_t)(1L << level) * (size_t)(c->cfg.bs - 1);
+  const size_t bytes = pts * c->cfg.nfields * sizeof(double);
+  mrb_status s;
+  double* dst = out;
+  if (!on_device) {
+    if ((s = ensure_scratch(c, bytes))) return s;
+    dst = c->dscratch;
+  }
+  const int n = (int)c->leaves.size();
+  ReadArgs a{topo(c), c->u, dst, level};
   HIPCHK(c, launch_read(c->shape, grid_for(c, n), a, c->stream));
   if (!on_device) HIPCHK(c, hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1456,12 +1583,13 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
                 "\"stage_tiles\": %d, \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"host_us\": {\"refine_plan\": %.1f, "
-                "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f}, "
+                "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
+                "\"plan_entries\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
                 c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
                 c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
                 c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
-                c->hus_launch, c->tune_log.c_str(), kern.c_str());
+                c->hus_launch, c->hus_index, c->hus_desc, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
   return MRB_OK;
 }
@@ -1798,6 +1926,8 @@ mrb_status mrb_mlp_predict(mrb_ctx* c, int8_t* pred, float* prob) {
   return MRB_OK;
 }
 
+}  // extern "C"
+
 namespace {
 // marked blocks plus every coarser leaf that must refine with them to keep the grid graded
 std::vector<int> graded_closure(mrb_ctx* c, const int8_t* mask) {
@@ -1826,6 +1956,8 @@ std::vector<int> graded_closure(mrb_ctx* c, const int8_t* mask) {
   return par;
 }
 }  // namespace
+
+extern "C" {
 
 mrb_status mrb_refine_marked(mrb_ctx* c, const int8_t* mask, int* n_refined) {
   if (!c || !mask) return MRB_E_ARG;

@@ -368,3 +368,51 @@ def test_graph_replay_matches_direct_launches():
         assert np.array_equal(_bits(outs[0][1]), _bits(o[1]))
     with pytest.raises(M.MrbError):
         M.Solver(cfg).set_graph(3)
+
+
+def _uniform_from_blocks(cfg, lv, co, data, L):
+    """Uniform level-L lattice from synchronised block values (the definition)."""
+    nl = (2 ** L) * (cfg.bs - 1)
+    out = np.full((cfg.nf,) + (nl,) * cfg.dim, np.nan)
+    loc = np.indices((cfg.bs,) * cfg.dim)[::-1].reshape(cfg.dim, -1)   # x fastest
+    for b in range(len(lv)):
+        sh = int(lv[b]) - L
+        g = [int(co[b][a]) * (cfg.bs - 1) + loc[a] for a in range(cfg.dim)]
+        on = np.ones(loc.shape[1], bool)
+        for a in range(cfg.dim):
+            on &= (g[a] % (1 << sh)) == 0
+        idx = tuple(((g[a][on] >> sh) % nl) for a in range(cfg.dim))[::-1]   # [z][y][x]
+        for f in range(cfg.nf):
+            out[(f,) + idx] = data[b, f][on]
+    return out
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("which", ["C1", "C4"])
+def test_read_uniform_matches_oracle_blocks(which):
+    if which == "C1":
+        cfg = W.C1(jmax=5)
+        s, o = _pair(cfg)
+        for n in range(3):
+            s.step(n * cfg.dt, cfg.dt)
+            o.step(n * cfg.dt, cfg.dt)
+    else:
+        cfg = W.C4(jmax=3)
+        s, o = M.Solver(cfg), oracle.Oracle(cfg)
+        o.init_forest(*W.random_graded_forest(3, 3, 7))
+        lv, co = o.read_forest()
+        s.init_forest(lv, co)
+        data = W.sample(cfg, lv, co)
+        s.load_blocks(data)
+        o.load_blocks(data)
+    lv, co = o.read_forest()
+    lmin = int(lv.min())
+    ob = o.read_blocks()
+    for L in range(1, lmin + 1):
+        got = s.read_uniform(L)
+        want = _uniform_from_blocks(cfg, lv, co, ob, L)
+        assert not np.isnan(want).any()
+        assert np.array_equal(_bits(got), _bits(want)), L
+    with pytest.raises(M.MrbError):
+        s.read_uniform(lmin + 1)
+    s.close()
