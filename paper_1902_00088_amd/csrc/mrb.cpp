@@ -221,7 +221,7 @@ struct mrb_ctx {
   long n_steps = 0, n_rk4 = 0, n_block_updates = 0, n_mr = 0, n_fam = 0, n_refined = 0;
   // kernel timing: event pairs per kernel kind, resolved in mrb_stats
   bool timing = false;
-  struct Timed { int kind; hipEvent_t a, b; double bytes; };
+  struct Timed { int kind; hipEvent_t a, b; double bytes; int count; };
   std::vector<Timed> timed;
   std::vector<hipEvent_t> ev_pool;
   double t_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -266,20 +266,23 @@ hipEvent_t take_event(mrb_ctx* c) {
 
 // Bracket one launch with events when timing is on; `bytes` are the algorithmic
 // bytes the launch moves.
+// One event pair around `count` back-to-back launches of one kernel kind (count > 1
+// for the four stage launches of a sweep, so the pair's own overhead is paid once).
 struct TimeScope {
   mrb_ctx* c;
   int kind;
   double bytes;
+  int count;
   hipEvent_t a = nullptr;
-  TimeScope(mrb_ctx* c_, int k, double b) : c(c_), kind(k), bytes(b) {
-    if (c->timing && (a = take_event(c))) (void)hipEventRecord(a, c->stream);
+  TimeScope(mrb_ctx* c_, int k, double b, int n = 1, bool on = true) : c(c_), kind(k), bytes(b), count(n) {
+    if (on && c->timing && (a = take_event(c))) (void)hipEventRecord(a, c->stream);
   }
   ~TimeScope() {
     if (!a) return;
     hipEvent_t b = take_event(c);
     if (!b) { c->ev_pool.push_back(a); return; }
     (void)hipEventRecord(b, c->stream);
-    c->timed.push_back(mrb_ctx::Timed{kind, a, b, bytes});
+    c->timed.push_back(mrb_ctx::Timed{kind, a, b, bytes, count});
   }
 };
 
@@ -291,7 +294,7 @@ void resolve_timing(mrb_ctx* c) {
     if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
       c->t_ms[t.kind] += ms;
       c->t_bytes[t.kind] += t.bytes;
-      c->t_launches[t.kind]++;
+      c->t_launches[t.kind] += t.count;
     }
     c->ev_pool.push_back(t.a);
     c->ev_pool.push_back(t.b);
@@ -737,7 +740,7 @@ int pick_aux(const mrb_ctx* c, long n_items, int forced = 0) {
 }
 
 // launch one RK stage (fused) or ghost + RHS per level (plain)
-mrb_status run_stage(mrb_ctx* c, int s, const StageArgs& a0, bool fixed_grid = false) {
+mrb_status run_stage(mrb_ctx* c, int s, const StageArgs& a0, bool fixed_grid = false, bool time_it = true) {
   StageArgs a = a0;
   const int n = (int)c->hblk.size();
   if (c->cfg.form == MRB_FORM_PLAIN) {
@@ -754,7 +757,7 @@ mrb_status run_stage(mrb_ctx* c, int s, const StageArgs& a0, bool fixed_grid = f
   const int nsub = pick_nsub(c);
   long work = n;
   for (int d = 0; d < c->cfg.dim; ++d) work *= nsub;
-  TimeScope ts(c, T_STAGE, (double)n * c->bsz * stage_bytes(c, s));
+  TimeScope ts(c, T_STAGE, (double)n * c->bsz * stage_bytes(c, s), 1, time_it);
   HIPCHK(c, launch_stage(c->shape, c->cfg.precision, Variant{nsub}, fixed_grid ? c->grid : grid_for(c, work), a,
                          c->stream));
   return MRB_OK;
@@ -785,6 +788,11 @@ mrb_status sweep(mrb_ctx* c, double t, double dt, bool fixed_grid = false) {
   StageArgs a = stage_args(c);
   a.h6 = h6;
   const double alpha[4] = {0.0, h2, h2, dt};
+  // fused form: one event pair around the four stage launches
+  const bool fused = c->cfg.form == MRB_FORM_FUSED;
+  double sweep_bytes = 0.0;
+  for (int s = 1; s <= 4; ++s) sweep_bytes += (double)c->hblk.size() * c->bsz * stage_bytes(c, s);
+  TimeScope sweep_scope(c, T_STAGE, sweep_bytes, 4, fused);
   for (int s = 1; s <= 4; ++s) {
     a.stage = s;
     a.alpha = alpha[s - 1];
@@ -792,7 +800,7 @@ mrb_status sweep(mrb_ctx* c, double t, double dt, bool fixed_grid = false) {
     a.kout = s < 4 ? c->k[s - 1] : nullptr;
     a.cfac = 1.0;
     if (c->cfg.physics == MRB_ADV_SWIRL && c->cfg.phys[0] > 0.0) a.cfac = std::cos(M_PI * ts[s - 1] / c->cfg.phys[0]);
-    mrb_status r = run_stage(c, s, a, fixed_grid);
+    mrb_status r = run_stage(c, s, a, fixed_grid, !fused);
     if (r) return r;
   }
   return MRB_OK;
