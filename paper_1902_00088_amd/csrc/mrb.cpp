@@ -182,6 +182,12 @@ struct mrb_ctx {
   int st_cur = 0;
   int8_t* h_flags = nullptr;   // pinned, mapped
   double* h_maxd = nullptr;    // pinned, mapped
+  // a second mapped set, written by the speculative second analysis of an adapt
+  int8_t *h_flags2 = nullptr, *dflags2 = nullptr;
+  double *h_maxd2 = nullptr, *dmaxd2 = nullptr;
+  int flag_set = 0;                    // set the next analysis writes
+  std::vector<int8_t> spec_flags;      // first-pass flags of the last adapt
+  long spec_hits = 0, spec_misses = 0;
   int ncu = 256;
   int nsub = 0;                // stage sub-tiles per axis (0 = choose by block count)
   int nsub_mr = -1;            // analysis sub-tiles per axis (-1 = whole blocks, measured best)
@@ -928,8 +934,8 @@ MrArgs mr_args(mrb_ctx* c) {
   MrArgs a;
   a.topo = topo(c);
   a.u = c->u;
-  a.flags = c->dflags;
-  a.maxd = c->dmaxd;
+  a.flags = c->flag_set ? c->dflags2 : c->dflags;
+  a.maxd = c->flag_set ? c->dmaxd2 : c->dmaxd;
   a.acc = c->dacc;
   a.done = c->ddone;
   for (int f = 0; f < 4; ++f) a.thr[f] = f < (int)c->thr.size() ? c->thr[f] : 0.0;
@@ -1026,6 +1032,21 @@ std::vector<uint64_t> coarsenable(mrb_ctx* c, const int8_t* flags) {
   return out;
 }
 
+// a memoised coarsening: adopt its forest and plan, launch the coarsening kernel
+mrb_status coarsen_from_memo(mrb_ctx* c, mrb_ctx::Memo& e) {
+  memo_apply(c, e);
+  c->hcount_ref_zero = true;
+  CoarsenArgs a{topo(c), c->u};
+  const long total = (long)e.nfam * c->np;
+  {
+    TimeScope ts(c, T_COARSEN, (double)total * c->cfg.nfields * 16.0);
+    HIPCHK(c, launch_coarsen(c->shape, (int)std::min(4096L, (total + 255) / 256), a, c->stream));
+  }
+  c->n_fam += e.nfam;
+  c->have_flags = false;
+  return MRB_OK;
+}
+
 mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
   HostTimer ht(&c->hus_coarsen_plan);
   const int d = c->cfg.dim, nch = 1 << d;
@@ -1039,17 +1060,7 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
         ++c->memo_hits;
         return MRB_OK;
       }
-      memo_apply(c, *e);
-      c->hcount_ref_zero = true;
-      CoarsenArgs a{topo(c), c->u};
-      const long total = (long)e->nfam * c->np;
-      {
-        TimeScope ts(c, T_COARSEN, (double)total * c->cfg.nfields * 16.0);
-        HIPCHK(c, launch_coarsen(c->shape, (int)std::min(4096L, (total + 255) / 256), a, c->stream));
-      }
-      c->n_fam += e->nfam;
-      c->have_flags = false;
-      return MRB_OK;
+      return coarsen_from_memo(c, *e);
     }
   }
   std::vector<uint64_t> fams = coarsenable(c, flags);
@@ -1119,17 +1130,100 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
   return MRB_OK;
 }
 
+// flags and maxima of the analysis just finished (mapped set `set`, n blocks)
+mrb_status take_flags(mrb_ctx* c, int set, size_t n) {
+  const int8_t* f = set ? c->h_flags2 : c->h_flags;
+  const double* m = set ? c->h_maxd2 : c->h_maxd;
+  c->last_flags.assign(f, f + n);
+  c->last_maxd.assign(m, m + n * c->cfg.nfields);
+  c->have_flags = true;
+  c->n_mr++;
+  for (double v : c->last_maxd)
+    if (!std::isfinite(v)) return fail(c, MRB_E_NONFINITE, "detail norm is not finite");
+  return MRB_OK;
+}
+
+// Adapt: analysis, coarsening, repeated until nothing merges (Sec. 2.1 item 3).
+// On small forests that repeat, the first coarsening is speculated from the memo:
+// if the forest is in a state whose first-pass flags were seen last time, the
+// memoised coarsening and the second analysis are launched before anything is
+// read back; if the first-pass flags then differ, the host state is put back (the
+// device data of the uncoarsened grid is untouched: the coarsening writes only new
+// slots, and the second analysis writes back into shared nodes the values the first
+// one wrote) and the adapt continues from the real flags.
 mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false) {
-  int passes = 0;
-  for (;;) {
-    mrb_status s = (first_launched && passes == 0) ? mr_readback(c) : do_mr_pass(c);
-    ++passes;
+  mrb_status s;
+  int passes = 1;
+  c->flag_set = 0;
+  if (!first_launched && (s = launch_mr_kernel(c, false))) return s;
+  const size_t n1 = c->leaves.size();
+  mrb_ctx::Memo* e = nullptr;
+  if (n1 <= kMemoMaxLeaves && c->spec_flags.size() == n1) {
+    std::vector<int> mat;
+    memo_material(c, 1, c->spec_flags.data(), mat);
+    e = memo_find(c, 1, mat);
+    if (e && e->nfam == 0) e = nullptr;
+  }
+  if (!e) {
+    {
+      HostTimer ht(&c->hus_wait);
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if ((s = take_flags(c, 0, n1))) return s;
+    c->spec_flags = c->last_flags;
+  } else {
+    // state of the uncoarsened grid, to put back if the speculation fails
+    std::vector<Leaf> leaves0 = c->leaves;
+    std::vector<BlockDesc> hblk0 = c->hblk;
+    std::vector<NbEntry> hnb0 = c->hnb;
+    std::vector<int> hlist0 = c->hlist, level0 = c->level_off;
+    std::vector<int> popped(c->free_slots.end() - (long)e->pop, c->free_slots.end());
+    const size_t npushed = e->pushed.size();
+    char* arena0 = c->arena;
+    const size_t arena_bytes0 = c->arena_bytes;
+    const bool ref_zero0 = c->hcount_ref_zero;
+    const int nfam = e->nfam;
+    if ((s = coarsen_from_memo(c, *e))) return s;
+    c->flag_set = 1;
+    s = launch_mr_kernel(c, false);
+    c->flag_set = 0;
     if (s) return s;
+    {
+      HostTimer ht(&c->hus_wait);
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (std::equal(c->h_flags, c->h_flags + n1, c->spec_flags.begin())) {
+      ++c->spec_hits;
+      if ((s = take_flags(c, 0, n1))) return s;
+      if ((s = take_flags(c, 1, c->leaves.size()))) return s;
+      passes = 2;
+    } else {
+      ++c->spec_misses;
+      c->leaves.swap(leaves0);
+      c->index.clear();
+      for (size_t i = 0; i < c->leaves.size(); ++i) c->index.set(pack_key(c->leaves[i].level, c->leaves[i].c), (int)i);
+      c->hblk.swap(hblk0);
+      c->hnb.swap(hnb0);
+      c->hlist.swap(hlist0);
+      c->level_off.swap(level0);
+      c->free_slots.resize(c->free_slots.size() - npushed);
+      c->free_slots.insert(c->free_slots.end(), popped.begin(), popped.end());
+      c->arena = arena0;
+      c->arena_bytes = arena_bytes0;
+      c->hcount_ref_zero = ref_zero0;
+      c->n_fam -= nfam;
+      if ((s = take_flags(c, 0, n1))) return s;
+      c->spec_flags = c->last_flags;
+    }
+  }
+  for (;;) {
     int nc = 0;
     std::vector<int8_t> fl = c->last_flags;
     if ((s = do_coarsen(c, fl.data(), &nc))) return s;
     if (nc == 0) break;
     if (passes > c->cfg.jmax + 2) return fail(c, MRB_E_STATE, "adapt did not reach a fixed point");
+    if ((s = do_mr_pass(c))) return s;
+    ++passes;
   }
   if (npass) *npass = passes;
   return MRB_OK;
@@ -1329,7 +1423,11 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
     ok = hipHostMalloc((void**)&c->h_flags, mb, fl) == hipSuccess &&
          hipHostMalloc((void**)&c->h_maxd, mb * cfg->nfields * sizeof(double), fl) == hipSuccess &&
          hipHostGetDevicePointer((void**)&c->dflags, c->h_flags, 0) == hipSuccess &&
-         hipHostGetDevicePointer((void**)&c->dmaxd, c->h_maxd, 0) == hipSuccess;
+         hipHostGetDevicePointer((void**)&c->dmaxd, c->h_maxd, 0) == hipSuccess &&
+         hipHostMalloc((void**)&c->h_flags2, mb, fl) == hipSuccess &&
+         hipHostMalloc((void**)&c->h_maxd2, mb * cfg->nfields * sizeof(double), fl) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&c->dflags2, c->h_flags2, 0) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&c->dmaxd2, c->h_maxd2, 0) == hipSuccess;
     if (!ok) c->err = "hipHostMalloc (mapped) failed";
   }
   if (ok) {
@@ -1365,6 +1463,8 @@ mrb_status mrb_destroy(mrb_ctx* c) {
     if (p) (void)hipFree(p);
   if (c->h_flags) (void)hipHostFree(c->h_flags);
   if (c->h_maxd) (void)hipHostFree(c->h_maxd);
+  if (c->h_flags2) (void)hipHostFree(c->h_flags2);
+  if (c->h_maxd2) (void)hipHostFree(c->h_maxd2);
   delete c;
   return MRB_OK;
 }
@@ -1590,13 +1690,13 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
                 "\"plan_entries\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
                 c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
                 c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
-                c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
+                c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
                 c->hus_launch, c->hus_index, c->hus_desc, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
   return MRB_OK;

@@ -152,8 +152,11 @@ def test_c2_full_size_sampled_steps():
         if n % 10 == 9:
             assert_same(s, o, f"step {n + 1}")
     # the forest cycles through the same refine / coarsen transitions every step:
-    # from the second step on the library replays memoised plans
-    assert s.stats()["memo_hits"] >= 2 * 38
+    # from the second step on the library replays memoised plans, and the first
+    # coarsening of each adapt is speculated (and confirmed) before the flags are read
+    st = s.stats()
+    assert st["memo_hits"] >= 2 * 38
+    assert st["spec_hits"] >= 35 and st["spec_misses"] == 0
 
 
 @pytest.mark.gpu
