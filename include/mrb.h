@@ -154,7 +154,8 @@ mrb_status mrb_timing(mrb_ctx *ctx, int enable);
 /* Block tilings (the autotuner).  nsub > 0 forces nsub sub-tiles per axis (one
  * workgroup each) for the fused stage sweep; nsub = 0 with reps > 0 times reps dry
  * sweeps (four stages into k1..k3/u_new, the state u is not advanced) of every
- * compiled stage tiling on the current forest and keeps the fastest, then does the
+ * compiled stage tiling, in forest (Morton) order and in level-sorted order, on the
+ * current forest and keeps the fastest pair, then does the
  * same for the analysis kernel (one pass; flags are recomputed) and, if the last
  * refinement plan is still the uploaded one (right after mrb_refine_all), for the
  * refinement kernel (re-run on the same parents); nsub = 0 with reps = 0 returns to

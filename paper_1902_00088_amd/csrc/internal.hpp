@@ -86,6 +86,7 @@ struct Physics {
 struct StageArgs {
   Topo topo;
   int lvl_begin, lvl_end; // plain form: range of the level-sorted block list (else 0, -1)
+  int order;              // fused form: 0 forest (Morton) order, 1 level-sorted order
   const double* u;
   const void* kprev;
   double alpha;

@@ -785,7 +785,7 @@ __global__ void __launch_bounds__(StageThreads<DIM>::v) k_stage(StageArgs A) {
   const NbEntry* nb = A.topo.nb();
   for (XcdWork it(nblk * NSUBT); it.ok(); it.next()) {
     const int w = it.w;
-    const int b = w / NSUBT;
+    const int b = A.order ? A.topo.list()[w / NSUBT] : w / NSUBT;
     const BlockDesc d = blk[b];
     int r0[3], cnt[3];
     subregion<DIM>(w % NSUBT, NSUB, S, BS, r0, cnt);

@@ -192,6 +192,7 @@ struct mrb_ctx {
   int nsub = 0;                // stage sub-tiles per axis (0 = choose by block count)
   int nsub_mr = -1;            // analysis sub-tiles per axis (-1 = whole blocks, measured best)
   int nsub_ref = 0;            // refinement sub-tiles per axis (0 = choose by work count)
+  int order = 0;               // stage processing order: 0 forest (Morton), 1 level-sorted
   std::string tune_log;
   // captured step graphs (refine, four stages, first analysis), keyed by launch parameters
   bool use_graph = true;
@@ -775,6 +776,7 @@ StageArgs stage_args(mrb_ctx* c) {
   a.topo = topo(c);
   a.lvl_begin = 0;
   a.lvl_end = -1;
+  a.order = c->order;
   a.u = c->u;
   a.unew = c->unew;
   a.k1 = c->k[0];
@@ -1267,7 +1269,8 @@ mrb_status step_graph(mrb_ctx* c, double t, double dt) {
   const int ns = pick_nsub(c);
   const int nsm = pick_aux(c, (long)c->hblk.size(), c->nsub_mr);
   const int nsr = pick_aux(c, (long)std::max(1, c->pending_ref) << c->cfg.dim, c->nsub_ref);
-  const uint64_t key[6] = {(uint64_t)(uintptr_t)c->u, (uint64_t)ns, (uint64_t)nsm, (uint64_t)nsr, dtb,
+  const uint64_t key[6] = {(uint64_t)(uintptr_t)c->u, (uint64_t)ns | ((uint64_t)c->order << 8), (uint64_t)nsm,
+                           (uint64_t)nsr, dtb,
                            (uint64_t)(uintptr_t)c->arena};
   hipGraphExec_t exec = nullptr;
   for (auto& g : c->graphs)
@@ -1690,12 +1693,13 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
                 "\"plan_entries\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
                 c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
                 c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
+                c->order ? "level-sorted" : "forest",
                 c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
                 c->hus_launch, c->hus_index, c->hus_desc, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
@@ -1723,23 +1727,28 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->tune_log.clear();
     const bool was_timing = c->timing;
     c->timing = false;
-    for (int i = 0; i < nv; ++i) {
-      c->nsub = v[i];
-      mrb_status r = sweep(c, 0.0, dt);  // warm-up
-      if (r) return r;
-      HIPCHK(c, hipEventRecord(e0, c->stream));
-      for (int k = 0; k < reps; ++k)
-        if ((r = sweep(c, 0.0, dt))) return r;
-      HIPCHK(c, hipEventRecord(e1, c->stream));
-      HIPCHK(c, hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-      char buf[64];
-      std::snprintf(buf, sizeof buf, "%s\"%d\": %.4f", c->tune_log.empty() ? "" : ", ", v[i], ms / reps);
-      c->tune_log += buf;
-      if (ms < best) { best = ms; best_v = v[i]; }
-    }
+    int best_o = 0;
+    for (int i = 0; i < nv; ++i)
+      for (int o = 0; o < 2; ++o) {   // forest (Morton) order, level-sorted order
+        c->nsub = v[i];
+        c->order = o;
+        mrb_status r = sweep(c, 0.0, dt);  // warm-up
+        if (r) return r;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int k = 0; k < reps; ++k)
+          if ((r = sweep(c, 0.0, dt))) return r;
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        char buf[64];
+        std::snprintf(buf, sizeof buf, "%s\"%d%s\": %.4f", c->tune_log.empty() ? "" : ", ", v[i], o ? "L" : "",
+                      ms / reps);
+        c->tune_log += buf;
+        if (ms < best) { best = ms; best_v = v[i]; best_o = o; }
+      }
     c->nsub = best_v;
+    c->order = best_o;
     // analysis tilings: a pass only synchronises redundant nodes (idempotent) and
     // rewrites flags and maxima
     int va[8];
@@ -1801,6 +1810,7 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->nsub = 0;
     c->nsub_mr = -1;
     c->nsub_ref = 0;
+    c->order = 0;
   }
   if (chosen) *chosen = c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1;
   return MRB_OK;
