@@ -426,13 +426,12 @@ __device__ __forceinline__ int sf(int t, int mode) { return mode == 2 ? 2 * t : 
 // mask word and x-dependent terms stay in registers) and walks rows of its row
 // group; B rows per round, loads issued unconditionally (a lane with no point
 // loads the block's first node and discards it).
-template <int DIM, int BS, int S, int HW, int NF, bool HASC, typename TT, typename SRC>
+template <int DIM, int BS, int S, int HW, int NF, bool HASC, typename TT, int B = 8, typename SRC>
 __device__ void sgather(TT* tile, TT* carr, const GState<DIM, S + 2 * (HW + 3)>& g, const SEnt* se, int slot,
                         const int* r0, const int* cnt, const SRC& src) {
   using G = SGeo<DIM, BS, S, HW>;
   constexpr int TW = G::TW, TSZ = G::TSZ, CW = G::CW, CSZ = G::CSZ, NP = G::NP, H = G::H;
   constexpr int NT = 256, RG = NT / TW, NROW = Pow<DIM - 1, TW>::v;
-  constexpr int B = 8;
   static_assert(RG >= 1, "tile row wider than the workgroup");
   const int self = slot * NF * NP;
   int cb0[3] = {0, 0, 0};
@@ -767,6 +766,9 @@ struct StageThreads { static constexpr int v = 256; };
 template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
 __global__ void __launch_bounds__(StageThreads<DIM>::v) k_stage(StageArgs A) {
   constexpr int S = (BS + NSUB - 1) / NSUB, H = HW + 3;
+  // rows per lane and gather round: a 3D tile needs ~5 rounds of 8; its occupancy is
+  // bound by LDS (3 workgroups per CU), so 10 loads in flight per lane cost nothing
+  constexpr int SB = DIM > 2 && NSUB == 1 ? 10 : 8;
   using SG = SGeo<DIM, BS, S, HW>;
   using G = Geo<DIM, BS, S, HW>;  // tile indexing of the right-hand sides
   constexpr int NP = G::NP, TSZ = G::TSZ;
@@ -797,12 +799,12 @@ __global__ void __launch_bounds__(StageThreads<DIM>::v) k_stage(StageArgs A) {
     const bool hasc = d.n_coarse > 0;
     if (A.stage == 1) {
       YSrc<TT, KT, false> src{A.u, nullptr, 0.0, A.off};
-      if (hasc) sgather<DIM, BS, S, HW, NF, true, TT>(tile, carr, g, se, d.slot, r0, cnt, src);
-      else sgather<DIM, BS, S, HW, NF, false, TT>(tile, carr, g, se, d.slot, r0, cnt, src);
+      if (hasc) sgather<DIM, BS, S, HW, NF, true, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
+      else sgather<DIM, BS, S, HW, NF, false, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
     } else {
       YSrc<TT, KT, true> src{A.u, (const KT*)A.kprev, A.alpha, A.off};
-      if (hasc) sgather<DIM, BS, S, HW, NF, true, TT>(tile, carr, g, se, d.slot, r0, cnt, src);
-      else sgather<DIM, BS, S, HW, NF, false, TT>(tile, carr, g, se, d.slot, r0, cnt, src);
+      if (hasc) sgather<DIM, BS, S, HW, NF, true, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
+      else sgather<DIM, BS, S, HW, NF, false, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
     }
     if (hasc) spredict<DIM, BS, S, HW, NF, TT>(tile, carr, g, r0, cnt);
     TT r;
