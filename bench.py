@@ -232,7 +232,7 @@ def main():
             print(f"bench: predictor study {name} steps={args.c5_steps}", file=sys.stderr, flush=True)
             s = M.Solver(cfg)
             s.init_grid()
-            c5[name] = P.gain_study(s, W.mlp_init_params(64 * cfg.nf, 5), nsteps=args.c5_steps)
+            c5[name] = P.gain_study(s, W.mlp_init_params(64 * cfg.nf, 5), nsteps=args.c5_steps, guard=[0.0, 4.0])
             s.close()
         out["predictor"] = c5
     if not args.no_cpu:

@@ -207,9 +207,13 @@ mrb_status mrb_mlp_predict(mrb_ctx *ctx, int8_t *pred, float *prob);
  * must follow to keep the grid graded; children take the synchronised finer values
  * as in mrb_refine_all.  *n_refined (may be NULL) receives the number refined. */
 mrb_status mrb_refine_marked(mrb_ctx *ctx, const int8_t *mask, int *n_refined);
-/* One predictor-guided MR step: refine the blocks predicted 'refine' or predicted with
- * probability < tau (graded closure), RK4, then adapt by the exact detail threshold. */
-mrb_status mrb_step_predicted(mrb_ctx *ctx, double t, double dt, float tau, int *n_refined);
+/* One predictor-guided MR step: refine the blocks predicted 'refine', those predicted
+ * with probability < tau, and, when guard > 0, every block whose detail maximum from
+ * the last analysis (Sec. 2.3) reaches guard x eps x field_scale for some field (all
+ * blocks if the current grid has not been analysed); close under gradedness; RK4;
+ * adapt by the exact detail threshold.  guard <= 0 leaves the choice to the
+ * predictor alone. */
+mrb_status mrb_step_predicted(mrb_ctx *ctx, double t, double dt, float tau, float guard, int *n_refined);
 /* Training labels at a horizon (no context): block i of the grid "now" is 0 (refine)
  * if a finer block of the later grid overlaps it, 2 (coarsen) if it lies inside a
  * coarser block of the later grid, else 1 (keep). */

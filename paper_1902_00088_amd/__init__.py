@@ -96,7 +96,8 @@ def lib():
             "mrb_mlp_train": [_vp, _fp, _i8p, _fp, ctypes.c_int, ctypes.c_int, ctypes.c_float, _fp],
             "mrb_mlp_predict": [_vp, _i8p, _fp],
             "mrb_refine_marked": [_vp, _i8p, ctypes.POINTER(ctypes.c_int)],
-            "mrb_step_predicted": [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.POINTER(ctypes.c_int)],
+            "mrb_step_predicted": [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_float, ctypes.c_float,
+                                   ctypes.POINTER(ctypes.c_int)],
             "mrb_horizon_labels": [ctypes.c_int, ctypes.c_int, _i8p, _i32p, ctypes.c_int, _i8p, _i32p, _i8p],
         }
         for name, args in sig.items():
@@ -340,9 +341,9 @@ class Solver:
         self._chk(lib().mrb_refine_marked(self.h, _ptr(m, _i8p), ctypes.byref(k)))
         return k.value
 
-    def step_predicted(self, t, dt, tau=0.9) -> int:
+    def step_predicted(self, t, dt, tau=0.9, guard=0.0) -> int:
         k = ctypes.c_int()
-        self._chk(lib().mrb_step_predicted(self.h, t, dt, tau, ctypes.byref(k)))
+        self._chk(lib().mrb_step_predicted(self.h, t, dt, tau, guard, ctypes.byref(k)))
         return k.value
 
     def init_grid(self, fn=None, max_iter: int = 0):

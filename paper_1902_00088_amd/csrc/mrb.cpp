@@ -598,8 +598,9 @@ Topo topo(const mrb_ctx* c) { return Topo{(const TopoHeader*)c->arena}; }
 constexpr size_t kMemoMaxLeaves = 1024;
 constexpr size_t kMemoEntries = 8;
 
-// everything a refine-all (kind 0) or a coarsening (kind 1) plan depends on: the
-// leaves with their slots, the free-list tail the plan can consume, and the flags
+// everything a refine-all (kind 0), a coarsening (kind 1) or a marked refinement
+// (kind 2) plan depends on: the leaves with their slots, the free-list tail the plan
+// can consume, and the flags or the mask
 void memo_material(const mrb_ctx* c, int kind, const int8_t* flags, std::vector<int>& m) {
   const size_t n = c->leaves.size(), nch = (size_t)1 << c->cfg.dim;
   m.clear();
@@ -613,10 +614,10 @@ void memo_material(const mrb_ctx* c, int kind, const int8_t* flags, std::vector<
     m.push_back(L.c[2]);
     m.push_back(L.slot);
   }
-  const size_t k = std::min(c->free_slots.size(), kind == 0 ? n * nch : n / nch + 1);
+  const size_t k = std::min(c->free_slots.size(), kind == 1 ? n / nch + 1 : n * nch);
   m.push_back((int)c->free_slots.size());
   m.insert(m.end(), c->free_slots.end() - (long)k, c->free_slots.end());
-  if (kind == 1)
+  if (kind >= 1)   // coarsening: the flags; marked refinement: the mask
     for (size_t i = 0; i < n; ++i) m.push_back(flags[i]);
 }
 
@@ -837,7 +838,8 @@ mrb_status launch_refine_kernel(mrb_ctx* c, int nref, bool fixed_grid) {
 
 // Plan the safety-zone refinement (new forest, descriptors, one upload) and, if
 // launch is set, run the refinement kernel.
-mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch, bool memoize = false);
+mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch, bool memoize = false,
+                     const int8_t* mask = nullptr);
 
 mrb_status do_refine_all(mrb_ctx* c, bool launch = true) {
   std::vector<int> par;
@@ -848,7 +850,7 @@ mrb_status do_refine_all(mrb_ctx* c, bool launch = true) {
 
 // refine the listed blocks (forest positions, all below jmax; the caller keeps the
 // grid graded)
-mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch, bool memoize) {
+mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch, bool memoize, const int8_t* mask) {
   HostTimer ht(&c->hus_refine_plan);
   const int d = c->cfg.dim, nch = 1 << d;
   c->pending_ref = 0;
@@ -858,8 +860,8 @@ mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch, bool 
   }
   std::vector<int> material;
   if (memoize && c->leaves.size() <= kMemoMaxLeaves) {
-    memo_material(c, 0, nullptr, material);
-    if (mrb_ctx::Memo* e = memo_find(c, 0, material)) {
+    memo_material(c, mask ? 2 : 0, mask, material);
+    if (mrb_ctx::Memo* e = memo_find(c, mask ? 2 : 0, material)) {
       memo_apply(c, *e);
       c->hcount_ref_zero = false;
       c->n_refined += e->npar;
@@ -926,7 +928,8 @@ mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch, bool 
   c->n_refined += (long)par.size();
   c->have_flags = false;
   c->pending_ref = (int)ref.size();
-  if (!material.empty() && (s = memo_record(c, 0, material, taken.size(), freed, c->pending_ref, 0, (int)par.size())))
+  if (!material.empty() &&
+      (s = memo_record(c, mask ? 2 : 0, material, taken.size(), freed, c->pending_ref, 0, (int)par.size())))
     return s;
   if (!launch) return MRB_OK;
   return launch_refine_kernel(c, c->pending_ref, false);
@@ -2082,10 +2085,10 @@ mrb_status mrb_refine_marked(mrb_ctx* c, const int8_t* mask, int* n_refined) {
   if (!check_state(c, true)) return MRB_E_STATE;
   std::vector<int> par = graded_closure(c, mask);
   if (n_refined) *n_refined = (int)par.size();
-  return do_refine(c, par, true);
+  return do_refine(c, par, true, true, mask);
 }
 
-mrb_status mrb_step_predicted(mrb_ctx* c, double t, double dt, float tau, int* n_refined) {
+mrb_status mrb_step_predicted(mrb_ctx* c, double t, double dt, float tau, float guard, int* n_refined) {
   if (!c) return MRB_E_ARG;
   if (!check_state(c, true)) return MRB_E_STATE;
   if (mlp_ready(c)) return MRB_E_STATE;
@@ -2095,8 +2098,21 @@ mrb_status mrb_step_predicted(mrb_ctx* c, double t, double dt, float tau, int* n
   std::vector<float> prob(n);
   mrb_status r = mrb_mlp_predict(c, pred.data(), prob.data());
   if (r) return r;
-  // refine what the predictor calls 'refine' and everything it is unsure about
-  for (int i = 0; i < n; ++i) mask[i] = (pred[i] == 0 || prob[i] < tau) ? 1 : 0;
+  // refine what the predictor calls 'refine', everything it is unsure about, and (the
+  // exact fallback) every block whose last detail maximum reaches guard x threshold
+  // for some field, or all blocks if no analysis of the current grid is at hand
+  const int nf = c->cfg.nfields;
+  const bool have = c->have_flags && c->last_maxd.size() == (size_t)n * nf;
+  for (int i = 0; i < n; ++i) {
+    bool m = pred[i] == 0 || prob[i] < tau;
+    if (!m && guard > 0.0f) {
+      if (!have) m = true;
+      else
+        for (int f = 0; f < nf; ++f)
+          if (!(c->last_maxd[(size_t)i * nf + f] < (double)guard * c->thr[f])) m = true;
+    }
+    mask[i] = m ? 1 : 0;
+  }
   if ((r = mrb_refine_marked(c, mask.data(), n_refined))) return r;
   if ((r = do_rk4(c, t, dt))) return r;
   if ((r = do_adapt(c, nullptr))) return r;

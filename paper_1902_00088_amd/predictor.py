@@ -155,7 +155,7 @@ class GuidedRun:
 
 
 def run_guided(solver, nsteps: int, tau: float = 0.9, judge_every: int = 10, t0: float = 0.0,
-               adaptive_dt: bool = True) -> GuidedRun:
+               adaptive_dt: bool = True, guard: float = 0.0) -> GuidedRun:
     """Advance nsteps with predictor-guided refinement.  Every judge_every-th step
     (0 = never) a plain step from the same state decides: where the grids differ the
     plain result is adopted and the step counts as mispredicted."""
@@ -179,7 +179,7 @@ def run_guided(solver, nsteps: int, tau: float = 0.9, judge_every: int = 10, t0:
         bu = solver.stats()["block_updates"]
         torch.cuda.synchronize()
         tw = time.perf_counter()
-        r.refined += solver.step_predicted(t, dt, tau)
+        r.refined += solver.step_predicted(t, dt, tau, guard)
         torch.cuda.synchronize()
         r.wall_s += time.perf_counter() - tw
         r.block_updates += solver.stats()["block_updates"] - bu
@@ -255,11 +255,11 @@ def run_plain(solver, nsteps: int, t0: float = 0.0, adaptive_dt: bool = True):
 
 def gain_study(solver, params0, nsteps: int = 2000, train_frac: float = 0.8, horizon: int = 5, epochs: int = 60,
                batch: int = 1024, lr: float = 1e-3, seed: int = 5, tau: float = 0.97, judge_every: int = 10,
-               adaptive_dt: bool = True, log=None):
+               adaptive_dt: bool = True, guard: float = 0.0, log=None):
     """Record the plain method, train the predictor on the first part of the run, test
-    it on the rest, then rerun from the same initial grid with guided refinement and
-    compare cost and solution with the plain run.  The solver must hold the initial
-    grid on entry."""
+    it on the rest, then rerun from the same initial grid with guided refinement (once
+    per detail guard if `guard` is a list) and compare cost and solution with the
+    plain run.  The solver must hold the initial grid on entry."""
     cfg = solver.cfg
     say = log or (lambda *_: None)
     init = _state(solver)
@@ -283,14 +283,25 @@ def gain_study(solver, params0, nsteps: int = 2000, train_frac: float = 0.8, hor
     wall_p, bu_p = run_plain(solver, nsteps, adaptive_dt=adaptive_dt)
     plain_end = _state(solver)
     plain_end = (plain_end[0], plain_end[1], plain_end[2].cpu().numpy())
-    # guided run
-    say("guided run")
-    _restore(solver, init)
-    g = run_guided(solver, nsteps, tau=tau, judge_every=judge_every, adaptive_dt=adaptive_dt)
-    lv, co = solver.read_forest()
-    guided_end = (lv, co, solver.read_blocks())
-    dmax, ref, npts = compare_grids(cfg, guided_end, plain_end)
-    rel = [float(d / r) if r > 0 else float(d) for d, r in zip(dmax, ref)]
+    guided = {}
+    for gd in (guard,) if not isinstance(guard, (list, tuple)) else guard:
+        say(f"guided run, detail guard {gd}")
+        _restore(solver, init)
+        g = run_guided(solver, nsteps, tau=tau, judge_every=judge_every, adaptive_dt=adaptive_dt, guard=gd)
+        lv, co = solver.read_forest()
+        dmax, ref, npts = compare_grids(cfg, (lv, co, solver.read_blocks()), plain_end)
+        rel = [float(d / r) if r > 0 else float(d) for d, r in zip(dmax, ref)]
+        guided[gd] = {
+            "block_updates_per_step": g.block_updates / nsteps,
+            "judge_block_updates_per_step": g.judge_block_updates / nsteps,
+            "ms_per_step": 1e3 * g.wall_s / nsteps, "refined_per_step": g.refined / nsteps,
+            "judged": g.judged, "mispredicted_steps": g.mispredicted_steps,
+            "mispredicted_blocks": g.mispredicted_blocks, "blocks_end": int(len(lv)),
+            "block_updates_saved": 1.0 - g.block_updates / max(1, bu_p),
+            "rel_err_vs_plain": rel, "compared_nodes": int(npts),
+            "within_bound": bool(max(rel) <= 10.0 * cfg.eps),
+        }
+    first = guided[next(iter(guided))]
     return {
         "steps": nsteps, "horizon": horizon, "epochs": epochs, "tau": tau, "judge_every": judge_every,
         "adaptive_dt": adaptive_dt,
@@ -300,12 +311,9 @@ def gain_study(solver, params0, nsteps: int = 2000, train_frac: float = 0.8, hor
         "record_s": t_rec, "train_s": t_train,
         "plain": {"block_updates_per_step": bu_p / nsteps, "ms_per_step": 1e3 * wall_p / nsteps,
                   "blocks_end": int(len(plain_end[0]))},
-        "guided": {"block_updates_per_step": g.block_updates / nsteps,
-                   "judge_block_updates_per_step": g.judge_block_updates / nsteps,
-                   "ms_per_step": 1e3 * g.wall_s / nsteps, "refined_per_step": g.refined / nsteps,
-                   "judged": g.judged, "mispredicted_steps": g.mispredicted_steps,
-                   "mispredicted_blocks": g.mispredicted_blocks, "blocks_end": int(len(lv))},
-        "block_updates_saved": 1.0 - g.block_updates / max(1, bu_p),
-        "rel_err_vs_plain": rel, "compared_nodes": int(npts), "bound": 10.0 * cfg.eps,
-        "within_bound": bool(max(rel) <= 10.0 * cfg.eps),
+        "bound": 10.0 * cfg.eps,
+        # the first (or only) guard's results at top level, every guard under "guards"
+        "guided": first, "block_updates_saved": first["block_updates_saved"],
+        "rel_err_vs_plain": first["rel_err_vs_plain"], "within_bound": first["within_bound"],
+        "guards": {str(k): v for k, v in guided.items()},
     }

@@ -220,19 +220,30 @@ def _constant_model(nf, b3):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("mode", ["refine", "unsure", "keep"])
+@pytest.mark.parametrize("mode", ["refine", "unsure", "keep", "guard"])
 def test_step_predicted_limits(mode):
     """Confident 'refine' everywhere, or probability below tau everywhere, is the plain
-    step; confident 'keep' everywhere is RK4 on the unrefined grid plus adaptation."""
+    step; confident 'keep' everywhere is RK4 on the unrefined grid plus adaptation;
+    confident 'keep' with a detail guard refines exactly the blocks whose last detail
+    maximum reaches guard x eps."""
     cfg = W.C1(jmax=5)
     s, o = _pair(cfg, 3)
-    b3 = {"refine": (30.0, 0.0, 0.0), "unsure": (0.0, 0.0, 0.0), "keep": (0.0, 30.0, 0.0)}[mode]
+    b3 = {"refine": (30.0, 0.0, 0.0), "unsure": (0.0, 0.0, 0.0), "keep": (0.0, 30.0, 0.0),
+          "guard": (0.0, 30.0, 0.0)}[mode]
+    guard = 0.05 if mode == "guard" else 0.0
     s.mlp_init(*_constant_model(1, b3))
     t = 3 * cfg.dt
     for _ in range(3):
-        k = s.step_predicted(t, cfg.dt, 0.9)
+        k = s.step_predicted(t, cfg.dt, 0.9, guard)
         if mode == "keep":
             assert k == 0
+            o.rk4(t, cfg.dt)
+            o.adapt()
+        elif mode == "guard":
+            _, md = o.mr_pass()
+            mask = (md >= guard * cfg.eps).any(axis=1).astype(np.int8)
+            assert 0 < mask.sum() < len(mask)
+            assert o.refine_marked(mask) == k
             o.rk4(t, cfg.dt)
             o.adapt()
         else:
