@@ -12,8 +12,8 @@ blocks that refinement is needed for, a few steps ahead:
 * a guided step refines only blocks predicted 'refine' or predicted with softmax
   probability below tau (the safety zone stays the fallback), closed under
   gradedness; the exact detail threshold still decides every coarsening;
-* a judge runs, every K-th step, the plain step from the same state: where the two
-  grids differ the step counts as mispredicted and the plain result is adopted.
+* every K-th step a shadow plain step runs from the same state: where the two grids
+  differ the step counts as mispredicted and the plain result is adopted.
 
 Global time stepping: the step size is set by the finest level the step can reach
 (Sec. 4, global time stepping), i.e. one level above the finest leaf of G^n.
@@ -145,18 +145,18 @@ def _forest_key(lv, co):
 class GuidedRun:
     steps: int = 0
     block_updates: int = 0          # RK4 block updates of the guided steps
-    judge_block_updates: int = 0    # of the shadow plain steps
+    shadow_block_updates: int = 0    # of the shadow plain steps
     refined: int = 0
-    judged: int = 0
+    shadowed: int = 0
     mispredicted_steps: int = 0
     mispredicted_blocks: int = 0
     wall_s: float = 0.0
     blocks: list = field(default_factory=list)
 
 
-def run_guided(solver, nsteps: int, tau: float = 0.9, judge_every: int = 10, t0: float = 0.0,
+def run_guided(solver, nsteps: int, tau: float = 0.9, shadow_every: int = 10, t0: float = 0.0,
                adaptive_dt: bool = True, guard: float = 0.0) -> GuidedRun:
-    """Advance nsteps with predictor-guided refinement.  Every judge_every-th step
+    """Advance nsteps with predictor-guided refinement.  Every shadow_every-th step
     (0 = never) a plain step from the same state decides: where the grids differ the
     plain result is adopted and the step counts as mispredicted."""
     cfg = solver.cfg
@@ -166,12 +166,12 @@ def run_guided(solver, nsteps: int, tau: float = 0.9, judge_every: int = 10, t0:
     for n in range(nsteps):
         lv, co = solver.read_forest()
         dt = step_size(cfg, lv) if adaptive_dt else cfg.dt
-        judge = judge_every > 0 and n % judge_every == 0
-        if judge:
+        shadow = shadow_every > 0 and n % shadow_every == 0
+        if shadow:
             snap = solver.read_blocks(on_device=True)
             bu = solver.stats()["block_updates"]
             solver.step(t, dt)
-            r.judge_block_updates += solver.stats()["block_updates"] - bu
+            r.shadow_block_updates += solver.stats()["block_updates"] - bu
             plv, pco = solver.read_forest()
             pdata = solver.read_blocks(on_device=True)
             solver.init_forest(lv, co)
@@ -183,8 +183,8 @@ def run_guided(solver, nsteps: int, tau: float = 0.9, judge_every: int = 10, t0:
         torch.cuda.synchronize()
         r.wall_s += time.perf_counter() - tw
         r.block_updates += solver.stats()["block_updates"] - bu
-        if judge:
-            r.judged += 1
+        if shadow:
+            r.shadowed += 1
             glv, gco = solver.read_forest()
             if _forest_key(glv, gco) != _forest_key(plv, pco):
                 a = {(int(l),) + tuple(int(v) for v in c) for l, c in zip(glv, gco)}
@@ -254,7 +254,7 @@ def run_plain(solver, nsteps: int, t0: float = 0.0, adaptive_dt: bool = True):
 
 
 def gain_study(solver, params0, nsteps: int = 2000, train_frac: float = 0.8, horizon: int = 5, epochs: int = 60,
-               batch: int = 1024, lr: float = 1e-3, seed: int = 5, tau: float = 0.97, judge_every: int = 10,
+               batch: int = 1024, lr: float = 1e-3, seed: int = 5, tau: float = 0.97, shadow_every: int = 10,
                adaptive_dt: bool = True, guard: float = 0.0, log=None):
     """Record the plain method, train the predictor on the first part of the run, test
     it on the rest, then rerun from the same initial grid with guided refinement (once
@@ -287,15 +287,15 @@ def gain_study(solver, params0, nsteps: int = 2000, train_frac: float = 0.8, hor
     for gd in (guard,) if not isinstance(guard, (list, tuple)) else guard:
         say(f"guided run, detail guard {gd}")
         _restore(solver, init)
-        g = run_guided(solver, nsteps, tau=tau, judge_every=judge_every, adaptive_dt=adaptive_dt, guard=gd)
+        g = run_guided(solver, nsteps, tau=tau, shadow_every=shadow_every, adaptive_dt=adaptive_dt, guard=gd)
         lv, co = solver.read_forest()
         dmax, ref, npts = compare_grids(cfg, (lv, co, solver.read_blocks()), plain_end)
         rel = [float(d / r) if r > 0 else float(d) for d, r in zip(dmax, ref)]
         guided[gd] = {
             "block_updates_per_step": g.block_updates / nsteps,
-            "judge_block_updates_per_step": g.judge_block_updates / nsteps,
+            "shadow_block_updates_per_step": g.shadow_block_updates / nsteps,
             "ms_per_step": 1e3 * g.wall_s / nsteps, "refined_per_step": g.refined / nsteps,
-            "judged": g.judged, "mispredicted_steps": g.mispredicted_steps,
+            "shadowed": g.shadowed, "mispredicted_steps": g.mispredicted_steps,
             "mispredicted_blocks": g.mispredicted_blocks, "blocks_end": int(len(lv)),
             "block_updates_saved": 1.0 - g.block_updates / max(1, bu_p),
             "rel_err_vs_plain": rel, "compared_nodes": int(npts),
@@ -303,7 +303,7 @@ def gain_study(solver, params0, nsteps: int = 2000, train_frac: float = 0.8, hor
         }
     first = guided[next(iter(guided))]
     return {
-        "steps": nsteps, "horizon": horizon, "epochs": epochs, "tau": tau, "judge_every": judge_every,
+        "steps": nsteps, "horizon": horizon, "epochs": epochs, "tau": tau, "shadow_every": shadow_every,
         "adaptive_dt": adaptive_dt,
         "labels_train": np.bincount(ytr, minlength=3).tolist(), "labels_test": np.bincount(yte, minlength=3).tolist(),
         "loss_first_last": [float(losses[0]), float(losses[-1])],

@@ -282,18 +282,18 @@ def test_predictor_errors():
 @pytest.mark.gpu
 def test_guided_run_gain_on_advected_blob():
     """Record 1000 plain steps of the advected blob (Jmax 6, eps 1e-4), train on the
-    first 800, guide a rerun from the same grid with a judge every 10 steps: fewer
+    first 800, guide a rerun from the same grid with a shadow plain step every 10 steps: fewer
     block updates than the plain method, solution within 10 eps of the plain one."""
     from paper_1902_00088_amd import predictor as P
     cfg = W.C1(jmax=6, eps=1e-4)
     s = M.Solver(cfg)
     s.init_grid()
-    r = P.gain_study(s, W.mlp_init_params(64, 5), nsteps=1000, judge_every=10)
+    r = P.gain_study(s, W.mlp_init_params(64, 5), nsteps=1000, shadow_every=10)
     print({k: r[k] for k in ("labels_train", "test_accuracy", "block_updates_saved", "rel_err_vs_plain")},
           r["guided"])
     assert r["labels_train"][0] > 0 and r["labels_train"][2] > 0     # all three classes occur
     assert r["loss_first_last"][1] < r["loss_first_last"][0]
     assert r["block_updates_saved"] > 0.1
-    assert r["guided"]["mispredicted_steps"] <= 0.1 * r["guided"]["judged"]
+    assert r["guided"]["mispredicted_steps"] <= 0.1 * r["guided"]["shadowed"]
     assert r["within_bound"], r["rel_err_vs_plain"]
     s.close()
