@@ -419,3 +419,31 @@ def test_read_uniform_matches_oracle_blocks(which):
     with pytest.raises(M.MrbError):
         s.read_uniform(lmin + 1)
     s.close()
+
+
+@pytest.mark.gpu
+def test_speculative_coarsening_rolls_back_when_flags_change():
+    """The first coarsening of an adapt is speculated from the previous step; a
+    perturbation that changes the flags makes the speculation miss, and the step
+    must still equal the oracle's bit for bit."""
+    cfg = W.C2(form=W.FORM_FUSED)
+    s, o = _pair(cfg)
+    t = 0.0
+    for _ in range(4):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    assert s.stats()["spec_hits"] >= 2
+    # a narrow bump in one block: its refined children keep large details
+    lv, co = o.read_forest()
+    bump = W.sample(cfg, lv, co, fn=lambda x, y: 0.5 * np.exp(-((x - 0.3) ** 2 + (y - 0.6) ** 2) / 4e-5))
+    data = o.read_blocks() + bump
+    s.load_blocks(data)
+    o.load_blocks(data)
+    miss0 = s.stats()["spec_misses"]
+    for n in range(3):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+        assert_same(s, o, f"step {n + 1} after the perturbation")
+    assert s.stats()["spec_misses"] > miss0
