@@ -79,6 +79,7 @@ def run_form(M, W, torch, cfg, steps, warmup, tune=False):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = s.stats()
+    tiles = st["stage_tiles"]
     host_us = {k: (v - st0["host_us"][k]) / steps for k, v in st["host_us"].items()}
     bu = st["block_updates"] - b0
     wall = t1 - t0
@@ -100,6 +101,7 @@ def run_form(M, W, torch, cfg, steps, warmup, tune=False):
         "sweep_block_updates_per_s": bu / (sweep_ms * 1e-3) if sweep_ms > 0 else None,
         "kernels": kst,
         "host_us_per_step": host_us,
+        "stage_tiles": tiles,
     }
 
 
@@ -134,7 +136,8 @@ def headline(args, res):
     dom = max(ks, key=lambda k: ks[k]["ms"])
     ach = ks[dom]["bytes"] / (ks[dom]["ms"] * 1e-3) / 1e9 if ks[dom]["ms"] > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": counter_traffic("c2") if dom == "stage" else None,
+                "frac": ach / PEAK_HBM_GBS,
+                "traffic": counter_traffic(f"c2 nsub {head['stage_tiles']}") if dom == "stage" else None,
                 "traffic_unit": "bytes per launch", "kernel": dom,
                 "algorithmic_bytes_per_launch": ks[dom]["bytes"] / max(1, ks[dom]["launches"]),
                 "launches": ks[dom]["launches"], "avg_launch_us": 1e3 * ks[dom]["ms"] / max(1, ks[dom]["launches"])}
@@ -221,7 +224,8 @@ def main():
             ach4 = ks4["bytes"] / (ks4["ms"] * 1e-3) / 1e9 if ks4["ms"] > 0 else 0.0
             out["c4"]["roofline_stage_mixed"] = {
                 "bound": "hbm", "achieved": ach4, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach4 / PEAK_HBM_GBS,
-                "traffic": counter_traffic("c4"), "traffic_unit": "bytes per launch",
+                "traffic": counter_traffic(f"c4 nsub {c4['mixed_fused']['stage_tiles']}"),
+                "traffic_unit": "bytes per launch",
                 "algorithmic_bytes_per_launch": ks4["bytes"] / max(1, ks4["launches"]),
                 "avg_launch_us": 1e3 * ks4["ms"] / max(1, ks4["launches"])}
 
