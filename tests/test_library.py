@@ -447,3 +447,35 @@ def test_speculative_coarsening_rolls_back_when_flags_change():
         t += cfg.dt
         assert_same(s, o, f"step {n + 1} after the perturbation")
     assert s.stats()["spec_misses"] > miss0
+
+
+@pytest.mark.gpu
+def test_headline_configuration_mixed_step_path_within_1e5():
+    """The benchmark's headline run: 2D swirl at full size (Bs 33, Jmax 7, eps 1e-4),
+    mixed form, autotuned tilings, the library's own step loop (memoised plans,
+    speculated coarsening, automatic graph choice).  Against FP64 oracle steps: same
+    forest every step, per-field error <= 1e-5 relative."""
+    cfg = W.C2()
+    o = oracle.Oracle(cfg)
+    o.init_grid()
+    lv, co = o.read_forest()
+    s = M.Solver(cfg.replace(precision=W.MIXED, form=W.FORM_FUSED))
+    s.init_forest(lv, co)
+    s.load_blocks(o.read_blocks())
+    s.refine_all()
+    s.tune(reps=2)
+    s.init_forest(lv, co)
+    s.load_blocks(o.read_blocks())
+    t, worst = 0.0, 0.0
+    for n in range(30):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+        assert np.array_equal(s.read_forest()[0], o.read_forest()[0]), n
+        a, b = s.read_blocks(), o.read_blocks()
+        worst = max(worst, float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+    st = s.stats()
+    print("worst rel", worst, "spec", st["spec_hits"], "memo", st["memo_hits"], "graph", st["graph_in_use"])
+    assert 0.0 < worst <= 1e-5
+    assert st["spec_hits"] > 20
+    s.close()
