@@ -14,6 +14,9 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <thread>
 #include <unordered_map>
 #include <unordered_set>
@@ -112,6 +115,66 @@ struct LeafIndex {
   size_t size() const { return n; }
 };
 
+// Host worker threads kept for the life of a context (spawning threads per plan costs
+// more than the work they would share).  run(n, f) calls f(0..n-1), f(0) on the caller.
+struct WorkerPool {
+  std::vector<std::thread> th;
+  std::mutex m;
+  std::condition_variable cv, done_cv;
+  std::function<void(int)> job;
+  int njobs = 0, next = 1, pending = 0;
+  long gen = 0;
+  bool stop = false;
+  ~WorkerPool() {
+    {
+      std::lock_guard<std::mutex> g(m);
+      stop = true;
+    }
+    cv.notify_all();
+    for (auto& t : th) t.join();
+  }
+  void ensure(int nthreads) {
+    while ((int)th.size() < nthreads) th.emplace_back([this] { loop(); });
+  }
+  void loop() {
+    long seen = 0;
+    for (;;) {
+      int j;
+      {
+        std::unique_lock<std::mutex> g(m);
+        cv.wait(g, [&] { return stop || (gen != seen && next < njobs); });
+        if (stop) return;
+        j = next++;
+        if (next >= njobs) seen = gen;
+      }
+      job(j);
+      {
+        std::lock_guard<std::mutex> g(m);
+        if (--pending == 0) done_cv.notify_all();
+      }
+    }
+  }
+  void run(int n, const std::function<void(int)>& f) {
+    if (n <= 1) {
+      f(0);
+      return;
+    }
+    ensure(n - 1);
+    {
+      std::lock_guard<std::mutex> g(m);
+      job = f;
+      njobs = n;
+      next = 1;
+      pending = n - 1;
+      ++gen;
+    }
+    cv.notify_all();
+    f(0);
+    std::unique_lock<std::mutex> g(m);
+    done_cv.wait(g, [&] { return pending == 0; });
+  }
+};
+
 // Pinned host staging buffer; an event guards reuse while a copy is in flight.
 struct Staging {
   void* h = nullptr;
@@ -143,6 +206,7 @@ struct mrb_ctx {
   std::vector<int> hlist, level_off;         // blocks grouped by level (plain form)
   std::vector<NbEntry> hnb_next;             // descriptor build buffers, reused
   std::vector<std::vector<NbEntry>> desc_parts;
+  WorkerPool pool;
   long desc_thread_min = 1024;               // forests at least this large use host threads
 
   char* arena = nullptr;        // packed topology in use: header, blocks, entries, lists, plans
@@ -487,15 +551,7 @@ mrb_status build_descriptors(mrb_ctx* c) {
     part[t].reserve((size_t)(hi - lo) * (d == 2 ? 13 : 57));
     for (int i = lo; i < hi && !err[t]; ++i) err[t] = block_entries(c, i, part[t], hblk[i], co, sa, fi);
   };
-  if (nt == 1) {
-    work(0);
-  } else {
-    std::vector<std::thread> th;
-    th.reserve(nt - 1);
-    for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
-    work(0);
-    for (auto& x : th) x.join();
-  }
+  c->pool.run(nt, work);
   for (int t = 0; t < nt; ++t)
     if (err[t]) return fail(c, MRB_E_TOPOLOGY, err[t]);
   std::vector<NbEntry>& hnb = c->hnb_next;
