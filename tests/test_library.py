@@ -479,3 +479,25 @@ def test_headline_configuration_mixed_step_path_within_1e5():
     assert 0.0 < worst <= 1e-5
     assert st["spec_hits"] > 20
     s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("eps", [0.0, 1e30])
+def test_degenerate_thresholds_match_oracle(eps):
+    """eps = 0: nothing ever coarsens, the forest fills up to Jmax; eps = 1e30:
+    everything coarsens down to level 1 (level-1 blocks never coarsen)."""
+    cfg = W.C1(jmax=4, eps=eps)
+    lv, co = W.uniform_forest(cfg, 2)
+    s, o = _pair(cfg, lv, co)
+    t = 0.0
+    for n in range(4):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+        assert_same(s, o, f"eps {eps} step {n + 1}")
+    lv, _ = s.read_forest()
+    if eps == 0.0:
+        assert (lv == cfg.jmax).all()
+    else:
+        assert (lv == 1).all()
+    s.close()
