@@ -57,7 +57,7 @@ _lib = None
 
 
 def build(verbose: bool = False) -> str:
-    from . import build as _b
+    from . import hipbuild as _b
     return _b.build(verbose=verbose)
 
 

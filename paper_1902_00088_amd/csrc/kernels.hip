@@ -43,25 +43,8 @@ __device__ __forceinline__ float D4(float um2, float um1, float up1, float up2, 
 }
 
 // Tensor-product prediction: per axis either one point (n = 1) or four points
-// base + q*stride (n = 4) combined by P4; x first, then y, then z.
-template <int DIM, typename T, typename AT>
-__device__ __forceinline__ T tensor_p(const AT& at, const int* base, const int* stride, const int* n) {
-  T vz[4] = {T(0), T(0), T(0), T(0)};
-  const int nz = DIM > 2 ? n[2] : 1;
-  for (int iz = 0; iz < nz; ++iz) {
-    T vy[4] = {T(0), T(0), T(0), T(0)};
-    for (int iy = 0; iy < n[1]; ++iy) {
-      T vx[4] = {T(0), T(0), T(0), T(0)};
-      for (int ix = 0; ix < n[0]; ++ix)
-        vx[ix] = at(base[0] + ix * stride[0], base[1] + iy * stride[1], DIM > 2 ? base[2] + iz * stride[2] : 0);
-      vy[iy] = n[0] == 4 ? P4(vx[0], vx[1], vx[2], vx[3]) : vx[0];
-    }
-    vz[iz] = n[1] == 4 ? P4(vy[0], vy[1], vy[2], vy[3]) : vy[0];
-  }
-  return nz == 4 ? P4(vz[0], vz[1], vz[2], vz[3]) : vz[0];
-}
-
-// Same, with the number of points per axis fixed at compile time (fully unrolled).
+// base + q*stride (n = 4) combined by P4; x first, then y, then z.  The number of
+// points per axis is fixed at compile time (fully unrolled).
 template <int NX, int NY, int NZ, typename T, typename AT>
 __device__ __forceinline__ T tensor_fixed(const AT& at, const int* base, const int* stride) {
   T vz[4];
@@ -182,33 +165,6 @@ __device__ void gsetup(GState<DIM, S + 2 * H>& g, const BlockDesc& d, const NbEn
   }
   __syncthreads();
 }
-
-// Tile point p -> tile coords, block-local coords, distance to the region, parity,
-// and the candidate mask.
-template <int DIM, int S, int H>
-struct PointInfo {
-  int i[3], t[3], dist;
-  bool even;
-  unsigned long long cand;
-  __device__ __forceinline__ PointInfo(int p, const GState<DIM, S + 2 * H>& g, const int* r0, const int* cnt) {
-    constexpr int TW = S + 2 * H;
-    i[0] = p % TW;
-    i[1] = DIM > 2 ? (p / TW) % TW : p / TW;
-    i[2] = DIM > 2 ? p / (TW * TW) : 0;
-    t[2] = 0;
-    dist = 0;
-    even = true;
-    cand = ~0ull;
-    for (int a = 0; a < DIM; ++a) {
-      const int u = i[a] - H;
-      t[a] = r0[a] + u;
-      const int da = u < 0 ? -u : (u >= cnt[a] ? u - cnt[a] + 1 : 0);
-      dist = da > dist ? da : dist;
-      if (t[a] & 1) even = false;
-      cand &= g.m[a][i[a]];
-    }
-  }
-};
 
 // Work items of a launch, XCD-aware: workgroups are dealt round-robin to the 8 XCDs
 // (each with its own L2), so XCD x takes the contiguous chunk x of the work list
@@ -758,13 +714,8 @@ __device__ __forceinline__ void ns_rhs(const double* T, const CT* W, int ux0, in
 // ---------------------------------------------------------------------------
 // fused stage kernel: gather y_s, predict missing ghosts, RHS, store
 // ---------------------------------------------------------------------------
-// threads per workgroup of the stage kernel (the gather and RHS loops lay lanes
-// out along x for 256; 1024 measured slower on 3D blocks)
-template <int DIM>
-struct StageThreads { static constexpr int v = 256; };
-
 template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
-__global__ void __launch_bounds__(StageThreads<DIM>::v) k_stage(StageArgs A) {
+__global__ void __launch_bounds__(256) k_stage(StageArgs A) {
   constexpr int S = (BS + NSUB - 1) / NSUB, H = HW + 3;
   // rows per lane and gather round: a 3D tile needs ~5 rounds of 8; its occupancy is
   // bound by LDS (3 workgroups per CU), so 10 loads in flight per lane cost nothing
@@ -1268,13 +1219,13 @@ __global__ void __launch_bounds__(256) k_scatter(const double* src, const int* s
 // launchers
 // ---------------------------------------------------------------------------
 template <typename K, typename Arg>
-static hipError_t go(K kern, int grid, size_t lds, hipStream_t st, const Arg& a, int threads = 256) {
+static hipError_t go(K kern, int grid, size_t lds, hipStream_t st, const Arg& a) {
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   grid = ((grid > 0 ? grid : 1) + 7) & ~7;  // XcdWork needs a multiple of 8
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
@@ -1285,7 +1236,7 @@ static hipError_t stage_go(int grid, const StageArgs& a, hipStream_t st) {
   using SG = SGeo<DIM, BS, S, HW>;
   size_t lds = sizeof(TT) * NF * (SG::TSZ + SG::CSZ);
   if (NF == 4) lds += sizeof(CT) * 5 * (S + 4) * (S + 4);
-  return go(k_stage<DIM, BS, HW, NF, NSUB, TT, KT, CT>, grid, lds, st, a, StageThreads<DIM>::v);
+  return go(k_stage<DIM, BS, HW, NF, NSUB, TT, KT, CT>, grid, lds, st, a);
 }
 
 // FP64: FP64 tile, slopes and arithmetic.  Mixed: FP32 slopes and arithmetic; the

@@ -33,6 +33,20 @@ def test_library_exports_every_declared_entry_point():
         assert hasattr(L, n), n
 
 
+def test_build_entry_reaches_the_hip_build(monkeypatch):
+    """build() goes through the package's build() to the hipcc driver module
+    (the stubs stand in for the compilers so the test stays fast)."""
+    import importlib
+    import __graft_entry__ as G
+    hb = importlib.import_module("paper_1902_00088_amd.hipbuild")
+    calls = []
+    monkeypatch.setattr(hb, "build", lambda verbose=False: calls.append("hip") or M.LIB_PATH)
+    monkeypatch.setattr(oracle, "build", lambda *a, **k: calls.append("oracle"))
+    G.build()
+    assert calls == ["hip", "oracle"]
+    assert callable(M.build)
+
+
 def test_solver_refuses_to_run_without_gpu():
     import torch
     if torch.cuda.is_available():
