@@ -15,7 +15,7 @@ struct BlockDesc {
   int slot;       // pool slot of the block's data
   int level;
   int c[3];       // integer coordinates at its level
-  int nb_begin;   // first neighbour entry
+  int nb_begin;   // first neighbour entry in the host's packed list
   int n_ent;      // entries: coarser leaves first, then same-level leaves (the block
   int n_coarse;   // itself included), then finer leaves
 };
@@ -30,10 +30,9 @@ struct NbEntry {
 };
 static_assert(sizeof(NbEntry) == 8, "NbEntry packs into 8 bytes");
 
-// Refinement work: the parent's descriptor index (parent section) and the slots of
-// its 2^dim children (child bit a = coordinate bit along axis a).
+// Refinement work r: the slots of the 2^dim children of parent r of the parent
+// section (child bit a = coordinate bit along axis a).
 struct RefineDesc {
-  int pblk;
   int child[8];
 };
 
@@ -44,25 +43,37 @@ struct FamilyDesc {
 };
 
 // Header of the packed topology buffer (one host->device copy per topology change).
-// Offsets are in bytes from the start of the buffer.
+// Offsets are in bytes from the start of the buffer.  Block b's neighbour entries sit
+// at off_nb + b * nb_stride entries (nb_stride = the largest entry count of the
+// upload), and refinement r's parent entries at off_pnb + r * pnb_stride, so a
+// kernel can load a block's descriptor and its entries at the same time.
 struct TopoHeader {
   int n_blocks;   // current grid
   int n_ref;      // refinement work items
   int n_fam;      // coarsening families
-  int n_pblk;     // parents (refinement)
+  int n_pblk;     // parents (refinement); parent r belongs to refinement r
   int off_blk, off_nb, off_list, off_pblk, off_pnb, off_ref, off_fam;
-  int pad[5];
+  int nb_stride, pnb_stride;
+  int pad[3];
 };
+static_assert(sizeof(TopoHeader) == 64, "the header is 64 bytes (graph keys hold it as 8 words)");
 
+// Kernel view of the topology: the buffer and a copy of its header, passed by value
+// so that no launch waits on a load of the header.
 struct Topo {
-  const TopoHeader* h;
-  __device__ __forceinline__ const BlockDesc* blk() const { return (const BlockDesc*)((const char*)h + h->off_blk); }
-  __device__ __forceinline__ const NbEntry* nb() const { return (const NbEntry*)((const char*)h + h->off_nb); }
-  __device__ __forceinline__ const int* list() const { return (const int*)((const char*)h + h->off_list); }
-  __device__ __forceinline__ const BlockDesc* pblk() const { return (const BlockDesc*)((const char*)h + h->off_pblk); }
-  __device__ __forceinline__ const NbEntry* pnb() const { return (const NbEntry*)((const char*)h + h->off_pnb); }
-  __device__ __forceinline__ const RefineDesc* ref() const { return (const RefineDesc*)((const char*)h + h->off_ref); }
-  __device__ __forceinline__ const FamilyDesc* fam() const { return (const FamilyDesc*)((const char*)h + h->off_fam); }
+  const char* base;
+  TopoHeader h;
+  __device__ __forceinline__ const BlockDesc* blk() const { return (const BlockDesc*)(base + h.off_blk); }
+  __device__ __forceinline__ const NbEntry* nb(int b) const {
+    return (const NbEntry*)(base + h.off_nb) + (size_t)b * h.nb_stride;
+  }
+  __device__ __forceinline__ const int* list() const { return (const int*)(base + h.off_list); }
+  __device__ __forceinline__ const BlockDesc* pblk() const { return (const BlockDesc*)(base + h.off_pblk); }
+  __device__ __forceinline__ const NbEntry* pnb(int r) const {
+    return (const NbEntry*)(base + h.off_pnb) + (size_t)r * h.pnb_stride;
+  }
+  __device__ __forceinline__ const RefineDesc* ref() const { return (const RefineDesc*)(base + h.off_ref); }
+  __device__ __forceinline__ const FamilyDesc* fam() const { return (const FamilyDesc*)(base + h.off_fam); }
 };
 
 struct LevelTab {

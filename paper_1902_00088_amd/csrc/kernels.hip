@@ -147,10 +147,12 @@ struct YSrc {
 
 // Load the block's entries and build the per-axis candidate masks of the tile.
 template <int DIM, int BS, int S, int H>
-__device__ void gsetup(GState<DIM, S + 2 * H>& g, const BlockDesc& d, const NbEntry* nb, const int* r0) {
+__device__ void gsetup(GState<DIM, S + 2 * H>& g, const BlockDesc& d, const NbEntry* ent, int stride, const int* r0) {
   constexpr int TW = S + 2 * H;
+  // all `stride` entries of the padded row (in bounds; those past n_ent are unused),
+  // so the loads need not wait for the descriptor
+  for (int i = threadIdx.x; i < stride; i += blockDim.x) g.ent[i] = ent[i];
   const int ne = d.n_ent;
-  for (int i = threadIdx.x; i < ne; i += blockDim.x) g.ent[i] = nb[d.nb_begin + i];
   __syncthreads();
   for (int q = threadIdx.x; q < DIM * TW; q += blockDim.x) {
     const int a = q / TW, it = q % TW, t = r0[a] - H + it;
@@ -733,16 +735,15 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs A) {
   TT* tile = reinterpret_cast<TT*>(smem);
   TT* carr = tile + NF * TSZ;
   CT* W = reinterpret_cast<CT*>(carr + NF * SG::CSZ);  // NS stresses / fluxes
-  const int nblk = A.topo.h->n_blocks;
+  const int nblk = A.topo.h.n_blocks;
   const BlockDesc* blk = A.topo.blk();
-  const NbEntry* nb = A.topo.nb();
   for (XcdWork it(nblk * NSUBT); it.ok(); it.next()) {
     const int w = it.w;
     const int b = A.order ? A.topo.list()[w / NSUBT] : w / NSUBT;
     const BlockDesc d = blk[b];
     int r0[3], cnt[3];
     subregion<DIM>(w % NSUBT, NSUB, S, BS, r0, cnt);
-    gsetup<DIM, BS, S, H>(g, d, nb, r0);
+    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(b), A.topo.h.nb_stride, r0);
     sent_setup<DIM, BS, NF>(se, g.ent, d.n_ent);
     const bool sw_lds = DIM == 2 && NF == 1 && A.ph.kind == 1;
     if (sw_lds) load_swirl<BS, S>(swirl, d, r0, cnt, A);
@@ -832,7 +833,7 @@ __global__ void __launch_bounds__(256) k_ghost(StageArgs A) {
     const int b = A.topo.list()[A.lvl_begin + w];
     const BlockDesc d = A.topo.blk()[b];
     int r0[3] = {0, 0, 0}, cnt[3] = {BS, DIM > 1 ? BS : 1, DIM > 2 ? BS : 1};
-    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(), r0);
+    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(b), A.topo.h.nb_stride, r0);
     const int h_even = d.n_coarse > 0 ? H : 0;
     if (A.stage == 1) {
       YSrc<double, double, false> src{A.u, nullptr, 0.0, A.off};
@@ -1005,14 +1006,14 @@ __global__ void __launch_bounds__(256) k_mr(MrArgs A) {
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
   double* carr = tile + NF * TSZ;
-  const int nblk = A.topo.h->n_blocks;
+  const int nblk = A.topo.h.n_blocks;
   for (XcdWork it(nblk * NSUBT); it.ok(); it.next()) {
     const int w = it.w;
     const int b = w / NSUBT;
     const BlockDesc d = A.topo.blk()[b];
     int r0[3], cnt[3];
     subregion<DIM>(w % NSUBT, NSUB, S, BS, r0, cnt);
-    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(), r0);
+    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(b), A.topo.h.nb_stride, r0);
     sent_setup<DIM, BS, NF>(se, g.ent, d.n_ent);
     __syncthreads();
     YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
@@ -1099,12 +1100,12 @@ __global__ void __launch_bounds__(256) k_refine(RefineArgs A) {
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
   double* carr = tile + NF * SG::TSZ;
-  const int nref = A.topo.h->n_ref;
+  const int nref = A.topo.h.n_ref;
   for (XcdWork it(nref * NCH * NSUBT); it.ok(); it.next()) {
     const int w = it.w;
     const int ri = w / (NCH * NSUBT), ch = (w / NSUBT) % NCH;
     const RefineDesc R = A.topo.ref()[ri];
-    const BlockDesc d = A.topo.pblk()[R.pblk];
+    const BlockDesc d = A.topo.pblk()[ri];
     int q0[3], qn[3];
     subregion<DIM>(w % NSUBT, NSUB, SQ, BS, q0, qn);
     // parent region holding the sub-tile's fine nodes Q = cb (bs-1) + q (parent coords Q/2)
@@ -1114,7 +1115,7 @@ __global__ void __launch_bounds__(256) k_refine(RefineArgs A) {
       r0[a] = (off + q0[a]) >> 1;
       cnt[a] = ((off + q0[a] + qn[a]) >> 1) - r0[a] + 1;
     }
-    gsetup<DIM, BS, S, H>(g, d, A.topo.pnb(), r0);
+    gsetup<DIM, BS, S, H>(g, d, A.topo.pnb(ri), A.topo.h.pnb_stride, r0);
     sent_setup<DIM, BS, NF>(se, g.ent, d.n_ent);
     __syncthreads();
     YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
@@ -1142,7 +1143,7 @@ __global__ void __launch_bounds__(256) k_refine(RefineArgs A) {
 template <int DIM, int BS, int NF>
 __global__ void __launch_bounds__(256) k_coarsen(CoarsenArgs A) {
   constexpr int NP = Pow<DIM, BS>::v;
-  const int nfam = A.topo.h->n_fam;
+  const int nfam = A.topo.h.n_fam;
   const long total = (long)nfam * NP;
   const FamilyDesc* fam = A.topo.fam();
   for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < total; p += (long)gridDim.x * blockDim.x) {
@@ -1171,12 +1172,12 @@ __global__ void __launch_bounds__(256) k_read(ReadArgs A) {
   __shared__ GState<DIM, G::TW> g;
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
-  const int nblk = A.topo.h->n_blocks;
+  const int nblk = A.topo.h.n_blocks;
   for (XcdWork it(nblk); it.ok(); it.next()) {
     const int b = it.w;
     const BlockDesc d = A.topo.blk()[b];
     int r0[3] = {0, 0, 0}, cnt[3] = {BS, BS, DIM > 2 ? BS : 1};
-    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(), r0);
+    gsetup<DIM, BS, S, H>(g, d, A.topo.nb(b), A.topo.h.nb_stride, r0);
     YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
     gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, 0, 0, src);
     if (A.level == 0) {

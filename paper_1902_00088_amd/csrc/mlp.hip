@@ -42,8 +42,7 @@ __global__ void __launch_bounds__(256) k_pool(MlpPoolArgs A) {
   constexpr int W = (BS - 1) / 8;
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
-  const TopoHeader* h = A.topo.h;
-  const int nblk = h->n_blocks;
+  const int nblk = A.topo.h.n_blocks;
   for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
     const BlockDesc d = A.topo.blk()[b];
     // owner of each node: the block itself except on its boundary, where a finer
@@ -52,8 +51,8 @@ __global__ void __launch_bounds__(256) k_pool(MlpPoolArgs A) {
       const int f = p / NPT, q = p % NPT, x = q % BS, y = q / BS;
       double v = A.u[((size_t)d.slot * A.nf + f) * NPT + q];
       if (x == 0 || y == 0 || x == BS - 1 || y == BS - 1) {
-        for (int e = d.nb_begin; e < d.nb_begin + d.n_ent; ++e) {
-          const NbEntry E = A.topo.nb()[e];
+        for (int e = 0; e < d.n_ent; ++e) {
+          const NbEntry E = A.topo.nb(b)[e];
           if (E.dl <= 0) continue;
           const int lx = x - E.o[0], ly = y - E.o[1];
           if (lx >= 0 && lx <= (BS - 1) / 2 && ly >= 0 && ly <= (BS - 1) / 2) {

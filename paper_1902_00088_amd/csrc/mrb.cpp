@@ -210,6 +210,7 @@ struct mrb_ctx {
   long desc_thread_min = 1024;               // forests at least this large use host threads
 
   char* arena = nullptr;        // packed topology in use: header, blocks, entries, lists, plans
+  TopoHeader arena_hdr{};       // its header (kernels take it by value)
   char* work_arena = nullptr;   // the arena uploads go to (owned)
   size_t arena_cap = 0, arena_bytes = 0;
   // memo of topology transitions on small forests: a refine-all or a coarsening from a
@@ -227,6 +228,7 @@ struct mrb_ctx {
     std::vector<int> pushed;            // slots returned, in order
     int pending_ref = 0, nfam = 0, npar = 0;
     char* arena = nullptr;
+    TopoHeader hdr{};
     size_t arena_bytes = 0;
   };
   std::vector<Memo> memo;
@@ -264,7 +266,7 @@ struct mrb_ctx {
   // paths until each has ten samples, then the faster median wall time wins)
   int graph_mode = 2;
   std::vector<double> probe_us[2];
-  struct GraphEntry { uint64_t key[6]; hipGraphExec_t exec; };
+  struct GraphEntry { uint64_t key[6 + sizeof(TopoHeader) / 8]; hipGraphExec_t exec; };
   std::vector<GraphEntry> graphs;
   long n_graph_launches = 0;
   // host-side time (microseconds) by phase
@@ -593,6 +595,14 @@ mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
   h.n_ref = ref ? (int)ref->size() : 0;
   h.n_fam = fam ? (int)fam->size() : 0;
   h.n_pblk = pblk ? (int)pblk->size() : 0;
+  // entries padded to the largest count, block b's at b * stride
+  auto stride_of = [](const std::vector<BlockDesc>& v) {
+    int m = 1;
+    for (const BlockDesc& d : v) m = std::max(m, d.n_ent);
+    return m;
+  };
+  h.nb_stride = stride_of(c->hblk);
+  h.pnb_stride = pblk ? stride_of(*pblk) : 1;
   size_t off = align16(sizeof(TopoHeader));
   auto place = [&](size_t bytes) {
     size_t o = off;
@@ -600,10 +610,10 @@ mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
     return (int)o;
   };
   h.off_blk = place(c->hblk.size() * sizeof(BlockDesc));
-  h.off_nb = place(c->hnb.size() * sizeof(NbEntry));
+  h.off_nb = place(c->hblk.size() * (size_t)h.nb_stride * sizeof(NbEntry));
   h.off_list = place(c->hlist.size() * sizeof(int));
   h.off_pblk = place(pblk ? pblk->size() * sizeof(BlockDesc) : 0);
-  h.off_pnb = place(pnb ? pnb->size() * sizeof(NbEntry) : 0);
+  h.off_pnb = place(pblk ? pblk->size() * (size_t)h.pnb_stride * sizeof(NbEntry) : 0);
   h.off_ref = place(ref ? ref->size() * sizeof(RefineDesc) : 0);
   h.off_fam = place(fam ? fam->size() * sizeof(FamilyDesc) : 0);
   const size_t total = off;
@@ -617,6 +627,7 @@ mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
     c->arena_cap = cap;
   }
   c->arena = c->work_arena;
+  c->arena_hdr = h;
   c->arena_bytes = total;
   Staging& S = c->st_topo[c->st_cur];
   c->st_cur ^= 1;
@@ -636,10 +647,14 @@ mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
   std::memcpy(b, &h, sizeof h);
   auto put = [&](int o, const void* p, size_t n) { if (n) std::memcpy(b + o, p, n); };
   put(h.off_blk, c->hblk.data(), c->hblk.size() * sizeof(BlockDesc));
-  put(h.off_nb, c->hnb.data(), c->hnb.size() * sizeof(NbEntry));
+  auto put_entries = [&](int o, int stride, const std::vector<BlockDesc>& v, const std::vector<NbEntry>& e) {
+    for (size_t i = 0; i < v.size(); ++i)
+      put(o + (int)(i * stride * sizeof(NbEntry)), e.data() + v[i].nb_begin, v[i].n_ent * sizeof(NbEntry));
+  };
+  put_entries(h.off_nb, h.nb_stride, c->hblk, c->hnb);
   put(h.off_list, c->hlist.data(), c->hlist.size() * sizeof(int));
   if (pblk) put(h.off_pblk, pblk->data(), pblk->size() * sizeof(BlockDesc));
-  if (pnb) put(h.off_pnb, pnb->data(), pnb->size() * sizeof(NbEntry));
+  if (pblk && pnb) put_entries(h.off_pnb, h.pnb_stride, *pblk, *pnb);
   if (ref) put(h.off_ref, ref->data(), ref->size() * sizeof(RefineDesc));
   if (fam) put(h.off_fam, fam->data(), fam->size() * sizeof(FamilyDesc));
   HIPCHK(c, hipMemcpyAsync(c->arena, S.h, total, hipMemcpyHostToDevice, c->stream));
@@ -648,7 +663,7 @@ mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
   return MRB_OK;
 }
 
-Topo topo(const mrb_ctx* c) { return Topo{(const TopoHeader*)c->arena}; }
+Topo topo(const mrb_ctx* c) { return Topo{c->arena, c->arena_hdr}; }
 
 // ---- memo of topology transitions (small forests) ----------------------------------
 constexpr size_t kMemoMaxLeaves = 1024;
@@ -694,6 +709,7 @@ void memo_apply(mrb_ctx* c, mrb_ctx::Memo& e) {
   c->free_slots.resize(c->free_slots.size() - e.pop);
   c->free_slots.insert(c->free_slots.end(), e.pushed.begin(), e.pushed.end());
   c->arena = e.arena;
+  c->arena_hdr = e.hdr;
   c->arena_bytes = e.arena_bytes;
   e.last_use = ++c->memo_clock;
   ++c->memo_hits;
@@ -719,6 +735,7 @@ mrb_status memo_record(mrb_ctx* c, int kind, std::vector<int>& material, size_t 
   }
   if (!e->arena) HIPCHK(c, hipMalloc((void**)&e->arena, c->arena_bytes));
   e->arena_bytes = c->arena_bytes;
+  e->hdr = c->arena_hdr;
   e->kind = kind;
   e->material.swap(material);
   e->last_use = ++c->memo_clock;
@@ -942,7 +959,6 @@ mrb_status do_refine(mrb_ctx* c, const std::vector<int>& par, bool launch, bool 
     pblk[r].nb_begin = (int)pnb.size();
     pnb.insert(pnb.end(), c->hnb.begin() + c->hblk[par[r]].nb_begin,
                c->hnb.begin() + c->hblk[par[r]].nb_begin + c->hblk[par[r]].n_ent);
-    ref[r].pblk = (int)r;
     for (int b = 0; b < 8; ++b) ref[r].child[b] = -1;
     for (int b = 0; b < nch; ++b) {
       const int slot = c->free_slots.back();
@@ -1241,6 +1257,7 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false) {
     std::vector<int> popped(c->free_slots.end() - (long)e->pop, c->free_slots.end());
     const size_t npushed = e->pushed.size();
     char* arena0 = c->arena;
+    const TopoHeader hdr0 = c->arena_hdr;
     const size_t arena_bytes0 = c->arena_bytes;
     const bool ref_zero0 = c->hcount_ref_zero;
     const int nfam = e->nfam;
@@ -1270,6 +1287,7 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false) {
       c->free_slots.resize(c->free_slots.size() - npushed);
       c->free_slots.insert(c->free_slots.end(), popped.begin(), popped.end());
       c->arena = arena0;
+      c->arena_hdr = hdr0;
       c->arena_bytes = arena_bytes0;
       c->hcount_ref_zero = ref_zero0;
       c->n_fam -= nfam;
@@ -1328,9 +1346,10 @@ mrb_status step_graph(mrb_ctx* c, double t, double dt) {
   const int ns = pick_nsub(c);
   const int nsm = pick_aux(c, (long)c->hblk.size(), c->nsub_mr);
   const int nsr = pick_aux(c, (long)std::max(1, c->pending_ref) << c->cfg.dim, c->nsub_ref);
-  const uint64_t key[6] = {(uint64_t)(uintptr_t)c->u, (uint64_t)ns | ((uint64_t)c->order << 8), (uint64_t)nsm,
-                           (uint64_t)nsr, dtb,
-                           (uint64_t)(uintptr_t)c->arena};
+  // the launches take the topology header by value: a replay needs the same header
+  uint64_t key[6 + sizeof(TopoHeader) / 8] = {(uint64_t)(uintptr_t)c->u, (uint64_t)ns | ((uint64_t)c->order << 8),
+                                              (uint64_t)nsm, (uint64_t)nsr, dtb, (uint64_t)(uintptr_t)c->arena};
+  std::memcpy(key + 6, &c->arena_hdr, sizeof(TopoHeader));
   hipGraphExec_t exec = nullptr;
   for (auto& g : c->graphs)
     if (std::memcmp(g.key, key, sizeof key) == 0) exec = g.exec;
