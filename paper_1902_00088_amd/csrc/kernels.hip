@@ -881,22 +881,25 @@ __global__ void __launch_bounds__(256) k_rhs_plain(StageArgs A) {
   }
 }
 
-// child nodes of one parity class (see k_refine)
-template <int DIM, int BS, int S, int H, int NF>
+// child nodes of one parity class (see k_refine).  fm[a][i]: finer entries whose region
+// holds fine coordinate Q = cb + q0 + i along axis a (null when the parent has no finer
+// neighbour); the first such entry in list order supplies a node they hold.
+template <int DIM, int BS, int S, int H, int NF, int SQ>
 struct RefineBody {
   using G = Geo<DIM, BS, S, H>;
   const double* tile;
   const NbEntry* ent;
+  const unsigned long long (*fm)[SQ];
   const int* q0;
   const int* qn;
   const int* r0;
   const int* cb;
-  int n_ent;
   size_t cbase;
   double* u;
-  __device__ __forceinline__ RefineBody(const double* t_, const NbEntry* e_, const int* q0_, const int* qn_,
-                                 const int* r0_, const int* cb_, int ne, size_t cb0, double* u_)
-      : tile(t_), ent(e_), q0(q0_), qn(qn_), r0(r0_), cb(cb_), n_ent(ne), cbase(cb0), u(u_) {}
+  __device__ __forceinline__ RefineBody(const double* t_, const NbEntry* e_, const unsigned long long (*fm_)[SQ],
+                                        const int* q0_, const int* qn_, const int* r0_, const int* cb_, size_t cb0,
+                                        double* u_)
+      : tile(t_), ent(e_), fm(fm_), q0(q0_), qn(qn_), r0(r0_), cb(cb_), cbase(cb0), u(u_) {}
   template <int NX, int NY, int NZ>
   __device__ __forceinline__ void go(int cls) {
     ParityClass<DIM> pc(cls, q0, qn);
@@ -912,26 +915,20 @@ struct RefineBody {
         Q[a] = qq[a] + cb[a];
         if (Q[a] == 0 || Q[a] == 2 * (BS - 1)) bnd = true;
       }
-      int src_slot = -1, sidx = 0;
-      if (cls != 0 && bnd) {
-        for (int e = 0; e < n_ent && src_slot < 0; ++e) {
-          const NbEntry& E = ent[e];
-          if (E.dl <= 0) continue;
-          bool in = true;
+      if (cls != 0 && bnd && fm) {
+        unsigned long long cand = ~0ull;
+        for (int a = 0; a < DIM; ++a) cand &= fm[a][qq[a] - q0[a]];
+        if (cand) {
+          const NbEntry& E = ent[__ffsll((long long)cand) - 1];
           int s = 0, mul = 1;
           for (int a = 0; a < DIM; ++a) {
-            const int l = Q[a] - 2 * E.o[a];
-            if (l < 0 || l > BS - 1) in = false;
-            s += l * mul;
+            s += (Q[a] - 2 * E.o[a]) * mul;
             mul *= BS;
           }
-          if (in) { src_slot = E.slot; sidx = s; }
-        }
-      }
-      if (src_slot >= 0) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) u[cbase + (size_t)f * NP + q] = u[((size_t)src_slot * NF + f) * NP + sidx];
-        continue;
+          for (int f = 0; f < NF; ++f) u[cbase + (size_t)f * NP + q] = u[((size_t)E.slot * NF + f) * NP + s];
+          continue;
+        }
       }
       // parent coordinate -> region-local -> tile coordinate
       const int bb[3] = {NX == 4 ? (Q[0] - 3) / 2 - r0[0] + H : Q[0] / 2 - r0[0] + H,
@@ -1097,6 +1094,7 @@ __global__ void __launch_bounds__(256) k_refine(RefineArgs A) {
   constexpr int NSUBT = Pow<DIM, NSUB>::v;
   __shared__ GState<DIM, S + 2 * H> g;
   __shared__ SEnt se[kMaxEnt];
+  __shared__ unsigned long long fm[DIM][SQ];
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
   double* carr = tile + NF * SG::TSZ;
@@ -1128,10 +1126,26 @@ __global__ void __launch_bounds__(256) k_refine(RefineArgs A) {
     const size_t cbase = (size_t)R.child[ch] * NF * NP;
     int cb[3] = {0, 0, 0};
     for (int a = 0; a < DIM; ++a) cb[a] = ((ch >> a) & 1) * (BS - 1);
+    // finer entries come last in the list: the lookup table is needed only if the last
+    // entry is finer (a uniform branch)
+    const bool has_fine = d.n_ent > 0 && g.ent[d.n_ent - 1].dl > 0;
+    if (has_fine) {
+      for (int k = threadIdx.x; k < DIM * SQ; k += blockDim.x) {
+        const int a = k / SQ, i = k % SQ;
+        const int Q = cb[a] + q0[a] + i;
+        unsigned long long mm = 0;
+        for (int e = 0; e < d.n_ent; ++e) {
+          const int l = Q - 2 * g.ent[e].o[a];
+          if (g.ent[e].dl > 0 && l >= 0 && l <= BS - 1) mm |= 1ull << e;
+        }
+        fm[a][i] = mm;
+      }
+      __syncthreads();
+    }
     // one parity class of child nodes at a time (fine parity = parity of q, since
     // bs-1 is even): even nodes copy the parent, odd ones are predicted, and nodes on
     // the parent's boundary held by a finer neighbour take that neighbour's value
-    RefineBody<DIM, BS, S, HWR, NF> rf(tile, g.ent, q0, qn, r0, cb, d.n_ent, cbase, A.u);
+    RefineBody<DIM, BS, S, HWR, NF, SQ> rf(tile, g.ent, has_fine ? fm : nullptr, q0, qn, r0, cb, cbase, A.u);
     rf.template go<1, 1, 1>(0);
     for_odd_classes<DIM>(rf);
     __syncthreads();
