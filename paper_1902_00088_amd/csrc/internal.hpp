@@ -54,7 +54,9 @@ struct TopoHeader {
   int n_pblk;     // parents (refinement); parent r belongs to refinement r
   int off_blk, off_nb, off_list, off_pblk, off_pnb, off_ref, off_fam;
   int nb_stride, pnb_stride;
-  int pad[3];
+  int off_smap;   // coarsening uploads: per block of the grid before, mother slot * 8 +
+                  // child index or -1 (read by a later analysis that speculates it); 0: none
+  int pad[2];
 };
 static_assert(sizeof(TopoHeader) == 64, "the header is 64 bytes (graph keys hold it as 8 words)");
 
@@ -123,6 +125,8 @@ struct MrArgs {
   unsigned long long* acc;// [max_blocks][nf] partial maxima (bit patterns), zero between passes
   int* done;              // [max_blocks] sub-tiles finished, zero between passes
   double thr[4];
+  const int* smap;        // [n] speculated coarsening whose mothers the pass writes:
+                          // mother slot * 8 + child index of block b, or -1; null: none
 };
 
 struct RefineArgs {

@@ -1008,6 +1008,8 @@ __global__ void __launch_bounds__(256) k_mr(MrArgs A) {
     const int w = it.w;
     const int b = w / NSUBT;
     const BlockDesc d = A.topo.blk()[b];
+    // speculated coarsening: mother slot * 8 + child index of the block, or -1
+    const int sm = A.smap ? A.smap[b] : -1;
     int r0[3], cnt[3];
     subregion<DIM>(w % NSUBT, NSUB, S, BS, r0, cnt);
     gsetup<DIM, BS, S, H>(g, d, A.topo.nb(b), A.topo.h.nb_stride, r0);
@@ -1073,6 +1075,39 @@ __global__ void __launch_bounds__(256) k_mr(MrArgs A) {
           if (!(v[f] < A.thr[f])) coarse = false;
         }
         A.flags[b] = coarse ? (int8_t)-1 : (int8_t)0;
+      }
+    }
+    if (sm >= 0) {
+      // the block is child `ch` of a speculated family: write the mother's nodes it
+      // supplies (R keeps every second node; a node shared by several children comes
+      // from the lowest child index), with the values the block holds after the
+      // write-back above -- the coarsening kernel's result, without its launch
+      const int ch = sm & 7;
+      const size_t mbase = (size_t)(sm >> 3) * NF * NP;
+      ParityClass<DIM> pc(0, r0, cnt);
+      for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
+        int t[3];
+        pc.coords(p, t);
+        bool skip = false, bnd = false;
+        unsigned long long cand = ~0ull;
+        int node = 0, mnode = 0, mul = 1;
+        for (int a = 0; a < DIM; ++a) {
+          const int bit = (ch >> a) & 1;
+          if (bit && t[a] == 0) skip = true;
+          if (t[a] == 0 || t[a] == BS - 1) bnd = true;
+          cand &= g.m[a][t[a] - r0[a] + H];
+          node += t[a] * mul;
+          mnode += (t[a] / 2 + bit * (BS - 1) / 2) * mul;
+          mul *= BS;
+        }
+        if (skip) continue;
+        // interior nodes and nodes written back above: the tile; others: the block's own
+        // stored value (a boundary node the tile took from a neighbour)
+        const bool from_tile = !bnd || g.ent[63 - __clzll((long long)cand)].dl > 0;
+        const int ti = SG::idx(t[0] - r0[0], t[1] - r0[1], DIM > 2 ? t[2] - r0[2] : 0);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          A.u[mbase + (size_t)f * NP + mnode] = from_tile ? tile[f * TSZ + ti] : A.u[base + (size_t)f * NP + node];
       }
     }
     __syncthreads();

@@ -230,6 +230,7 @@ struct mrb_ctx {
     char* arena = nullptr;
     TopoHeader hdr{};
     size_t arena_bytes = 0;
+    const int* smap = nullptr;          // coarsenings: the arena's speculation map, or null
   };
   std::vector<Memo> memo;
   long memo_clock = 0, memo_hits = 0;
@@ -587,7 +588,7 @@ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 // (with their entries) or the coarsening families.
 mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
                        const std::vector<NbEntry>* pnb = nullptr, const std::vector<RefineDesc>* ref = nullptr,
-                       const std::vector<FamilyDesc>* fam = nullptr) {
+                       const std::vector<FamilyDesc>* fam = nullptr, const std::vector<int>* smap = nullptr) {
   HostTimer ht(&c->hus_upload);
   TopoHeader h;
   std::memset(&h, 0, sizeof h);
@@ -616,6 +617,7 @@ mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
   h.off_pnb = place(pblk ? pblk->size() * (size_t)h.pnb_stride * sizeof(NbEntry) : 0);
   h.off_ref = place(ref ? ref->size() * sizeof(RefineDesc) : 0);
   h.off_fam = place(fam ? fam->size() * sizeof(FamilyDesc) : 0);
+  h.off_smap = smap ? place(smap->size() * sizeof(int)) : 0;
   const size_t total = off;
   if (total > (size_t)0x7fffffff) return fail(c, MRB_E_CAPACITY, "topology buffer exceeds 2 GiB");
   if (total > c->arena_cap) {
@@ -657,6 +659,7 @@ mrb_status upload_topo(mrb_ctx* c, const std::vector<BlockDesc>* pblk = nullptr,
   if (pblk && pnb) put_entries(h.off_pnb, h.pnb_stride, *pblk, *pnb);
   if (ref) put(h.off_ref, ref->data(), ref->size() * sizeof(RefineDesc));
   if (fam) put(h.off_fam, fam->data(), fam->size() * sizeof(FamilyDesc));
+  if (smap) put(h.off_smap, smap->data(), smap->size() * sizeof(int));
   HIPCHK(c, hipMemcpyAsync(c->arena, S.h, total, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipEventRecord(S.ev, c->stream));
   S.pending = true;
@@ -749,6 +752,7 @@ mrb_status memo_record(mrb_ctx* c, int kind, std::vector<int>& material, size_t 
   e->pending_ref = pending_ref;
   e->nfam = nfam;
   e->npar = npar;
+  e->smap = e->hdr.off_smap ? (const int*)(e->arena + e->hdr.off_smap) : nullptr;
   HIPCHK(c, hipMemcpyAsync(e->arena, c->arena, c->arena_bytes, hipMemcpyDeviceToDevice, c->stream));
   return MRB_OK;
 }
@@ -1016,12 +1020,15 @@ MrArgs mr_args(mrb_ctx* c) {
   a.acc = c->dacc;
   a.done = c->ddone;
   for (int f = 0; f < 4; ++f) a.thr[f] = f < (int)c->thr.size() ? c->thr[f] : 0.0;
+  a.smap = nullptr;
   return a;
 }
 
-mrb_status launch_mr_kernel(mrb_ctx* c, bool fixed_grid) {
+// `spec`: a memoised coarsening of the current grid whose mothers the pass also writes
+mrb_status launch_mr_kernel(mrb_ctx* c, bool fixed_grid, const mrb_ctx::Memo* spec = nullptr) {
   const int n = (int)c->hblk.size();
   MrArgs a = mr_args(c);
+  if (spec) a.smap = spec->smap;
   const int ns = pick_aux(c, n, c->nsub_mr);
   long work = n;
   for (int q = 0; q < c->cfg.dim; ++q) work *= ns;
@@ -1110,12 +1117,13 @@ std::vector<uint64_t> coarsenable(mrb_ctx* c, const int8_t* flags) {
 }
 
 // a memoised coarsening: adopt its forest and plan, launch the coarsening kernel
-mrb_status coarsen_from_memo(mrb_ctx* c, mrb_ctx::Memo& e) {
+// `written`: the analysis pass already wrote the mothers
+mrb_status coarsen_from_memo(mrb_ctx* c, mrb_ctx::Memo& e, bool written = false) {
   memo_apply(c, e);
   c->hcount_ref_zero = true;
   CoarsenArgs a{topo(c), c->u};
   const long total = (long)e.nfam * c->np;
-  {
+  if (!written) {
     TimeScope ts(c, T_COARSEN, (double)total * c->cfg.nfields * 16.0);
     HIPCHK(c, launch_coarsen(c->shape, (int)std::min(4096L, (total + 255) / 256), a, c->stream));
   }
@@ -1153,6 +1161,7 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
   if (c->free_slots.size() < fams.size()) return fail(c, MRB_E_CAPACITY, "coarsen: pool too small");
   std::vector<FamilyDesc> fd(fams.size());
   std::vector<char> gone(c->leaves.size(), 0);
+  std::vector<int> smap(c->leaves.size(), -1);   // per block: mother slot * 8 + child index
   std::vector<Leaf> parents;
   for (size_t i = 0; i < fams.size(); ++i) {
     const uint64_t pk = fams[i];
@@ -1171,6 +1180,7 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
       const int mi = c->index.find(pack_key(l + 1, ch));
       fd[i].child[b] = c->leaves[mi].slot;
       gone[mi] = 1;
+      smap[mi] = P.slot * 8 + b;
     }
     parents.push_back(P);
   }
@@ -1185,7 +1195,7 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
   c->leaves.swap(nl);
   sort_and_index(c);
   mrb_status s = build_descriptors(c);
-  if (!s) s = upload_topo(c, nullptr, nullptr, nullptr, &fd);
+  if (!s) s = upload_topo(c, nullptr, nullptr, nullptr, &fd, material.empty() ? nullptr : &smap);
   if (s) {
     c->leaves.swap(old);
     sort_and_index(c);
@@ -1232,7 +1242,6 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false) {
   mrb_status s;
   int passes = 1;
   c->flag_set = 0;
-  if (!first_launched && (s = launch_mr_kernel(c, false))) return s;
   const size_t n1 = c->leaves.size();
   mrb_ctx::Memo* e = nullptr;
   if (n1 <= kMemoMaxLeaves && c->spec_flags.size() == n1) {
@@ -1241,6 +1250,9 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false) {
     e = memo_find(c, 1, mat);
     if (e && e->nfam == 0) e = nullptr;
   }
+  // a first pass launched here also writes the speculated mothers
+  const bool fused = e && !first_launched && e->smap;
+  if (!first_launched && (s = launch_mr_kernel(c, false, fused ? e : nullptr))) return s;
   if (!e) {
     {
       HostTimer ht(&c->hus_wait);
@@ -1261,7 +1273,7 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false) {
     const size_t arena_bytes0 = c->arena_bytes;
     const bool ref_zero0 = c->hcount_ref_zero;
     const int nfam = e->nfam;
-    if ((s = coarsen_from_memo(c, *e))) return s;
+    if ((s = coarsen_from_memo(c, *e, fused))) return s;
     c->flag_set = 1;
     s = launch_mr_kernel(c, false);
     c->flag_set = 0;
