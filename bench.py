@@ -102,6 +102,11 @@ def run_form(M, W, torch, cfg, steps, warmup, tune=False):
         "kernels": kst,
         "host_us_per_step": host_us,
         "stage_tiles": tiles,
+        "tune_ms": st.get("tune_ms"),
+        "graph_in_use": st.get("graph_in_use"),
+        "memo_hits": st.get("memo_hits"),
+        "spec_hits": st.get("spec_hits"),
+        "spec_misses": st.get("spec_misses"),
     }
 
 

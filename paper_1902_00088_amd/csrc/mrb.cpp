@@ -1812,90 +1812,107 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    float best = 1e30f;
-    int best_v = 0;
     c->tune_log.clear();
     const bool was_timing = c->timing;
     c->timing = false;
-    int best_o = 0;
-    for (int i = 0; i < nv; ++i)
-      for (int o = 0; o < 2; ++o) {   // forest (Morton) order, level-sorted order
-        c->nsub = v[i];
-        c->order = o;
-        mrb_status r = sweep(c, 0.0, dt);  // warm-up
-        if (r) return r;
-        HIPCHK(c, hipEventRecord(e0, c->stream));
-        for (int k = 0; k < reps; ++k)
-          if ((r = sweep(c, 0.0, dt))) return r;
-        HIPCHK(c, hipEventRecord(e1, c->stream));
-        HIPCHK(c, hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-        char buf[64];
-        std::snprintf(buf, sizeof buf, "%s\"%d%s\": %.4f", c->tune_log.empty() ? "" : ", ", v[i], o ? "L" : "",
-                      ms / reps);
-        c->tune_log += buf;
-        if (ms < best) { best = ms; best_v = v[i]; best_o = o; }
-      }
-    c->nsub = best_v;
-    c->order = best_o;
-    // analysis tilings: a pass only synchronises redundant nodes (idempotent) and
-    // rewrites flags and maxima
+    auto done = [&](mrb_status r) {
+      c->have_flags = false;
+      c->timing = was_timing;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return r;
+    };
+    // stage tilings x processing order (forest/Morton, level-sorted); as below, the
+    // fastest of several rounds counts
+    constexpr int kRounds = 5;
+    float best_s[16];
+    for (int i = 0; i < 2 * nv; ++i) best_s[i] = 1e30f;
+    for (int round = 0; round < kRounds; ++round)
+      for (int i = 0; i < nv; ++i)
+        for (int o = 0; o < 2; ++o) {
+          c->nsub = v[i];
+          c->order = o;
+          mrb_status r = sweep(c, 0.0, dt);  // warm-up
+          if (r) return done(r);
+          if (hipEventRecord(e0, c->stream) != hipSuccess) return done(fail(c, MRB_E_DEVICE, "tune: event"));
+          for (int k = 0; k < reps; ++k)
+            if ((r = sweep(c, 0.0, dt))) return done(r);
+          float ms = 0.f;
+          if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return done(fail(c, MRB_E_DEVICE, "tune: event"));
+          best_s[2 * i + o] = std::min(best_s[2 * i + o], ms / reps);
+        }
+    int bs = 0;
+    for (int i = 0; i < 2 * nv; ++i) {
+      char buf[64];
+      std::snprintf(buf, sizeof buf, "%s\"%d%s\": %.4f", i ? ", " : "", v[i / 2], (i & 1) ? "L" : "", best_s[i]);
+      c->tune_log += buf;
+      if (best_s[i] < best_s[bs]) bs = i;
+    }
+    c->nsub = v[bs / 2];
+    c->order = bs & 1;
+    // analysis and refinement tilings: several rounds over the candidates, the fastest
+    // round of each counts (single launches of these kernels are a few microseconds on
+    // small grids, where one round is at the mercy of noise)
     int va[8];
     const int na = aux_variants(c->shape, 0, va, 8);
-    float best_a = 1e30f;
-    int best_va = 0;
-    c->tune_log += ", \"mr\": {";
-    for (int i = 0; i < na; ++i) {
-      c->nsub_mr = va[i];
+    auto time_variants = [&](const char* name, int* choice, auto&& run) -> mrb_status {
+      float best_v[8];
+      for (int i = 0; i < na; ++i) best_v[i] = 1e30f;
+      for (int round = 0; round < kRounds; ++round)
+        for (int i = 0; i < na; ++i) {
+          *choice = va[i];
+          mrb_status r = run(va[i], 1);  // warm-up (also loads the variant)
+          if (r) return r;
+          if (hipEventRecord(e0, c->stream) != hipSuccess) return fail(c, MRB_E_DEVICE, "tune: event");
+          if ((r = run(va[i], reps))) return r;
+          float ms = 0.f;
+          if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return fail(c, MRB_E_DEVICE, "tune: event");
+          best_v[i] = std::min(best_v[i], ms / reps);
+        }
+      int bi = 0;
+      c->tune_log += std::string(", \"") + name + "\": {";
+      for (int i = 0; i < na; ++i) {
+        char buf[64];
+        std::snprintf(buf, sizeof buf, "%s\"%d\": %.4f", i ? ", " : "", va[i], best_v[i]);
+        c->tune_log += buf;
+        if (best_v[i] < best_v[bi]) bi = i;
+      }
+      c->tune_log += "}";
+      *choice = va[bi];
+      return MRB_OK;
+    };
+    // an analysis pass only synchronises redundant nodes (idempotent) and rewrites
+    // flags and maxima
+    {
       mrb_status r = do_mr_pass(c);
-      if (r && r != MRB_E_NONFINITE) return r;
-      HIPCHK(c, hipEventRecord(e0, c->stream));
+      if (r && r != MRB_E_NONFINITE) return done(r);
+    }
+    mrb_status tr = time_variants("mr", &c->nsub_mr, [&](int v, int k) -> mrb_status {
       MrArgs a = mr_args(c);
       const int n = (int)c->hblk.size();
       long work = n;
-      for (int q = 0; q < c->cfg.dim; ++q) work *= va[i];
-      for (int k = 0; k < reps; ++k) HIPCHK(c, launch_mr(c->shape, va[i], grid_for(c, work), a, c->stream));
-      HIPCHK(c, hipEventRecord(e1, c->stream));
-      HIPCHK(c, hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-      char buf[64];
-      std::snprintf(buf, sizeof buf, "%s\"%d\": %.4f", i ? ", " : "", va[i], ms / reps);
-      c->tune_log += buf;
-      if (ms < best_a) { best_a = ms; best_va = va[i]; }
-    }
-    c->tune_log += "}";
-    c->nsub_mr = best_va;
-    // refinement tilings, while the last refinement plan is still the uploaded one:
-    // re-running it rewrites the same children from the untouched parents
+      for (int q = 0; q < c->cfg.dim; ++q) work *= v;
+      for (int j = 0; j < k; ++j) HIPCHK(c, launch_mr(c->shape, v, grid_for(c, work), a, c->stream));
+      return MRB_OK;
+    });
+    if (tr) return done(tr);
+    // refinement, while the last refinement plan is still the uploaded one: re-running
+    // it rewrites the same children from the untouched parents
     if (c->pending_ref > 0) {
-      float best_r = 1e30f;
-      int best_vr = 0;
-      c->tune_log += ", \"refine\": {";
-      for (int i = 0; i < na; ++i) {
-        c->nsub_ref = va[i];
-        mrb_status r = launch_refine_kernel(c, c->pending_ref, false);  // warm-up
-        if (r) return r;
-        HIPCHK(c, hipEventRecord(e0, c->stream));
-        for (int k = 0; k < reps; ++k)
-          if ((r = launch_refine_kernel(c, c->pending_ref, false))) return r;
-        HIPCHK(c, hipEventRecord(e1, c->stream));
-        HIPCHK(c, hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-        char buf[64];
-        std::snprintf(buf, sizeof buf, "%s\"%d\": %.4f", i ? ", " : "", va[i], ms / reps);
-        c->tune_log += buf;
-        if (ms < best_r) { best_r = ms; best_vr = va[i]; }
-      }
-      c->tune_log += "}";
-      c->nsub_ref = best_vr;
+      tr = time_variants("refine", &c->nsub_ref, [&](int, int k) -> mrb_status {
+        for (int j = 0; j < k; ++j) {
+          mrb_status r = launch_refine_kernel(c, c->pending_ref, false);
+          if (r) return r;
+        }
+        return MRB_OK;
+      });
+      if (tr) return done(tr);
     }
-    c->have_flags = false;
-    c->timing = was_timing;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    (void)done(MRB_OK);
   } else {
     c->nsub = 0;
     c->nsub_mr = -1;
