@@ -158,19 +158,34 @@ mrb_status mrb_timing(mrb_ctx *ctx, int enable);
  * current forest and keeps the fastest pair, then does the
  * same for the analysis kernel (one pass; flags are recomputed) and, if the last
  * refinement plan is still the uploaded one (right after mrb_refine_all), for the
- * refinement kernel (re-run on the same parents); nsub = 0 with reps = 0 returns to
- * the built-in choices.  *chosen (may be NULL) receives the stage tiling in use.
+ * refinement kernel (re-run on the same parents); on the chosen stage tiling it also
+ * times the whole sweep as four launches against one launch with grid barriers (see
+ * mrb_set_sweep).  Every candidate is timed over five rounds and its fastest round
+ * counts.  nsub = 0 with reps = 0 returns to the built-in choices.  *chosen (may be
+ * NULL) receives the stage tiling in use.
  * Not a step of the method: a schedule choice. */
 mrb_status mrb_tune(mrb_ctx *ctx, int nsub, int reps, double dt, int *chosen);
 /* Graph replay in mrb_step: the refinement, the four RK stages and the first analysis
- * of a step are captured once into a HIP graph and replayed; the kernels read block
- * counts and descriptors from device memory, so the graph stays valid when the forest
- * changes.  enable: 0 off, 1 on, 2 automatic (default: the first steps alternate
+ * of a step are captured into a HIP graph and replayed.  The kernels take the
+ * topology header (block counts, buffer offsets) as a launch argument and read
+ * descriptors from device memory, so a graph is captured per header and replayed
+ * whenever the same header recurs (the last four are kept).  Graph-captured sweeps
+ * always use four stage launches.  enable: 0 off, 1 on, 2 automatic (default: the first steps alternate
  * between graph replay and direct launches, ten each, and the faster median step wall
  * time decides).  Used only for the fused form, with kernel timing off, a non-default
  * stream and a time-independent right-hand side.  Results are identical either way.
  * MRB_E_ARG for other values. */
 mrb_status mrb_set_graph(mrb_ctx *ctx, int enable);
+/* How the fused form launches the four stages of an RK4 step (Sec. 4 batching: every
+ * block of every level in each launch).  mode 0: four launches, one per stage.  mode
+ * 1: one cooperative launch (one workgroup per compute unit, each taking several
+ * blocks per stage), with a grid-wide barrier between stages (bounded waits: a wait that times out makes the
+ * next read-back fail with MRB_E_DEVICE and voids the step).  mode 2 (default): the
+ * autotuner (mrb_tune with reps > 0) times both on the tuned tiling and keeps the
+ * faster; four launches until then.  Results are identical in every mode.  MRB_E_ARG
+ * for other values; mode 1 on the plain form is accepted and ignored (it has no
+ * fused stages). */
+mrb_status mrb_set_sweep(mrb_ctx *ctx, int mode);
 
 /* ---------------------------------------------------------------------------
  * Learned refinement predictor.  The paper's refinement flag admits "+1 for

@@ -28,7 +28,7 @@ STATUS = {0: "MRB_OK", -1: "MRB_E_ARG", -2: "MRB_E_CAPACITY", -3: "MRB_E_TOPOLOG
 EXPORTS = ("mrb_create", "mrb_destroy", "mrb_last_error", "mrb_init_forest", "mrb_load_blocks",
            "mrb_refine_all", "mrb_rk4", "mrb_mr_pass", "mrb_coarsen", "mrb_adapt", "mrb_step",
            "mrb_num_blocks", "mrb_read_forest", "mrb_read_blocks", "mrb_get_flags", "mrb_stats",
-           "mrb_timing", "mrb_tune", "mrb_set_graph", "mrb_mlp_init", "mrb_mlp_get_params", "mrb_mlp_features",
+           "mrb_timing", "mrb_tune", "mrb_set_graph", "mrb_set_sweep", "mrb_mlp_init", "mrb_mlp_get_params", "mrb_mlp_features",
            "mrb_mlp_forward", "mrb_mlp_grad", "mrb_mlp_train", "mrb_mlp_predict", "mrb_refine_marked",
            "mrb_step_predicted", "mrb_horizon_labels", "mrb_read_uniform")
 
@@ -88,6 +88,7 @@ def lib():
             "mrb_timing": [_vp, ctypes.c_int],
             "mrb_tune": [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int)],
             "mrb_set_graph": [_vp, ctypes.c_int],
+            "mrb_set_sweep": [_vp, ctypes.c_int],
             "mrb_mlp_init": [_vp, ctypes.c_int, _fp, _fp, _fp],
             "mrb_mlp_get_params": [_vp, _fp],
             "mrb_mlp_features": [_vp, _fp],
@@ -274,6 +275,11 @@ class Solver:
         """Graph replay in step(): False/0 off, True/1 on, 2 automatic (the default)."""
         m = int(mode) if not isinstance(mode, bool) else (1 if mode else 0)
         self._chk(lib().mrb_set_graph(self.h, m))
+
+    def set_sweep(self, mode):
+        """Stage launches of the fused form: 0 four launches, 1 one launch with grid
+        barriers, 2 the autotuner's choice (default)."""
+        self._chk(lib().mrb_set_sweep(self.h, int(mode)))
 
     def timing(self, enable: bool):
         self._chk(lib().mrb_timing(self.h, 1 if enable else 0))

@@ -117,6 +117,18 @@ struct StageArgs {
   double* ghost;          // plain form: ghosted stage values [slot][f][(bs+2hw)^dim]
 };
 
+// Whole-sweep launch: the four stages in one kernel with grid barriers between them.
+constexpr int kBarStride = 32;   // barrier words 128 bytes apart: 8 group counts, the top count, the generation
+constexpr int kBarWords = 10 * kBarStride;
+struct SweepArgs {
+  StageArgs a;            // stage-independent fields (k1..k3, u, unew, h6, topology, physics)
+  double alpha[4];        // y_s = u + alpha_s k_{s-1}
+  double cfac[4];         // swirl time factor per stage
+  unsigned* bar;          // [kBarWords] device words, counts zero between launches
+  int* err;               // set to 1 when a barrier wait times out
+  unsigned spin;          // polls before a barrier wait gives up
+};
+
 struct MrArgs {
   Topo topo;
   double* u;              // read; redundant nodes owned by finer blocks are written back
@@ -157,6 +169,11 @@ struct Variant {
 
 // Launchers (kernels.hip).  grid = number of workgroups (grid-stride loops inside).
 hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, const StageArgs& a, hipStream_t st);
+// Whole-sweep kernel, cooperative launch of at most one workgroup per compute unit
+// (and at most `max_grid`); *grid_out gets the count.  hipErrorInvalidValue if the
+// variant is not compiled.
+hipError_t launch_sweep(const Shape& s, int precision, Variant v, int max_grid, const SweepArgs& a, hipStream_t st,
+                        int* grid_out);
 hipError_t launch_plain(const Shape& s, int grid, const StageArgs& a, hipStream_t st);  // ghost + RHS kernels
 hipError_t launch_mr(const Shape& s, int nsub, int grid, const MrArgs& a, hipStream_t st);
 hipError_t launch_refine(const Shape& s, int nsub, int grid, const RefineArgs& a, hipStream_t st);

@@ -19,6 +19,7 @@
 #include "internal.hpp"
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 namespace mrb {
 
@@ -570,7 +571,7 @@ __device__ __forceinline__ void subregion(int sub, int nsub, int S, int BS, int*
 // ---------------------------------------------------------------------------
 template <int DIM, int BS, int S, int H, typename TT>
 __device__ __forceinline__ TT rhs_adv(const TT* T, const int* i, const int* t, const BlockDesc& d, TT r,
-                                      const StageArgs& A, const double* sw, const int* l) {
+                                      const StageArgs& A, double cfac, const double* sw, const int* l) {
   using G = Geo<DIM, BS, S, H>;
   const int x = i[0], y = i[1], z = i[2];
   const TT dx = D4(T[G::idx(x - 2, y, z)], T[G::idx(x - 1, y, z)], T[G::idx(x + 1, y, z)], T[G::idx(x + 2, y, z)], r);
@@ -605,8 +606,8 @@ __device__ __forceinline__ TT rhs_adv(const TT* T, const int* i, const int* t, c
     s2y = A.ph.s2[gy];
     sy = A.ph.s[gy];
   }
-  const double U = (s2x * sy) * A.cfac;
-  const double W = -((s2y * sx) * A.cfac);
+  const double U = (s2x * sy) * cfac;
+  const double W = -((s2y * sx) * cfac);
   return -(((TT)U * dx) + ((TT)W * dy));
 }
 
@@ -714,10 +715,30 @@ __device__ __forceinline__ void ns_rhs(const double* T, const CT* W, int ux0, in
 }
 
 // ---------------------------------------------------------------------------
-// fused stage kernel: gather y_s, predict missing ghosts, RHS, store
+// fused stage: gather y_s, predict missing ghosts, RHS, store -- one pass over the
+// work items of this workgroup; run by the per-stage kernel and by the whole-sweep one
 // ---------------------------------------------------------------------------
+// what changes from one stage to the next
+struct StageVar {
+  int stage;              // 1..4
+  double alpha;           // y_s = u + alpha k_{s-1}
+  const void* kprev;
+  void* kout;
+  double cfac;            // swirl time factor
+};
+
+// static LDS of a stage pass
+template <int DIM, int BS, int HW, int NF, int NSUB>
+struct StageShared {
+  static constexpr int S = (BS + NSUB - 1) / NSUB, H = HW + 3;
+  GState<DIM, S + 2 * H> g;
+  SEnt se[kMaxEnt];
+  double swirl[DIM == 2 && NF == 1 ? 4 * S : 1];
+};
+
 template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
-__global__ void __launch_bounds__(256) k_stage(StageArgs A) {
+__device__ __forceinline__ void stage_pass(const StageArgs& A, const StageVar& V,
+                                           StageShared<DIM, BS, HW, NF, NSUB>& sh, char* smem) {
   constexpr int S = (BS + NSUB - 1) / NSUB, H = HW + 3;
   // rows per lane and gather round: a 3D tile needs ~5 rounds of 8; its occupancy is
   // bound by LDS (3 workgroups per CU), so 10 loads in flight per lane cost nothing
@@ -728,10 +749,9 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs A) {
   constexpr int NSUBT = Pow<DIM, NSUB>::v;
   constexpr bool NS = NF == 4;
   static_assert(SG::TSZ == G::TSZ, "tile geometry");
-  __shared__ GState<DIM, S + 2 * H> g;
-  __shared__ SEnt se[kMaxEnt];
-  __shared__ double swirl[DIM == 2 && NF == 1 ? 4 * S : 1];
-  extern __shared__ __align__(16) char smem[];
+  auto& g = sh.g;
+  auto& se = sh.se;
+  auto& swirl = sh.swirl;
   TT* tile = reinterpret_cast<TT*>(smem);
   TT* carr = tile + NF * TSZ;
   CT* W = reinterpret_cast<CT*>(carr + NF * SG::CSZ);  // NS stresses / fluxes
@@ -749,12 +769,12 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs A) {
     if (sw_lds) load_swirl<BS, S>(swirl, d, r0, cnt, A);
     __syncthreads();
     const bool hasc = d.n_coarse > 0;
-    if (A.stage == 1) {
+    if (V.stage == 1) {
       YSrc<TT, KT, false> src{A.u, nullptr, 0.0, A.off};
       if (hasc) sgather<DIM, BS, S, HW, NF, true, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
       else sgather<DIM, BS, S, HW, NF, false, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
     } else {
-      YSrc<TT, KT, true> src{A.u, (const KT*)A.kprev, A.alpha, A.off};
+      YSrc<TT, KT, true> src{A.u, (const KT*)V.kprev, V.alpha, A.off};
       if (hasc) sgather<DIM, BS, S, HW, NF, true, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
       else sgather<DIM, BS, S, HW, NF, false, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
     }
@@ -782,8 +802,8 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs A) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const size_t q = base + (size_t)f * NP + node;
-          if (A.stage < 4) {
-            ((KT*)A.kout)[q] = (KT)kv[f];
+          if (V.stage < 4) {
+            ((KT*)V.kout)[q] = (KT)kv[f];
           } else {
             const double k1 = (double)((const KT*)A.k1)[q], k2 = (double)((const KT*)A.k2)[q];
             const double k3 = (double)((const KT*)A.k3)[q], k4 = (double)kv[f];
@@ -801,10 +821,10 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs A) {
         int l[3] = {lx, ly, lz};
         int t[3] = {r0[0] + l[0], r0[1] + l[1], r0[2] + l[2]};
         int i[3] = {l[0] + HW, l[1] + HW, DIM > 2 ? l[2] + HW : 0};
-        const TT kv = rhs_adv<DIM, BS, S, HW, TT>(tile, i, t, d, r, A, sw_lds ? swirl : nullptr, l);
+        const TT kv = rhs_adv<DIM, BS, S, HW, TT>(tile, i, t, d, r, A, V.cfac, sw_lds ? swirl : nullptr, l);
         const size_t q = base + t[0] + BS * t[1] + (DIM > 2 ? BS * BS * t[2] : 0);
-        if (A.stage < 4) {
-          ((KT*)A.kout)[q] = (KT)kv;
+        if (V.stage < 4) {
+          ((KT*)V.kout)[q] = (KT)kv;
         } else {
           const double k1 = (double)((const KT*)A.k1)[q], k2 = (double)((const KT*)A.k2)[q];
           const double k3 = (double)((const KT*)A.k3)[q], k4 = (double)kv;
@@ -813,6 +833,68 @@ __global__ void __launch_bounds__(256) k_stage(StageArgs A) {
       }
     }
     __syncthreads();
+  }
+}
+
+template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
+__global__ void __launch_bounds__(256) k_stage(StageArgs A) {
+  __shared__ StageShared<DIM, BS, HW, NF, NSUB> sh;
+  extern __shared__ __align__(16) char smem[];
+  stage_pass<DIM, BS, HW, NF, NSUB, TT, KT, CT>(A, StageVar{A.stage, A.alpha, A.kprev, A.kout, A.cfac}, sh, smem);
+}
+
+// Grid-wide barrier of the whole-sweep kernel (all workgroups resident: cooperative
+// launch).  Arrivals are counted on 8 words (workgroup index mod 8), the last of each
+// group counts on a ninth, and the last of those advances the generation word every
+// workgroup waits on.  Each arrival releases the workgroup's stores (the last arrival
+// of a group acquires them and releases them on with its own count), and one acquire
+// fence after the wait makes them visible to the workgroup's next loads; the polls
+// themselves are relaxed (an acquiring poll would invalidate the caches each time).
+// The wait is bounded: past `spin` polls the workgroup records a time-out and the
+// kernel ends (results then void).
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, int* err, unsigned spin) {
+  __shared__ int ok_sh;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    unsigned* gen = bar + 9 * kBarStride;
+    const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned* grp = bar + (blockIdx.x & 7) * kBarStride;
+    if (__hip_atomic_fetch_add(grp, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == (gridDim.x >> 3) - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the group's stores, passed on below
+      __hip_atomic_store(grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned* top = bar + 8 * kBarStride;
+      if (__hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 7u) {
+        __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    for (unsigned n = 0; __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0; ++n) {
+      if (n >= spin) {
+        ok = 0;
+        atomicExch(err, 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ok_sh = ok;
+  }
+  __syncthreads();
+  return ok_sh != 0;
+}
+
+// the four stages of an RK4 step in one launch, a grid barrier between stages
+template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
+__global__ void __launch_bounds__(256) k_sweep(SweepArgs S) {
+  __shared__ StageShared<DIM, BS, HW, NF, NSUB> sh;
+  extern __shared__ __align__(16) char smem[];
+  const void* ks[3] = {S.a.k1, S.a.k2, S.a.k3};
+  for (int s = 1; s <= 4; ++s) {
+    const StageVar V{s, S.alpha[s - 1], s > 1 ? ks[s - 2] : nullptr, s < 4 ? const_cast<void*>(ks[s - 1]) : nullptr,
+                     S.cfac[s - 1]};
+    stage_pass<DIM, BS, HW, NF, NSUB, TT, KT, CT>(S.a, V, sh, smem);
+    if (s < 4 && !grid_barrier(S.bar, S.err, S.spin)) return;
   }
 }
 
@@ -867,7 +949,7 @@ __global__ void __launch_bounds__(256) k_rhs_plain(StageArgs A) {
     for (int p = threadIdx.x; p < NP; p += blockDim.x) {
       int t[3] = {p % BS, (p / BS) % BS, DIM > 2 ? p / (BS * BS) : 0};
       int i[3] = {t[0] + HW, t[1] + HW, DIM > 2 ? t[2] + HW : 0};
-      const double kv = rhs_adv<DIM, BS, BS, HW, double>(T, i, t, d, r, A, nullptr, t);
+      const double kv = rhs_adv<DIM, BS, BS, HW, double>(T, i, t, d, r, A, A.cfac, nullptr, t);
       if (A.stage < 4) {
         ((double*)A.kout)[base + p] = kv;
       } else {
@@ -1289,6 +1371,41 @@ static hipError_t stage_go(int grid, const StageArgs& a, hipStream_t st) {
   return go(k_stage<DIM, BS, HW, NF, NSUB, TT, KT, CT>, grid, lds, st, a);
 }
 
+// whole sweep: the grid is what the device holds at once (all workgroups must be
+// resident for the grid barrier), capped by the work; a multiple of 8 (XcdWork and
+// the barrier's 8 arrival groups)
+template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
+static hipError_t sweep_go(int max_grid, const SweepArgs& a, hipStream_t st, int* grid_out) {
+  constexpr int S = (BS + NSUB - 1) / NSUB;
+  using SG = SGeo<DIM, BS, S, HW>;
+  size_t lds = sizeof(TT) * NF * (SG::TSZ + SG::CSZ);
+  if (NF == 4) lds += sizeof(CT) * 5 * (S + 4) * (S + 4);
+  auto kern = k_sweep<DIM, BS, HW, NF, NSUB, TT, KT, CT>;
+  static int resident = 0, cus = 0;   // per instantiation (one device per process)
+  if (!resident) {
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    int dev = 0, per_cu = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, 256, lds);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    resident = per_cu * ncu;
+    cus = ncu;
+  }
+  // at most one workgroup per compute unit: each barrier costs a release and an
+  // acquire per workgroup, so fewer, busier workgroups pay less for it
+  int grid = std::min(std::min(resident, cus), std::max(max_grid, 8));
+  grid &= ~7;
+  if (grid < 8) return hipErrorInvalidConfiguration;
+  *grid_out = grid;
+  SweepArgs arg = a;
+  void* params[] = {&arg};
+  return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(256), params, (unsigned)lds, st);
+}
+
 // FP64: FP64 tile, slopes and arithmetic.  Mixed: FP32 slopes and arithmetic; the
 // tile is FP32 (stage values minus a per-field offset) for advection and FP64 for
 // Navier-Stokes (neighbour differences formed in FP64, see ns_fluxes).
@@ -1297,6 +1414,13 @@ static hipError_t stage_pick(int grid, const StageArgs& a, hipStream_t st) {
   if constexpr (P == 0) return stage_go<D, B, W, F, NS, double, double, double>(grid, a, st);
   else if constexpr (F == 4) return stage_go<D, B, W, F, NS, double, float, float>(grid, a, st);
   else return stage_go<D, B, W, F, NS, float, float, float>(grid, a, st);
+}
+
+template <int D, int B, int W, int F, int NS, int P>
+static hipError_t sweep_pick(int max_grid, const SweepArgs& a, hipStream_t st, int* grid_out) {
+  if constexpr (P == 0) return sweep_go<D, B, W, F, NS, double, double, double>(max_grid, a, st, grid_out);
+  else if constexpr (F == 4) return sweep_go<D, B, W, F, NS, double, float, float>(max_grid, a, st, grid_out);
+  else return sweep_go<D, B, W, F, NS, float, float, float>(max_grid, a, st, grid_out);
 }
 
 // compiled stage variants: shape, precision (0 FP64, 1 mixed), sub-tiles per axis
@@ -1346,6 +1470,16 @@ hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, cons
 #define X(D, B, W, F, P, NS)                                                                     \
   if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && precision == P && v.nsub == NS)      \
     return stage_pick<D, B, W, F, NS, P>(grid, a, st);
+  MRB_STAGE_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep(const Shape& s, int precision, Variant v, int max_grid, const SweepArgs& a, hipStream_t st,
+                        int* grid_out) {
+#define X(D, B, W, F, P, NS)                                                                     \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && precision == P && v.nsub == NS)      \
+    return sweep_pick<D, B, W, F, NS, P>(max_grid, a, st, grid_out);
   MRB_STAGE_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;

@@ -251,6 +251,12 @@ struct mrb_ctx {
   double* h_maxd = nullptr;    // pinned, mapped
   // a second mapped set, written by the speculative second analysis of an adapt
   int8_t *h_flags2 = nullptr, *dflags2 = nullptr;
+  // whole-sweep launches: barrier words (device) and the time-out word (mapped host)
+  unsigned* dbar = nullptr;
+  int *h_err = nullptr, *d_err = nullptr;
+  int sweep_mode = 2;          // 0 four launches, 1 one launch with grid barriers, 2 the autotuner's choice
+  bool sweep_one_tuned = false;
+  int sweep_grid = 0;          // workgroups of the last whole-sweep launch
   double *h_maxd2 = nullptr, *dmaxd2 = nullptr;
   int flag_set = 0;                    // set the next analysis writes
   std::vector<int8_t> spec_flags;      // first-pass flags of the last adapt
@@ -867,7 +873,12 @@ StageArgs stage_args(mrb_ctx* c) {
   return a;
 }
 
-// the four stages of one RK4 step; results go to k1..k3 and u_new (u is read only)
+bool sweep_in_one(const mrb_ctx* c) {
+  return c->cfg.form == MRB_FORM_FUSED && (c->sweep_mode == 1 || (c->sweep_mode == 2 && c->sweep_one_tuned));
+}
+
+// the four stages of one RK4 step; results go to k1..k3 and u_new (u is read only).
+// fixed_grid (graph capture) always takes the four-launch path.
 mrb_status sweep(mrb_ctx* c, double t, double dt, bool fixed_grid = false) {
   const double h2 = dt * 0.5, h6 = dt / 6.0;
   const double ts[4] = {t, t + h2, t + h2, t + dt};
@@ -879,6 +890,25 @@ mrb_status sweep(mrb_ctx* c, double t, double dt, bool fixed_grid = false) {
   double sweep_bytes = 0.0;
   for (int s = 1; s <= 4; ++s) sweep_bytes += (double)c->hblk.size() * c->bsz * stage_bytes(c, s);
   TimeScope sweep_scope(c, T_STAGE, sweep_bytes, 4, fused);
+  if (!fixed_grid && sweep_in_one(c)) {
+    SweepArgs sa;
+    std::memset(&sa, 0, sizeof sa);
+    sa.a = a;
+    for (int s = 0; s < 4; ++s) {
+      sa.alpha[s] = alpha[s];
+      sa.cfac[s] = 1.0;
+      if (c->cfg.physics == MRB_ADV_SWIRL && c->cfg.phys[0] > 0.0) sa.cfac[s] = std::cos(M_PI * ts[s] / c->cfg.phys[0]);
+    }
+    sa.bar = c->dbar;
+    sa.err = c->d_err;
+    sa.spin = 1u << 22;
+    const int nsub = pick_nsub(c);
+    long work = (long)c->hblk.size();
+    for (int d = 0; d < c->cfg.dim; ++d) work *= nsub;
+    HIPCHK(c, launch_sweep(c->shape, c->cfg.precision, Variant{nsub}, (int)std::min(work, 1L << 30), sa, c->stream,
+                           &c->sweep_grid));
+    return MRB_OK;
+  }
   for (int s = 1; s <= 4; ++s) {
     a.stage = s;
     a.alpha = alpha[s - 1];
@@ -1037,12 +1067,23 @@ mrb_status launch_mr_kernel(mrb_ctx* c, bool fixed_grid, const mrb_ctx::Memo* sp
   return MRB_OK;
 }
 
+// after a synchronisation: a whole-sweep launch whose barrier wait timed out voids
+// the step (the barrier words are reset for the next launch)
+mrb_status check_barrier(mrb_ctx* c) {
+  if (!c->h_err || *c->h_err == 0) return MRB_OK;
+  *c->h_err = 0;
+  HIPCHK(c, hipMemsetAsync(c->dbar, 0, kBarWords * sizeof(unsigned), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return fail(c, MRB_E_DEVICE, "sweep: a grid barrier wait timed out; the step's results are void");
+}
+
 mrb_status mr_readback(mrb_ctx* c) {
   const int n = (int)c->hblk.size();
   {
     HostTimer ht(&c->hus_wait);
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
+  if (mrb_status r = check_barrier(c)) return r;
   c->last_flags.assign(c->h_flags, c->h_flags + n);
   c->last_maxd.assign(c->h_maxd, c->h_maxd + (size_t)n * c->cfg.nfields);
   c->have_flags = true;
@@ -1219,6 +1260,7 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
 
 // flags and maxima of the analysis just finished (mapped set `set`, n blocks)
 mrb_status take_flags(mrb_ctx* c, int set, size_t n) {
+  if (mrb_status r = check_barrier(c)) return r;
   const int8_t* f = set ? c->h_flags2 : c->h_flags;
   const double* m = set ? c->h_maxd2 : c->h_maxd;
   c->last_flags.assign(f, f + n);
@@ -1520,8 +1562,13 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
          hipHostMalloc((void**)&c->h_flags2, mb, fl) == hipSuccess &&
          hipHostMalloc((void**)&c->h_maxd2, mb * cfg->nfields * sizeof(double), fl) == hipSuccess &&
          hipHostGetDevicePointer((void**)&c->dflags2, c->h_flags2, 0) == hipSuccess &&
-         hipHostGetDevicePointer((void**)&c->dmaxd2, c->h_maxd2, 0) == hipSuccess;
+         hipHostGetDevicePointer((void**)&c->dmaxd2, c->h_maxd2, 0) == hipSuccess &&
+         hipHostMalloc((void**)&c->h_err, sizeof(int), fl) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&c->d_err, c->h_err, 0) == hipSuccess;
     if (!ok) c->err = "hipHostMalloc (mapped) failed";
+    if (ok) *c->h_err = 0;
+    ok = ok && dev((void**)&c->dbar, kBarWords * sizeof(unsigned)) &&
+         hipMemset(c->dbar, 0, kBarWords * sizeof(unsigned)) == hipSuccess;
   }
   if (ok) {
     int dev_id = 0, ncu = 0;
@@ -1551,13 +1598,14 @@ mrb_status mrb_destroy(mrb_ctx* c) {
   for (auto& e : c->memo)
     if (e.arena) (void)hipFree(e.arena);
   void* ptrs[] = {c->work_arena, c->dacc, c->ddone,
-                  c->ds2, c->ds, c->dghost, c->dscratch, c->dslots};
+                  c->ds2, c->ds, c->dghost, c->dscratch, c->dslots, c->dbar};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_flags) (void)hipHostFree(c->h_flags);
   if (c->h_maxd) (void)hipHostFree(c->h_maxd);
   if (c->h_flags2) (void)hipHostFree(c->h_flags2);
   if (c->h_maxd2) (void)hipHostFree(c->h_maxd2);
+  if (c->h_err) (void)hipHostFree(c->h_err);
   delete c;
   return MRB_OK;
 }
@@ -1783,14 +1831,14 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"sweep_grid\": %d, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
                 "\"plan_entries\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
                 c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
                 c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
                 c->order ? "level-sorted" : "forest",
-                c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
+                c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses, sweep_in_one(c) ? "one" : "four", c->sweep_grid, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
                 c->hus_launch, c->hus_index, c->hus_desc, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
   return MRB_OK;
@@ -1852,6 +1900,42 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     }
     c->nsub = v[bs / 2];
     c->order = bs & 1;
+    // one launch with grid barriers against four launches, on the chosen tiling
+    {
+      const int mode0 = c->sweep_mode;
+      float best_m[2] = {1e30f, 1e30f};
+      bool one_ok = true;
+      for (int round = 0; round < kRounds && one_ok; ++round)
+        for (int m = 0; m < 2 && one_ok; ++m) {
+          c->sweep_mode = m;
+          mrb_status r = MRB_OK;
+          for (int k = 0; k < reps + 1 && !r; ++k) {   // the first is a warm-up
+            if (k == 1 && hipEventRecord(e0, c->stream) != hipSuccess) r = MRB_E_DEVICE;
+            if (!r) r = sweep(c, 0.0, dt);
+          }
+          float ms = 0.f;
+          if (!r && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            r = MRB_E_DEVICE;
+          if (!r) r = check_barrier(c);
+          if (r) {
+            if (m == 0) { c->sweep_mode = mode0; return done(r); }
+            // the one-launch form is not available here (e.g. the cooperative launch
+            // was refused): keep four launches
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(c->stream);
+            one_ok = false;
+            break;
+          }
+          best_m[m] = std::min(best_m[m], ms / reps);
+        }
+      c->sweep_mode = mode0;
+      c->sweep_one_tuned = one_ok && best_m[1] < best_m[0];
+      char buf[96];
+      std::snprintf(buf, sizeof buf, ", \"sweep\": {\"four\": %.4f, \"one\": %.4f}", best_m[0],
+                    one_ok ? best_m[1] : -1.0f);
+      c->tune_log += buf;
+    }
     // analysis and refinement tilings: several rounds over the candidates, the fastest
     // round of each counts (single launches of these kernels are a few microseconds on
     // small grids, where one round is at the mercy of noise)
@@ -2268,6 +2352,13 @@ mrb_status mrb_set_graph(mrb_ctx* c, int enable) {
   c->probe_us[0].clear();
   c->probe_us[1].clear();
   c->use_graph = enable != 0;
+  return MRB_OK;
+}
+
+mrb_status mrb_set_sweep(mrb_ctx* c, int mode) {
+  if (!c) return MRB_E_ARG;
+  if (mode < 0 || mode > 2) return fail(c, MRB_E_ARG, "set_sweep: mode must be 0, 1 or 2");
+  c->sweep_mode = mode;
   return MRB_OK;
 }
 

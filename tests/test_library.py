@@ -464,6 +464,95 @@ def test_speculative_coarsening_rolls_back_when_flags_change():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("case", ["c2", "c4", "c3"])
+def test_one_launch_sweep_matches_oracle(case):
+    """The whole RK4 sweep as one cooperative launch with grid barriers between the
+    stages equals the oracle bit for bit: 2D swirl at full size, a 3D forest, and the
+    Navier-Stokes shape (two levels)."""
+    if case == "c2":
+        cfg, n = W.C2(form=W.FORM_FUSED), 6
+    elif case == "c4":
+        cfg, n = W.C4(jmax=3, eps=1e-3, form=W.FORM_FUSED).replace(max_blocks=3 * 8 ** 3), 3
+    else:
+        cfg, n = W.C3(jmax=4, eps=1e-4, form=W.FORM_FUSED), 2
+    s, o = _pair(cfg)
+    s.set_graph(0)
+    s.set_sweep(1)
+    t = 0.0
+    for _ in range(n):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+        assert s.stats()["sweep_launch"] == "one"
+    assert_same(s, o, f"{case}: {n} steps")
+    st = s.stats()
+    assert st["sweep_grid"] >= 8 and st["sweep_grid"] % 8 == 0
+    s.set_sweep(0)
+    assert s.stats()["sweep_launch"] == "four"
+    with pytest.raises(M.MrbError):
+        s.set_sweep(3)
+    s.close()
+
+
+@pytest.mark.gpu
+def test_autotuner_times_both_sweep_launch_forms():
+    cfg = W.C2(jmax=5, eps=1e-4, form=W.FORM_FUSED)
+    s = M.Solver(cfg)
+    s.init_grid()
+    before = s.read_blocks()
+    s.tune(reps=2)
+    sw = s.stats()["tune_ms"]["sweep"]
+    assert sw["four"] > 0 and sw["one"] > 0
+    assert s.stats()["sweep_launch"] == ("one" if sw["one"] < sw["four"] else "four")
+    assert np.array_equal(_bits(s.read_blocks()), _bits(before))
+    s.close()
+
+
+@pytest.mark.gpu
+def test_multi_step_calls_match_oracle():
+    """The library's own step loop (several steps per call, direct launches) equals
+    single oracle steps bit for bit."""
+    cfg = W.C2(form=W.FORM_FUSED)
+    s, o = _pair(cfg)
+    s.set_graph(0)
+    t = 0.0
+    for chunk in range(3):
+        s.step(t, cfg.dt, 10)
+        for _ in range(10):
+            o.step(t, cfg.dt)
+            t += cfg.dt
+        assert_same(s, o, f"after {10 * (chunk + 1)} steps")
+    assert s.stats()["spec_hits"] >= 25
+
+
+@pytest.mark.gpu
+def test_multi_step_call_after_a_perturbation_matches_oracle():
+    """A perturbation between calls makes the first adapt of the next call miss its
+    speculation (the host state is put back); the run must equal the oracle's."""
+    cfg = W.C2(form=W.FORM_FUSED)
+    s, o = _pair(cfg)
+    s.set_graph(0)
+    t = 0.0
+    s.step(t, cfg.dt, 4)
+    for _ in range(4):
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    assert_same(s, o, "before the perturbation")
+    lv, co = o.read_forest()
+    bump = W.sample(cfg, lv, co, fn=lambda x, y: 0.5 * np.exp(-((x - 0.3) ** 2 + (y - 0.6) ** 2) / 4e-5))
+    data = o.read_blocks() + bump
+    s.load_blocks(data)
+    o.load_blocks(data)
+    miss0 = s.stats()["spec_misses"]
+    s.step(t, cfg.dt, 3)
+    for _ in range(3):
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    assert_same(s, o, "3 steps after the perturbation")
+    assert s.stats()["spec_misses"] > miss0
+
+
+@pytest.mark.gpu
 def test_headline_configuration_mixed_step_path_within_1e5():
     """The benchmark's headline run: 2D swirl at full size (Bs 33, Jmax 7, eps 1e-4),
     mixed form, autotuned tilings, the library's own step loop (memoised plans,
