@@ -165,6 +165,7 @@ struct Shape {
 // Kernel variant of the stage sweep: sub-tiles per axis (1, 2 or 4).
 struct Variant {
   int nsub;
+  int tpb = 256;          // threads per workgroup (stage kernel)
 };
 
 // Launchers (kernels.hip).  grid = number of workgroups (grid-stride loops inside).
@@ -183,6 +184,8 @@ hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz
 bool shape_supported(const Shape& s);
 // sub-tile counts compiled for this shape and precision; returns count
 int stage_variants(const Shape& s, int precision, int* nsub, int cap);
+// threads-per-workgroup choices compiled for a stage tiling (256 always among them)
+int stage_threads(const Shape& s, int precision, int nsub, int* tpb, int cap);
 // sub-tile counts of the analysis (kind 0) and refinement (kind 1) kernels
 int aux_variants(const Shape& s, int kind, int* nsub, int cap);
 

@@ -385,12 +385,12 @@ __device__ __forceinline__ int sf(int t, int mode) { return mode == 2 ? 2 * t : 
 // mask word and x-dependent terms stay in registers) and walks rows of its row
 // group; B rows per round, loads issued unconditionally (a lane with no point
 // loads the block's first node and discards it).
-template <int DIM, int BS, int S, int HW, int NF, bool HASC, typename TT, int B = 8, typename SRC>
+template <int DIM, int BS, int S, int HW, int NF, bool HASC, typename TT, int B = 8, int NT = 256, typename SRC>
 __device__ void sgather(TT* tile, TT* carr, const GState<DIM, S + 2 * (HW + 3)>& g, const SEnt* se, int slot,
                         const int* r0, const int* cnt, const SRC& src) {
   using G = SGeo<DIM, BS, S, HW>;
   constexpr int TW = G::TW, TSZ = G::TSZ, CW = G::CW, CSZ = G::CSZ, NP = G::NP, H = G::H;
-  constexpr int NT = 256, RG = NT / TW, NROW = Pow<DIM - 1, TW>::v;
+  constexpr int RG = NT / TW, NROW = Pow<DIM - 1, TW>::v;
   static_assert(RG >= 1, "tile row wider than the workgroup");
   const int self = slot * NF * NP;
   int cb0[3] = {0, 0, 0};
@@ -736,7 +736,7 @@ struct StageShared {
   double swirl[DIM == 2 && NF == 1 ? 4 * S : 1];
 };
 
-template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
+template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT, int TPB = 256>
 __device__ __forceinline__ void stage_pass(const StageArgs& A, const StageVar& V,
                                            StageShared<DIM, BS, HW, NF, NSUB>& sh, char* smem) {
   constexpr int S = (BS + NSUB - 1) / NSUB, H = HW + 3;
@@ -771,12 +771,12 @@ __device__ __forceinline__ void stage_pass(const StageArgs& A, const StageVar& V
     const bool hasc = d.n_coarse > 0;
     if (V.stage == 1) {
       YSrc<TT, KT, false> src{A.u, nullptr, 0.0, A.off};
-      if (hasc) sgather<DIM, BS, S, HW, NF, true, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
-      else sgather<DIM, BS, S, HW, NF, false, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
+      if (hasc) sgather<DIM, BS, S, HW, NF, true, TT, SB, TPB>(tile, carr, g, se, d.slot, r0, cnt, src);
+      else sgather<DIM, BS, S, HW, NF, false, TT, SB, TPB>(tile, carr, g, se, d.slot, r0, cnt, src);
     } else {
       YSrc<TT, KT, true> src{A.u, (const KT*)V.kprev, V.alpha, A.off};
-      if (hasc) sgather<DIM, BS, S, HW, NF, true, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
-      else sgather<DIM, BS, S, HW, NF, false, TT, SB>(tile, carr, g, se, d.slot, r0, cnt, src);
+      if (hasc) sgather<DIM, BS, S, HW, NF, true, TT, SB, TPB>(tile, carr, g, se, d.slot, r0, cnt, src);
+      else sgather<DIM, BS, S, HW, NF, false, TT, SB, TPB>(tile, carr, g, se, d.slot, r0, cnt, src);
     }
     if (hasc) spredict<DIM, BS, S, HW, NF, TT>(tile, carr, g, r0, cnt);
     TT r;
@@ -813,7 +813,7 @@ __device__ __forceinline__ void stage_pass(const StageArgs& A, const StageVar& V
       }
     } else {
       // lanes along x, rows of the region walked by row groups
-      constexpr int RGS = 256 / S, NR = Pow<DIM - 1, S>::v;
+      constexpr int RGS = TPB / S, NR = Pow<DIM - 1, S>::v;
       const int lx = (int)threadIdx.x % S, rgs = (int)threadIdx.x / S;
       for (int row = rgs; rgs < RGS && lx < cnt[0] && row < NR; row += RGS) {
         const int ly = DIM > 2 ? row % S : row, lz = DIM > 2 ? row / S : 0;
@@ -836,11 +836,12 @@ __device__ __forceinline__ void stage_pass(const StageArgs& A, const StageVar& V
   }
 }
 
-template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
-__global__ void __launch_bounds__(256) k_stage(StageArgs A) {
+template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT, int TPB>
+__global__ void __launch_bounds__(TPB) k_stage(StageArgs A) {
   __shared__ StageShared<DIM, BS, HW, NF, NSUB> sh;
   extern __shared__ __align__(16) char smem[];
-  stage_pass<DIM, BS, HW, NF, NSUB, TT, KT, CT>(A, StageVar{A.stage, A.alpha, A.kprev, A.kout, A.cfac}, sh, smem);
+  stage_pass<DIM, BS, HW, NF, NSUB, TT, KT, CT, TPB>(A, StageVar{A.stage, A.alpha, A.kprev, A.kout, A.cfac}, sh,
+                                                     smem);
 }
 
 // Grid-wide barrier of the whole-sweep kernel (all workgroups resident: cooperative
@@ -1351,24 +1352,24 @@ __global__ void __launch_bounds__(256) k_scatter(const double* src, const int* s
 // launchers
 // ---------------------------------------------------------------------------
 template <typename K, typename Arg>
-static hipError_t go(K kern, int grid, size_t lds, hipStream_t st, const Arg& a) {
+static hipError_t go(K kern, int grid, size_t lds, hipStream_t st, const Arg& a, int threads = 256) {
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   grid = ((grid > 0 ? grid : 1) + 7) & ~7;  // XcdWork needs a multiple of 8
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
-// TT: tile type, KT: slope storage type, CT: arithmetic type
-template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT>
+// TT: tile type, KT: slope storage type, CT: arithmetic type, TPB: threads per workgroup
+template <int DIM, int BS, int HW, int NF, int NSUB, typename TT, typename KT, typename CT, int TPB>
 static hipError_t stage_go(int grid, const StageArgs& a, hipStream_t st) {
   constexpr int S = (BS + NSUB - 1) / NSUB;
   using SG = SGeo<DIM, BS, S, HW>;
   size_t lds = sizeof(TT) * NF * (SG::TSZ + SG::CSZ);
   if (NF == 4) lds += sizeof(CT) * 5 * (S + 4) * (S + 4);
-  return go(k_stage<DIM, BS, HW, NF, NSUB, TT, KT, CT>, grid, lds, st, a);
+  return go(k_stage<DIM, BS, HW, NF, NSUB, TT, KT, CT, TPB>, grid, lds, st, a, TPB);
 }
 
 // whole sweep: the grid is what the device holds at once (all workgroups must be
@@ -1409,11 +1410,11 @@ static hipError_t sweep_go(int max_grid, const SweepArgs& a, hipStream_t st, int
 // FP64: FP64 tile, slopes and arithmetic.  Mixed: FP32 slopes and arithmetic; the
 // tile is FP32 (stage values minus a per-field offset) for advection and FP64 for
 // Navier-Stokes (neighbour differences formed in FP64, see ns_fluxes).
-template <int D, int B, int W, int F, int NS, int P>
+template <int D, int B, int W, int F, int NS, int P, int T>
 static hipError_t stage_pick(int grid, const StageArgs& a, hipStream_t st) {
-  if constexpr (P == 0) return stage_go<D, B, W, F, NS, double, double, double>(grid, a, st);
-  else if constexpr (F == 4) return stage_go<D, B, W, F, NS, double, float, float>(grid, a, st);
-  else return stage_go<D, B, W, F, NS, float, float, float>(grid, a, st);
+  if constexpr (P == 0) return stage_go<D, B, W, F, NS, double, double, double, T>(grid, a, st);
+  else if constexpr (F == 4) return stage_go<D, B, W, F, NS, double, float, float, T>(grid, a, st);
+  else return stage_go<D, B, W, F, NS, float, float, float, T>(grid, a, st);
 }
 
 template <int D, int B, int W, int F, int NS, int P>
@@ -1423,26 +1424,32 @@ static hipError_t sweep_pick(int max_grid, const SweepArgs& a, hipStream_t st, i
   else return sweep_go<D, B, W, F, NS, float, float, float>(max_grid, a, st, grid_out);
 }
 
-// compiled stage variants: shape, precision (0 FP64, 1 mixed), sub-tiles per axis
+// compiled stage variants: shape, precision (0 FP64, 1 mixed), sub-tiles per axis,
+// threads per workgroup (512 only where a sub-tile has enough points for them)
 #define MRB_STAGE_VARIANTS(X) \
-  X(2, 17, 2, 1, 0, 1)        \
-  X(2, 17, 2, 1, 0, 2)        \
-  X(2, 17, 2, 1, 1, 1)        \
-  X(2, 17, 2, 1, 1, 2)        \
-  X(2, 33, 2, 1, 0, 1)        \
-  X(2, 33, 2, 1, 0, 2)        \
-  X(2, 33, 2, 1, 0, 4)        \
-  X(2, 33, 2, 1, 1, 1)        \
-  X(2, 33, 2, 1, 1, 2)        \
-  X(2, 33, 2, 1, 1, 4)        \
-  X(2, 33, 4, 4, 0, 2)        \
-  X(2, 33, 4, 4, 0, 4)        \
-  X(2, 33, 4, 4, 1, 1)        \
-  X(2, 33, 4, 4, 1, 2)        \
-  X(2, 33, 4, 4, 1, 4)        \
-  X(3, 17, 2, 1, 0, 2)        \
-  X(3, 17, 2, 1, 1, 1)        \
-  X(3, 17, 2, 1, 1, 2)
+  X(2, 17, 2, 1, 0, 1, 256)   \
+  X(2, 17, 2, 1, 0, 2, 256)   \
+  X(2, 17, 2, 1, 1, 1, 256)   \
+  X(2, 17, 2, 1, 1, 2, 256)   \
+  X(2, 33, 2, 1, 0, 1, 256)   \
+  X(2, 33, 2, 1, 0, 1, 512)   \
+  X(2, 33, 2, 1, 0, 2, 256)   \
+  X(2, 33, 2, 1, 0, 4, 256)   \
+  X(2, 33, 2, 1, 1, 1, 256)   \
+  X(2, 33, 2, 1, 1, 1, 512)   \
+  X(2, 33, 2, 1, 1, 2, 256)   \
+  X(2, 33, 2, 1, 1, 4, 256)   \
+  X(2, 33, 4, 4, 0, 2, 256)   \
+  X(2, 33, 4, 4, 0, 4, 256)   \
+  X(2, 33, 4, 4, 1, 1, 256)   \
+  X(2, 33, 4, 4, 1, 2, 256)   \
+  X(2, 33, 4, 4, 1, 4, 256)   \
+  X(3, 17, 2, 1, 0, 2, 256)   \
+  X(3, 17, 2, 1, 0, 2, 512)   \
+  X(3, 17, 2, 1, 1, 1, 256)   \
+  X(3, 17, 2, 1, 1, 1, 512)   \
+  X(3, 17, 2, 1, 1, 2, 256)   \
+  X(3, 17, 2, 1, 1, 2, 512)
 
 #define MRB_SHAPES(X) \
   X(2, 17, 2, 1)      \
@@ -1459,17 +1466,28 @@ bool shape_supported(const Shape& s) {
 
 int stage_variants(const Shape& s, int precision, int* nsub, int cap) {
   int n = 0;
-#define X(D, B, W, F, P, NS) \
-  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && precision == P && n < cap) nsub[n++] = NS;
+#define X(D, B, W, F, P, NS, T)                                                                  \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && precision == P && T == 256 && n < cap) \
+    nsub[n++] = NS;
+  MRB_STAGE_VARIANTS(X)
+#undef X
+  return n;
+}
+
+int stage_threads(const Shape& s, int precision, int nsub, int* tpb, int cap) {
+  int n = 0;
+#define X(D, B, W, F, P, NS, T) \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && precision == P && NS == nsub && n < cap) tpb[n++] = T;
   MRB_STAGE_VARIANTS(X)
 #undef X
   return n;
 }
 
 hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, const StageArgs& a, hipStream_t st) {
-#define X(D, B, W, F, P, NS)                                                                     \
-  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && precision == P && v.nsub == NS)      \
-    return stage_pick<D, B, W, F, NS, P>(grid, a, st);
+#define X(D, B, W, F, P, NS, T)                                                                  \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && precision == P && v.nsub == NS &&     \
+      v.tpb == T)                                                                                \
+    return stage_pick<D, B, W, F, NS, P, T>(grid, a, st);
   MRB_STAGE_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -1477,8 +1495,8 @@ hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, cons
 
 hipError_t launch_sweep(const Shape& s, int precision, Variant v, int max_grid, const SweepArgs& a, hipStream_t st,
                         int* grid_out) {
-#define X(D, B, W, F, P, NS)                                                                     \
-  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && precision == P && v.nsub == NS)      \
+#define X(D, B, W, F, P, NS, T)                                                                  \
+  if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && precision == P && v.nsub == NS && T == 256) \
     return sweep_pick<D, B, W, F, NS, P>(max_grid, a, st, grid_out);
   MRB_STAGE_VARIANTS(X)
 #undef X

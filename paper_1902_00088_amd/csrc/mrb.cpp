@@ -263,6 +263,7 @@ struct mrb_ctx {
   long spec_hits = 0, spec_misses = 0;
   int ncu = 256;
   int nsub = 0;                // stage sub-tiles per axis (0 = choose by block count)
+  int tpb = 256;               // stage threads per workgroup (for the tuned nsub)
   int nsub_mr = -1;            // analysis sub-tiles per axis (-1 = whole blocks, measured best)
   int nsub_ref = 0;            // refinement sub-tiles per axis (0 = choose by work count)
   int order = 0;               // stage processing order: 0 forest (Morton), 1 level-sorted
@@ -813,6 +814,9 @@ int pick_nsub(const mrb_ctx* c) {
   return v[nv - 1];
 }
 
+// threads per workgroup of the stage kernel: the tuned choice for the tuned tiling
+int pick_tpb(const mrb_ctx* c, int nsub) { return c->nsub == nsub ? c->tpb : 256; }
+
 // sub-tiles per axis for the analysis / refinement kernels: the smallest count whose
 // workgroups (n_items each) cover the chip twice
 int pick_aux(const mrb_ctx* c, long n_items, int forced = 0) {
@@ -849,7 +853,8 @@ mrb_status run_stage(mrb_ctx* c, int s, const StageArgs& a0, bool fixed_grid = f
   long work = n;
   for (int d = 0; d < c->cfg.dim; ++d) work *= nsub;
   TimeScope ts(c, T_STAGE, (double)n * c->bsz * stage_bytes(c, s), 1, time_it);
-  HIPCHK(c, launch_stage(c->shape, c->cfg.precision, Variant{nsub}, fixed_grid ? c->grid : grid_for(c, work), a,
+  HIPCHK(c, launch_stage(c->shape, c->cfg.precision, Variant{nsub, pick_tpb(c, nsub)},
+                         fixed_grid ? c->grid : grid_for(c, work), a,
                          c->stream));
   return MRB_OK;
 }
@@ -1831,12 +1836,13 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"sweep_grid\": %d, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"sweep_grid\": %d, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
                 "\"plan_entries\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
                 c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
                 c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
+                c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_tpb(c, pick_nsub(c)) : 256,
                 c->order ? "level-sorted" : "forest",
                 c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses, sweep_in_one(c) ? "one" : "four", c->sweep_grid, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
                 c->hus_launch, c->hus_index, c->hus_desc, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
@@ -1853,6 +1859,7 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     for (int i = 0; i < nv; ++i) ok = ok || v[i] == nsub;
     if (!ok) return fail(c, MRB_E_ARG, "tune: tiling not compiled for this shape and precision");
     c->nsub = nsub;
+    c->tpb = 256;
   } else if (reps > 0) {
     if (!check_state(c, true)) return MRB_E_STATE;
     if (!(dt > 0.0)) return fail(c, MRB_E_ARG, "tune: dt must be positive");
@@ -1870,36 +1877,46 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
       (void)hipEventDestroy(e1);
       return r;
     };
-    // stage tilings x processing order (forest/Morton, level-sorted); as below, the
-    // fastest of several rounds counts
+    // stage tilings (sub-tiles per axis x threads per workgroup) x processing order
+    // (forest/Morton, level-sorted); as below, the fastest of several rounds counts
     constexpr int kRounds = 5;
-    float best_s[16];
-    for (int i = 0; i < 2 * nv; ++i) best_s[i] = 1e30f;
-    for (int round = 0; round < kRounds; ++round)
-      for (int i = 0; i < nv; ++i)
-        for (int o = 0; o < 2; ++o) {
-          c->nsub = v[i];
-          c->order = o;
-          mrb_status r = sweep(c, 0.0, dt);  // warm-up
-          if (r) return done(r);
-          if (hipEventRecord(e0, c->stream) != hipSuccess) return done(fail(c, MRB_E_DEVICE, "tune: event"));
-          for (int k = 0; k < reps; ++k)
-            if ((r = sweep(c, 0.0, dt))) return done(r);
-          float ms = 0.f;
-          if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-              hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-            return done(fail(c, MRB_E_DEVICE, "tune: event"));
-          best_s[2 * i + o] = std::min(best_s[2 * i + o], ms / reps);
-        }
-    int bs = 0;
-    for (int i = 0; i < 2 * nv; ++i) {
-      char buf[64];
-      std::snprintf(buf, sizeof buf, "%s\"%d%s\": %.4f", i ? ", " : "", v[i / 2], (i & 1) ? "L" : "", best_s[i]);
-      c->tune_log += buf;
-      if (best_s[i] < best_s[bs]) bs = i;
+    struct Cand { int nsub, tpb, order; float ms; };
+    std::vector<Cand> cand;
+    for (int i = 0; i < nv; ++i) {
+      int tv[4];
+      const int nt = stage_threads(c->shape, c->cfg.precision, v[i], tv, 4);
+      for (int j = 0; j < nt; ++j)
+        for (int o = 0; o < 2; ++o) cand.push_back(Cand{v[i], tv[j], o, 1e30f});
     }
-    c->nsub = v[bs / 2];
-    c->order = bs & 1;
+    for (int round = 0; round < kRounds; ++round)
+      for (Cand& k : cand) {
+        c->nsub = k.nsub;
+        c->tpb = k.tpb;
+        c->order = k.order;
+        mrb_status r = sweep(c, 0.0, dt);  // warm-up
+        if (r) return done(r);
+        if (hipEventRecord(e0, c->stream) != hipSuccess) return done(fail(c, MRB_E_DEVICE, "tune: event"));
+        for (int q = 0; q < reps; ++q)
+          if ((r = sweep(c, 0.0, dt))) return done(r);
+        float ms = 0.f;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+          return done(fail(c, MRB_E_DEVICE, "tune: event"));
+        k.ms = std::min(k.ms, ms / reps);
+      }
+    size_t bi = 0;
+    for (size_t i = 0; i < cand.size(); ++i) {
+      // keys: sub-tiles per axis, "t<threads>" unless 256, "L" for the level-sorted order
+      char buf[64], tp[16] = "";
+      if (cand[i].tpb != 256) std::snprintf(tp, sizeof tp, "t%d", cand[i].tpb);
+      std::snprintf(buf, sizeof buf, "%s\"%d%s%s\": %.4f", i ? ", " : "", cand[i].nsub, tp, cand[i].order ? "L" : "",
+                    cand[i].ms);
+      c->tune_log += buf;
+      if (cand[i].ms < cand[bi].ms) bi = i;
+    }
+    c->nsub = cand[bi].nsub;
+    c->tpb = cand[bi].tpb;
+    c->order = cand[bi].order;
     // one launch with grid barriers against four launches, on the chosen tiling
     {
       const int mode0 = c->sweep_mode;
@@ -1999,6 +2016,7 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     (void)done(MRB_OK);
   } else {
     c->nsub = 0;
+    c->tpb = 256;
     c->nsub_mr = -1;
     c->nsub_ref = 0;
     c->order = 0;
