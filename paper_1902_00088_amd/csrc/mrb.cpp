@@ -19,7 +19,6 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
-#include <unordered_set>
 #include <vector>
 
 using namespace mrb;
@@ -207,7 +206,7 @@ struct mrb_ctx {
   std::vector<NbEntry> hnb_next;             // descriptor build buffers, reused
   std::vector<std::vector<NbEntry>> desc_parts;
   WorkerPool pool;
-  long desc_thread_min = 1024;               // forests at least this large use host threads
+  long desc_thread_min = 256;                // forests at least this large use host threads
 
   char* arena = nullptr;        // packed topology in use: header, blocks, entries, lists, plans
   TopoHeader arena_hdr{};       // its header (kernels take it by value)
@@ -548,7 +547,7 @@ mrb_status build_descriptors(mrb_ctx* c) {
   int nt = 1;
   if (n >= (int)c->desc_thread_min) {
     const int hc = (int)std::max(1u, std::thread::hardware_concurrency());
-    nt = std::max(1, std::min({16, hc, n / 256}));
+    nt = std::max(1, std::min({16, hc, n / 64}));
   }
   // per-thread entry lists kept between calls (no fresh pages to fault in)
   if ((int)c->desc_parts.size() < nt) c->desc_parts.resize(nt);
@@ -1107,57 +1106,75 @@ mrb_status do_mr_pass(mrb_ctx* c) {
 // largest set of complete, flagged families whose merge keeps the grid graded
 std::vector<uint64_t> coarsenable(mrb_ctx* c, const int8_t* flags) {
   HostTimer ht(&c->hus_fixed);
-  const int d = c->cfg.dim, nch = 1 << d;
-  std::unordered_set<uint64_t> cand;
-  for (size_t i = 0; i < c->leaves.size(); ++i) {
+  const int d = c->cfg.dim, nch = 1 << d, bs = c->cfg.bs;
+  const int n = (int)c->leaves.size();
+  // complete families with every member flagged, each found once from its child 0
+  std::vector<uint64_t> key;     // mother keys
+  std::vector<int> mem;          // members' forest positions, nch per family
+  std::vector<int> fam_of(n, -1);
+  for (int i = 0; i < n; ++i) {
     const Leaf& L = c->leaves[i];
     if (L.level < 2 || flags[i] != -1) continue;
-    int p[3] = {L.c[0] >> 1, L.c[1] >> 1, L.c[2] >> 1};
-    if (d < 3) p[2] = 0;
-    const uint64_t pk = pack_key(L.level - 1, p);
-    if (cand.count(pk)) continue;
+    bool child0 = true;
+    for (int a = 0; a < d; ++a) child0 = child0 && (L.c[a] & 1) == 0;
+    if (!child0) continue;
+    int p[3] = {L.c[0] >> 1, L.c[1] >> 1, d > 2 ? L.c[2] >> 1 : 0};
+    int m[8];
     bool all = true;
     for (int b = 0; b < nch && all; ++b) {
       int ch[3] = {0, 0, 0};
       for (int a = 0; a < d; ++a) ch[a] = 2 * p[a] + ((b >> a) & 1);
-      const int j = c->index.find(pack_key(L.level, ch));
-      if (j < 0 || flags[j] != -1) all = false;
+      m[b] = c->index.find(pack_key(L.level, ch));
+      if (m[b] < 0 || flags[m[b]] != -1) all = false;
     }
-    if (all) cand.insert(pk);
+    if (!all) continue;
+    for (int b = 0; b < nch; ++b) {
+      fam_of[m[b]] = (int)key.size();
+      mem.push_back(m[b]);
+    }
+    key.push_back(pack_key(L.level - 1, p));
   }
-  // demote families with a finer neighbour outside the set, until stable
-  bool changed = true;
-  while (changed) {
-    changed = false;
-    std::vector<uint64_t> cur(cand.begin(), cand.end());
-    for (uint64_t pk : cur) {
-      const int l = (int)(pk >> 60) + 1;
-      int p[3] = {(int)(pk & 0xFFFFF), (int)((pk >> 20) & 0xFFFFF), (int)((pk >> 40) & 0xFFFFF)};
-      bool ok = true;
-      for (int b = 0; b < nch && ok; ++b) {
-        int ch[3] = {0, 0, 0};
-        for (int a = 0; a < d; ++a) ch[a] = 2 * p[a] + ((b >> a) & 1);
-        const int mi = c->index.find(pack_key(l, ch));
-        const BlockDesc& B = c->hblk[mi];
-        for (int e = B.nb_begin; e < B.nb_begin + B.n_ent && ok; ++e) {
-          // the finer neighbour's family (its mother at this member's level)
-          const NbEntry& E = c->hnb[e];
-          if (E.dl <= 0) continue;
-          int fc[3] = {0, 0, 0};
-          for (int a = 0; a < d; ++a) {
-            const int fine = 2 * ch[a] + (E.o[a] * 2) / (c->cfg.bs - 1);  // coords of the finer leaf (unwrapped)
-            fc[a] = wrapi(fine, 1 << (l + 1)) >> 1;
-          }
-          if (!cand.count(pack_key(l, fc))) ok = false;
+  // demote families with a finer neighbour whose own family is not (or no longer) a
+  // candidate, until stable; each pass checks every family against the previous set
+  // (the greatest fixed point does not depend on the order of demotions)
+  const int nf = (int)key.size();
+  std::vector<char> alive(nf, 1), demote(nf, 0);
+  auto check = [&](int f) {
+    demote[f] = 0;
+    if (!alive[f]) return;
+    for (int b = 0; b < nch; ++b) {
+      const int mi = mem[(size_t)f * nch + b];
+      const Leaf& M = c->leaves[mi];
+      const BlockDesc& B = c->hblk[mi];
+      for (int e = B.nb_begin; e < B.nb_begin + B.n_ent; ++e) {
+        const NbEntry& E = c->hnb[e];
+        if (E.dl <= 0) continue;
+        int fine[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) fine[a] = wrapi(2 * M.c[a] + (E.o[a] * 2) / (bs - 1), 1 << (M.level + 1));
+        const int j = c->index.find(pack_key(M.level + 1, fine));
+        if (j < 0 || fam_of[j] < 0 || !alive[fam_of[j]]) {
+          demote[f] = 1;
+          return;
         }
       }
-      if (!ok) {
-        cand.erase(pk);
+    }
+  };
+  const int nt = nf >= 512 ? std::min(8, nf / 256) : 1;
+  for (bool changed = true; changed;) {
+    c->pool.run(nt, [&](int t) {
+      const int lo = (int)((long)nf * t / nt), hi = (int)((long)nf * (t + 1) / nt);
+      for (int f = lo; f < hi; ++f) check(f);
+    });
+    changed = false;
+    for (int f = 0; f < nf; ++f)
+      if (demote[f]) {
+        alive[f] = 0;
         changed = true;
       }
-    }
   }
-  std::vector<uint64_t> out(cand.begin(), cand.end());
+  std::vector<uint64_t> out;
+  for (int f = 0; f < nf; ++f)
+    if (alive[f]) out.push_back(key[f]);
   std::sort(out.begin(), out.end());
   return out;
 }
