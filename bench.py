@@ -50,6 +50,12 @@ def counter_traffic(key):
     return vals["bytes"]
 
 
+def tkey(form):
+    """Key suffix of the counter summary for the stage kernel's threads per workgroup."""
+    t = form.get("stage_threads") or 256
+    return "" if t == 256 else f" t{t}"
+
+
 def run_form(M, W, torch, cfg, steps, warmup, tune=False):
     s = M.Solver(cfg)
     s.init_grid()
@@ -102,6 +108,7 @@ def run_form(M, W, torch, cfg, steps, warmup, tune=False):
         "kernels": kst,
         "host_us_per_step": host_us,
         "stage_tiles": tiles,
+        "stage_threads": st.get("stage_threads"),
         "tune_ms": st.get("tune_ms"),
         "graph_in_use": st.get("graph_in_use"),
         "memo_hits": st.get("memo_hits"),
@@ -142,7 +149,7 @@ def headline(args, res):
     ach = ks[dom]["bytes"] / (ks[dom]["ms"] * 1e-3) / 1e9 if ks[dom]["ms"] > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS,
-                "traffic": counter_traffic(f"c2 nsub {head['stage_tiles']}") if dom == "stage" else None,
+                "traffic": counter_traffic(f"c2 nsub {head['stage_tiles']}" + tkey(head)) if dom == "stage" else None,
                 "traffic_unit": "bytes per launch", "kernel": dom,
                 "algorithmic_bytes_per_launch": ks[dom]["bytes"] / max(1, ks[dom]["launches"]),
                 "launches": ks[dom]["launches"], "avg_launch_us": 1e3 * ks[dom]["ms"] / max(1, ks[dom]["launches"])}
