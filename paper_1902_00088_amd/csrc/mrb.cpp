@@ -279,6 +279,7 @@ struct mrb_ctx {
   // host-side time (microseconds) by phase
   double hus_refine_plan = 0, hus_coarsen_plan = 0, hus_upload = 0, hus_wait = 0, hus_launch = 0;
   double hus_index = 0, hus_desc = 0, hus_fixed = 0;   // parts of the plans: ordering, entries, fixed point
+  double hus_desc_par = 0;                              // entries: the per-block (threaded) part
   // learned predictor: model, Adam state and batch workspace (device)
   int mlp_nin = 0, mlp_np = 0, mlp_t = 0, mlp_cap = 0;
   float *mp = nullptr, *mgrad = nullptr, *mm = nullptr, *mv = nullptr, *mnorm = nullptr;
@@ -560,7 +561,10 @@ mrb_status build_descriptors(mrb_ctx* c) {
     part[t].reserve((size_t)(hi - lo) * (d == 2 ? 13 : 57));
     for (int i = lo; i < hi && !err[t]; ++i) err[t] = block_entries(c, i, part[t], hblk[i], co, sa, fi);
   };
-  c->pool.run(nt, work);
+  {
+    HostTimer hp(&c->hus_desc_par);
+    c->pool.run(nt, work);
+  }
   for (int t = 0; t < nt; ++t)
     if (err[t]) return fail(c, MRB_E_TOPOLOGY, err[t]);
   std::vector<NbEntry>& hnb = c->hnb_next;
@@ -1855,14 +1859,14 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
                 "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"sweep_grid\": %d, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
-                "\"plan_entries\": %.1f, \"plan_fixed_point\": %.1f}, "
+                "\"plan_entries\": %.1f, \"plan_entries_per_block\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
                 c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
                 c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
                 c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_tpb(c, pick_nsub(c)) : 256,
                 c->order ? "level-sorted" : "forest",
                 c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses, sweep_in_one(c) ? "one" : "four", c->sweep_grid, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
-                c->hus_launch, c->hus_index, c->hus_desc, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
+                c->hus_launch, c->hus_index, c->hus_desc, c->hus_desc_par, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
   return MRB_OK;
 }
