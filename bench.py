@@ -188,6 +188,7 @@ def main():
     ap.add_argument("--forms", default="fp64_plain,fp64_fused,mixed_fused")
     ap.add_argument("--c4-steps", type=int, default=20, help="steps of the 3D workload (0 = skip)")
     ap.add_argument("--c4-forms", default="fp64_fused,mixed_fused")
+    ap.add_argument("--c3-steps", type=int, default=20, help="steps of the Navier-Stokes workload (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="default tilings instead of the autotuner")
     ap.add_argument("--c5-steps", type=int, default=2000,
                     help="recorded steps of the learned-predictor study (0 = skip)")
@@ -240,6 +241,24 @@ def main():
                 "traffic_unit": "bytes per launch",
                 "algorithmic_bytes_per_launch": ks4["bytes"] / max(1, ks4["launches"]),
                 "avg_launch_us": 1e3 * ks4["ms"] / max(1, ks4["launches"])}
+
+    if args.c3_steps > 0:
+        # compressible Navier-Stokes mixing layer: 4 fields, halo 4, nested derivatives
+        c3 = {}
+        for name in ("fp64_fused", "mixed_fused"):
+            prec, form = forms[name]
+            print(f"bench: C3 {name} steps={args.c3_steps}", file=sys.stderr, flush=True)
+            c3[name] = run_form(M, W, torch, W.C3().replace(precision=prec, form=form), args.c3_steps, 2,
+                                tune=not args.no_tune)
+        out["c3"] = {"workload": "C3 2D compressible Navier-Stokes temporal mixing layer (rho, u, v, p), Bs=33, "
+                                 "Jmax=8, eps=1e-3, Re=1000, Mach 0.4", "forms": c3}
+        ks3 = c3["mixed_fused"]["kernels"]["stage"]
+        ach3 = ks3["bytes"] / (ks3["ms"] * 1e-3) / 1e9 if ks3["ms"] > 0 else 0.0
+        out["c3"]["roofline_stage_mixed"] = {
+            "bound": "hbm", "achieved": ach3, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach3 / PEAK_HBM_GBS,
+            "traffic": None, "traffic_unit": "bytes per launch",
+            "algorithmic_bytes_per_launch": ks3["bytes"] / max(1, ks3["launches"]),
+            "avg_launch_us": 1e3 * ks3["ms"] / max(1, ks3["launches"])}
 
     if args.c5_steps > 0:
         from paper_1902_00088_amd import predictor as P

@@ -1226,6 +1226,24 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
     return MRB_OK;
   }
   if (c->free_slots.size() < fams.size()) return fail(c, MRB_E_CAPACITY, "coarsen: pool too small");
+  // Slots: mothers take theirs from the free list in reverse forest order, and the
+  // children's slots go back in reverse forest order.  A refinement pushes its
+  // parents' slots in forest order and hands out children's slots from the back, so
+  // a coarsening that undoes it returns every block to the slot it had: a forest
+  // cycling through the same refinement and coarsening repeats its slots exactly and
+  // its plans are found in the memo.
+  std::vector<int> mslot(fams.size());
+  std::vector<std::pair<uint64_t, int>> ord(fams.size());
+  for (size_t i = 0; i < fams.size(); ++i) {
+    const uint64_t pk = fams[i];
+    const int p[3] = {(int)(pk & 0xFFFFF), (int)((pk >> 20) & 0xFFFFF), (int)((pk >> 40) & 0xFFFFF)};
+    ord[i] = {morton_of(c, (int)(pk >> 60), p), (int)i};
+  }
+  std::sort(ord.begin(), ord.end());
+  for (size_t k = ord.size(); k-- > 0;) {
+    mslot[ord[k].second] = c->free_slots.back();
+    c->free_slots.pop_back();
+  }
   std::vector<FamilyDesc> fd(fams.size());
   std::vector<char> gone(c->leaves.size(), 0);
   std::vector<int> smap(c->leaves.size(), -1);   // per block: mother slot * 8 + child index
@@ -1237,8 +1255,7 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
     Leaf P;
     P.level = l;
     for (int a = 0; a < 3; ++a) P.c[a] = p[a];
-    P.slot = c->free_slots.back();
-    c->free_slots.pop_back();
+    P.slot = mslot[i];
     fd[i].parent = P.slot;
     for (int b = 0; b < 8; ++b) fd[i].child[b] = -1;
     for (int b = 0; b < nch; ++b) {
@@ -1258,6 +1275,7 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
     if (gone[i]) freed.push_back(c->leaves[i].slot);
     else nl.push_back(c->leaves[i]);
   }
+  std::reverse(freed.begin(), freed.end());
   nl.insert(nl.end(), parents.begin(), parents.end());
   c->leaves.swap(nl);
   sort_and_index(c);
@@ -1266,7 +1284,7 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
   if (s) {
     c->leaves.swap(old);
     sort_and_index(c);
-    for (auto& P : parents) c->free_slots.push_back(P.slot);
+    for (const auto& o : ord) c->free_slots.push_back(mslot[o.second]);   // the free list as it was
     build_descriptors(c);
     return s;
   }
