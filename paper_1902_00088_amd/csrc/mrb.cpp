@@ -273,7 +273,7 @@ struct mrb_ctx {
   // paths until each has ten samples, then the faster median wall time wins)
   int graph_mode = 2;
   std::vector<double> probe_us[2];
-  struct GraphEntry { uint64_t key[6 + sizeof(TopoHeader) / 8]; hipGraphExec_t exec; };
+  struct GraphEntry { uint64_t key[7 + sizeof(TopoHeader) / 8]; hipGraphExec_t exec; };
   std::vector<GraphEntry> graphs;
   long n_graph_launches = 0;
   // host-side time (microseconds) by phase
@@ -1324,20 +1324,27 @@ mrb_status take_flags(mrb_ctx* c, int set, size_t n) {
 // device data of the uncoarsened grid is untouched: the coarsening writes only new
 // slots, and the second analysis writes back into shared nodes the values the first
 // one wrote) and the adapt continues from the real flags.
-mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false) {
+// the memoised coarsening that the last adapt's first-pass flags would give on the
+// current grid (the speculation of do_adapt), or null
+mrb_ctx::Memo* spec_entry(mrb_ctx* c) {
+  const size_t n = c->leaves.size();
+  if (n > kMemoMaxLeaves || c->spec_flags.size() != n) return nullptr;
+  std::vector<int> mat;
+  memo_material(c, 1, c->spec_flags.data(), mat);
+  mrb_ctx::Memo* e = memo_find(c, 1, mat);
+  return e && e->nfam > 0 ? e : nullptr;
+}
+
+// first_launched: the first pass is already queued (graph replay); first_fused: that
+// pass was given the speculated coarsening's map and wrote its mothers
+mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false, bool first_fused = false) {
   mrb_status s;
   int passes = 1;
   c->flag_set = 0;
   const size_t n1 = c->leaves.size();
-  mrb_ctx::Memo* e = nullptr;
-  if (n1 <= kMemoMaxLeaves && c->spec_flags.size() == n1) {
-    std::vector<int> mat;
-    memo_material(c, 1, c->spec_flags.data(), mat);
-    e = memo_find(c, 1, mat);
-    if (e && e->nfam == 0) e = nullptr;
-  }
+  mrb_ctx::Memo* e = spec_entry(c);
   // a first pass launched here also writes the speculated mothers
-  const bool fused = e && !first_launched && e->smap;
+  const bool fused = e && e->smap && (first_launched ? first_fused : true);
   if (!first_launched && (s = launch_mr_kernel(c, false, fused ? e : nullptr))) return s;
   if (!e) {
     {
@@ -1444,10 +1451,15 @@ mrb_status step_graph(mrb_ctx* c, double t, double dt) {
   const int ns = pick_nsub(c);
   const int nsm = pick_aux(c, (long)c->hblk.size(), c->nsub_mr);
   const int nsr = pick_aux(c, (long)std::max(1, c->pending_ref) << c->cfg.dim, c->nsub_ref);
+  // the first analysis pass writes the speculated coarsening's mothers when there is one
+  // (its map is read at replay time from the memo's device copy)
+  mrb_ctx::Memo* se = spec_entry(c);
+  const int* smap = se ? se->smap : nullptr;
   // the launches take the topology header by value: a replay needs the same header
-  uint64_t key[6 + sizeof(TopoHeader) / 8] = {(uint64_t)(uintptr_t)c->u, (uint64_t)ns | ((uint64_t)c->order << 8),
-                                              (uint64_t)nsm, (uint64_t)nsr, dtb, (uint64_t)(uintptr_t)c->arena};
-  std::memcpy(key + 6, &c->arena_hdr, sizeof(TopoHeader));
+  uint64_t key[7 + sizeof(TopoHeader) / 8] = {
+      (uint64_t)(uintptr_t)c->u, (uint64_t)ns | ((uint64_t)c->order << 8) | ((uint64_t)pick_tpb(c, ns) << 16),
+      (uint64_t)nsm, (uint64_t)nsr, dtb, (uint64_t)(uintptr_t)c->arena, (uint64_t)(uintptr_t)smap};
+  std::memcpy(key + 7, &c->arena_hdr, sizeof(TopoHeader));
   hipGraphExec_t exec = nullptr;
   for (auto& g : c->graphs)
     if (std::memcmp(g.key, key, sizeof key) == 0) exec = g.exec;
@@ -1458,7 +1470,7 @@ mrb_status step_graph(mrb_ctx* c, double t, double dt) {
     double* u0 = c->u;
     if (!e) {
       std::swap(c->u, c->unew);
-      e = launch_mr_kernel(c, true);
+      e = launch_mr_kernel(c, true, smap ? se : nullptr);
       std::swap(c->u, c->unew);
     }
     hipGraph_t graph = nullptr;
@@ -1486,7 +1498,7 @@ mrb_status step_graph(mrb_ctx* c, double t, double dt) {
   std::swap(c->u, c->unew);
   c->n_rk4++;
   c->n_block_updates += (long)c->hblk.size();
-  return do_adapt(c, nullptr, true);
+  return do_adapt(c, nullptr, true, smap != nullptr);
 }
 
 bool graph_ok(const mrb_ctx* c) {
