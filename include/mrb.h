@@ -126,7 +126,12 @@ mrb_status mrb_coarsen(mrb_ctx *ctx, const int8_t *flags, int *n_coarsened);
  * *n_passes (may be NULL) receives the number of analyses. */
 mrb_status mrb_adapt(mrb_ctx *ctx, int *n_passes);
 
-/* nsteps multiresolution time steps: {refine_all; rk4(t, dt); adapt}, t advancing by dt. */
+/* nsteps multiresolution time steps: {refine_all; rk4(t, dt); adapt}, t advancing by dt.
+ * The results are those of that sequence; the schedule differs: on forests of at
+ * most 1,024 leaves, topology changes seen before replay their memoised plans, and
+ * the first coarsening of each adapt is speculated from the previous step (the
+ * analysis pass writes the speculated mothers; if its flags differ, the host state
+ * is put back and the adapt continues from the real flags). */
 mrb_status mrb_step(mrb_ctx *ctx, double t0, double dt, int nsteps);
 
 mrb_status mrb_num_blocks(mrb_ctx *ctx, int *n);
