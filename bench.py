@@ -117,8 +117,8 @@ def run_form(M, W, torch, cfg, steps, warmup, tune=False):
     }
 
 
-def cpu_baseline(W, cfg, budget_s):
-    import oracle
+def _oracle_rate(oracle, cfg, budget_s):
+    """Block-updates/s of the oracle's plain steps from the workload's initial grid."""
     o = oracle.Oracle(cfg)
     o.init_grid()
     t = 0.0
@@ -134,10 +134,26 @@ def cpu_baseline(W, cfg, budget_s):
         elapsed += time.perf_counter() - t0
         t += cfg.dt
         nsteps += 1
+    return nbu / elapsed, (f"first {nsteps} steps of the same workload from the same initial grid "
+                           f"({nbu} block-updates in {elapsed:.1f} s)")
+
+
+def cpu_baseline(W, cfg, budget_s):
+    import ctypes
+    import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": nbu / elapsed, "unit": "block-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {nsteps} steps of the same workload from the same initial grid "
-                      f"({nbu} block-updates in {elapsed:.1f} s)"}
+    value, sample = _oracle_rate(oracle, cfg, budget_s)
+    out = {"value": value, "unit": "block-updates/s", "cores": cores, "kind": "oracle", "sample": sample}
+    # the same on one thread (OpenMP of the oracle's library set to 1 for the sample)
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        v1, s1 = _oracle_rate(oracle, cfg, budget_s / 3)
+        gomp.omp_set_num_threads(cores)
+        out["single_thread"] = {"value": v1, "cores": 1, "sample": s1}
+    except OSError:
+        pass
+    return out
 
 
 def headline(args, res):
