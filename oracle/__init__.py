@@ -12,7 +12,8 @@ uniform level-1 forest, then repeat {refine all, resample the analytic initial
 condition, adapt, resample} until the forest stops changing.
 
 parity unpinned: the Navier-Stokes right-hand side (a formulation of our own;
-only free-stream preservation and mass conservation pin it).
+free-stream preservation, mass conservation and single-mode closed forms of each
+term pin it, nothing beyond them).
 """
 from __future__ import annotations
 

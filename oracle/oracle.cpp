@@ -21,8 +21,8 @@
 // ones that shape code here are restated next to the code.
 //
 // parity unpinned: the compressible Navier-Stokes right-hand side (its
-// formulation is a reading, not the paper's; only free-stream preservation and
-// mass conservation pin it).
+// formulation is a reading, not the paper's; free-stream preservation, mass
+// conservation and single-mode closed forms of each term pin it, nothing beyond).
 #include <cmath>
 #include <cstdint>
 #include <cstring>
