@@ -604,3 +604,13 @@ def test_degenerate_thresholds_match_oracle(eps):
     else:
         assert (lv == 1).all()
     s.close()
+
+
+def test_hip_build_flags():
+    """gfx950 code objects, no FMA contraction (the FP64 path rounds as written), and
+    the packed-FP32 instructions switched off."""
+    from paper_1902_00088_amd import hipbuild
+    f = hipbuild.HIPFLAGS
+    assert "--offload-arch=gfx950" in f and "-ffp-contract=off" in f
+    i = f.index("-packed-fp32-ops")
+    assert f[i - 3:i] == ["-Xclang", "-target-feature", "-Xclang"]
