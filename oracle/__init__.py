@@ -72,6 +72,7 @@ def lib():
             ("orc_refine_all", [ctypes.c_void_p]),
             ("orc_refine_marked", [ctypes.c_void_p, _i8p]),
             ("orc_mr_pass", [ctypes.c_void_p, _i8p, _dp]),
+            ("orc_details", [ctypes.c_void_p, _dp]),
             ("orc_coarsen", [ctypes.c_void_p, _i8p]),
             ("orc_coarsenable", [ctypes.c_void_p, _i8p, _i8p, _i32p]),
             ("orc_adapt", [ctypes.c_void_p, ctypes.c_int]),
@@ -194,6 +195,12 @@ class Oracle:
         md = np.zeros((n, self.cfg.nf))
         self._chk(lib().orc_mr_pass(self.h, _ptr(fl, _i8p), _ptr(md, _dp)))
         return fl, md
+
+    def details(self):
+        """Per-node details d = u - P(R(u)) of the last mr_pass: [n][nf][bs^dim] (0 at all-even nodes)."""
+        out = np.zeros((self.num_blocks(), self.cfg.nf, self.cfg.npts))
+        self._chk(lib().orc_details(self.h, _ptr(out, _dp)))
+        return out
 
     def coarsen(self, flags) -> int:
         fl = np.ascontiguousarray(np.asarray(flags, dtype=np.int8))

@@ -55,6 +55,7 @@ struct Leaf {
   std::vector<double> u, y, k1, k2, k3, k4;   // each nf * bs^dim, x fastest
   int flag = 0;
   std::vector<double> maxd;                     // per field, last MR pass
+  std::vector<double> det;                      // details of the last MR pass, nf * bs^dim (0 at all-even nodes)
 };
 
 typedef std::vector<double> Leaf::*Arr;
@@ -419,6 +420,7 @@ struct Oracle {
         return T[(size_t)f * ts + ti];
       };
       lf.maxd.assign(nf, 0.0);
+      lf.det.assign((size_t)nf * np, 0.0);
       int hi1 = dim > 1 ? bs : 1, hi2 = dim > 2 ? bs : 1;
       for (int f = 0; f < nf; ++f)
         for (int i2 = 0; i2 < hi2; ++i2)
@@ -449,6 +451,7 @@ struct Oracle {
               }
               double pred = n[2] == 4 ? P4(vz[0], vz[1], vz[2], vz[3]) : vz[0];
               double d = at(f, ii) - pred;
+              lf.det[(size_t)f * np + i0 + (size_t)bs * i1 + (size_t)bs * bs * i2] = d;
               double ad = std::fabs(d);
               if (ad > lf.maxd[f] || std::isnan(ad)) lf.maxd[f] = ad;
             }
@@ -833,6 +836,21 @@ int orc_mr_pass(void* h, int8_t* flags, double* maxd) {
       const Leaf& lf = O->F[ord[i]];
       if (flags) flags[i] = (int8_t)lf.flag;
       if (maxd) for (int f = 0; f < O->nf; ++f) maxd[i * O->nf + f] = lf.maxd[f];
+    }
+    return 0;
+  })
+}
+
+// details of the last MR pass, per node: out [n][nf][bs^dim], forest order (test access
+// to the values whose maxima decide the flags)
+int orc_details(void* h, double* out) {
+  ORC_TRY({
+    auto ord = O->order();
+    const size_t bsz = (size_t)O->nf * O->np;
+    for (size_t i = 0; i < ord.size(); ++i) {
+      const Leaf& lf = O->F[ord[i]];
+      if (lf.det.size() != bsz) throw std::runtime_error("details: no analysis on the current grid");
+      std::memcpy(out + i * bsz, lf.det.data(), bsz * sizeof(double));
     }
     return 0;
   })

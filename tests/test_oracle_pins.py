@@ -228,6 +228,50 @@ def test_details_closed_form_for_sinusoid_and_exact_flag_flip():
         assert fl2[5] == flag
 
 
+def test_details_closed_form_in_3d_for_every_odd_parity_class():
+    """3D (Sec. 2.3, detail equation; prediction is the tensor product of the 1D midpoint
+    rule): for f = sin(kx x+a) sin(ky y+b) sin(kz z+c) the detail at a node whose odd axes
+    form the set A is f (1 - prod_{a in A} W(k_a)), W(k) = 9/8 cos(kh) - 1/8 cos(3kh), and 0
+    at all-even nodes.  Checked node by node in each of the seven odd classes, with a
+    different wavenumber per axis so that every axis' stencil shows; then the flag flips
+    exactly when eps crosses the block maximum (strict '<')."""
+    cfg = W.C4(jmax=3, eps=1e-3)
+    o = _uniform(cfg, 2)
+    lv, co = o.read_forest()
+    k = (3, 2, 5)
+    ph = (0.3, 1.1, -0.7)
+    f = lambda x, y, z: (np.sin(2 * np.pi * k[0] * x + ph[0]) * np.sin(2 * np.pi * k[1] * y + ph[1])
+                         * np.sin(2 * np.pi * k[2] * z + ph[2]))
+    o.load_blocks(W.sample(cfg, lv, co, fn=f))
+    fl, md = o.mr_pass()
+    d = o.details()[:, 0]
+    n = 4 * (cfg.bs - 1)
+    h = 1.0 / n
+    Wk = [9 / 8 * np.cos(2 * np.pi * kk * h) - 1 / 8 * np.cos(6 * np.pi * kk * h) for kk in k]
+    xs = W.node_coords(cfg, lv, co)
+    odd = [np.rint(xa * n).astype(int) % 2 for xa in xs]
+    prod = np.ones_like(xs[0])
+    for a in range(3):
+        prod = prod * np.where(odd[a] == 1, Wk[a], 1.0)
+    want = f(*xs) * (1 - prod)
+    cls = odd[0] + 2 * odd[1] + 4 * odd[2]
+    assert np.all(d[cls == 0] == 0.0)
+    for c in range(1, 8):
+        sel = cls == c
+        assert np.max(np.abs(want[sel])) > 1e-4, c       # every class carries a visible detail
+        assert np.max(np.abs(d[sel] - want[sel])) < 1e-13, c
+    assert np.array_equal(md[:, 0], np.max(np.abs(d), axis=1))
+    # exact flip around one block's maximum
+    b = 37
+    m = float(md[b, 0])
+    for eps, flag in ((m * (1 + 1e-12), -1), (m, 0), (m * (1 - 1e-12), 0)):
+        o2 = _uniform(cfg.replace(eps=eps), 2)
+        o2.load_blocks(W.sample(cfg, lv, co, fn=f))
+        fl2, md2 = o2.mr_pass()
+        assert md2[b, 0] == m
+        assert fl2[b] == flag
+
+
 def test_level_one_never_coarsens_and_eps_limits():
     cfg = W.C1(jmax=3, eps=1e300)
     o = _uniform(cfg, 1)
