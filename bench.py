@@ -59,21 +59,27 @@ def tkey(form):
 def run_form(M, W, torch, cfg, steps, warmup, tune=False):
     s = M.Solver(cfg)
     s.init_grid()
-    if tune:
-        s.refine_all()
-        s.tune(reps=3)
-        s.init_grid()
     lv0, co0 = s.read_forest()
     data0 = s.read_blocks()
-    t = 0.0
-    for _ in range(warmup):
-        s.step(t, cfg.dt)
-        t += cfg.dt
 
     def reset():
         s.init_forest(lv0, co0)
         s.load_blocks(data0)
         torch.cuda.synchronize()
+
+    if tune:
+        # set-up, before the warm-up: the autotuner on the refined initial grid, then 20
+        # steps for the library's choice between graph replay and direct launches (ten
+        # each way), so that no probing happens inside the timed region
+        s.refine_all()
+        s.tune(reps=3)
+        reset()
+        s.step(0.0, cfg.dt, 20)
+        reset()
+    t = 0.0
+    for _ in range(warmup):
+        s.step(t, cfg.dt)
+        t += cfg.dt
 
     # timed pass (no per-kernel instrumentation)
     reset()
@@ -117,6 +123,62 @@ def run_form(M, W, torch, cfg, steps, warmup, tune=False):
     }
 
 
+FIELD_NAMES = {1: ["phi"], 4: ["rho", "u", "v", "p"]}
+
+
+def mixed_accuracy(M, W, cfg, steps):
+    """Accuracy of the mixed fused form against the FP64 fused form (which equals the FP64
+    oracle bit for bit in the parity tests), both started from the FP64 initial grid, with
+    the FP64 run's coarsening flags replayed on the mixed run (same topology every step).
+    Per field: max|mixed - fp64| / max|fp64| and the relative 2-norm after `steps` steps;
+    also how many block flags the mixed state's own analyses set differently."""
+    import numpy as np
+    s64 = M.Solver(cfg.replace(precision=W.FP64, form=W.FORM_FUSED))
+    s32 = M.Solver(cfg.replace(precision=W.MIXED, form=W.FORM_FUSED))
+    s64.init_grid()
+    lv, co = s64.read_forest()
+    s32.init_forest(lv, co)
+    s32.load_blocks(s64.read_blocks())
+    t, flags_total, flags_differ, analyses = 0.0, 0, 0, 0
+    for _ in range(steps):
+        for s in (s64, s32):
+            s.refine_all()
+            s.rk4(t, cfg.dt)
+        while True:
+            f64, _ = s64.mr_pass()
+            f32, _ = s32.mr_pass()
+            analyses += 1
+            flags_total += len(f64)
+            flags_differ += int(np.sum(f64 != f32))
+            n = s64.coarsen(f64)
+            s32.coarsen(f64)
+            if n == 0:
+                break
+        t += cfg.dt
+    a, b = s32.read_blocks(), s64.read_blocks()
+    same_forest = all(np.array_equal(x, y) for x, y in zip(s32.read_forest(), s64.read_forest()))
+    s64.close()
+    s32.close()
+    names = FIELD_NAMES.get(cfg.nf, [f"f{i}" for i in range(cfg.nf)])
+    inf = np.max(np.abs(a - b), axis=(0, 2)) / np.maximum(np.max(np.abs(b), axis=(0, 2)), 1e-300)
+    l2 = np.sqrt(np.sum((a - b) ** 2, axis=(0, 2)) / np.maximum(np.sum(b * b, axis=(0, 2)), 1e-300))
+    return {"steps": steps, "topology": "FP64 run's flags replayed", "same_forest": bool(same_forest),
+            "rel_inf_per_field": {k: float(v) for k, v in zip(names, inf)},
+            "rel_l2_per_field": {k: float(v) for k, v in zip(names, l2)},
+            "max_rel_inf": float(np.max(inf)), "within_1e-5": bool(np.max(inf) <= 1e-5),
+            "own_flags_differing": flags_differ, "flags_compared": flags_total, "analyses": analyses}
+
+
+def speedup_entry(res, acc, fast="mixed_fused", base="fp64_plain"):
+    """Speedup of one form over another on the same GPU, stated with the accuracy of the
+    mixed form measured on the same workload."""
+    if fast not in res or base not in res:
+        return None
+    return {"speedup": res[fast]["value"] / res[base]["value"], "of": fast, "over": base,
+            "max_rel_inf_error_of_mixed": acc["max_rel_inf"] if acc else None,
+            "within_1e-5": acc["within_1e-5"] if acc else None}
+
+
 def _oracle_rate(oracle, cfg, budget_s):
     """Block-updates/s of the oracle's plain steps from the workload's initial grid."""
     o = oracle.Oracle(cfg)
@@ -138,12 +200,24 @@ def _oracle_rate(oracle, cfg, budget_s):
                            f"({nbu} block-updates in {elapsed:.1f} s)")
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or None
+
+
 def cpu_baseline(W, cfg, budget_s):
     import ctypes
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     value, sample = _oracle_rate(oracle, cfg, budget_s)
-    out = {"value": value, "unit": "block-updates/s", "cores": cores, "kind": "oracle", "sample": sample}
+    out = {"value": value, "unit": "block-updates/s", "cores": cores, "kind": "oracle", "sample": sample,
+           "cpu_model": cpu_model(), "host_threads_available": os.cpu_count()}
     # the same on one thread (OpenMP of the oracle's library set to 1 for the sample)
     try:
         gomp = ctypes.CDLL("libgomp.so.1")
@@ -156,8 +230,8 @@ def cpu_baseline(W, cfg, budget_s):
     return out
 
 
-def headline(args, res):
-    """The JSON line's headline fields from the 2D swirl forms."""
+def headline(args, res, acc=None):
+    """The JSON line's headline fields from the 2D swirl forms (acc: the mixed form's accuracy)."""
     head = res.get("mixed_fused") or next(iter(res.values()))
     head_name = "mixed_fused" if "mixed_fused" in res else next(iter(res))
     ks = head["kernels"]
@@ -182,13 +256,14 @@ def headline(args, res):
         "vs_baseline": None,
         "dtype": "f32-stencil/f64-state" if head_name.startswith("mixed") else "f64",
         "data": "synthetic",
-        "config": {"workload": "C2 2D swirl advection: 3 seeded Gaussian blobs (beta=0.01), Bs=33, Jmax=7, "
-                               "eps=1e-4, dt=2^-13, 500 steps", "form": head_name,
+        "config": {"workload": f"C2 2D swirl advection: 3 seeded Gaussian blobs (beta=0.01), Bs=33, Jmax=7, "
+                               f"eps=1e-4, dt=2^-13; {args.steps} timed steps from the initial grid "
+                               f"(the full run is 500 steps)", "form": head_name,
                    "blocks_initial": head["blocks_initial"], "parallelism": "single GPU"},
         "roofline": roofline,
         "forms": res,
-        "speedup_mixed_fused_vs_fp64_plain": (res["mixed_fused"]["value"] / res["fp64_plain"]["value"]
-                                              if "fp64_plain" in res and "mixed_fused" in res else None),
+        "speedup_mixed_fused_vs_fp64_plain": speedup_entry(res, acc),
+        "mixed_accuracy": acc,
     }
 
 
@@ -203,7 +278,9 @@ def main():
                     help="first run a plain device copy of this many MiB five times (counter calibration)")
     ap.add_argument("--forms", default="fp64_plain,fp64_fused,mixed_fused")
     ap.add_argument("--c4-steps", type=int, default=20, help="steps of the 3D workload (0 = skip)")
-    ap.add_argument("--c4-forms", default="fp64_fused,mixed_fused")
+    ap.add_argument("--c4-forms", default="fp64_plain,fp64_fused,mixed_fused")
+    ap.add_argument("--acc-steps", type=int, default=40,
+                    help="steps of the mixed-vs-FP64 accuracy runs (C2; C3 and C4 take half; 0 = skip)")
     ap.add_argument("--c3-steps", type=int, default=20, help="steps of the Navier-Stokes workload (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="default tilings instead of the autotuner")
     ap.add_argument("--c5-steps", type=int, default=2000,
@@ -236,8 +313,12 @@ def main():
         res[name] = run_form(M, W, torch, base.replace(precision=prec, form=form), args.steps, args.warmup,
                              tune=form == W.FORM_FUSED and not args.no_tune)
     out = {}
+    acc2 = None
+    if args.acc_steps > 0:
+        print(f"bench: C2 mixed accuracy steps={args.acc_steps}", file=sys.stderr, flush=True)
+        acc2 = mixed_accuracy(M, W, base, args.acc_steps)
     if res:
-        out = headline(args, res)
+        out = headline(args, res, acc2)
     if args.c4_steps > 0:
         # the 3D set-up: a ragged forest of ~3,000 blocks of 17^3 after refine-all, HBM bound
         c4 = {}
@@ -245,9 +326,16 @@ def main():
             prec, form = forms[name]
             print(f"bench: C4 {name} steps={args.c4_steps}", file=sys.stderr, flush=True)
             c4[name] = run_form(M, W, torch, W.C4().replace(precision=prec, form=form), args.c4_steps, 2,
-                                tune=not args.no_tune)
-        out["c4"] = {"workload": "C4 3D advection: 4 seeded blobs sigma=0.04, Bs=17^3, Jmax=6, eps=1e-4, dt=2^-11",
-                     "forms": c4}
+                                tune=form == W.FORM_FUSED and not args.no_tune)
+        acc4 = None
+        if args.acc_steps > 0:
+            print(f"bench: C4 mixed accuracy steps={max(1, args.acc_steps // 2)}", file=sys.stderr, flush=True)
+            acc4 = mixed_accuracy(M, W, W.C4(), max(1, args.acc_steps // 2))
+        out["c4"] = {"workload": f"C4 3D advection: 4 seeded blobs sigma=0.04, Bs=17^3, Jmax=6, eps=1e-4, "
+                                 f"dt=2^-11; {args.c4_steps} timed steps from the initial grid",
+                     "forms": c4, "mixed_accuracy": acc4,
+                     "speedup_mixed_fused_vs_fp64_plain": speedup_entry(c4, acc4),
+                     "speedup_mixed_fused_vs_fp64_fused": speedup_entry(c4, acc4, base="fp64_fused")}
         if "mixed_fused" in c4:
             ks4 = c4["mixed_fused"]["kernels"]["stage"]
             ach4 = ks4["bytes"] / (ks4["ms"] * 1e-3) / 1e9 if ks4["ms"] > 0 else 0.0
@@ -266,13 +354,20 @@ def main():
             print(f"bench: C3 {name} steps={args.c3_steps}", file=sys.stderr, flush=True)
             c3[name] = run_form(M, W, torch, W.C3().replace(precision=prec, form=form), args.c3_steps, 2,
                                 tune=not args.no_tune)
-        out["c3"] = {"workload": "C3 2D compressible Navier-Stokes temporal mixing layer (rho, u, v, p), Bs=33, "
-                                 "Jmax=8, eps=1e-3, Re=1000, Mach 0.4", "forms": c3}
+        acc3 = None
+        if args.acc_steps > 0:
+            print(f"bench: C3 mixed accuracy steps={max(1, args.acc_steps // 2)}", file=sys.stderr, flush=True)
+            acc3 = mixed_accuracy(M, W, W.C3(), max(1, args.acc_steps // 2))
+        out["c3"] = {"workload": f"C3 2D compressible Navier-Stokes temporal mixing layer (rho, u, v, p), Bs=33, "
+                                 f"Jmax=8, eps=1e-3, Re=1000, Mach 0.4; {args.c3_steps} timed steps",
+                     "forms": c3, "mixed_accuracy": acc3,
+                     "speedup_mixed_fused_vs_fp64_fused": speedup_entry(c3, acc3, base="fp64_fused")}
         ks3 = c3["mixed_fused"]["kernels"]["stage"]
         ach3 = ks3["bytes"] / (ks3["ms"] * 1e-3) / 1e9 if ks3["ms"] > 0 else 0.0
         out["c3"]["roofline_stage_mixed"] = {
             "bound": "hbm", "achieved": ach3, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach3 / PEAK_HBM_GBS,
-            "traffic": None, "traffic_unit": "bytes per launch",
+            "traffic": counter_traffic(f"c3 nsub {c3['mixed_fused']['stage_tiles']}"),
+            "traffic_unit": "bytes per launch",
             "algorithmic_bytes_per_launch": ks3["bytes"] / max(1, ks3["launches"]),
             "avg_launch_us": 1e3 * ks3["ms"] / max(1, ks3["launches"])}
 

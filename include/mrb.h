@@ -25,6 +25,8 @@
  *  - Errors.  Every call returns an mrb_status; none aborts or throws across the
  *    ABI.  On error the solver state is unchanged (capacity and topology are
  *    checked before any device write) and mrb_last_error() describes the cause.
+ *    The one exception is a grid-barrier time-out of the one-launch sweep (see
+ *    mrb_set_sweep), which voids the block data.
  *  - Streams.  All device work is enqueued on the HIP stream given to mrb_create.
  *    Calls that return host data (mrb_num_blocks, mrb_read_*, mrb_get_flags,
  *    mrb_mr_pass, mrb_adapt, mrb_step) synchronise that stream before returning.
@@ -119,7 +121,10 @@ mrb_status mrb_mr_pass(mrb_ctx *ctx, int8_t *flags, double *maxd);
  * blocks all flagged -1 merge into their mother when the result stays graded
  * (completeness + gradedness, Sec. 2.3 last paragraph; the largest such set).
  * The mother keeps every second node (restriction R).  *n_coarsened (may be
- * NULL) receives the number of merged families. */
+ * NULL) receives the number of merged families.  This is also the topology-replay
+ * call ("apply flags"): given flags computed elsewhere (e.g. by an FP64 run of the
+ * same step), it reproduces that run's coarsening on this context's data, which is
+ * how the mixed-precision form is compared on the FP64 topology. */
 mrb_status mrb_coarsen(mrb_ctx *ctx, const int8_t *flags, int *n_coarsened);
 
 /* Repeat {mrb_mr_pass; mrb_coarsen} until no family merges (Sec. 2.1 item 3).
@@ -181,15 +186,19 @@ mrb_status mrb_tune(mrb_ctx *ctx, int nsub, int reps, double dt, int *chosen);
  * stream and a time-independent right-hand side.  Results are identical either way.
  * MRB_E_ARG for other values. */
 mrb_status mrb_set_graph(mrb_ctx *ctx, int enable);
-/* How the fused form launches the four stages of an RK4 step (Sec. 4 batching: every
- * block of every level in each launch).  mode 0: four launches, one per stage.  mode
- * 1: one cooperative launch (one workgroup per compute unit, each taking several
- * blocks per stage), with a grid-wide barrier between stages (bounded waits: a wait that times out makes the
- * next read-back fail with MRB_E_DEVICE and voids the step).  mode 2 (default): the
- * autotuner (mrb_tune with reps > 0) times both on the tuned tiling and keeps the
- * faster; four launches until then.  Results are identical in every mode.  MRB_E_ARG
- * for other values; mode 1 on the plain form is accepted and ignored (it has no
- * fused stages). */
+/* How the fused form launches the four stages of an RK4 step (every block of every
+ * level in each launch).  mode 0: four launches, one per stage.  mode 1: one
+ * cooperative launch (one workgroup per compute unit, each taking several blocks per
+ * stage), with a grid-wide barrier between stages.  The barrier waits are bounded:
+ * a wait that times out ends the kernel early, the next call that synchronises the
+ * stream returns MRB_E_DEVICE, and the block data is then undefined (this is the one
+ * exception to "on error the state is unchanged"): every later call that needs it
+ * returns MRB_E_STATE until mrb_load_blocks (or mrb_init_forest) supplies new data.
+ * mode 2 (default): the autotuner (mrb_tune with reps > 0) times both on the tuned
+ * tiling and keeps the faster; four launches until then.  Results are identical in
+ * every mode.  MRB_E_ARG for other values; mode 1 on the plain form is accepted and
+ * ignored (it has no fused stages).
+ * Not a step of the method: a schedule choice. */
 mrb_status mrb_set_sweep(mrb_ctx *ctx, int mode);
 
 /* ---------------------------------------------------------------------------

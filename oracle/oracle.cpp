@@ -530,54 +530,67 @@ struct Oracle {
   // replace every family in `fam` by its parent, which takes the synchronised
   // values at its own (coarser) lattice points: restriction by injection
   void coarsen(const std::set<Key>& fam) {
-    std::vector<std::pair<Key, std::vector<double>>> made;
-    for (auto& p : fam) {
-      std::vector<double> v((size_t)nf * np);
-      int hi1 = dim > 1 ? bs : 1, hi2 = dim > 2 ? bs : 1;
-      for (int f = 0; f < nf; ++f)
-        for (int i2 = 0; i2 < hi2; ++i2)
-          for (int i1 = 0; i1 < hi1; ++i1)
-            for (int i0 = 0; i0 < bs; ++i0) {
-              int ii[3] = {i0, i1, i2};
-              long g[3] = {0, 0, 0};
-              for (int a = 0; a < dim; ++a) g[a] = (long)p.c[a] * (bs - 1) + ii[a];
-              v[(size_t)f * np + idx(ii)] = V(&Leaf::u, p.l, g, f);
-            }
-      made.push_back({p, v});
-    }
-    for (auto& pr : made) {
-      for (auto& c : children(pr.first)) F.erase(c);
+    std::vector<Key> keys(fam.begin(), fam.end());
+    std::vector<std::vector<double>> vals(keys.size());
+    parallel_over(keys.size(), [&](size_t i) { vals[i] = lattice_values(keys[i]); });
+    for (size_t i = 0; i < keys.size(); ++i) {
+      for (auto& c : children(keys[i])) F.erase(c);
       Leaf lf;
-      lf.u = pr.second;
-      F[pr.first] = lf;
+      lf.u = vals[i];
+      F[keys[i]] = lf;
     }
+  }
+
+  // V at every node of the block with key p, evaluated on the current grid (a mother on
+  // the grid before coarsening: restriction; a child on the grid before refinement:
+  // the synchronised finer values, predicted where no leaf holds them)
+  std::vector<double> lattice_values(const Key& p) const {
+    std::vector<double> v((size_t)nf * np);
+    int hi1 = dim > 1 ? bs : 1, hi2 = dim > 2 ? bs : 1;
+    for (int f = 0; f < nf; ++f)
+      for (int i2 = 0; i2 < hi2; ++i2)
+        for (int i1 = 0; i1 < hi1; ++i1)
+          for (int i0 = 0; i0 < bs; ++i0) {
+            int ii[3] = {i0, i1, i2};
+            long g[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a) g[a] = (long)p.c[a] * (bs - 1) + ii[a];
+            v[(size_t)f * np + idx(ii)] = V(&Leaf::u, p.l, g, f);
+          }
+    return v;
+  }
+
+  // run body(i) for i = 0..n-1 in parallel (independent, read-only work on the
+  // current grid), collecting the first error
+  template <class Fn>
+  void parallel_over(size_t n, Fn body) const {
+    std::string e;
+    bool bad = false;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < (long)n; ++i) {
+      try {
+        body((size_t)i);
+      } catch (std::exception& ex) {
+#pragma omp critical
+        { if (!bad) { bad = true; e = ex.what(); } }
+      }
+    }
+    if (bad) throw std::runtime_error(e);
   }
 
   // replace every leaf of R by its 2^d children, whose nodes take the synchronised
   // value at level l+1 on the grid before any replacement (prediction where needed)
   void refine_set(const std::set<Key>& R) {
-    std::vector<std::pair<Key, std::vector<double>>> made;
-    for (auto& k : R) {
-      for (auto& c : children(k)) {
-        std::vector<double> v((size_t)nf * np);
-        int hi1 = dim > 1 ? bs : 1, hi2 = dim > 2 ? bs : 1;
-        for (int f = 0; f < nf; ++f)
-          for (int i2 = 0; i2 < hi2; ++i2)
-            for (int i1 = 0; i1 < hi1; ++i1)
-              for (int i0 = 0; i0 < bs; ++i0) {
-                int ii[3] = {i0, i1, i2};
-                long g[3] = {0, 0, 0};
-                for (int a = 0; a < dim; ++a) g[a] = (long)c.c[a] * (bs - 1) + ii[a];
-                v[(size_t)f * np + idx(ii)] = V(&Leaf::u, c.l, g, f);
-              }
-        made.push_back({c, v});
-      }
-    }
+    std::vector<Key> kids;
+    for (auto& k : R)
+      for (auto& c : children(k)) kids.push_back(c);
+    // every child's nodes: V at level l+1 on the grid before any replacement
+    std::vector<std::vector<double>> vals(kids.size());
+    parallel_over(kids.size(), [&](size_t i) { vals[i] = lattice_values(kids[i]); });
     for (auto& k : R) F.erase(k);
-    for (auto& pr : made) {
+    for (size_t i = 0; i < kids.size(); ++i) {
       Leaf lf;
-      lf.u = pr.second;
-      F[pr.first] = lf;
+      lf.u = vals[i];
+      F[kids[i]] = lf;
     }
   }
 

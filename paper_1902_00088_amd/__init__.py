@@ -1,7 +1,8 @@
 """MI355X block-multiresolution solver (arXiv 1902.00088): Python binding.
 
 A thin ctypes layer over the C ABI in ``include/mrb.h`` (``libmrb.so``, built
-in-tree for gfx950 by :mod:`paper_1902_00088_amd.build`).  PyTorch supplies the
+in-tree for gfx950 by :func:`paper_1902_00088_amd.build`, which drives
+:mod:`paper_1902_00088_amd.hipbuild`).  PyTorch supplies the
 device pool arrays and the stream; every step of the method runs in the HIP
 kernels of the library.  There is no CPU fallback: importing works anywhere,
 but creating a :class:`Solver` needs the built library and a GPU, and raises

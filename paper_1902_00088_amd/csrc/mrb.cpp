@@ -1076,13 +1076,17 @@ mrb_status launch_mr_kernel(mrb_ctx* c, bool fixed_grid, const mrb_ctx::Memo* sp
 }
 
 // after a synchronisation: a whole-sweep launch whose barrier wait timed out voids
-// the step (the barrier words are reset for the next launch)
+// the block data (the sweep ended early, so u_new -- now u -- is incomplete); calls
+// that need data fail with MRB_E_STATE until new data is loaded.  The barrier words
+// are reset for the next launch.
 mrb_status check_barrier(mrb_ctx* c) {
   if (!c->h_err || *c->h_err == 0) return MRB_OK;
   *c->h_err = 0;
+  c->have_data = false;
+  c->have_flags = false;
   HIPCHK(c, hipMemsetAsync(c->dbar, 0, kBarWords * sizeof(unsigned), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  return fail(c, MRB_E_DEVICE, "sweep: a grid barrier wait timed out; the step's results are void");
+  return fail(c, MRB_E_DEVICE, "sweep: a grid barrier wait timed out; the block data is void (load new data)");
 }
 
 mrb_status mr_readback(mrb_ctx* c) {

@@ -88,6 +88,25 @@ def _pair(cfg, levels=None, coords=None, fn=None):
     return s, o
 
 
+def oracle_flags_on_state(cfg, lv, co, data):
+    """The oracle's analysis (Sec. 2.3) applied to a given state: the flag function checked
+    on the GPU's own (mixed-precision) state.  The data here is the GPU's, so this is a
+    check of the analysis alone, not a parity case for the fields."""
+    o = oracle.Oracle(cfg.replace(precision=W.FP64))
+    o.init_forest(lv, co)
+    o.load_blocks(data)
+    return o.mr_pass()
+
+
+def assert_own_flags(s, cfg, fs, ms):
+    """The GPU's flags and detail maxima from its own mr_pass equal the oracle's analysis of
+    the state the GPU holds after that pass (bitwise: the analysis is FP64 in both forms)."""
+    lv, co = s.read_forest()
+    fo, mo = oracle_flags_on_state(cfg, lv, co, s.read_blocks())
+    assert np.array_equal(fs, fo), f"{int(np.sum(fs != fo))} flags differ"
+    assert np.array_equal(_bits(ms), _bits(mo))
+
+
 def _two_level():
     keys = [(2, x, y) for x in range(4) for y in range(4) if (x, y) != (1, 1)]
     keys += [(3, 2 + bx, 2 + by) for bx in range(2) for by in range(2)]
@@ -237,7 +256,9 @@ def test_mixed_precision_within_1e5_on_replayed_topology():
             x.rk4(t, cfg.dt)
         while True:
             fo, _ = o.mr_pass()
-            fs, _ = s.mr_pass()
+            fs, ms = s.mr_pass()
+            if n % 5 == 0:
+                assert_own_flags(s, cfg, fs, ms)
             if o.coarsen(fo) == 0:
                 assert s.coarsen(fo) == 0
                 break
@@ -338,7 +359,8 @@ def test_ns_mixed_within_1e5():
             x.rk4(t, cfg.dt)
         while True:
             fo, _ = o.mr_pass()
-            s.mr_pass()
+            fs, ms = s.mr_pass()
+            assert_own_flags(s, cfg, fs, ms)
             if o.coarsen(fo) == 0:
                 assert s.coarsen(fo) == 0
                 break

@@ -401,8 +401,7 @@ def test_eps_zero_adaptive_run_equals_uniform_solver_bitwise():
     assert np.all(lv == cfg.jmax)
     n = (2 ** cfg.jmax) * (cfg.bs - 1)
     g = np.arange(n) / n
-    X, Y = np.meshgrid(g, g)
-    U0 = W._blobs(cfg, [X, Y])
+    U0 = W.blob_field(cfg, [g, g])
     U = _uniform_solver(U0, cfg.phys, n / 12.0, cfg.dt, nsteps)
     got = o.read_blocks()[:, 0, :].reshape(len(lv), cfg.bs, cfg.bs)
     for b in range(len(lv)):
@@ -414,7 +413,7 @@ def test_eps_zero_adaptive_run_equals_uniform_solver_bitwise():
 
 def _exact_translated(cfg, T, x, y):
     c = cfg.phys
-    return W._blobs(cfg, [np.mod(x - c[0] * T, 1.0), np.mod(y - c[1] * T, 1.0)])
+    return W.blob_at(cfg, [np.mod(x - c[0] * T, 1.0), np.mod(y - c[1] * T, 1.0)])
 
 
 @pytest.mark.slow

@@ -146,18 +146,76 @@ def node_coords(cfg: Config, levels: np.ndarray, coords: np.ndarray):
     return out
 
 
-def _blobs(cfg: Config, xs):
-    """Sum of periodic Gaussian blobs exp(-|x-c-n|^2/beta), images n in {-1,0,1}^d."""
-    val = np.zeros_like(xs[0])
-    shifts = np.indices((3,) * cfg.dim).reshape(cfg.dim, -1).T - 1
+def _axis_coords(cfg: Config, levels, coords):
+    """Per block and axis, the physical coordinates of the bs node positions: list of
+    dim arrays [n, bs]."""
+    levels = np.asarray(levels, dtype=np.int64)
+    coords = np.asarray(coords, dtype=np.int64).reshape(len(levels), cfg.dim)
+    nl = (2 ** levels) * (cfg.bs - 1)
+    i = np.arange(cfg.bs, dtype=np.int64)
+    return [np.mod(coords[:, a:a + 1] * (cfg.bs - 1) + i[None, :], nl[:, None]).astype(np.float64)
+            / nl[:, None].astype(np.float64) for a in range(cfg.dim)]
+
+
+def _blob_axis_factor(cfg: Config, c_a: float, x):
+    """G(x) = sum_{n in {-1,0,1}} exp(-(x - c_a - n)^2 / beta), evaluated once per distinct
+    value of x (so equal coordinates get bitwise equal factors)."""
+    u, inv = np.unique(x, return_inverse=True)
+    g = np.zeros_like(u)
+    for m in (-1.0, 0.0, 1.0):
+        dd = u - c_a - m
+        g = g + np.exp(-(dd * dd) / cfg.blob_beta)
+    return g[inv.reshape(np.shape(x))]
+
+
+def blob_field(cfg: Config, axes):
+    """Sum of periodic Gaussian blobs exp(-|x-c-n|^2/beta) over the images n in {-1,0,1}^d on
+    the tensor grid of the 1D coordinate arrays axes[a] ([..., len(axes[1]), len(axes[0])],
+    x fastest).  The images form a Cartesian product and the Gaussian factorises over axes,
+    so each blob is the product over axes of its 1D factors, x factor first."""
+    d = cfg.dim
+    shape = [len(axes[a]) for a in reversed(range(d))]
+    val = np.zeros(shape)
     for c in cfg.blob_centers:
-        for n in shifts:
-            r2 = np.zeros_like(xs[0])
-            for a in range(cfg.dim):
-                d = xs[a] - c[a] - n[a]
-                r2 = r2 + d * d
-            val = val + np.exp(-r2 / cfg.blob_beta)
+        prod = None
+        for a in range(d):
+            sh = [1] * d
+            sh[d - 1 - a] = len(axes[a])
+            ga = _blob_axis_factor(cfg, c[a], np.asarray(axes[a], dtype=np.float64)).reshape(sh)
+            prod = ga if prod is None else prod * ga
+        val = val + prod
     return val
+
+
+def blob_at(cfg: Config, xs):
+    """The blob sum at arbitrary points (xs[a]: arrays of one shape), images n in {-1,0,1}^d."""
+    val = np.zeros(np.shape(xs[0]))
+    for c in cfg.blob_centers:
+        prod = None
+        for a in range(cfg.dim):
+            g = np.zeros(np.shape(xs[a]))
+            for m in (-1.0, 0.0, 1.0):
+                dd = np.asarray(xs[a]) - c[a] - m
+                g = g + np.exp(-(dd * dd) / cfg.blob_beta)
+            prod = g if prod is None else prod * g
+        val = val + prod
+    return val
+
+
+def _blobs(cfg: Config, levels, coords):
+    """blob_field at the nodes of each block: [n, bs^dim], x fastest."""
+    ax = _axis_coords(cfg, levels, coords)
+    n, bs, d = len(ax[0]), cfg.bs, cfg.dim
+    val = np.zeros((n,) + (bs,) * d)
+    for c in cfg.blob_centers:
+        prod = None
+        for a in range(d):
+            shape = [n] + [1] * d
+            shape[d - a] = bs                                 # axis a varies along array dim d - a
+            ga = _blob_axis_factor(cfg, c[a], ax[a]).reshape(shape)
+            prod = ga if prod is None else prod * ga
+        val = val + prod
+    return val.reshape(n, bs ** d)
 
 
 def mixing_layer_fields(cfg: Config, x, y):
@@ -180,16 +238,17 @@ def mixing_layer_fields(cfg: Config, x, y):
 
 def sample(cfg: Config, levels, coords, fn: Optional[Callable] = None) -> np.ndarray:
     """Initial-condition values at every node of the given blocks: float64 [n, nf, bs**dim]."""
-    xs = node_coords(cfg, levels, coords)
     n = len(np.asarray(levels))
     out = np.empty((n, cfg.nf, cfg.npts), dtype=np.float64)
+    if fn is None and cfg.ic == "blobs":
+        out[:, 0, :] = _blobs(cfg, levels, coords)
+        return out
+    xs = node_coords(cfg, levels, coords)
     if fn is not None:
         vals = fn(*xs)
         vals = vals if isinstance(vals, (tuple, list)) else (vals,)
         for f in range(cfg.nf):
             out[:, f, :] = vals[f]
-    elif cfg.ic == "blobs":
-        out[:, 0, :] = _blobs(cfg, xs)
     elif cfg.ic == "mixing_layer":
         for f, v in enumerate(mixing_layer_fields(cfg, xs[0], xs[1])):
             out[:, f, :] = v
