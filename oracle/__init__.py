@@ -73,6 +73,7 @@ def lib():
             ("orc_refine_marked", [ctypes.c_void_p, _i8p]),
             ("orc_mr_pass", [ctypes.c_void_p, _i8p, _dp]),
             ("orc_details", [ctypes.c_void_p, _dp]),
+            ("orc_read_uniform", [ctypes.c_void_p, ctypes.c_int, _dp]),
             ("orc_coarsen", [ctypes.c_void_p, _i8p]),
             ("orc_coarsenable", [ctypes.c_void_p, _i8p, _i8p, _i32p]),
             ("orc_adapt", [ctypes.c_void_p, ctypes.c_int]),
@@ -162,6 +163,13 @@ class Oracle:
     def read_stored(self):
         out = np.zeros((self.num_blocks(), self.cfg.nf, self.cfg.npts))
         self._chk(lib().orc_read_stored(self.h, _ptr(out, _dp)))
+        return out
+
+    def read_uniform(self, level: int):
+        """The synchronised solution on the uniform level-`level` lattice: [nf][N]*dim, x fastest."""
+        nl = (2 ** level) * (self.cfg.bs - 1)
+        out = np.zeros((self.cfg.nf,) + (nl,) * self.cfg.dim)
+        self._chk(lib().orc_read_uniform(self.h, level, _ptr(out, _dp)))
         return out
 
     def tile(self, bi: int, halo: int):

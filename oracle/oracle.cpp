@@ -108,6 +108,14 @@ struct Oracle {
   double V(Arr arr, int l, const long* gin, int f) const {
     long g[3] = {0, 0, 0};
     for (int a = 0; a < dim; ++a) g[a] = imod(gin[a], N(l));
+    double val = 0.0;
+    if (held(arr, l, g, f, val)) return val;
+    return predicted(arr, l, g, f, nullptr);
+  }
+
+  // The stored value of the highest-level leaf holding the level-l lattice point g
+  // (periodic, already reduced) on its own lattice, if any leaf does.
+  bool held(Arr arr, int l, const long* g, int f, double& out) const {
     for (int L = jmax; L >= 1; --L) {
       long m[3] = {0, 0, 0};
       bool on = true;
@@ -143,8 +151,18 @@ struct Oracle {
             found = true;
             val = v;
           }
-      if (found) return val;
+      if (found) {
+        out = val;
+        return true;
+      }
     }
+    return false;
+  }
+
+  // A point held by no leaf: the prediction from level l-1, axis x first, then y, then z.
+  // The coarse values are V(l-1, .), or, when `coarse` is given, read from it: the
+  // uniform array of V at level l-1, [N(l-1)^dim] x fastest, field f.
+  double predicted(Arr arr, int l, const long* g, int f, const std::vector<double>* coarse) const {
     if (l <= 1) throw std::runtime_error("point not covered by any leaf");
     // coarse stencil per axis
     long cs[3][4];
@@ -164,13 +182,56 @@ struct Oracle {
         double vx[4] = {0, 0, 0, 0};
         for (int ix = 0; ix < n[0]; ++ix) {
           long cg[3] = {cs[0][ix], cs[1][iy], cs[2][iz]};
-          vx[ix] = V(arr, l - 1, cg, f);
+          if (coarse) {
+            const long nc = N(l - 1);
+            long q = 0, mul = 1;
+            for (int a = 0; a < dim; ++a) {
+              q += imod(cg[a], nc) * mul;
+              mul *= nc;
+            }
+            vx[ix] = (*coarse)[(size_t)q];
+          } else {
+            vx[ix] = V(arr, l - 1, cg, f);
+          }
         }
         vy[iy] = n[0] == 4 ? P4(vx[0], vx[1], vx[2], vx[3]) : vx[0];
       }
       vz[iz] = n[1] == 4 ? P4(vy[0], vy[1], vy[2], vy[3]) : vy[0];
     }
     return n[2] == 4 ? P4(vz[0], vz[1], vz[2], vz[3]) : vz[0];
+  }
+
+  // V on the whole uniform lattice of level L: out[f][N(L)^dim], x fastest.  Built level by
+  // level from 1 up: a point some leaf holds takes the holder's stored value, any other
+  // point the prediction from the previous level's array -- V's definition, with the
+  // coarser values read from arrays instead of being recomputed.
+  void uniform(Arr arr, int L, double* out) const {
+    for (int f = 0; f < nf; ++f) {
+      std::vector<double> prev, cur;
+      for (int l = 1; l <= L; ++l) {
+        const long nl = N(l);
+        long tot = 1;
+        for (int a = 0; a < dim; ++a) tot *= nl;
+        cur.assign((size_t)tot, 0.0);
+        std::string e;
+        bool bad = false;
+#pragma omp parallel for schedule(static)
+        for (long q = 0; q < tot; ++q) {
+          try {
+            long g[3] = {q % nl, dim > 1 ? (q / nl) % nl : 0, dim > 2 ? q / (nl * nl) : 0};
+            double v = 0.0;
+            if (!held(arr, l, g, f, v)) v = predicted(arr, l, g, f, &prev);
+            cur[(size_t)q] = v;
+          } catch (std::exception& ex) {
+#pragma omp critical
+            { if (!bad) { bad = true; e = ex.what(); } }
+          }
+        }
+        if (bad) throw std::runtime_error(e);
+        prev.swap(cur);
+      }
+      std::memcpy(out + (size_t)f * prev.size(), prev.data(), prev.size() * sizeof(double));
+    }
   }
 
   // Tile of V over a block and a halo of width H: T[f][(bs+2H)^dim], x fastest.
@@ -850,6 +911,16 @@ int orc_mr_pass(void* h, int8_t* flags, double* maxd) {
       if (flags) flags[i] = (int8_t)lf.flag;
       if (maxd) for (int f = 0; f < O->nf; ++f) maxd[i * O->nf + f] = lf.maxd[f];
     }
+    return 0;
+  })
+}
+
+// the synchronised state on the uniform lattice of `level` (Sec. 2.2 synchronised
+// values; prediction of Sec. 2.3 inside coarser leaves): out [nf][N_level^dim], x fastest
+int orc_read_uniform(void* h, int level, double* out) {
+  ORC_TRY({
+    if (level < 1 || level > O->jmax) throw std::runtime_error("read_uniform: level out of range");
+    O->uniform(&Leaf::u, level, out);
     return 0;
   })
 }

@@ -741,3 +741,87 @@ def test_refine_marked_is_graded_minimal_and_matches_refine_all(dim, seed):
     l4, c4 = c_.read_forest()
     assert np.array_equal(l4, lv3) and np.array_equal(c4, co3)
     assert np.array_equal(c_.read_stored(), db)
+
+
+# ---------------------------------------------------------------------------------------
+# the solution on a uniform lattice of any level (Sec. 2.2 synchronised values, Sec. 2.3
+# prediction inside coarser blocks; Sec. 4 takes spectra after refining to a fixed level)
+# ---------------------------------------------------------------------------------------
+
+def _inject(cfg, lv, co, data, L):
+    """Uniform level-L array from block values at the points the blocks hold (L <= every
+    block's level): each block's nodes that lie on the level-L lattice."""
+    nl = (2 ** L) * (cfg.bs - 1)
+    out = np.full((cfg.nf,) + (nl,) * cfg.dim, np.nan)
+    loc = np.indices((cfg.bs,) * cfg.dim)[::-1].reshape(cfg.dim, -1)
+    for b in range(len(lv)):
+        sh = int(lv[b]) - L
+        g = [int(co[b][a]) * (cfg.bs - 1) + loc[a] for a in range(cfg.dim)]
+        on = np.ones(loc.shape[1], bool)
+        for a in range(cfg.dim):
+            on &= (g[a] % (1 << sh)) == 0
+        idx = tuple(((g[a][on] >> sh) % nl) for a in range(cfg.dim))[::-1]
+        for f in range(cfg.nf):
+            out[(f,) + idx] = data[b, f][on]
+    return out
+
+
+def test_read_uniform_at_or_below_the_coarsest_leaf_is_injection():
+    cfg = W.C1(jmax=4)
+    o = oracle.Oracle(cfg)
+    o.init_forest(*_two_level_forest())
+    lv, co = o.read_forest()
+    o.load_blocks(W.sample(cfg, lv, co, fn=lambda x, y: np.sin(2 * np.pi * x) * np.cos(4 * np.pi * y)))
+    for L in (1, 2):
+        want = _inject(cfg, lv, co, o.read_blocks(), L)
+        assert not np.isnan(want).any()
+        assert np.array_equal(o.read_uniform(L).view(np.uint64), want.view(np.uint64))
+
+
+def test_read_uniform_reproduces_cubics_through_several_prediction_levels():
+    """Tensor-cubic data on a two-level 2D forest read on the level-5 lattice: points inside
+    the level-2 blocks are predicted through three levels, which the 4-point rule does
+    exactly for cubics (away from the periodic seam, where the data is not periodic)."""
+    cfg = W.C1(jmax=5)
+    o = oracle.Oracle(cfg)
+    o.init_forest(*_two_level_forest())
+    lv, co = o.read_forest()
+    p = lambda x: (x - 0.3) * (x - 0.55) * (x + 0.2)
+    q = lambda y: 1.0 + y * (0.5 - y * y)
+    o.load_blocks(W.sample(cfg, lv, co, fn=lambda x, y: p(x) * q(y)))
+    L = 5
+    U = o.read_uniform(L)[0]
+    n = (2 ** L) * (cfg.bs - 1)
+    g = np.arange(n) / n
+    Y, X = np.meshgrid(g, g, indexing="ij")
+    inner = (X > 0.12) & (X < 0.88) & (Y > 0.12) & (Y < 0.88)
+    assert np.max(np.abs(U - p(X) * q(Y))[inner]) < 1e-13
+    # and the data is really predicted there: sin data is not reproduced exactly
+    o.load_blocks(W.sample(cfg, lv, co, fn=lambda x, y: np.sin(6 * np.pi * x)))
+    U = o.read_uniform(L)[0]
+    assert np.max(np.abs(U - np.sin(6 * np.pi * X))[inner]) > 1e-9
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_read_uniform_is_unchanged_by_the_safety_zone_refinement(dim):
+    """Refinement gives the children the synchronised finer values (Sec. 2.1 item 1, Sec. 2.3
+    prediction), so the solution read on any finer uniform lattice is the same before and
+    after refine_all, bit for bit: the level-by-level read agrees with the point-by-point
+    ghost values that refinement uses."""
+    if dim == 2:
+        cfg = W.C1(jmax=5)
+        lv, co = W.random_graded_forest(2, 4, 5, p_refine=0.5)
+        fn = lambda x, y: np.sin(2 * np.pi * x + 0.4) * np.cos(2 * np.pi * (x + 2 * y))
+    else:
+        cfg = W.C4(jmax=4).replace(max_blocks=8 ** 4)
+        lv, co = W.random_graded_forest(3, 3, 2, p_refine=0.4)
+        fn = lambda x, y, z: np.sin(2 * np.pi * (x + 0.2 * z)) * np.cos(2 * np.pi * y)
+    o = oracle.Oracle(cfg)
+    o.init_forest(lv, co)
+    lv, co = o.read_forest()
+    o.load_blocks(W.sample(cfg, lv, co, fn=fn))
+    L = int(lv.max()) + 1
+    before = o.read_uniform(L)
+    o.refine_all()
+    after = o.read_uniform(L)
+    assert np.array_equal(before.view(np.uint64), after.view(np.uint64))
