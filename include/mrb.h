@@ -117,6 +117,18 @@ mrb_status mrb_rk4(mrb_ctx *ctx, double t, double dt);
  * (double, may be NULL) receive the result in forest order (host arrays). */
 mrb_status mrb_mr_pass(mrb_ctx *ctx, int8_t *flags, double *maxd);
 
+/* For callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): mrb_mr_pass without any device or
+ * host allocation.  Same arguments and results as mrb_mr_pass (bitwise), computed with
+ * sub-tiled analysis workgroups whose per-block partial maxima and completion counters
+ * live in a static device array of the library (2 MiB per GPU, held until the process
+ * ends; it needs n_blocks * (8 * nfields) + 4 * n_blocks bytes, rounded up, so at most
+ * about 174,000 blocks with one field or 58,000 with four: MRB_E_CAPACITY beyond).  The
+ * array is cleared by a fill kernel at each call.  Every context on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other threads) race.
+ * MRB_E_DEVICE if the array's address could not be looked up when the context was made. */
+mrb_status mrb_mr_pass_noalloc(mrb_ctx *ctx, int8_t *flags, double *maxd);
+
 /* Coarsen with the given flags (host, forest order): families of 2^dim sister
  * blocks all flagged -1 merge into their mother when the result stays graded
  * (completeness + gradedness, Sec. 2.3 last paragraph; the largest such set).

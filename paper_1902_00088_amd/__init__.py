@@ -31,7 +31,7 @@ EXPORTS = ("mrb_create", "mrb_destroy", "mrb_last_error", "mrb_init_forest", "mr
            "mrb_num_blocks", "mrb_read_forest", "mrb_read_blocks", "mrb_get_flags", "mrb_stats",
            "mrb_timing", "mrb_tune", "mrb_set_graph", "mrb_set_sweep", "mrb_mlp_init", "mrb_mlp_get_params", "mrb_mlp_features",
            "mrb_mlp_forward", "mrb_mlp_grad", "mrb_mlp_train", "mrb_mlp_predict", "mrb_refine_marked",
-           "mrb_step_predicted", "mrb_horizon_labels", "mrb_read_uniform")
+           "mrb_step_predicted", "mrb_horizon_labels", "mrb_read_uniform", "mrb_mr_pass_noalloc")
 
 
 class MrbError(RuntimeError):
@@ -77,6 +77,7 @@ def lib():
             "mrb_refine_all": [_vp],
             "mrb_rk4": [_vp, ctypes.c_double, ctypes.c_double],
             "mrb_mr_pass": [_vp, _i8p, _dp],
+            "mrb_mr_pass_noalloc": [_vp, _i8p, _dp],
             "mrb_coarsen": [_vp, _i8p, ctypes.POINTER(ctypes.c_int)],
             "mrb_adapt": [_vp, ctypes.POINTER(ctypes.c_int)],
             "mrb_step": [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_int],
@@ -242,6 +243,14 @@ class Solver:
         fl = np.zeros(n, dtype=np.int8)
         md = np.zeros((n, self.cfg.nf))
         self._chk(lib().mrb_mr_pass(self.h, _ptr(fl, _i8p), _ptr(md, _dp)))
+        return fl, md
+
+    def mr_pass_noalloc(self):
+        """mr_pass through the entry point that allocates nothing (library scratch)."""
+        n = self.num_blocks()
+        fl = np.zeros(n, dtype=np.int8)
+        md = np.zeros((n, self.cfg.nf))
+        self._chk(lib().mrb_mr_pass_noalloc(self.h, _ptr(fl, _i8p), _ptr(md, _dp)))
         return fl, md
 
     def coarsen(self, flags) -> int:

@@ -181,6 +181,12 @@ hipError_t launch_refine(const Shape& s, int nsub, int grid, const RefineArgs& a
 hipError_t launch_coarsen(const Shape& s, int grid, const CoarsenArgs& a, hipStream_t st);
 hipError_t launch_read(const Shape& s, int grid, const ReadArgs& a, hipStream_t st);
 hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst, hipStream_t st);
+// Library-owned device scratch of kScratchBytes per GPU (a static device array, no
+// allocation): scratch_setup stores its address on the current device in *out.
+constexpr size_t kScratchBytes = (size_t)2 << 20;
+hipError_t scratch_setup(void** out);
+// zero `bytes` (a multiple of 4) at p with a fill kernel
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 bool shape_supported(const Shape& s);
 // sub-tile counts compiled for this shape and precision; returns count
 int stage_variants(const Shape& s, int precision, int* nsub, int cap);

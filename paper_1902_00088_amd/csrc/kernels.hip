@@ -20,6 +20,7 @@
 
 #include <hip/hip_runtime.h>
 #include <algorithm>
+#include <mutex>
 
 namespace mrb {
 
@@ -1584,6 +1585,52 @@ hipError_t launch_read(const Shape& s, int grid, const ReadArgs& a, hipStream_t 
   MRB_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Library-owned scratch for the entry point that allocates nothing (the analysis
+// with sub-tiled workgroups: per-block partial maxima and completion counters).
+// Every GPU the library runs on holds one copy of this array until the process ends,
+// shared by every call on that GPU.  Host code never passes the array's name to a
+// kernel: it looks up the device address once per device and passes that.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_addr[kMaxDevices];
+}  // namespace
+
+hipError_t scratch_setup(void** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(scratch_mu);
+  if (!scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_addr[dev] = p;
+  }
+  *out = scratch_addr[dev];
+  return hipSuccess;
+}
+
+// zero fill (used instead of hipMemsetAsync where a caller may capture the work)
+__global__ void __launch_bounds__(256) k_zero(unsigned* p, size_t nwords) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t nw = bytes / sizeof(unsigned);
+  if (nw == 0) return hipSuccess;
+  const int grid = (int)std::min<size_t>((nw + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, st, (unsigned*)p, nw);
+  return hipGetLastError();
 }
 
 hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst, hipStream_t st) {

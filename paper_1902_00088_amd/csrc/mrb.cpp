@@ -294,9 +294,12 @@ struct mrb_ctx {
   Physics ph;
   int grid = 2048;
 
-  std::vector<int8_t> last_flags;
+  std::vector<int8_t> last_flags;     // capacity reserved for max_blocks at create
   std::vector<double> last_maxd;
   bool have_flags = false;
+  // the library's static device scratch on this context's GPU (mrb_mr_pass_noalloc)
+  void* scratch_dev = nullptr;
+  std::string scratch_err;
 
   // statistics
   long n_steps = 0, n_rk4 = 0, n_block_updates = 0, n_mr = 0, n_fam = 0, n_refined = 0;
@@ -1631,6 +1634,13 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
          hipMemset(c->dbar, 0, kBarWords * sizeof(unsigned)) == hipSuccess;
   }
   if (ok) {
+    // looked up once per device here; a failure only disables mrb_mr_pass_noalloc
+    hipError_t e = scratch_setup(&c->scratch_dev);
+    if (e != hipSuccess) c->scratch_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    c->last_flags.reserve(mb);
+    c->last_maxd.reserve(mb * cfg->nfields);
+  }
+  if (ok) {
     int dev_id = 0, ncu = 0;
     (void)hipGetDevice(&dev_id);
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) == hipSuccess && ncu > 0) {
@@ -1754,6 +1764,39 @@ mrb_status mrb_mr_pass(mrb_ctx* c, int8_t* flags, double* maxd) {
   if (flags) std::memcpy(flags, c->last_flags.data(), c->last_flags.size());
   if (maxd) std::memcpy(maxd, c->last_maxd.data(), c->last_maxd.size() * sizeof(double));
   return s;
+}
+
+mrb_status mrb_mr_pass_noalloc(mrb_ctx* c, int8_t* flags, double* maxd) {
+  if (!c) return MRB_E_ARG;
+  if (!check_state(c, true)) return MRB_E_STATE;
+  if (!c->scratch_dev) return fail(c, MRB_E_DEVICE, "mr_pass_noalloc: no scratch on this device: " + c->scratch_err);
+  const size_t n = c->hblk.size(), nf = (size_t)c->cfg.nfields;
+  const size_t acc_bytes = (n * nf * sizeof(unsigned long long) + 255) & ~(size_t)255;
+  const size_t need = acc_bytes + n * sizeof(int);
+  if (need > kScratchBytes)
+    return fail(c, MRB_E_CAPACITY, "mr_pass_noalloc: " + std::to_string(n) + " blocks x " + std::to_string(nf) +
+                                       " fields exceed the " + std::to_string(kScratchBytes) + "-byte scratch");
+  // sub-tiled workgroups: the tuned analysis tiling when it is sub-tiled, else 2 per axis
+  int va[8];
+  const int na = aux_variants(c->shape, 0, va, 8);
+  int ns = c->nsub_mr > 1 ? c->nsub_mr : 2;
+  bool compiled = false;
+  for (int i = 0; i < na; ++i) compiled = compiled || va[i] == ns;
+  if (!compiled) return fail(c, MRB_E_ARG, "mr_pass_noalloc: no sub-tiled analysis kernel for this shape");
+  // partial maxima and completion counters start at zero (the previous call may have
+  // left other contents; a fill kernel, so the call can be captured)
+  char* base = (char*)c->scratch_dev;
+  HIPCHK(c, launch_zero(base, need, c->stream));
+  MrArgs a = mr_args(c);
+  a.acc = (unsigned long long*)base;
+  a.done = (int*)(base + acc_bytes);
+  long work = (long)n;
+  for (int q = 0; q < c->cfg.dim; ++q) work *= ns;
+  HIPCHK(c, launch_mr(c->shape, ns, grid_for(c, work), a, c->stream));
+  mrb_status r = mr_readback(c);
+  if (flags) std::memcpy(flags, c->last_flags.data(), c->last_flags.size());
+  if (maxd) std::memcpy(maxd, c->last_maxd.data(), c->last_maxd.size() * sizeof(double));
+  return r;
 }
 
 mrb_status mrb_coarsen(mrb_ctx* c, const int8_t* flags, int* n_coarsened) {
