@@ -159,10 +159,14 @@ mrb_status mrb_read_forest(mrb_ctx *ctx, int8_t *level, int32_t *coords);
 mrb_status mrb_read_blocks(mrb_ctx *ctx, double *out, int on_device);
 /* The solution on the uniform lattice of `level` (periodic, N = 2^level (bs-1) nodes
  * per direction): out[nfields][N^dim], x fastest, host (on_device = 0) or device
- * memory of nfields * N^dim doubles.  Node m takes the synchronised value of the
- * finest leaf holding it (Sec. 2.2), so level may not exceed the coarsest leaf's
- * level (every lattice point is then a node of every leaf covering it); MRB_E_ARG
- * otherwise. */
+ * memory of nfields * N^dim doubles; level = 1..jmax.  Node m takes the synchronised
+ * value V(level, m): the stored value of the finest leaf holding it on its own lattice
+ * (Sec. 2.2), or, inside a coarser leaf, the prediction of Sec. 2.3 from the next
+ * coarser level, applied level by level (Sec. 4 takes spectra "after refining the mesh
+ * to a fixed level").  Leaves coarser than `level` are refined for the read into free
+ * pool slots and the forest is put back afterwards: the solver's state is unchanged.
+ * MRB_E_CAPACITY if the pool lacks the free slots for that refinement; MRB_E_ARG for a
+ * level outside 1..jmax. */
 mrb_status mrb_read_uniform(mrb_ctx *ctx, int level, double *out, int on_device);
 /* Last analysis: flags[n], maxd[n*nfields] in forest order (host; maxd may be NULL). */
 mrb_status mrb_get_flags(mrb_ctx *ctx, int8_t *flags, double *maxd);

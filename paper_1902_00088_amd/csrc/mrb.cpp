@@ -1508,6 +1508,72 @@ mrb_status step_graph(mrb_ctx* c, double t, double dt) {
   return do_adapt(c, nullptr, true, smap != nullptr);
 }
 
+// The synchronised solution on the uniform lattice of `level` into device memory dst
+// ([nf][N^dim], x fastest).  Every lattice point is a node of the finest leaf holding
+// it once no leaf is coarser than `level`, so leaves below `level` are refined first --
+// level by level, into free pool slots, with the refinement kernel, whose children take
+// the synchronised finer values (prediction where no leaf holds a node) -- on a copy of
+// the forest: the refinement writes only new slots, the solver's own slots are never
+// handed out, and the host forest and the device topology are put back afterwards.
+mrb_status read_uniform_to(mrb_ctx* c, int level, double* dst) {
+  const int nch = 1 << c->cfg.dim;
+  bool deeper = false;
+  for (const Leaf& L : c->leaves) deeper = deeper || L.level < level;
+  if (!deeper) {
+    ReadArgs a{topo(c), c->u, dst, level};
+    HIPCHK(c, launch_read(c->shape, grid_for(c, (long)c->leaves.size()), a, c->stream));
+    return MRB_OK;
+  }
+  // state to put back
+  std::vector<Leaf> leaves0 = c->leaves;
+  std::vector<BlockDesc> hblk0 = c->hblk;
+  std::vector<NbEntry> hnb0 = c->hnb;
+  std::vector<int> hlist0 = c->hlist, level0 = c->level_off, free0 = c->free_slots;
+  const long n_refined0 = c->n_refined;
+  const bool have_flags0 = c->have_flags;
+  std::vector<char> own((size_t)c->cfg.max_blocks, 0);
+  for (const Leaf& L : c->leaves) own[(size_t)L.slot] = 1;
+  mrb_status s = MRB_OK;
+  for (;;) {
+    std::vector<int> par;
+    for (int i = 0; i < (int)c->leaves.size(); ++i)
+      if (c->leaves[i].level < level) par.push_back(i);
+    if (par.empty()) break;
+    if (c->free_slots.size() < par.size() * (size_t)nch) {
+      s = fail(c, MRB_E_CAPACITY, "read_uniform: the pool has too few free slots to refine to this level");
+      break;
+    }
+    if ((s = do_refine(c, par, true, false))) break;
+    // slots of the solver's own blocks return to the free list as parents: keep them out
+    c->free_slots.erase(std::remove_if(c->free_slots.begin(), c->free_slots.end(),
+                                       [&](int sl) { return own[(size_t)sl] != 0; }),
+                        c->free_slots.end());
+  }
+  if (!s) {
+    ReadArgs a{topo(c), c->u, dst, level};
+    if (hipError_t e = launch_read(c->shape, grid_for(c, (long)c->leaves.size()), a, c->stream))
+      s = fail(c, MRB_E_DEVICE, std::string("read_uniform: ") + hipGetErrorString(e));
+  }
+  // the kernels above read the topology buffer that the restore below overwrites
+  hipError_t es = hipStreamSynchronize(c->stream);
+  c->leaves.swap(leaves0);
+  c->index.clear();
+  for (size_t i = 0; i < c->leaves.size(); ++i) c->index.set(pack_key(c->leaves[i].level, c->leaves[i].c), (int)i);
+  c->hblk.swap(hblk0);
+  c->hnb.swap(hnb0);
+  c->hlist.swap(hlist0);
+  c->level_off.swap(level0);
+  c->free_slots.swap(free0);
+  c->n_refined = n_refined0;
+  c->pending_ref = 0;
+  c->hcount_ref_zero = true;
+  mrb_status su = upload_topo(c);
+  c->have_flags = have_flags0;
+  if (s) return s;
+  if (es != hipSuccess) return fail(c, MRB_E_DEVICE, std::string("read_uniform: ") + hipGetErrorString(es));
+  return su;
+}
+
 bool graph_ok(const mrb_ctx* c) {
   return c->use_graph && !c->timing && c->cfg.form == MRB_FORM_FUSED &&
          !(c->cfg.physics == MRB_ADV_SWIRL && c->cfg.phys[0] > 0.0) && c->stream != nullptr;
@@ -1891,10 +1957,8 @@ mrb_status mrb_read_blocks(mrb_ctx* c, double* out, int on_device) {
 mrb_status mrb_read_uniform(mrb_ctx* c, int level, double* out, int on_device) {
   if (!c || !out) return MRB_E_ARG;
   if (!check_state(c, true)) return MRB_E_STATE;
-  int lmin = c->cfg.jmax;
-  for (const Leaf& L : c->leaves) lmin = std::min(lmin, L.level);
-  if (level < 1 || level > lmin)
-    return fail(c, MRB_E_ARG, "read_uniform: level must be between 1 and the coarsest leaf level");
+  if (level < 1 || level > c->cfg.jmax)
+    return fail(c, MRB_E_ARG, "read_uniform: level must be between 1 and jmax");
   size_t pts = 1;
   for (int a = 0; a < c->cfg.dim; ++a) pts *= (size_t)(1L << level) * (size_t)(c->cfg.bs - 1);
   const size_t bytes = pts * c->cfg.nfields * sizeof(double);
@@ -1904,9 +1968,7 @@ mrb_status mrb_read_uniform(mrb_ctx* c, int level, double* out, int on_device) {
     if ((s = ensure_scratch(c, bytes))) return s;
     dst = c->dscratch;
   }
-  const int n = (int)c->leaves.size();
-  ReadArgs a{topo(c), c->u, dst, level};
-  HIPCHK(c, launch_read(c->shape, grid_for(c, n), a, c->stream));
+  if ((s = read_uniform_to(c, level, dst))) return s;
   if (!on_device) HIPCHK(c, hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return MRB_OK;

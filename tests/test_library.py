@@ -409,51 +409,39 @@ def test_graph_replay_matches_direct_launches():
         M.Solver(cfg).set_graph(3)
 
 
-def _uniform_from_blocks(cfg, lv, co, data, L):
-    """Uniform level-L lattice from synchronised block values (the definition)."""
-    nl = (2 ** L) * (cfg.bs - 1)
-    out = np.full((cfg.nf,) + (nl,) * cfg.dim, np.nan)
-    loc = np.indices((cfg.bs,) * cfg.dim)[::-1].reshape(cfg.dim, -1)   # x fastest
-    for b in range(len(lv)):
-        sh = int(lv[b]) - L
-        g = [int(co[b][a]) * (cfg.bs - 1) + loc[a] for a in range(cfg.dim)]
-        on = np.ones(loc.shape[1], bool)
-        for a in range(cfg.dim):
-            on &= (g[a] % (1 << sh)) == 0
-        idx = tuple(((g[a][on] >> sh) % nl) for a in range(cfg.dim))[::-1]   # [z][y][x]
-        for f in range(cfg.nf):
-            out[(f,) + idx] = data[b, f][on]
-    return out
-
-
 @pytest.mark.gpu
-@pytest.mark.parametrize("which", ["C1", "C4"])
-def test_read_uniform_matches_oracle_blocks(which):
+@pytest.mark.parametrize("which", ["C1", "C4", "C3"])
+def test_read_uniform_matches_oracle_at_every_level(which):
+    """read_uniform at every level 1..jmax equals the oracle's level-by-level V bit for
+    bit (injection at or below the coarsest leaf, prediction through several levels above
+    it), leaves the solver's state unchanged, and the next step still equals the oracle's."""
     if which == "C1":
-        cfg = W.C1(jmax=5)
+        cfg = W.C1(jmax=5, form=W.FORM_FUSED)
         s, o = _pair(cfg)
         for n in range(3):
             s.step(n * cfg.dt, cfg.dt)
             o.step(n * cfg.dt, cfg.dt)
+    elif which == "C4":
+        cfg = W.C4(jmax=4, form=W.FORM_FUSED).replace(max_blocks=8 ** 4 + 600)
+        s, o = _pair(cfg, *W.random_graded_forest(3, 3, 7), fn=SMOOTH3)
     else:
-        cfg = W.C4(jmax=3)
-        s, o = M.Solver(cfg), oracle.Oracle(cfg)
-        o.init_forest(*W.random_graded_forest(3, 3, 7))
-        lv, co = o.read_forest()
-        s.init_forest(lv, co)
-        data = W.sample(cfg, lv, co)
-        s.load_blocks(data)
-        o.load_blocks(data)
+        cfg = W.C3(jmax=5, eps=1e-4, form=W.FORM_FUSED)
+        s, o = _pair(cfg)
     lv, co = o.read_forest()
-    lmin = int(lv.min())
-    ob = o.read_blocks()
-    for L in range(1, lmin + 1):
+    assert len(np.unique(lv)) >= 2
+    before = s.read_blocks()
+    for L in range(1, cfg.jmax + 1):
         got = s.read_uniform(L)
-        want = _uniform_from_blocks(cfg, lv, co, ob, L)
-        assert not np.isnan(want).any()
-        assert np.array_equal(_bits(got), _bits(want)), L
-    with pytest.raises(M.MrbError):
-        s.read_uniform(lmin + 1)
+        want = o.read_uniform(L)
+        assert np.array_equal(_bits(got), _bits(want)), (which, L)
+    assert_same(s, o, "after the reads")
+    assert np.array_equal(_bits(s.read_blocks()), _bits(before))
+    for bad in (0, cfg.jmax + 1):
+        with pytest.raises(M.MrbError):
+            s.read_uniform(bad)
+    s.step(0.5, cfg.dt)
+    o.step(0.5, cfg.dt)
+    assert_same(s, o, "step after the reads")
     s.close()
 
 
