@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <mutex>
 
+
 namespace mrb {
 
 template <int DIM, int N>
@@ -813,23 +814,49 @@ __device__ __forceinline__ void stage_pass(const StageArgs& A, const StageVar& V
         }
       }
     } else {
-      // lanes along x, rows of the region walked by row groups
+      // lanes along x, rows of the region walked by row groups, ER rows per lane and
+      // round: the last stage's operands (u, k1, k2, k3) of a round's rows are loaded
+      // together, before any of them is used, so their latencies overlap
       constexpr int RGS = TPB / S, NR = Pow<DIM - 1, S>::v;
+      constexpr int ER = 4;
       const int lx = (int)threadIdx.x % S, rgs = (int)threadIdx.x / S;
-      for (int row = rgs; rgs < RGS && lx < cnt[0] && row < NR; row += RGS) {
-        const int ly = DIM > 2 ? row % S : row, lz = DIM > 2 ? row / S : 0;
-        if (ly >= cnt[1] || (DIM > 2 && lz >= cnt[2])) continue;
-        int l[3] = {lx, ly, lz};
-        int t[3] = {r0[0] + l[0], r0[1] + l[1], r0[2] + l[2]};
-        int i[3] = {l[0] + HW, l[1] + HW, DIM > 2 ? l[2] + HW : 0};
-        const TT kv = rhs_adv<DIM, BS, S, HW, TT>(tile, i, t, d, r, A, V.cfac, sw_lds ? swirl : nullptr, l);
-        const size_t q = base + t[0] + BS * t[1] + (DIM > 2 ? BS * BS * t[2] : 0);
-        if (V.stage < 4) {
-          ((KT*)V.kout)[q] = (KT)kv;
-        } else {
-          const double k1 = (double)((const KT*)A.k1)[q], k2 = (double)((const KT*)A.k2)[q];
-          const double k3 = (double)((const KT*)A.k3)[q], k4 = (double)kv;
-          A.unew[q] = A.u[q] + A.h6 * ((k1 + k4) + 2.0 * (k2 + k3));
+      for (int row0 = rgs; rgs < RGS && lx < cnt[0] && row0 < NR; row0 += ER * RGS) {
+        int tq[ER][3];
+        bool ok[ER];
+        size_t qa[ER];
+#pragma unroll
+        for (int e = 0; e < ER; ++e) {
+          const int row = row0 + e * RGS;
+          const int ly = DIM > 2 ? row % S : row, lz = DIM > 2 ? row / S : 0;
+          ok[e] = row < NR && ly < cnt[1] && (DIM < 3 || lz < cnt[2]);
+          tq[e][0] = r0[0] + lx;
+          tq[e][1] = r0[1] + ly;
+          tq[e][2] = DIM > 2 ? r0[2] + lz : 0;
+          // rows past the region read the block's first node (in bounds) and are dropped
+          qa[e] = ok[e] ? base + tq[e][0] + BS * tq[e][1] + (DIM > 2 ? BS * BS * tq[e][2] : 0) : base;
+        }
+        double e1[ER], e2[ER], e3[ER], eu[ER];
+        if (V.stage == 4) {
+#pragma unroll
+          for (int e = 0; e < ER; ++e) {
+            e1[e] = (double)((const KT*)A.k1)[qa[e]];
+            e2[e] = (double)((const KT*)A.k2)[qa[e]];
+            e3[e] = (double)((const KT*)A.k3)[qa[e]];
+            eu[e] = A.u[qa[e]];
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < ER; ++e) {
+          if (!ok[e]) continue;
+          int l[3] = {lx, tq[e][1] - r0[1], DIM > 2 ? tq[e][2] - r0[2] : 0};
+          int i[3] = {l[0] + HW, l[1] + HW, DIM > 2 ? l[2] + HW : 0};
+          const TT kv = rhs_adv<DIM, BS, S, HW, TT>(tile, i, tq[e], d, r, A, V.cfac, sw_lds ? swirl : nullptr, l);
+          if (V.stage < 4) {
+            ((KT*)V.kout)[qa[e]] = (KT)kv;
+          } else {
+            const double k4 = (double)kv;
+            A.unew[qa[e]] = eu[e] + A.h6 * ((e1[e] + k4) + 2.0 * (e2[e] + e3[e]));
+          }
         }
       }
     }
