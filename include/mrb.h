@@ -217,6 +217,22 @@ mrb_status mrb_set_graph(mrb_ctx *ctx, int enable);
  * Not a step of the method: a schedule choice. */
 mrb_status mrb_set_sweep(mrb_ctx *ctx, int mode);
 
+/* Where mrb_step plans the topology changes of a step: the safety-zone refinement,
+ * the completeness and gradedness fixed point of each coarsening (Sec. 2.3, last
+ * paragraph) and the neighbour entries of every new grid.  mode 0: on the host (plans of
+ * forests of at most 1,024 leaves are memoised, see mrb_step).  mode 1: on the device,
+ * by plan kernels (prefix sums over the forest order, a free-slot stack and a dense index
+ * of every possible block of every level), so a step reads back only a few counts per
+ * analysis pass.  mode 2 (default): on the device when the refined grid would exceed
+ * 1,024 leaves, on the host below.  Results are identical in every mode (same forest,
+ * same slots).  The device path needs the fused form and a dense index of at most 2^26
+ * blocks over all levels (otherwise the host plans), and processes blocks in forest
+ * order.  Entry points other than mrb_step, mrb_num_blocks, mrb_mr_pass_noalloc and the
+ * settings bring the host forest up to date first (a copy of the descriptors and the
+ * free list back from the device).  MRB_E_ARG for other values.
+ * Not a step of the method: a schedule choice. */
+mrb_status mrb_set_topology(mrb_ctx *ctx, int mode);
+
 /* ---------------------------------------------------------------------------
  * Learned refinement predictor.  The paper's refinement flag admits "+1 for
  * refinement" from arbitrary indicators besides the detail test (Sec. 2.3, after the

@@ -31,7 +31,8 @@ EXPORTS = ("mrb_create", "mrb_destroy", "mrb_last_error", "mrb_init_forest", "mr
            "mrb_num_blocks", "mrb_read_forest", "mrb_read_blocks", "mrb_get_flags", "mrb_stats",
            "mrb_timing", "mrb_tune", "mrb_set_graph", "mrb_set_sweep", "mrb_mlp_init", "mrb_mlp_get_params", "mrb_mlp_features",
            "mrb_mlp_forward", "mrb_mlp_grad", "mrb_mlp_train", "mrb_mlp_predict", "mrb_refine_marked",
-           "mrb_step_predicted", "mrb_horizon_labels", "mrb_read_uniform", "mrb_mr_pass_noalloc")
+           "mrb_step_predicted", "mrb_horizon_labels", "mrb_read_uniform", "mrb_mr_pass_noalloc",
+           "mrb_set_topology")
 
 
 class MrbError(RuntimeError):
@@ -91,6 +92,7 @@ def lib():
             "mrb_tune": [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int)],
             "mrb_set_graph": [_vp, ctypes.c_int],
             "mrb_set_sweep": [_vp, ctypes.c_int],
+            "mrb_set_topology": [_vp, ctypes.c_int],
             "mrb_mlp_init": [_vp, ctypes.c_int, _fp, _fp, _fp],
             "mrb_mlp_get_params": [_vp, _fp],
             "mrb_mlp_features": [_vp, _fp],
@@ -290,6 +292,10 @@ class Solver:
         """Stage launches of the fused form: 0 four launches, 1 one launch with grid
         barriers, 2 the autotuner's choice (default)."""
         self._chk(lib().mrb_set_sweep(self.h, int(mode)))
+
+    def set_topology(self, mode: int):
+        """Topology planning in step(): 0 host, 1 device, 2 device above 1,024 refined leaves (default)."""
+        self._chk(lib().mrb_set_topology(self.h, int(mode)))
 
     def timing(self, enable: bool):
         self._chk(lib().mrb_timing(self.h, 1 if enable else 0))

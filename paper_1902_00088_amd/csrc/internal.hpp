@@ -181,6 +181,38 @@ hipError_t launch_refine(const Shape& s, int nsub, int grid, const RefineArgs& a
 hipError_t launch_coarsen(const Shape& s, int grid, const CoarsenArgs& a, hipStream_t st);
 hipError_t launch_read(const Shape& s, int grid, const ReadArgs& a, hipStream_t st);
 hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst, hipStream_t st);
+// Device-resident topology transitions (topo.hip).  Arenas share the TopoHeader layout;
+// old_* is the current grid, new_* the next one.
+struct DevTopoArgs {
+  const char* old_base;
+  TopoHeader old_h;
+  char* new_base;
+  TopoHeader new_h;
+  int* cells;                       // dense index: position in the current grid, or -1
+  int cell_off[kMaxLevels + 1];     // first cell of each level
+  int* free_stack;
+  int free_top;                     // entries in the free stack at launch
+  const int8_t* flags;              // analysis flags of the current grid (coarsening plan)
+  const double* maxd;               // and its detail maxima [n][nf] (checked for finiteness)
+  int nf;
+  int* scratch;                     // [3 * max_blocks] ints
+  int* edges;                       // [2 + 2 * max_blocks * entry stride] ints (coarsening plan;
+                                    // first the candidates, then the edges)
+  int* err;                         // device word: error bits (1 not graded, 2 non-finite detail
+                                    // norm; the coarsening plan adds 4: too few free slots)
+  int* out;                         // mapped host ints (plain stores only): [0] parents or families,
+                                    // [1] new block count, [2] new free-stack top, [3] error bits
+                                    // (the coarsening plan moves and clears *err), [4..) level histogram
+  int dim, bs, jmax, nch;
+};
+hipError_t launch_plan_refine(const DevTopoArgs& a, hipStream_t st);
+hipError_t launch_plan_coarsen(const DevTopoArgs& a, int grid, hipStream_t st);   // four launches
+hipError_t launch_index(const DevTopoArgs& a, int set, int grid, hipStream_t st);   // set 0: clear old, 1: set new
+hipError_t launch_entries(const DevTopoArgs& a, int grid, hipStream_t st);
+hipError_t launch_fill_int(int* p, size_t n, int v, hipStream_t st);
+constexpr int kDevOutInts = 4 + kMaxLevels;
+constexpr int kAliveLds = 32768;   // families whose live flags the coarsening plan keeps in LDS
+
 // Library-owned device scratch of kScratchBytes per GPU (a static device array, no
 // allocation): scratch_setup stores its address on the current device in *out.
 constexpr size_t kScratchBytes = (size_t)2 << 20;

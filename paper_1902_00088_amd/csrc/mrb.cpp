@@ -300,6 +300,36 @@ struct mrb_ctx {
   // the library's static device scratch on this context's GPU (mrb_mr_pass_noalloc)
   void* scratch_dev = nullptr;
   std::string scratch_err;
+  // Device-resident topology (topo.hip): the step's refinement and coarsening plans and
+  // neighbour entries are built on the device; the host forest above is brought up to
+  // date (pulled) only when an entry point other than mrb_step needs it.
+  struct DevTopo {
+    bool ready = false;          // buffers allocated
+    bool active = false;         // the device holds the current grid (host copy stale)
+    bool unavailable = false;    // the dense index would not fit
+    int mode = 2;                // 0 host planning, 1 device, 2 device when the refined grid exceeds
+                                 // the memo limit (host plans are memoised below it)
+    char* arena[2] = {nullptr, nullptr};
+    size_t arena_bytes = 0;
+    int cur = 0;
+    int stride = 0;              // entry row stride: the most entries a block can have
+    int* cells = nullptr;
+    size_t ncells = 0;
+    int cell_off[kMaxLevels + 1];
+    int* stack = nullptr;        // free pool slots
+    int* scratch = nullptr;      // [3 * max_blocks]
+    int* edges = nullptr;        // coarsening plan: edge count, family count, edges
+    int* err = nullptr;          // device error word
+    int8_t* flags = nullptr;     // analysis flags and maxima of the device path
+    double* maxd = nullptr;
+    int* h_out = nullptr;        // mapped counts written by the plan kernels
+    int* d_out = nullptr;
+    int n = 0, top = 0;
+    long hist[kMaxLevels];
+    bool have_flags = false;     // flags/maxd above describe the current grid
+    Staging st_blk, st_stack;
+    long steps = 0, passes = 0, pushes = 0, pulls = 0;
+  } dev;
 
   // statistics
   long n_steps = 0, n_rk4 = 0, n_block_updates = 0, n_mr = 0, n_fam = 0, n_refined = 0;
@@ -334,8 +364,9 @@ mrb_status fail(mrb_ctx* c, mrb_status s, const std::string& m) {
 }
 
 // kernel kinds for timing
-enum { T_STAGE = 0, T_GHOST = 1, T_RHS_PLAIN = 2, T_MR = 3, T_REFINE = 4, T_COARSEN = 5, T_READ = 6, T_NKIND = 7 };
-const char* kKindName[T_NKIND] = {"stage", "ghost", "rhs_plain", "mr", "refine", "coarsen", "read"};
+enum { T_STAGE = 0, T_GHOST = 1, T_RHS_PLAIN = 2, T_MR = 3, T_REFINE = 4, T_COARSEN = 5, T_READ = 6, T_TOPO = 7,
+       T_NKIND = 8 };
+const char* kKindName[T_NKIND] = {"stage", "ghost", "rhs_plain", "mr", "refine", "coarsen", "read", "topology"};
 
 hipEvent_t take_event(mrb_ctx* c) {
   if (!c->ev_pool.empty()) {
@@ -772,6 +803,9 @@ mrb_status memo_record(mrb_ctx* c, int kind, std::vector<int>& material, size_t 
 
 int grid_for(const mrb_ctx* c, long n) { return (int)std::max(1L, std::min((long)c->grid, n)); }
 
+// blocks of the current grid (the device's count while it holds the topology)
+size_t nblk(const mrb_ctx* c) { return c->dev.active ? (size_t)c->dev.n : c->hblk.size(); }
+
 mrb_status check_forest(mrb_ctx* c) {
   const int d = c->cfg.dim, jmax = c->cfg.jmax;
   // no duplicates, no leaf inside another, volumes sum to the domain
@@ -811,7 +845,7 @@ int pick_nsub(const mrb_ctx* c) {
       if (v[i] == c->nsub) return c->nsub;
   }
   std::sort(v, v + nv);
-  const long n = (long)c->hblk.size();
+  const long n = (long)nblk(c);
   for (int i = 0; i < nv; ++i) {
     long w = n;
     for (int a = 0; a < c->cfg.dim; ++a) w *= v[i];
@@ -843,7 +877,7 @@ int pick_aux(const mrb_ctx* c, long n_items, int forced = 0) {
 // launch one RK stage (fused) or ghost + RHS per level (plain)
 mrb_status run_stage(mrb_ctx* c, int s, const StageArgs& a0, bool fixed_grid = false, bool time_it = true) {
   StageArgs a = a0;
-  const int n = (int)c->hblk.size();
+  const int n = (int)nblk(c);
   if (c->cfg.form == MRB_FORM_PLAIN) {
     for (int l = 1; l <= c->cfg.jmax; ++l) {
       const int b0 = c->level_off[l], b1 = c->level_off[l + 1];
@@ -871,7 +905,7 @@ StageArgs stage_args(mrb_ctx* c) {
   a.topo = topo(c);
   a.lvl_begin = 0;
   a.lvl_end = -1;
-  a.order = c->order;
+  a.order = c->dev.active ? 0 : c->order;   // the device path builds no level-sorted list
   a.u = c->u;
   a.unew = c->unew;
   a.k1 = c->k[0];
@@ -899,7 +933,7 @@ mrb_status sweep(mrb_ctx* c, double t, double dt, bool fixed_grid = false) {
   // fused form: one event pair around the four stage launches
   const bool fused = c->cfg.form == MRB_FORM_FUSED;
   double sweep_bytes = 0.0;
-  for (int s = 1; s <= 4; ++s) sweep_bytes += (double)c->hblk.size() * c->bsz * stage_bytes(c, s);
+  for (int s = 1; s <= 4; ++s) sweep_bytes += (double)nblk(c) * c->bsz * stage_bytes(c, s);
   TimeScope sweep_scope(c, T_STAGE, sweep_bytes, 4, fused);
   if (!fixed_grid && sweep_in_one(c)) {
     SweepArgs sa;
@@ -914,7 +948,7 @@ mrb_status sweep(mrb_ctx* c, double t, double dt, bool fixed_grid = false) {
     sa.err = c->d_err;
     sa.spin = 1u << 22;
     const int nsub = pick_nsub(c);
-    long work = (long)c->hblk.size();
+    long work = (long)nblk(c);
     for (int d = 0; d < c->cfg.dim; ++d) work *= nsub;
     HIPCHK(c, launch_sweep(c->shape, c->cfg.precision, Variant{nsub}, (int)std::min(work, 1L << 30), sa, c->stream,
                            &c->sweep_grid));
@@ -938,7 +972,7 @@ mrb_status do_rk4(mrb_ctx* c, double t, double dt) {
   if (r) return r;
   std::swap(c->u, c->unew);
   c->n_rk4++;
-  c->n_block_updates += (long)c->hblk.size();
+  c->n_block_updates += (long)nblk(c);
   return MRB_OK;
 }
 
@@ -1067,7 +1101,7 @@ MrArgs mr_args(mrb_ctx* c) {
 
 // `spec`: a memoised coarsening of the current grid whose mothers the pass also writes
 mrb_status launch_mr_kernel(mrb_ctx* c, bool fixed_grid, const mrb_ctx::Memo* spec = nullptr) {
-  const int n = (int)c->hblk.size();
+  const int n = (int)nblk(c);
   MrArgs a = mr_args(c);
   if (spec) a.smap = spec->smap;
   const int ns = pick_aux(c, n, c->nsub_mr);
@@ -1093,7 +1127,7 @@ mrb_status check_barrier(mrb_ctx* c) {
 }
 
 mrb_status mr_readback(mrb_ctx* c) {
-  const int n = (int)c->hblk.size();
+  const int n = (int)nblk(c);
   {
     HostTimer ht(&c->hus_wait);
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1574,6 +1608,316 @@ mrb_status read_uniform_to(mrb_ctx* c, int level, double* dst) {
   return su;
 }
 
+// ---------------------------------------------------------------------------
+// device-resident topology (the plan kernels are in topo.hip)
+// ---------------------------------------------------------------------------
+
+// Arena layout of the device path: fixed offsets for max_blocks blocks and entry rows of
+// the largest possible entry count, so a plan kernel can write a grid whose size the
+// host learns only afterwards.
+TopoHeader dev_header(const mrb_ctx* c, int n, int nref, int nfam) {
+  TopoHeader h;
+  std::memset(&h, 0, sizeof h);
+  const size_t cap = (size_t)c->cfg.max_blocks, S = (size_t)c->dev.stride;
+  size_t off = align16(sizeof(TopoHeader));
+  auto place = [&](size_t bytes) {
+    const size_t o = off;
+    off = align16(off + bytes);
+    return (int)o;
+  };
+  h.off_blk = place(cap * sizeof(BlockDesc));
+  h.off_nb = place(cap * S * sizeof(NbEntry));
+  h.off_list = place(cap * sizeof(int));
+  h.off_pblk = place(cap * sizeof(BlockDesc));
+  h.off_pnb = place(cap * S * sizeof(NbEntry));
+  h.off_ref = place(cap * sizeof(RefineDesc));
+  h.off_fam = place(cap * sizeof(FamilyDesc));
+  h.nb_stride = h.pnb_stride = (int)S;
+  h.n_blocks = n;
+  h.n_ref = h.n_pblk = nref;
+  h.n_fam = nfam;
+  h.pad[0] = (int)std::min(off, (size_t)0x7fffffff);   // bytes of the layout (host bookkeeping only)
+  return h;
+}
+
+// allocate the device path's buffers once; false (with dev.unavailable) if the dense
+// index of every possible block would not fit
+mrb_status dev_alloc(mrb_ctx* c) {
+  auto& D = c->dev;
+  if (D.ready) return MRB_OK;
+  const int d = c->cfg.dim;
+  size_t cells = 0;
+  for (int l = 0; l <= c->cfg.jmax + 1 && l <= kMaxLevels; ++l) {
+    D.cell_off[l] = (int)cells;
+    if (l >= 1 && l <= c->cfg.jmax) cells += (size_t)1 << (d * l);
+    if (cells > ((size_t)1 << 26)) {
+      D.unavailable = true;
+      return fail(c, MRB_E_ARG, "device topology: the dense block index of this jmax does not fit");
+    }
+  }
+  D.ncells = cells;
+  D.stride = d == 2 ? 13 : 57;
+  const TopoHeader h = dev_header(c, 0, 0, 0);
+  const size_t ab = (size_t)h.pad[0];
+  if (ab >= (size_t)0x7fffffff) return fail(c, MRB_E_CAPACITY, "device topology: arena exceeds 2 GiB");
+  const size_t mb = (size_t)c->cfg.max_blocks;
+  HIPCHK(c, hipMalloc((void**)&D.arena[0], ab));
+  HIPCHK(c, hipMalloc((void**)&D.arena[1], ab));
+  HIPCHK(c, hipMalloc((void**)&D.cells, cells * sizeof(int)));
+  HIPCHK(c, hipMalloc((void**)&D.stack, mb * sizeof(int)));
+  HIPCHK(c, hipMalloc((void**)&D.scratch, 3 * mb * sizeof(int)));
+  HIPCHK(c, hipMalloc((void**)&D.edges, (2 + 2 * mb * (size_t)D.stride) * sizeof(int)));
+  HIPCHK(c, hipMalloc((void**)&D.err, 256));
+  HIPCHK(c, hipMemset(D.err, 0, 256));
+  HIPCHK(c, hipMalloc((void**)&D.flags, std::max(mb, (size_t)256)));
+  HIPCHK(c, hipMalloc((void**)&D.maxd, std::max(mb * c->cfg.nfields * sizeof(double), (size_t)256)));
+  HIPCHK(c, hipHostMalloc((void**)&D.h_out, kDevOutInts * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+  HIPCHK(c, hipHostGetDevicePointer((void**)&D.d_out, D.h_out, 0));
+  D.arena_bytes = ab;
+  D.ready = true;
+  return MRB_OK;
+}
+
+void dev_release(mrb_ctx* c) {
+  auto& D = c->dev;
+  release_staging(D.st_blk);
+  release_staging(D.st_stack);
+  void* p[] = {D.arena[0], D.arena[1], D.cells, D.stack, D.scratch, D.edges, D.err, D.flags, D.maxd};
+  for (void* q : p)
+    if (q) (void)hipFree(q);
+  if (D.h_out) (void)hipHostFree(D.h_out);
+}
+
+DevTopoArgs dev_args(mrb_ctx* c, int from, const TopoHeader& oh, int to, const TopoHeader& nh) {
+  auto& D = c->dev;
+  DevTopoArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.old_base = D.arena[from];
+  a.old_h = oh;
+  a.new_base = D.arena[to];
+  a.new_h = nh;
+  a.cells = D.cells;
+  for (int l = 0; l <= kMaxLevels; ++l) a.cell_off[l] = D.cell_off[std::min(l, c->cfg.jmax + 1)];
+  a.free_stack = D.stack;
+  a.free_top = D.top;
+  a.flags = D.flags;
+  a.maxd = D.maxd;
+  a.nf = c->cfg.nfields;
+  a.scratch = D.scratch;
+  a.edges = D.edges;
+  a.err = D.err;
+  a.out = D.d_out;
+  a.dim = c->cfg.dim;
+  a.bs = c->cfg.bs;
+  a.jmax = c->cfg.jmax;
+  a.nch = 1 << c->cfg.dim;
+  return a;
+}
+
+int dev_grid(long waves) { return (int)std::max(1L, std::min(8192L, (waves + 3) / 4)); }
+
+// the device takes over the host forest: descriptors and free stack uploaded, dense
+// index and entries built on the device
+mrb_status dev_push(mrb_ctx* c) {
+  auto& D = c->dev;
+  if (mrb_status s = dev_alloc(c)) return s;
+  HostTimer ht(&c->hus_upload);
+  const int n = (int)c->leaves.size();
+  std::vector<BlockDesc> bd(n);
+  for (int i = 0; i < n; ++i) {
+    const Leaf& L = c->leaves[i];
+    bd[i].slot = L.slot;
+    bd[i].level = L.level;
+    for (int a = 0; a < 3; ++a) bd[i].c[a] = L.c[a];
+    bd[i].nb_begin = bd[i].n_ent = bd[i].n_coarse = 0;
+  }
+  D.cur = 0;
+  const TopoHeader h = dev_header(c, n, 0, 0);
+  if (mrb_status s = stage_upload(c, D.st_blk, bd.data(), n * sizeof(BlockDesc), D.arena[D.cur] + h.off_blk)) return s;
+  if (!c->free_slots.empty())
+    if (mrb_status s = stage_upload(c, D.st_stack, c->free_slots.data(), c->free_slots.size() * sizeof(int), D.stack))
+      return s;
+  HIPCHK(c, launch_fill_int(D.cells, D.ncells, -1, c->stream));
+  D.top = (int)c->free_slots.size();
+  D.n = n;
+  for (int l = 0; l < kMaxLevels; ++l) D.hist[l] = 0;
+  for (const Leaf& L : c->leaves) D.hist[L.level]++;
+  DevTopoArgs a = dev_args(c, D.cur, h, D.cur, h);
+  {
+    TimeScope ts(c, T_TOPO, 0.0);
+    HIPCHK(c, launch_index(a, 1, dev_grid(4L * n), c->stream));
+    HIPCHK(c, launch_entries(a, dev_grid(n), c->stream));
+  }
+  c->arena = D.arena[D.cur];
+  c->arena_hdr = h;
+  c->pending_ref = 0;
+  D.have_flags = false;
+  D.active = true;
+  D.pushes++;
+  return MRB_OK;
+}
+
+// the host takes the forest back from the device: descriptors and free stack
+// downloaded, host entries rebuilt and uploaded, flags of the last analysis kept
+mrb_status dev_pull(mrb_ctx* c) {
+  auto& D = c->dev;
+  if (!D.active) return MRB_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int err = 0;
+  HIPCHK(c, hipMemcpy(&err, D.err, sizeof(int), hipMemcpyDeviceToHost));
+  if (err & 1) return fail(c, MRB_E_TOPOLOGY, "device topology: a grid was not graded");
+  const TopoHeader h = c->arena_hdr;
+  std::vector<BlockDesc> bd(D.n);
+  std::vector<int> stack(D.top);
+  HIPCHK(c, hipMemcpy(bd.data(), D.arena[D.cur] + h.off_blk, D.n * sizeof(BlockDesc), hipMemcpyDeviceToHost));
+  if (D.top) HIPCHK(c, hipMemcpy(stack.data(), D.stack, D.top * sizeof(int), hipMemcpyDeviceToHost));
+  std::vector<int8_t> fl;
+  std::vector<double> md;
+  if (D.have_flags) {
+    fl.resize(D.n);
+    md.resize((size_t)D.n * c->cfg.nfields);
+    HIPCHK(c, hipMemcpy(fl.data(), D.flags, D.n, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(md.data(), D.maxd, md.size() * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  c->leaves.resize(D.n);
+  for (int i = 0; i < D.n; ++i) {
+    Leaf& L = c->leaves[i];
+    L.level = bd[i].level;
+    for (int a = 0; a < 3; ++a) L.c[a] = bd[i].c[a];
+    L.slot = bd[i].slot;
+  }
+  c->free_slots.swap(stack);
+  D.active = false;
+  D.pulls++;
+  sort_and_index(c);   // the device order is the forest order already; keys and index rebuilt
+  if (mrb_status s = build_descriptors(c)) return s;
+  c->hcount_ref_zero = true;
+  c->pending_ref = 0;
+  if (mrb_status s = upload_topo(c)) return s;
+  if (D.have_flags) {
+    c->last_flags.assign(fl.begin(), fl.end());
+    c->last_maxd.assign(md.begin(), md.end());
+    c->have_flags = true;
+  }
+  return MRB_OK;
+}
+
+// the safety-zone refinement planned and run on the device
+mrb_status dev_refine_all(mrb_ctx* c) {
+  auto& D = c->dev;
+  const int nch = 1 << c->cfg.dim;
+  const int nref = D.n - (int)D.hist[c->cfg.jmax];
+  c->pending_ref = 0;
+  if (nref == 0) return MRB_OK;
+  if (D.top < nref * nch) return fail(c, MRB_E_CAPACITY, "refine_all: pool too small");
+  const int nnew = D.n + nref * (nch - 1), nxt = D.cur ^ 1;
+  const TopoHeader nh = dev_header(c, nnew, nref, 0);
+  DevTopoArgs a = dev_args(c, D.cur, c->arena_hdr, nxt, nh);
+  {
+    TimeScope ts(c, T_TOPO, 0.0);
+    HIPCHK(c, launch_plan_refine(a, c->stream));
+    HIPCHK(c, launch_index(a, 0, dev_grid(4L * D.n), c->stream));
+    HIPCHK(c, launch_index(a, 1, dev_grid(4L * nnew), c->stream));
+    HIPCHK(c, launch_entries(a, dev_grid((long)nnew + nref), c->stream));
+  }
+  long h2[kMaxLevels] = {0};
+  for (int l = 1; l < kMaxLevels; ++l) {
+    if (l < c->cfg.jmax) h2[l + 1] += D.hist[l] * nch;
+    else h2[l] += D.hist[l];
+  }
+  for (int l = 0; l < kMaxLevels; ++l) D.hist[l] = h2[l];
+  D.top = D.top - nref * nch + nref;
+  D.n = nnew;
+  D.cur = nxt;
+  D.have_flags = false;
+  c->arena = D.arena[D.cur];
+  c->arena_hdr = nh;
+  c->pending_ref = nref;
+  c->n_refined += nref;
+  c->have_flags = false;
+  return launch_refine_kernel(c, nref, false);
+}
+
+// analysis and coarsening until nothing merges, planned on the device; one read-back
+// of a few counts per pass
+mrb_status dev_adapt(mrb_ctx* c, int* npass) {
+  auto& D = c->dev;
+  const int nch = 1 << c->cfg.dim;
+  int passes = 0;
+  for (;;) {
+    {
+      const int n = D.n;
+      MrArgs m = mr_args(c);
+      m.flags = D.flags;
+      m.maxd = D.maxd;
+      const int ns = pick_aux(c, n, c->nsub_mr);
+      long work = n;
+      for (int q = 0; q < c->cfg.dim; ++q) work *= ns;
+      TimeScope ts(c, T_MR, (double)n * c->bsz * 8.0);
+      HIPCHK(c, launch_mr(c->shape, ns, grid_for(c, work), m, c->stream));
+    }
+    ++passes;
+    c->n_mr++;
+    D.passes++;
+    const int nxt = D.cur ^ 1;
+    DevTopoArgs a = dev_args(c, D.cur, c->arena_hdr, nxt, dev_header(c, 0, 0, 0));
+    {
+      TimeScope ts(c, T_TOPO, 0.0);
+      HIPCHK(c, launch_plan_coarsen(a, dev_grid((long)D.n * D.stride / 16), c->stream));
+    }
+    {
+      HostTimer ht(&c->hus_wait);
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (mrb_status r = check_barrier(c)) return r;
+    const int m = D.h_out[0], nnew = D.h_out[1], top = D.h_out[2], err = D.h_out[3];
+    D.have_flags = true;
+    c->have_flags = false;
+    if (err & 1) return fail(c, MRB_E_TOPOLOGY, "device topology: a grid was not graded");
+    if (err & 2) return fail(c, MRB_E_NONFINITE, "detail norm is not finite");
+    if (err & 4) return fail(c, MRB_E_CAPACITY, "coarsen: pool too small");
+    if (m == 0) break;
+    if (passes > c->cfg.jmax + 2) return fail(c, MRB_E_STATE, "adapt did not reach a fixed point");
+    if (nnew != D.n - m * (nch - 1)) return fail(c, MRB_E_STATE, "device topology: inconsistent coarsening counts");
+    const TopoHeader nh = dev_header(c, nnew, 0, m);
+    a = dev_args(c, D.cur, c->arena_hdr, nxt, nh);
+    {
+      TimeScope ts(c, T_TOPO, 0.0);
+      HIPCHK(c, launch_index(a, 0, dev_grid(4L * D.n), c->stream));
+      HIPCHK(c, launch_index(a, 1, dev_grid(4L * nnew), c->stream));
+      HIPCHK(c, launch_entries(a, dev_grid(nnew), c->stream));
+    }
+    for (int l = 0; l < kMaxLevels; ++l) D.hist[l] = D.h_out[4 + l];
+    D.top = top;
+    D.n = nnew;
+    D.cur = nxt;
+    D.have_flags = false;
+    c->arena = D.arena[D.cur];
+    c->arena_hdr = nh;
+    c->n_fam += m;
+    CoarsenArgs ca{topo(c), c->u};
+    const long total = (long)m * c->np;
+    TimeScope ts(c, T_COARSEN, (double)total * c->cfg.nfields * 16.0);
+    HIPCHK(c, launch_coarsen(c->shape, (int)std::min(4096L, (total + 255) / 256), ca, c->stream));
+  }
+  if (npass) *npass = passes;
+  return MRB_OK;
+}
+
+// whether mrb_step plans on the device: fused form, a dense index that fits, and mode 1,
+// or mode 2 with a refined grid above the memo limit
+bool want_device(mrb_ctx* c) {
+  auto& D = c->dev;
+  if (D.mode == 0 || D.unavailable || c->cfg.form != MRB_FORM_FUSED) return false;
+  if (D.mode == 1) return true;
+  const long n = (long)nblk(c);
+  long below = 0;
+  if (D.active) below = n - D.hist[c->cfg.jmax];
+  else
+    for (const Leaf& L : c->leaves) below += L.level < c->cfg.jmax;
+  return n + below * ((1L << c->cfg.dim) - 1) > (long)kMemoMaxLeaves;
+}
+
 bool graph_ok(const mrb_ctx* c) {
   return c->use_graph && !c->timing && c->cfg.form == MRB_FORM_FUSED &&
          !(c->cfg.physics == MRB_ADV_SWIRL && c->cfg.phys[0] > 0.0) && c->stream != nullptr;
@@ -1733,6 +2077,7 @@ mrb_status mrb_destroy(mrb_ctx* c) {
     if (p) (void)hipFree(p);
   for (auto& e : c->memo)
     if (e.arena) (void)hipFree(e.arena);
+  dev_release(c);
   void* ptrs[] = {c->work_arena, c->dacc, c->ddone,
                   c->ds2, c->ds, c->dghost, c->dscratch, c->dslots, c->dbar};
   for (void* p : ptrs)
@@ -1748,6 +2093,10 @@ mrb_status mrb_destroy(mrb_ctx* c) {
 
 mrb_status mrb_init_forest(mrb_ctx* c, int n, const int8_t* level, const int32_t* coords) {
   if (!c) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (n <= 0 || !level || !coords) return fail(c, MRB_E_ARG, "init_forest: empty forest or null arrays");
   if (n > c->cfg.max_blocks) return fail(c, MRB_E_CAPACITY, "init_forest: more blocks than max_blocks");
   const int d = c->cfg.dim;
@@ -1788,6 +2137,10 @@ mrb_status mrb_init_forest(mrb_ctx* c, int n, const int8_t* level, const int32_t
 
 mrb_status mrb_load_blocks(mrb_ctx* c, const double* data, int on_device) {
   if (!c) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, false)) return MRB_E_STATE;
   if (!data) return fail(c, MRB_E_ARG, "load_blocks: null data");
   const int n = (int)c->leaves.size();
@@ -1811,12 +2164,20 @@ mrb_status mrb_load_blocks(mrb_ctx* c, const double* data, int on_device) {
 
 mrb_status mrb_refine_all(mrb_ctx* c) {
   if (!c) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, true)) return MRB_E_STATE;
   return do_refine_all(c);
 }
 
 mrb_status mrb_rk4(mrb_ctx* c, double t, double dt) {
   if (!c) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, true)) return MRB_E_STATE;
   if (!(dt > 0.0) || !std::isfinite(t)) return fail(c, MRB_E_ARG, "rk4: dt must be positive");
   c->have_flags = false;
@@ -1825,6 +2186,10 @@ mrb_status mrb_rk4(mrb_ctx* c, double t, double dt) {
 
 mrb_status mrb_mr_pass(mrb_ctx* c, int8_t* flags, double* maxd) {
   if (!c) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, true)) return MRB_E_STATE;
   mrb_status s = do_mr_pass(c);
   if (flags) std::memcpy(flags, c->last_flags.data(), c->last_flags.size());
@@ -1836,7 +2201,8 @@ mrb_status mrb_mr_pass_noalloc(mrb_ctx* c, int8_t* flags, double* maxd) {
   if (!c) return MRB_E_ARG;
   if (!check_state(c, true)) return MRB_E_STATE;
   if (!c->scratch_dev) return fail(c, MRB_E_DEVICE, "mr_pass_noalloc: no scratch on this device: " + c->scratch_err);
-  const size_t n = c->hblk.size(), nf = (size_t)c->cfg.nfields;
+  // works on whichever side holds the topology (no pull: that could allocate)
+  const size_t n = nblk(c), nf = (size_t)c->cfg.nfields;
   const size_t acc_bytes = (n * nf * sizeof(unsigned long long) + 255) & ~(size_t)255;
   const size_t need = acc_bytes + n * sizeof(int);
   if (need > kScratchBytes)
@@ -1860,6 +2226,7 @@ mrb_status mrb_mr_pass_noalloc(mrb_ctx* c, int8_t* flags, double* maxd) {
   for (int q = 0; q < c->cfg.dim; ++q) work *= ns;
   HIPCHK(c, launch_mr(c->shape, ns, grid_for(c, work), a, c->stream));
   mrb_status r = mr_readback(c);
+  c->dev.have_flags = false;   // the newest analysis is the host's copy
   if (flags) std::memcpy(flags, c->last_flags.data(), c->last_flags.size());
   if (maxd) std::memcpy(maxd, c->last_maxd.data(), c->last_maxd.size() * sizeof(double));
   return r;
@@ -1867,6 +2234,10 @@ mrb_status mrb_mr_pass_noalloc(mrb_ctx* c, int8_t* flags, double* maxd) {
 
 mrb_status mrb_coarsen(mrb_ctx* c, const int8_t* flags, int* n_coarsened) {
   if (!c) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, true)) return MRB_E_STATE;
   if (!flags) return fail(c, MRB_E_ARG, "coarsen: null flags");
   std::vector<int8_t> fl(flags, flags + c->leaves.size());
@@ -1875,6 +2246,10 @@ mrb_status mrb_coarsen(mrb_ctx* c, const int8_t* flags, int* n_coarsened) {
 
 mrb_status mrb_adapt(mrb_ctx* c, int* n_passes) {
   if (!c) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, true)) return MRB_E_STATE;
   return do_adapt(c, n_passes);
 }
@@ -1886,6 +2261,17 @@ mrb_status mrb_step(mrb_ctx* c, double t0, double dt, int nsteps) {
   constexpr size_t kGraphProbe = 10;
   for (int s = 0; s < nsteps; ++s) {
     mrb_status r;
+    // planning on the device or on the host (the forest moves between them as needed)
+    const bool on_dev = want_device(c);
+    if (on_dev != c->dev.active && (r = on_dev ? dev_push(c) : dev_pull(c))) return r;
+    if (on_dev) {
+      if ((r = dev_refine_all(c))) return r;
+      if ((r = do_rk4(c, t0 + s * dt, dt))) return r;
+      if ((r = dev_adapt(c, nullptr))) return r;
+      c->dev.steps++;
+      c->n_steps++;
+      continue;
+    }
     bool probing = false;
     if (c->graph_mode == 2) {
       const size_t n0 = c->probe_us[0].size(), n1 = c->probe_us[1].size();
@@ -1921,12 +2307,16 @@ mrb_status mrb_step(mrb_ctx* c, double t0, double dt, int nsteps) {
 mrb_status mrb_num_blocks(mrb_ctx* c, int* n) {
   if (!c || !n) return MRB_E_ARG;
   if (!check_state(c, false)) return MRB_E_STATE;
-  *n = (int)c->leaves.size();
+  *n = (int)nblk(c);
   return MRB_OK;
 }
 
 mrb_status mrb_read_forest(mrb_ctx* c, int8_t* level, int32_t* coords) {
   if (!c || !level || !coords) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, false)) return MRB_E_STATE;
   const int d = c->cfg.dim;
   for (size_t i = 0; i < c->leaves.size(); ++i) {
@@ -1938,6 +2328,10 @@ mrb_status mrb_read_forest(mrb_ctx* c, int8_t* level, int32_t* coords) {
 
 mrb_status mrb_read_blocks(mrb_ctx* c, double* out, int on_device) {
   if (!c || !out) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, true)) return MRB_E_STATE;
   const int n = (int)c->leaves.size();
   const size_t bytes = (size_t)n * c->bsz * sizeof(double);
@@ -1956,6 +2350,10 @@ mrb_status mrb_read_blocks(mrb_ctx* c, double* out, int on_device) {
 
 mrb_status mrb_read_uniform(mrb_ctx* c, int level, double* out, int on_device) {
   if (!c || !out) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, true)) return MRB_E_STATE;
   if (level < 1 || level > c->cfg.jmax)
     return fail(c, MRB_E_ARG, "read_uniform: level must be between 1 and jmax");
@@ -1976,6 +2374,10 @@ mrb_status mrb_read_uniform(mrb_ctx* c, int level, double* out, int on_device) {
 
 mrb_status mrb_get_flags(mrb_ctx* c, int8_t* flags, double* maxd) {
   if (!c || !flags) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!c->have_flags) return fail(c, MRB_E_STATE, "no analysis on the current grid");
   std::memcpy(flags, c->last_flags.data(), c->last_flags.size());
   if (maxd) std::memcpy(maxd, c->last_maxd.data(), c->last_maxd.size() * sizeof(double));
@@ -1996,15 +2398,16 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"sweep_grid\": %d, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
                 "\"plan_entries\": %.1f, \"plan_entries_per_block\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
-                c->leaves.size(), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
-                c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
+                nblk(c), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
+                c->dev.active ? (size_t)c->dev.top : c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
                 c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_tpb(c, pick_nsub(c)) : 256,
                 c->order ? "level-sorted" : "forest",
-                c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses, sweep_in_one(c) ? "one" : "four", c->sweep_grid, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
+                c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses, sweep_in_one(c) ? "one" : "four", c->sweep_grid, c->dev.active ? "device" : "host",
+                c->dev.mode, c->dev.steps, c->dev.passes, c->dev.pushes, c->dev.pulls, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
                 c->hus_launch, c->hus_index, c->hus_desc, c->hus_desc_par, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
   return MRB_OK;
@@ -2012,6 +2415,10 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
 
 mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
   if (!c) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   int v[8];
   const int nv = stage_variants(c->shape, c->cfg.precision, v, 8);
   if (nsub > 0) {
@@ -2312,6 +2719,10 @@ mrb_status mrb_mlp_get_params(mrb_ctx* c, float* params) {
 
 mrb_status mrb_mlp_features(mrb_ctx* c, float* feat) {
   if (!c || !feat) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, true)) return MRB_E_STATE;
   if (c->cfg.dim != 2 || (c->cfg.bs != 17 && c->cfg.bs != 33)) return fail(c, MRB_E_ARG, "features: 2D only");
   if (!c->mlp_nin) c->mlp_nin = c->cfg.nfields * 64;
@@ -2399,6 +2810,10 @@ mrb_status mrb_mlp_train(mrb_ctx* c, const float* x, const int8_t* y, const floa
 
 mrb_status mrb_mlp_predict(mrb_ctx* c, int8_t* pred, float* prob) {
   if (!c || !pred) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, true)) return MRB_E_STATE;
   if (mlp_ready(c)) return MRB_E_STATE;
   const int n = (int)c->hblk.size();
@@ -2448,6 +2863,10 @@ extern "C" {
 
 mrb_status mrb_refine_marked(mrb_ctx* c, const int8_t* mask, int* n_refined) {
   if (!c || !mask) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, true)) return MRB_E_STATE;
   std::vector<int> par = graded_closure(c, mask);
   if (n_refined) *n_refined = (int)par.size();
@@ -2456,6 +2875,10 @@ mrb_status mrb_refine_marked(mrb_ctx* c, const int8_t* mask, int* n_refined) {
 
 mrb_status mrb_step_predicted(mrb_ctx* c, double t, double dt, float tau, float guard, int* n_refined) {
   if (!c) return MRB_E_ARG;
+  if (c->dev.active) {
+    mrb_status ps = dev_pull(c);
+    if (ps) return ps;
+  }
   if (!check_state(c, true)) return MRB_E_STATE;
   if (mlp_ready(c)) return MRB_E_STATE;
   if (!(dt > 0.0)) return fail(c, MRB_E_ARG, "step_predicted: dt must be positive");
@@ -2537,6 +2960,13 @@ mrb_status mrb_set_sweep(mrb_ctx* c, int mode) {
   if (!c) return MRB_E_ARG;
   if (mode < 0 || mode > 2) return fail(c, MRB_E_ARG, "set_sweep: mode must be 0, 1 or 2");
   c->sweep_mode = mode;
+  return MRB_OK;
+}
+
+mrb_status mrb_set_topology(mrb_ctx* c, int mode) {
+  if (!c) return MRB_E_ARG;
+  if (mode < 0 || mode > 2) return fail(c, MRB_E_ARG, "set_topology: mode must be 0, 1 or 2");
+  c->dev.mode = mode;
   return MRB_OK;
 }
 

@@ -20,7 +20,7 @@ HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contrac
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
-    for src in ("kernels.hip", "mlp.hip", "mrb.cpp"):
+    for src in ("kernels.hip", "topo.hip", "mlp.hip", "mrb.cpp"):
         obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [hipcc] + HIPFLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]

@@ -624,3 +624,87 @@ def test_hip_build_flags():
     assert "--offload-arch=gfx950" in f and "-ffp-contract=off" in f
     i = f.index("-packed-fp32-ops")
     assert f[i - 3:i] == ["-Xclang", "-target-feature", "-Xclang"]
+
+
+# ------------------------------------------------------------------------------------------
+# device-resident topology: plans and neighbour entries built on the GPU (mrb_set_topology)
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", ["c1", "c2_deep", "c3", "c4_small"])
+def test_device_topology_steps_match_oracle(case):
+    """mrb_step with every refinement and coarsening planned on the device (mode 1): the
+    forest, the slots' values and every step equal the oracle's bit for bit, on forests
+    that change every step (narrow swirl blobs), a 3D forest and the 4-field shape."""
+    if case == "c1":
+        cfg, n = W.C1(form=W.FORM_FUSED), 12
+    elif case == "c2_deep":
+        cfg, n = W.C2(jmax=6, eps=1e-4, blob_beta=4e-4, form=W.FORM_FUSED), 8
+    elif case == "c3":
+        cfg, n = W.C3(jmax=5, eps=1e-4, form=W.FORM_FUSED), 3
+    else:
+        cfg, n = W.C4(jmax=4, eps=1e-4, form=W.FORM_FUSED).replace(max_blocks=8 ** 4 + 2000), 3
+    s, o = _pair(cfg)
+    s.set_topology(1)
+    t = 0.0
+    for k in range(n):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+        assert s.stats()["topology"] == "device"
+        if k % 4 == 3 or k == n - 1:
+            assert_same(s, o, f"{case}: step {k + 1}")     # pulls the forest back
+    st = s.stats()
+    assert st["device_topology"]["steps"] == n and st["device_topology"]["pushes"] >= 1
+    s.close()
+
+
+@pytest.mark.gpu
+def test_device_and_host_topology_agree_and_hand_over():
+    """Steps alternate between device and host planning (each switch moves the forest
+    across); the result equals a run planned on the host only, slots and flags included."""
+    cfg = W.C2(jmax=6, eps=1e-4, blob_beta=4e-4, form=W.FORM_FUSED)
+    a, b = M.Solver(cfg), M.Solver(cfg)
+    for s in (a, b):
+        s.init_grid()
+        s.set_graph(0)
+    a.set_topology(0)
+    t = 0.0
+    for k in range(8):
+        b.set_topology(1 if k % 3 != 2 else 0)
+        a.step(t, cfg.dt)
+        b.step(t, cfg.dt)
+        t += cfg.dt
+    la, lb = a.read_forest(), b.read_forest()
+    assert np.array_equal(la[0], lb[0]) and np.array_equal(la[1], lb[1])
+    assert np.array_equal(_bits(a.read_blocks()), _bits(b.read_blocks()))
+    fa, ma = a.get_flags()
+    fb, mb = b.get_flags()
+    assert np.array_equal(fa, fb) and np.array_equal(_bits(ma), _bits(mb))
+    st = b.stats()
+    assert st["device_topology"]["pushes"] >= 2 and st["device_topology"]["pulls"] >= 2
+    with pytest.raises(M.MrbError):
+        b.set_topology(3)
+    a.close()
+    b.close()
+
+
+@pytest.mark.gpu
+def test_device_topology_capacity_error_leaves_state():
+    """A refinement that does not fit the pool fails with MRB_E_CAPACITY before any
+    device write; the forest and values are unchanged."""
+    cfg = W.C1(jmax=4, eps=0.0, form=W.FORM_FUSED).replace(max_blocks=80)
+    s = M.Solver(cfg)
+    lv, co = W.uniform_forest(cfg, 2)
+    s.init_forest(lv, co)
+    s.load_blocks(W.sample(cfg, *s.read_forest()))
+    s.set_topology(1)
+    s.step(0.0, cfg.dt)                                  # 16 -> 64 blocks on level 3
+    before = s.read_blocks()
+    lvb, cob = s.read_forest()
+    with pytest.raises(M.MrbError) as e:
+        s.step(cfg.dt, cfg.dt)                           # 64 -> 256 does not fit in 80
+    assert e.value.code == -2
+    assert np.array_equal(s.read_forest()[0], lvb) and np.array_equal(s.read_forest()[1], cob)
+    assert np.array_equal(_bits(s.read_blocks()), _bits(before))
+    s.close()
