@@ -57,7 +57,12 @@ typedef enum {
 enum {
   MRB_ADV_CONST = 0,  /* -c.grad(phi), phys[0..2] = c                                   (Sec. 3 eq. form) */
   MRB_ADV_SWIRL = 1,  /* -u(x,y,t).grad(phi), the swirl field of Sec. 3; phys[0] = t_a (0 = steady)      */
-  MRB_NS2D = 2        /* compressible Navier-Stokes, fields rho,u,v,p; phys = {gamma, mu, Pr}  (Sec. 4) */
+  MRB_NS2D = 2        /* compressible Navier-Stokes, fields rho,u,v,p; phys = {gamma, mu, Pr, r_th} (Sec. 4);
+                         r_th > 0 applies the shock-capturing filter after every RK4 step (Sec. 4: a
+                         pressure sensor max(0, 1 - r_th/r), r = M/p^2 + 1e-16 with M the squared
+                         differences of Dp = (-p_{j+1} + 2p_j - p_{j-1})/4, switching a second-order
+                         filter in flux form, F = -(q_{j+1} - q_j)/4, on every field, per axis); the
+                         paper's filter reference is not available, this formulation is ours */
 };
 enum { MRB_FP64 = 0, MRB_MIXED = 1 };          /* MIXED: FP32 stencil + FP32 slopes, FP64 state     */
 enum { MRB_FORM_PLAIN = 0, MRB_FORM_FUSED = 1 };/* PLAIN: stored ghosts, per-level launches           */

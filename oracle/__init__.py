@@ -74,6 +74,7 @@ def lib():
             ("orc_mr_pass", [ctypes.c_void_p, _i8p, _dp]),
             ("orc_details", [ctypes.c_void_p, _dp]),
             ("orc_read_uniform", [ctypes.c_void_p, ctypes.c_int, _dp]),
+            ("orc_filter", [ctypes.c_void_p, ctypes.c_double]),
             ("orc_coarsen", [ctypes.c_void_p, _i8p]),
             ("orc_coarsenable", [ctypes.c_void_p, _i8p, _i8p, _i32p]),
             ("orc_adapt", [ctypes.c_void_p, ctypes.c_int]),
@@ -171,6 +172,10 @@ class Oracle:
         out = np.zeros((self.cfg.nf,) + (nl,) * self.cfg.dim)
         self._chk(lib().orc_read_uniform(self.h, level, _ptr(out, _dp)))
         return out
+
+    def filter(self, rth: float):
+        """The shock-capturing filter (Navier-Stokes) alone on the current state."""
+        self._chk(lib().orc_filter(self.h, rth))
 
     def tile(self, bi: int, halo: int):
         w = self.cfg.bs + 2 * halo

@@ -23,6 +23,11 @@
 // parity unpinned: the compressible Navier-Stokes right-hand side (its
 // formulation is a reading, not the paper's; free-stream preservation, mass
 // conservation and single-mode closed forms of each term pin it, nothing beyond).
+//
+// The shock-capturing filter of the shear-layer test (Sec. 4) is a formulation of our
+// own as well; it is pinned by: constant states unchanged, sub-threshold states
+// unchanged, the odd-even mode removed where the sensor saturates, and every field's
+// sum conserved on uniform periodic grids.
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -454,6 +459,55 @@ struct Oracle {
       for (size_t q = 0; q < lf.u.size(); ++q)
         lf.u[q] = lf.u[q] + h6 * ((lf.k1[q] + lf.k4[q]) + 2.0 * (lf.k2[q] + lf.k3[q]));
     }
+    if (physics == NS2D && phys.size() > 3 && phys[3] > 0.0) filter(phys[3]);
+  }
+
+  // ------------------------------------------------------------------
+  // Shock-capturing filter applied after every time step (Sec. 4).  The cited filter is
+  // not available; this formulation is ours (a reading).  Per axis, a pressure sensor
+  //   Dp_j = (-p_{j+1} + 2 p_j - p_{j-1}) / 4,
+  //   M_j  = ((Dp_j - Dp_{j+1})^2 + (Dp_j - Dp_{j-1})^2) / 2,
+  //   r_j  = M_j / p_j^2 + 1e-16,   s_j = max(0, 1 - r_th / r_j),
+  // switches a second-order filter in flux form on every field q (rho, u, v, p):
+  //   q_i <- q_i - [ (s_{i+1/2} F_{i+1/2} - s_{i-1/2} F_{i-1/2})_x + (...)_y ],
+  //   s_{i+1/2} = (s_i + s_{i+1}) / 2,   F_{i+1/2} = -(q_{i+1} - q_i) / 4,
+  // all evaluated on the synchronised state (a halo of 3 nodes).  Constant states pass
+  // unchanged; where the sensor saturates (s = 1) the odd-even mode is removed.
+  // ------------------------------------------------------------------
+  void filter(double rth) {
+    auto L = leaves();
+    std::vector<std::vector<double>> nu(L.size());
+    each(L, [&](size_t i, const Key& k, Leaf& lf) {
+      const int H = 4, w = tw(H);
+      const size_t ts = tsize(H);
+      std::vector<double> T;
+      tile(k, lf, &Leaf::u, H, T);
+      auto at = [&](int f, int x, int y) { return T[(size_t)f * ts + (size_t)(x + H) + (size_t)w * (y + H)]; };
+      auto sens = [&](int x, int y, int ax) -> double {
+        auto P = [&](int d) { return ax == 0 ? at(3, x + d, y) : at(3, x, y + d); };
+        auto Dp = [&](int d) { return ((-P(d + 1) + 2.0 * P(d)) - P(d - 1)) * 0.25; };
+        const double d0 = Dp(0), dp = Dp(1), dm = Dp(-1);
+        const double m = ((d0 - dp) * (d0 - dp) + (d0 - dm) * (d0 - dm)) * 0.5;
+        const double p0 = P(0);
+        const double r = m / (p0 * p0) + 1e-16;
+        const double sv = 1.0 - rth / r;
+        return sv > 0.0 ? sv : 0.0;
+      };
+      nu[i].assign((size_t)nf * np, 0.0);
+      for (int y = 0; y < bs; ++y)
+        for (int x = 0; x < bs; ++x) {
+          const double sx0 = sens(x, y, 0), sy0 = sens(x, y, 1);
+          const double sxm = (sens(x - 1, y, 0) + sx0) * 0.5, sxp = (sx0 + sens(x + 1, y, 0)) * 0.5;
+          const double sym = (sens(x, y - 1, 1) + sy0) * 0.5, syp = (sy0 + sens(x, y + 1, 1)) * 0.5;
+          for (int f = 0; f < nf; ++f) {
+            const double q = at(f, x, y);
+            const double fxp = -(at(f, x + 1, y) - q) * 0.25, fxm = -(q - at(f, x - 1, y)) * 0.25;
+            const double fyp = -(at(f, x, y + 1) - q) * 0.25, fym = -(q - at(f, x, y - 1)) * 0.25;
+            nu[i][(size_t)f * np + x + (size_t)bs * y] = q - ((sxp * fxp - sxm * fxm) + (syp * fyp - sym * fym));
+          }
+        }
+    });
+    for (size_t i = 0; i < L.size(); ++i) L[i].second->u = nu[i];
   }
 
   // store V at every node of every leaf (redundant nodes take the owner's value)
@@ -911,6 +965,15 @@ int orc_mr_pass(void* h, int8_t* flags, double* maxd) {
       if (flags) flags[i] = (int8_t)lf.flag;
       if (maxd) for (int f = 0; f < O->nf; ++f) maxd[i * O->nf + f] = lf.maxd[f];
     }
+    return 0;
+  })
+}
+
+// the shock-capturing filter alone on the current state (pins); threshold r_th
+int orc_filter(void* h, double rth) {
+  ORC_TRY({
+    if (O->physics != NS2D) throw std::runtime_error("filter: Navier-Stokes only");
+    O->filter(rth);
     return 0;
   })
 }

@@ -151,6 +151,14 @@ struct CoarsenArgs {
   double* u;
 };
 
+// shock-capturing filter of the Navier-Stokes shape: reads u, writes unew
+struct FilterArgs {
+  Topo topo;
+  const double* u;
+  double* unew;
+  double rth;             // sensor threshold
+};
+
 struct ReadArgs {
   Topo topo;
   const double* u;
@@ -180,6 +188,7 @@ hipError_t launch_mr(const Shape& s, int nsub, int grid, const MrArgs& a, hipStr
 hipError_t launch_refine(const Shape& s, int nsub, int grid, const RefineArgs& a, hipStream_t st);
 hipError_t launch_coarsen(const Shape& s, int grid, const CoarsenArgs& a, hipStream_t st);
 hipError_t launch_read(const Shape& s, int grid, const ReadArgs& a, hipStream_t st);
+hipError_t launch_filter(const Shape& s, int grid, const FilterArgs& a, hipStream_t st);   // NS shape only
 hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst, hipStream_t st);
 // Device-resident topology transitions (topo.hip).  Arenas share the TopoHeader layout;
 // old_* is the current grid, new_* the next one.

@@ -1323,6 +1323,76 @@ __global__ void __launch_bounds__(256) k_coarsen(CoarsenArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// shock-capturing filter after a time step (Navier-Stokes, 2D, whole blocks): per
+// axis a pressure sensor s = max(0, 1 - r_th / r) with r = M / p^2 + 1e-16,
+// M = ((Dp_j - Dp_{j+1})^2 + (Dp_j - Dp_{j-1})^2) / 2, Dp_j = (-p_{j+1} + 2 p_j - p_{j-1}) / 4,
+// switches a second-order filter in flux form on every field:
+// q_i - [(s_{i+1/2} F_{i+1/2} - s_{i-1/2} F_{i-1/2})_x + (...)_y], s_{i+1/2} = (s_i + s_{i+1}) / 2,
+// F_{i+1/2} = -(q_{i+1} - q_i) / 4, on the synchronised state; written to unew
+// ---------------------------------------------------------------------------
+template <int BS, int NF>
+__global__ void __launch_bounds__(256) k_filter(FilterArgs A) {
+  constexpr int HW = 4, S = BS, H = HW + 3, SW = BS + 2;
+  using SG = SGeo<2, BS, S, HW>;
+  constexpr int TSZ = SG::TSZ, NP = SG::NP;
+  __shared__ GState<2, S + 2 * H> g;
+  __shared__ SEnt se[kMaxEnt];
+  extern __shared__ __align__(16) char smem[];
+  double* tile = reinterpret_cast<double*>(smem);
+  double* carr = tile + NF * TSZ;
+  double* sx = carr + NF * SG::CSZ;   // sensor along x at x = -1..BS, y = 0..BS-1
+  double* sy = sx + SW * BS;          // sensor along y at x = 0..BS-1, y = -1..BS
+  const double rth = A.rth;
+  const int nblk = A.topo.h.n_blocks;
+  for (XcdWork it(nblk); it.ok(); it.next()) {
+    const int b = it.w;
+    const BlockDesc d = A.topo.blk()[b];
+    int r0[3] = {0, 0, 0}, cnt[3] = {BS, BS, 1};
+    gsetup<2, BS, S, H>(g, d, A.topo.nb(b), A.topo.h.nb_stride, r0);
+    sent_setup<2, BS, NF>(se, g.ent, d.n_ent);
+    __syncthreads();
+    YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
+    if (d.n_coarse > 0) {
+      sgather<2, BS, S, HW, NF, true, double>(tile, carr, g, se, d.slot, r0, cnt, src);
+      spredict<2, BS, S, HW, NF, double>(tile, carr, g, r0, cnt);
+    } else {
+      sgather<2, BS, S, HW, NF, false, double>(tile, carr, g, se, d.slot, r0, cnt, src);
+    }
+    auto Q = [&](int f, int x, int y) { return tile[f * TSZ + SG::idx(x + HW, y + HW, 0)]; };
+    auto sens = [&](int x, int y, int ax) -> double {
+      auto P = [&](int dd) { return ax == 0 ? Q(NF - 1, x + dd, y) : Q(NF - 1, x, y + dd); };
+      auto Dp = [&](int dd) { return ((-P(dd + 1) + 2.0 * P(dd)) - P(dd - 1)) * 0.25; };
+      const double d0 = Dp(0), dp = Dp(1), dm = Dp(-1);
+      const double m = ((d0 - dp) * (d0 - dp) + (d0 - dm) * (d0 - dm)) * 0.5;
+      const double p0 = P(0);
+      const double r = m / (p0 * p0) + 1e-16;
+      const double sv = 1.0 - rth / r;
+      return sv > 0.0 ? sv : 0.0;
+    };
+    for (int p = threadIdx.x; p < SW * BS; p += blockDim.x) {
+      sx[p] = sens(p % SW - 1, p / SW, 0);
+      sy[p] = sens(p % BS, p / BS - 1, 1);
+    }
+    __syncthreads();
+    const size_t base = (size_t)d.slot * NF * NP;
+    for (int p = threadIdx.x; p < BS * BS; p += blockDim.x) {
+      const int x = p % BS, y = p / BS;
+      const double sx0 = sx[(x + 1) + SW * y], sy0 = sy[x + BS * (y + 1)];
+      const double sxm = (sx[x + SW * y] + sx0) * 0.5, sxp = (sx0 + sx[(x + 2) + SW * y]) * 0.5;
+      const double sym = (sy[x + BS * y] + sy0) * 0.5, syp = (sy0 + sy[x + BS * (y + 2)]) * 0.5;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double q = Q(f, x, y);
+        const double fxp = -(Q(f, x + 1, y) - q) * 0.25, fxm = -(q - Q(f, x - 1, y)) * 0.25;
+        const double fyp = -(Q(f, x, y + 1) - q) * 0.25, fym = -(q - Q(f, x, y - 1)) * 0.25;
+        A.unew[base + (size_t)f * NP + x + BS * y] = q - ((sxp * fxp - sxm * fxm) + (syp * fyp - sym * fym));
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // read-back of synchronised block values in forest order
 template <int DIM, int BS, int NF>
 __global__ void __launch_bounds__(256) k_read(ReadArgs A) {
@@ -1658,6 +1728,15 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
   const int grid = (int)std::min<size_t>((nw + 255) / 256, 1024);
   hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, st, (unsigned*)p, nw);
   return hipGetLastError();
+}
+
+hipError_t launch_filter(const Shape& s, int grid, const FilterArgs& a, hipStream_t st) {
+  if (s.dim == 2 && s.bs == 33 && s.hw == 4 && s.nf == 4) {
+    using SG = SGeo<2, 33, 33, 4>;
+    const size_t lds = sizeof(double) * (4 * (SG::TSZ + SG::CSZ) + 2 * 35 * 33);
+    return go(k_filter<33, 4>, grid, lds, st, a);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_scatter(const double* src, const int* slots, int n, size_t bsz, double* dst, hipStream_t st) {

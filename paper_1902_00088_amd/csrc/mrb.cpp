@@ -338,9 +338,9 @@ struct mrb_ctx {
   struct Timed { int kind; hipEvent_t a, b; double bytes; int count; };
   std::vector<Timed> timed;
   std::vector<hipEvent_t> ev_pool;
-  double t_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  double t_bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  long t_launches[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double t_ms[16] = {};
+  double t_bytes[16] = {};
+  long t_launches[16] = {};
   std::string err;
 };
 
@@ -365,8 +365,9 @@ mrb_status fail(mrb_ctx* c, mrb_status s, const std::string& m) {
 
 // kernel kinds for timing
 enum { T_STAGE = 0, T_GHOST = 1, T_RHS_PLAIN = 2, T_MR = 3, T_REFINE = 4, T_COARSEN = 5, T_READ = 6, T_TOPO = 7,
-       T_NKIND = 8 };
-const char* kKindName[T_NKIND] = {"stage", "ghost", "rhs_plain", "mr", "refine", "coarsen", "read", "topology"};
+       T_FILTER = 8, T_NKIND = 9 };
+const char* kKindName[T_NKIND] = {"stage", "ghost", "rhs_plain", "mr", "refine", "coarsen", "read", "topology",
+                                  "filter"};
 
 hipEvent_t take_event(mrb_ctx* c) {
   if (!c->ev_pool.empty()) {
@@ -967,10 +968,25 @@ mrb_status sweep(mrb_ctx* c, double t, double dt, bool fixed_grid = false) {
   return MRB_OK;
 }
 
+// the shock-capturing filter after a time step (Navier-Stokes with r_th = phys[3] > 0)
+bool filter_on(const mrb_ctx* c) { return c->cfg.physics == MRB_NS2D && c->cfg.phys[3] > 0.0; }
+
+mrb_status do_filter(mrb_ctx* c) {
+  const long n = (long)nblk(c);
+  FilterArgs a{topo(c), c->u, c->unew, c->cfg.phys[3]};
+  {
+    TimeScope ts(c, T_FILTER, (double)n * c->bsz * 16.0);
+    HIPCHK(c, launch_filter(c->shape, grid_for(c, n), a, c->stream));
+  }
+  std::swap(c->u, c->unew);
+  return MRB_OK;
+}
+
 mrb_status do_rk4(mrb_ctx* c, double t, double dt) {
   mrb_status r = sweep(c, t, dt);
   if (r) return r;
   std::swap(c->u, c->unew);
+  if (filter_on(c) && (r = do_filter(c))) return r;
   c->n_rk4++;
   c->n_block_updates += (long)nblk(c);
   return MRB_OK;
@@ -1919,7 +1935,7 @@ bool want_device(mrb_ctx* c) {
 }
 
 bool graph_ok(const mrb_ctx* c) {
-  return c->use_graph && !c->timing && c->cfg.form == MRB_FORM_FUSED &&
+  return c->use_graph && !c->timing && c->cfg.form == MRB_FORM_FUSED && !filter_on(c) &&
          !(c->cfg.physics == MRB_ADV_SWIRL && c->cfg.phys[0] > 0.0) && c->stream != nullptr;
 }
 
@@ -1964,8 +1980,9 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
     return bad("swirl needs dim 2 and both tables");
   if ((cfg->physics == MRB_NS2D) != (cfg->nfields == 4) || (cfg->physics == MRB_NS2D && (cfg->dim != 2 || cfg->hw != 4)))
     return bad("Navier-Stokes needs dim 2, hw 4 and 4 fields (and only it has 4 fields)");
-  if (cfg->physics == MRB_NS2D && (cfg->phys[0] <= 1.0 || cfg->phys[1] < 0.0 || cfg->phys[2] <= 0.0))
-    return bad("Navier-Stokes needs gamma > 1, mu >= 0, Pr > 0");
+  if (cfg->physics == MRB_NS2D && (cfg->phys[0] <= 1.0 || cfg->phys[1] < 0.0 || cfg->phys[2] <= 0.0 ||
+                                    !(cfg->phys[3] >= 0.0)))
+    return bad("Navier-Stokes needs gamma > 1, mu >= 0, Pr > 0 and a filter threshold >= 0");
   if (cfg->form == MRB_FORM_PLAIN && cfg->nfields != 1) return bad("the plain form covers the advection shapes only");
   c->shape = Shape{cfg->dim, cfg->bs, cfg->hw, cfg->nfields};
   if (!shape_supported(c->shape)) return bad("unsupported (dim, bs, hw, nfields) combination");

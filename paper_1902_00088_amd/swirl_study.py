@@ -1,0 +1,153 @@
+"""The paper's swirl test (Sec. 3, Fig. 4) on the GPU path.
+
+Set-up of Sec. 3: one Gaussian blob exp(-((x-0.5)^2 + (y-0.75)^2)/beta) on the periodic
+unit square, advected by the swirling field cos(pi t/t_a) (sin^2(pi x) sin(2 pi y),
+-sin^2(pi y) sin(2 pi x)) with t_a = 5, blocks of 33 x 33 points, 4th-order central
+differences, classic RK4 and 4th-order prediction.
+
+Errors are taken where the paper takes them, at t_a/2 (the most deformed state), as
+||phi - phi_ref||_inf / ||phi_ref||_inf on the uniform lattice of the run's Jmax (the
+adaptive solution read through the synchronised values).  The paper's pseudo-spectral
+reference is not available; phi_ref is the same scheme on a uniform grid two levels
+finer than the finest run (eps = 0), so the convergence in Jmax is self-convergence.
+Each run then continues to t_a, where the exact solution is the initial condition: that
+reversal error measures what the thresholding and the time integration leave (on a
+fixed grid the semi-discrete problem is exactly reversible, since the integral of
+cos(pi t/t_a) over [0, t_a] vanishes).
+
+For each (beta, Jmax, eps) the run reports both errors, the compression rate (blocks of
+the adaptive grid relative to the uniform grid on Jmax: mean over the run and at the
+most refined instant) and the GPU wall time of the steps.  Every step runs in the
+library's kernels; this module only drives the entry points and measures.
+
+Usage: python -m paper_1902_00088_amd.swirl_study [--quick] > study.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+import workloads as W
+
+T_A = 5.0
+
+
+def swirl_config(jmax: int, eps: float, beta: float, t_a: float = T_A, precision: int = W.FP64):
+    """The swirl of Sec. 3 (blob at (0.5, 0.75), velocity factor cos(pi t / t_a))."""
+    nb = 4 ** jmax
+    return W.C2(jmax=jmax, eps=eps).replace(
+        blob_centers=np.array([[0.5, 0.75]]), blob_beta=beta, phys=(t_a,), precision=precision,
+        form=W.FORM_FUSED, max_blocks=min(3 * nb + 64, 1 << 20), steps=int(round(t_a / W.C2(jmax=jmax).dt)))
+
+
+def _advance(s, cfg, first: int, nsteps: int, chunk: int, counts):
+    done = 0
+    while done < nsteps:
+        k = min(chunk, nsteps - done)
+        s.step((first + done) * cfg.dt, cfg.dt, k)
+        done += k
+        counts.append(s.num_blocks())
+
+
+def run(M, cfg, ref=None, chunk: int = 32):
+    """From the initial grid to t_a/2 (error against ref, the uniform lattice of a finer
+    level at t_a/2, if given) and on to t_a (reversal error); return the record."""
+    import torch
+    half = cfg.steps // 2
+    s = M.Solver(cfg)
+    s.set_graph(0)
+    s.init_grid()
+    counts = [s.num_blocks()]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _advance(s, cfg, 0, half, chunk, counts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rec = {"jmax": cfg.jmax, "eps": cfg.eps, "beta": cfg.blob_beta, "steps_to_half": half}
+    if ref is not None:
+        jref = int(round(np.log2(ref.shape[-1] / (cfg.bs - 1))))
+        k = 2 ** (jref - cfg.jmax)
+        got = s.read_uniform(cfg.jmax)[0]
+        want = ref[0][::k, ::k]
+        rec["rel_err_half"] = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    rec.update({"compression_mean_half": float(np.mean(counts)) / 4 ** cfg.jmax,
+                "compression_max": float(np.max(counts)) / 4 ** cfg.jmax,
+                "gpu_wall_s_half": wall, "ms_per_step": 1e3 * wall / max(1, half)})
+    _advance(s, cfg, half, cfg.steps - half, chunk, counts)
+    lv, co = s.read_forest()
+    got = s.read_blocks()
+    s.close()
+    init = W.sample(cfg, lv, co)
+    rec["rel_err_reversal"] = float(np.max(np.abs(got - init)) / np.max(np.abs(init)))
+    rec["compression_mean"] = float(np.mean(counts)) / 4 ** cfg.jmax
+    return rec
+
+
+def reference(M, beta: float, jref: int):
+    """The uniform level-jref grid (eps = 0) at t_a/2: [1][N][N], x fastest."""
+    cfg = swirl_config(jref, 0.0, beta)
+    s = M.Solver(cfg)
+    s.set_graph(0)
+    s.init_grid()
+    _advance(s, cfg, 0, cfg.steps // 2, 64, [])
+    out = s.read_uniform(jref)
+    s.close()
+    return out
+
+
+def order_fit(xs, ys):
+    """Least-squares slope of log(ys) against log(xs)."""
+    return float(np.polyfit(np.log(np.asarray(xs, float)), np.log(np.asarray(ys, float)), 1)[0])
+
+
+def study(M, quick: bool = False):
+    out = {"set_up": "Sec. 3 swirl, t_a = 5, Bs = 33; errors at t_a/2 against the same scheme on a uniform "
+                     "grid two levels finer (eps = 0), and at t_a against the initial condition (reversal)",
+           "runs": [], "reference_jmax": {}}
+    if quick:
+        grid = {1e-2: ([3, 4], [1e-2, 1e-3, 1e-4, 1e-7])}
+    else:
+        grid = {1e-2: ([3, 4, 5], [1e-2, 1e-3, 1e-4, 1e-5, 1e-7]),
+                1e-4: ([4, 5], [1e-2, 1e-3, 1e-4, 1e-5, 1e-7])}
+    for beta, (jmaxs, epss) in grid.items():
+        jref = max(jmaxs) + 2
+        out["reference_jmax"][f"{beta:g}"] = jref
+        t0 = time.perf_counter()
+        ref = reference(M, beta, jref)
+        print(json.dumps({"reference": jref, "beta": beta, "s": time.perf_counter() - t0}), flush=True, file=sys.stderr)
+        for j in jmaxs:
+            for e in epss:
+                r = run(M, swirl_config(j, e, beta), ref)
+                out["runs"].append(r)
+                print(json.dumps(r), flush=True, file=sys.stderr)
+    # Fig. 4A: error against eps at the largest Jmax (order ~1 in eps until the
+    # discretisation error of that Jmax takes over); Fig. 4B: error against Jmax at the
+    # smallest eps (order ~4 in the number of points)
+    fits = {}
+    for beta, (jmaxs, epss) in grid.items():
+        rs = [r for r in out["runs"] if r["beta"] == beta]
+        jm = max(jmaxs)
+        big = sorted((r["eps"], r["rel_err_half"]) for r in rs if r["jmax"] == jm and r["eps"] >= 1e-4)
+        if len(big) >= 2:
+            fits[f"beta={beta:g}: eps order at Jmax={jm} (eps >= 1e-4)"] = order_fit(*zip(*big))
+        small = sorted((2 ** r["jmax"] * 32, r["rel_err_half"]) for r in rs if r["eps"] == min(epss))
+        if len(small) >= 2:
+            fits[f"beta={beta:g}: order in points per direction at eps={min(epss):g}"] = -order_fit(*zip(*small))
+    out["fits"] = fits
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true")
+    args = ap.parse_args()
+    import paper_1902_00088_amd as M
+    print(json.dumps(study(M, quick=args.quick)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

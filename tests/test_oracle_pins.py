@@ -825,3 +825,60 @@ def test_read_uniform_is_unchanged_by_the_safety_zone_refinement(dim):
     o.refine_all()
     after = o.read_uniform(L)
     assert np.array_equal(before.view(np.uint64), after.view(np.uint64))
+
+
+# ---------------------------------------------------------------------------------------
+# the shear-layer test's shock-capturing filter (Sec. 4; the formulation is our own)
+# ---------------------------------------------------------------------------------------
+
+def _ns_uniform(level=3, fn=None):
+    cfg = W.DSL(jmax=4)
+    o = oracle.Oracle(cfg)
+    lv, co = W.uniform_forest(cfg, level)
+    o.init_forest(lv, co)
+    lv, co = o.read_forest()
+    o.load_blocks(W.sample(cfg, lv, co, fn=fn))
+    return cfg, o, lv, co
+
+
+def test_filter_leaves_constant_and_sub_threshold_states_unchanged():
+    cfg, o, lv, co = _ns_uniform(fn=lambda x, y: (np.full_like(x, 1.5), np.full_like(x, 0.25),
+                                                  np.full_like(x, -0.5), np.full_like(x, 2.5)))
+    before = o.read_blocks()
+    o.filter(1e-5)
+    assert np.array_equal(o.read_blocks().view(np.uint64), before.view(np.uint64))
+    smooth = lambda x, y: (1.0 + 0.1 * np.sin(2 * np.pi * x), 0.2 * np.cos(2 * np.pi * y),
+                           0.1 * np.sin(2 * np.pi * (x + y)), 2.5 + 1e-3 * np.sin(2 * np.pi * x))
+    cfg, o, lv, co = _ns_uniform(fn=smooth)
+    before = o.read_blocks()
+    o.filter(1e-5)    # relative pressure curvature ~1e-12 << 1e-5: the sensor stays off
+    assert np.array_equal(o.read_blocks().view(np.uint64), before.view(np.uint64))
+
+
+def test_filter_removes_the_odd_even_mode_where_the_sensor_saturates():
+    """With every s = 1 the flux-form filter is q + (q_{i+1} - 2 q_i + q_{i-1})/4 per axis,
+    which maps an alternating mode to zero: dyadic data make it exact."""
+    n = 8 * 32
+    alt = lambda x: np.where(np.rint(x * n).astype(int) % 2 == 0, 1.0, -1.0)
+    fn = lambda x, y: (1.5 + 0.25 * alt(x), 0.5 * alt(x), -0.25 * alt(x), 2.5 + 0.25 * alt(x))
+    cfg, o, lv, co = _ns_uniform(fn=fn)
+    o.filter(1e-30)
+    got = o.read_blocks()
+    for f, c in enumerate((1.5, 0.0, 0.0, 2.5)):
+        assert np.all(got[:, f] == c), f
+
+
+def test_filter_conserves_every_field_on_a_uniform_periodic_grid():
+    """Flux form: the filter's contributions telescope, so the sum over the unique lattice
+    points is unchanged (to rounding); a steep pressure bump switches the sensor on."""
+    bump = lambda x, y: 2.5 + 0.5 * np.exp(-((x - 0.4) ** 2 + (y - 0.6) ** 2) / 2e-5)
+    fn = lambda x, y: (1.0 + 0.3 * np.exp(-((x - 0.5) ** 2) / 1e-3), 0.1 * np.sin(2 * np.pi * y),
+                       0.2 * np.cos(2 * np.pi * x), bump(x, y))
+    cfg, o, lv, co = _ns_uniform(fn=fn)
+    before = o.read_uniform(3)
+    o.filter(1e-5)
+    after = o.read_uniform(3)
+    assert np.max(np.abs(after - before)) > 1e-6          # the filter acted
+    for f in range(4):
+        s0, s1 = before[f].sum(), after[f].sum()
+        assert abs(s1 - s0) <= 1e-12 * np.abs(before[f]).sum(), f

@@ -114,6 +114,29 @@ def C3(jmax: int = 8, eps: float = 1e-3, steps: int = 500, **kw) -> Config:
     return cfg.replace(**kw)
 
 
+# The double shear layer of Sec. 4 lives on [0, 8]^2; the solver's domain is the unit
+# square, so coordinates are scaled by L = 8 (x = L x', t = L t'): velocities, density and
+# pressure are unchanged and the viscosity becomes mu / L (second derivatives carry one more
+# factor 1/L than the first ones).
+DSL_L = 8.0
+
+
+def DSL(jmax: int = 7, eps: float = 1e-3, t_end: float = 4.0, rth: float = 1e-5, **kw) -> Config:
+    """2D compressible Navier-Stokes double shear layer (Sec. 4): L = 8, layers at L/2 +- 0.25,
+    rho 2 / u 1 between them and rho 1 / u -1 outside, tanh jumps of width L/240, p = 2.5,
+    v = 0.1 sin(2 pi (x - L/2)), mu = 1e-6, gamma 1.4, Pr 0.71, shock-capturing filter with
+    threshold rth after every step, Bs = 33.  dt from CFL 0.5 on the finest level with
+    |u| + c <= 3; `steps` reaches t_end (in the paper's time units)."""
+    gamma, pr, mu = 1.4, 0.71, 1e-6
+    dt = _dt_from_cfl(33, jmax, 3.0)
+    cfg = Config(name="DSL", dim=2, bs=33, hw=4, nf=4, jmax=jmax, eps=eps,
+                 physics=NS2D, phys=(gamma, mu / DSL_L, pr, rth),
+                 dt=dt, steps=int(math.ceil(t_end / DSL_L / dt)),
+                 max_blocks=min(3 * 4 ** jmax + 64, 3 * 65536), ic="double_shear_layer",
+                 field_offset=(1.5, 0.0, 0.0, 2.5))
+    return cfg.replace(**kw)
+
+
 def C4(jmax: int = 6, eps: float = 1e-4, steps: int = 200, **kw) -> Config:
     """3D constant advection c=(1,0.5,0.25), four seeded blobs sigma=0.04, Bs=17."""
     centers = np.random.default_rng(4).uniform(0.25, 0.75, (4, 3))
@@ -236,6 +259,23 @@ def mixing_layer_fields(cfg: Config, x, y):
     return rho, u, v, p
 
 
+def double_shear_layer_fields(cfg: Config, x, y):
+    """rho, u, v, p of the double shear layer at unit-square coordinates (x, y) (Sec. 4; the
+    text names the jumping velocity 'y-velocity' and perturbs the 'x-velocity' along y; read
+    as the shear layer it describes: u jumps across the layers normal to y, v is perturbed
+    along x)."""
+    L = DSL_L
+    X, Y = L * x, L * y
+    lam_w = L / 240.0
+    y1, y2 = L / 2 - 0.25, L / 2 + 0.25
+    step = 0.5 * (np.tanh((Y - y1) / lam_w) - np.tanh((Y - y2) / lam_w))   # 1 between the layers
+    rho = 1.0 + (2.0 - 1.0) * step
+    u = -1.0 + (1.0 - (-1.0)) * step
+    v = 0.1 * np.sin(2.0 * math.pi * (X - L / 2))
+    p = np.full_like(X, 2.5)
+    return rho, u, v, p
+
+
 def sample(cfg: Config, levels, coords, fn: Optional[Callable] = None) -> np.ndarray:
     """Initial-condition values at every node of the given blocks: float64 [n, nf, bs**dim]."""
     n = len(np.asarray(levels))
@@ -251,6 +291,9 @@ def sample(cfg: Config, levels, coords, fn: Optional[Callable] = None) -> np.nda
             out[:, f, :] = vals[f]
     elif cfg.ic == "mixing_layer":
         for f, v in enumerate(mixing_layer_fields(cfg, xs[0], xs[1])):
+            out[:, f, :] = v
+    elif cfg.ic == "double_shear_layer":
+        for f, v in enumerate(double_shear_layer_fields(cfg, xs[0], xs[1])):
             out[:, f, :] = v
     else:
         raise ValueError(cfg.ic)
