@@ -341,7 +341,7 @@ def main():
             ach4 = ks4["bytes"] / (ks4["ms"] * 1e-3) / 1e9 if ks4["ms"] > 0 else 0.0
             out["c4"]["roofline_stage_mixed"] = {
                 "bound": "hbm", "achieved": ach4, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach4 / PEAK_HBM_GBS,
-                "traffic": counter_traffic(f"c4 nsub {c4['mixed_fused']['stage_tiles']}"),
+                "traffic": counter_traffic(f"c4 nsub {c4['mixed_fused']['stage_tiles']}" + tkey(c4['mixed_fused'])),
                 "traffic_unit": "bytes per launch",
                 "algorithmic_bytes_per_launch": ks4["bytes"] / max(1, ks4["launches"]),
                 "avg_launch_us": 1e3 * ks4["ms"] / max(1, ks4["launches"])}
@@ -366,7 +366,7 @@ def main():
         ach3 = ks3["bytes"] / (ks3["ms"] * 1e-3) / 1e9 if ks3["ms"] > 0 else 0.0
         out["c3"]["roofline_stage_mixed"] = {
             "bound": "hbm", "achieved": ach3, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach3 / PEAK_HBM_GBS,
-            "traffic": counter_traffic(f"c3 nsub {c3['mixed_fused']['stage_tiles']}"),
+            "traffic": counter_traffic(f"c3 nsub {c3['mixed_fused']['stage_tiles']}" + tkey(c3['mixed_fused'])),
             "traffic_unit": "bytes per launch",
             "algorithmic_bytes_per_launch": ks3["bytes"] / max(1, ks3["launches"]),
             "avg_launch_us": 1e3 * ks3["ms"] / max(1, ks3["launches"])}

@@ -183,15 +183,18 @@ mrb_status mrb_stats(mrb_ctx *ctx, char *json, int cap);
  * time and algorithmic bytes per kernel kind; enable = 0 stops and clears. */
 mrb_status mrb_timing(mrb_ctx *ctx, int enable);
 /* Block tilings (the autotuner).  nsub > 0 forces nsub sub-tiles per axis (one
- * workgroup each) for the fused stage sweep; nsub = 0 with reps > 0 times reps dry
+ * workgroup each) for the fused stage sweep, and for the overlapped-tile RK4 step
+ * (mrb_set_sweep mode 3) where that tiling is compiled; nsub = 0 with reps > 0 times reps dry
  * sweeps (four stages into k1..k3/u_new, the state u is not advanced) of every
  * compiled stage tiling, in forest (Morton) order and in level-sorted order, on the
  * current forest and keeps the fastest pair, then does the
  * same for the analysis kernel (one pass; flags are recomputed) and, if the last
  * refinement plan is still the uploaded one (right after mrb_refine_all), for the
  * refinement kernel (re-run on the same parents); on the chosen stage tiling it also
- * times the whole sweep as four launches against one launch with grid barriers (see
- * mrb_set_sweep).  Every candidate is timed over five rounds and its fastest round
+ * times the whole sweep as four launches against one launch with grid barriers, and,
+ * if every leaf is on one level and the shape has the kernel, every tiling of the
+ * overlapped-tile RK4 step against the stage launches (see mrb_set_sweep).  Every
+ * candidate is timed over five rounds and its fastest round
  * counts.  nsub = 0 with reps = 0 returns to the built-in choices.  *chosen (may be
  * NULL) receives the stage tiling in use.
  * Not a step of the method: a schedule choice. */
@@ -215,10 +218,20 @@ mrb_status mrb_set_graph(mrb_ctx *ctx, int enable);
  * stream returns MRB_E_DEVICE, and the block data is then undefined (this is the one
  * exception to "on error the state is unchanged"): every later call that needs it
  * returns MRB_E_STATE until mrb_load_blocks (or mrb_init_forest) supplies new data.
- * mode 2 (default): the autotuner (mrb_tune with reps > 0) times both on the tuned
- * tiling and keeps the faster; four launches until then.  Results are identical in
- * every mode.  MRB_E_ARG for other values; mode 1 on the plain form is accepted and
- * ignored (it has no fused stages).
+ * mode 3: where every leaf is on one level (2D, one field, halo 2: the advection
+ * shapes), one launch per RK4 step over overlapped tiles: a workgroup loads u over its
+ * region plus four halo widths and computes all four stages in LDS (k1 on the region
+ * plus three halo widths, k2 plus two, k3 plus one, k4 on the region), repeating at
+ * the halo exactly the operations the neighbours perform at their own nodes; k1..k3
+ * never reach HBM.  Other forests and shapes take four launches.  Tiling: the one
+ * forced or tuned by mrb_tune, else whole blocks.  In mrb_step the same launch also
+ * performs the first analysis pass of the step's adapt (its halo is then three points
+ * wider, so that u_new is known where the details' prediction reads it), unless the
+ * autotuner found an analysis launch after it faster.
+ * mode 2 (default): the autotuner (mrb_tune with reps > 0) times these forms on the
+ * tuned tiling and keeps the fastest; four launches until then.  Results are
+ * identical in every mode.  MRB_E_ARG for other values; modes 1 and 3 on the plain
+ * form are accepted and ignored (it has no fused stages).
  * Not a step of the method: a schedule choice. */
 mrb_status mrb_set_sweep(mrb_ctx *ctx, int mode);
 

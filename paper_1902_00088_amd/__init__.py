@@ -290,7 +290,8 @@ class Solver:
 
     def set_sweep(self, mode):
         """Stage launches of the fused form: 0 four launches, 1 one launch with grid
-        barriers, 2 the autotuner's choice (default)."""
+        barriers, 2 the autotuner's choice (default), 3 one launch per RK4 step over
+        overlapped tiles where every leaf is on one level (2D advection shapes)."""
         self._chk(lib().mrb_set_sweep(self.h, int(mode)))
 
     def set_topology(self, mode: int):

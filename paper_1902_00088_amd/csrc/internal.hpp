@@ -129,6 +129,27 @@ struct SweepArgs {
   unsigned spin;          // polls before a barrier wait gives up
 };
 
+// One-launch RK4 step over overlapped tiles (2D advection on a forest whose leaves
+// are all on one level): u over the region plus 4 halo widths, every stage in LDS.
+struct Rk4tArgs {
+  Topo topo;
+  const double* u;
+  double* unew;
+  double alpha[4];        // y_s = u + alpha_s k_{s-1}
+  double cfac[4];         // swirl time factor per stage
+  double h6;
+  double off;             // FP32 tile offset (one field)
+  LevelTab lt;
+  Physics ph;
+  // with the analysis of u_new folded in (the first pass of an adapt): as MrArgs
+  int8_t* flags;
+  double* maxd;
+  unsigned long long* acc;
+  int* done;
+  double thr;
+  const int* smap;
+};
+
 struct MrArgs {
   Topo topo;
   double* u;              // read; redundant nodes owned by finer blocks are written back
@@ -184,6 +205,11 @@ hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, cons
 hipError_t launch_sweep(const Shape& s, int precision, Variant v, int max_grid, const SweepArgs& a, hipStream_t st,
                         int* grid_out);
 hipError_t launch_plain(const Shape& s, int grid, const StageArgs& a, hipStream_t st);  // ghost + RHS kernels
+// overlapped-tile RK4 step; hipErrorInvalidValue if the shape has no such kernel
+// (threads per workgroup: 256; with the analysis on whole blocks also 512 or 1024)
+hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, int tpb, int grid,
+                       const Rk4tArgs& a, hipStream_t st);
+int rk4t_variants(const Shape& s, int precision, int* nsub, int cap);
 hipError_t launch_mr(const Shape& s, int nsub, int grid, const MrArgs& a, hipStream_t st);
 hipError_t launch_refine(const Shape& s, int nsub, int grid, const RefineArgs& a, hipStream_t st);
 hipError_t launch_coarsen(const Shape& s, int grid, const CoarsenArgs& a, hipStream_t st);

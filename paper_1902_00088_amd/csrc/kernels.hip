@@ -571,19 +571,21 @@ __device__ __forceinline__ void subregion(int sub, int nsub, int S, int BS, int*
 // ---------------------------------------------------------------------------
 // advection right-hand side at block-local node t (tile coordinates i)
 // ---------------------------------------------------------------------------
-template <int DIM, int BS, int S, int H, typename TT>
+// (sw: the swirl tables' slices along the region, SWS entries apart; see load_swirl)
+template <int DIM, int BS, int S, int H, typename TT, int SWS = S>
 __device__ __forceinline__ TT rhs_adv(const TT* T, const int* i, const int* t, const BlockDesc& d, TT r,
-                                      const StageArgs& A, double cfac, const double* sw, const int* l) {
+                                      const Physics& ph, const LevelTab& lt, double cfac, const double* sw,
+                                      const int* l) {
   using G = Geo<DIM, BS, S, H>;
   const int x = i[0], y = i[1], z = i[2];
   const TT dx = D4(T[G::idx(x - 2, y, z)], T[G::idx(x - 1, y, z)], T[G::idx(x + 1, y, z)], T[G::idx(x + 2, y, z)], r);
   const TT dy = D4(T[G::idx(x, y - 2, z)], T[G::idx(x, y - 1, z)], T[G::idx(x, y + 1, z)], T[G::idx(x, y + 2, z)], r);
-  if (A.ph.kind == 0) {
-    TT acc = (TT)A.ph.c[0] * dx;
-    acc = acc + (TT)A.ph.c[1] * dy;
+  if (ph.kind == 0) {
+    TT acc = (TT)ph.c[0] * dx;
+    acc = acc + (TT)ph.c[1] * dy;
     if constexpr (DIM > 2) {
       const TT dz = D4(T[G::idx(x, y, z - 2)], T[G::idx(x, y, z - 1)], T[G::idx(x, y, z + 1)], T[G::idx(x, y, z + 2)], r);
-      acc = acc + (TT)A.ph.c[2] * dz;
+      acc = acc + (TT)ph.c[2] * dz;
     }
     return -acc;
   }
@@ -592,21 +594,21 @@ __device__ __forceinline__ TT rhs_adv(const TT* T, const int* i, const int* t, c
   double s2x, sx, s2y, sy;
   if (sw) {
     s2x = sw[l[0]];
-    sx = sw[S + l[0]];
-    s2y = sw[2 * S + l[1]];
-    sy = sw[3 * S + l[1]];
+    sx = sw[SWS + l[0]];
+    s2y = sw[2 * SWS + l[1]];
+    sy = sw[3 * SWS + l[1]];
   } else {
-    const int nl = A.lt.nl[d.level], shift = A.ph.jmax - d.level;
+    const int nl = lt.nl[d.level], shift = ph.jmax - d.level;
     int gx = d.c[0] * (BS - 1) + t[0];
     int gy = d.c[1] * (BS - 1) + t[1];
     if (gx >= nl) gx -= nl;
     if (gy >= nl) gy -= nl;
     gx <<= shift;
     gy <<= shift;
-    s2x = A.ph.s2[gx];
-    sx = A.ph.s[gx];
-    s2y = A.ph.s2[gy];
-    sy = A.ph.s[gy];
+    s2x = ph.s2[gx];
+    sx = ph.s[gx];
+    s2y = ph.s2[gy];
+    sy = ph.s[gy];
   }
   const double U = (s2x * sy) * cfac;
   const double W = -((s2y * sx) * cfac);
@@ -850,7 +852,7 @@ __device__ __forceinline__ void stage_pass(const StageArgs& A, const StageVar& V
           if (!ok[e]) continue;
           int l[3] = {lx, tq[e][1] - r0[1], DIM > 2 ? tq[e][2] - r0[2] : 0};
           int i[3] = {l[0] + HW, l[1] + HW, DIM > 2 ? l[2] + HW : 0};
-          const TT kv = rhs_adv<DIM, BS, S, HW, TT>(tile, i, tq[e], d, r, A, V.cfac, sw_lds ? swirl : nullptr, l);
+          const TT kv = rhs_adv<DIM, BS, S, HW, TT>(tile, i, tq[e], d, r, A.ph, A.lt, V.cfac, sw_lds ? swirl : nullptr, l);
           if (V.stage < 4) {
             ((KT*)V.kout)[qa[e]] = (KT)kv;
           } else {
@@ -928,6 +930,204 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs S) {
 }
 
 // ---------------------------------------------------------------------------
+// One-launch RK4 step over overlapped tiles, for 2D advection on a forest whose
+// leaves all lie on one level.  There every point a stage reads is held by a
+// same-level leaf, and same-level holders compute identical stage values, so a
+// workgroup can run its region's four stages alone: it loads u over the region plus
+// E points and evaluates k1 on the region + E - HW, k2 on + E - 2 HW, ... -- the halo
+// work repeats, with the same operations in the same order, what the neighbours
+// compute at their own nodes, so the result is bitwise the four stage launches'.
+// k1..k3 stay in LDS; HBM sees u read once and u_new written once.  With ANA the
+// halo is 3 points wider, u_new is known up to 3 points beyond the region, and the
+// workgroup also runs the analysis of u_new (Sec. 2.3): details, their maxima, the
+// flag, and the speculated mothers' nodes, as the analysis kernel does for a forest
+// on one level (no finer neighbour, so no redundant node to write back).  A missing
+// neighbour (a forest not on one level) yields NaN.
+// ---------------------------------------------------------------------------
+template <int BS, int NSUB, bool ANA>
+struct TileGeo {
+  static constexpr int HW = 2, E = 4 * HW + (ANA ? 3 : 0);
+  static constexpr int S = (BS + NSUB - 1) / NSUB, TW = S + 2 * E, TSZ = TW * TW;
+};
+
+// details of u_new at the region's nodes with an odd coordinate, from the tile's even
+// points (stride 2): the analysis kernel's prediction, on the tile's indexing
+template <int BS, int S, int E>
+struct TileDetails {
+  using G = Geo<2, BS, S, E>;
+  const double* U;
+  const int* r0;
+  const int* cnt;
+  double* m;
+  template <int NX, int NY, int NZ>
+  __device__ __forceinline__ void go(int cls) {
+    ParityClass<2> pc(cls, r0, cnt);
+    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
+      int t[3];
+      pc.coords(p, t);
+      const int i0 = t[0] - r0[0] + E, i1 = t[1] - r0[1] + E;
+      const int bb[3] = {NX == 4 ? i0 - 3 : i0, NY == 4 ? i1 - 3 : i1, 0};
+      const int stride[3] = {2, 2, 2};
+      auto at = [&](int x, int y, int) { return U[G::idx(x, y, 0)]; };
+      const double pred = tensor_fixed<NX, NY, NZ, double>(at, bb, stride);
+      m[0] = nanmax(m[0], fabs(U[G::idx(i0, i1, 0)] - pred));
+    }
+  }
+};
+
+template <int BS, int NSUB, typename TT, typename KT, bool ANA, int TPB>
+__global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
+  using TG = TileGeo<BS, NSUB, ANA>;
+  constexpr int HW = TG::HW, E = TG::E, S = TG::S, TW = TG::TW, TSZ = TG::TSZ, NP = BS * BS;
+  constexpr int NSUBT = NSUB * NSUB;
+  using G = Geo<2, BS, S, E>;
+  static_assert(G::TW == TW, "tile geometry");
+  extern __shared__ __align__(16) char smem[];
+  double* U = reinterpret_cast<double*>(smem);
+  KT* K = reinterpret_cast<KT*>(U + TSZ);          // k1, k2, k3
+  TT* Y = reinterpret_cast<TT*>(K + 3 * TSZ);
+  __shared__ int tab[9];                            // same-level holder by direction
+  __shared__ double sw[4 * TW];
+  __shared__ double red[TPB / 64];
+  const int nblk = A.topo.h.n_blocks;
+  const BlockDesc* blk = A.topo.blk();
+  const int tid = threadIdx.x;
+  for (XcdWork it(nblk * NSUBT); it.ok(); it.next()) {
+    const int b = it.w / NSUBT;
+    const BlockDesc d = blk[b];
+    int r0[3], cnt[3];
+    subregion<2>(it.w % NSUBT, NSUB, S, BS, r0, cnt);
+    if (tid < 9) tab[tid] = -1;
+    __syncthreads();
+    const NbEntry* ent = A.topo.nb(b);
+    for (int e = tid; e < d.n_ent; e += blockDim.x) {
+      const NbEntry q = ent[e];
+      const int ox = q.o[0], oy = q.o[1];
+      if (q.dl == 0 && ox % (BS - 1) == 0 && oy % (BS - 1) == 0 && ox >= -(BS - 1) && ox <= BS - 1 &&
+          oy >= -(BS - 1) && oy <= BS - 1)
+        tab[(oy / (BS - 1) + 1) * 3 + ox / (BS - 1) + 1] = q.slot;
+    }
+    if (A.ph.kind == 1) {
+      const int nl = A.lt.nl[d.level], shift = A.ph.jmax - d.level;
+      for (int q = tid; q < 4 * TW; q += blockDim.x) {
+        const int k = q / TW, l = q % TW, ax = k / 2;
+        int gg = d.c[ax] * (BS - 1) + r0[ax] - E + l;
+        gg = gg < 0 ? gg + nl : (gg >= nl ? gg - nl : gg);
+        gg <<= shift;
+        sw[q] = (k & 1) ? A.ph.s[gg] : A.ph.s2[gg];
+      }
+    }
+    __syncthreads();
+    // u over the region + E
+    {
+      const int nx = cnt[0] + 2 * E, ny = cnt[1] + 2 * E;
+      for (int p = tid; p < nx * ny; p += blockDim.x) {
+        const int ix = p % nx, iy = p / nx;
+        const int tx = r0[0] - E + ix, ty = r0[1] - E + iy;
+        const int dx = tx < 0 ? 0 : (tx > BS - 1 ? 2 : 1), dy = ty < 0 ? 0 : (ty > BS - 1 ? 2 : 1);
+        const int slot = tab[dy * 3 + dx];
+        const int lx = tx - (dx - 1) * (BS - 1), ly = ty - (dy - 1) * (BS - 1);
+        U[G::idx(ix, iy, 0)] = slot >= 0 ? A.u[(size_t)slot * NP + lx + BS * ly] : __builtin_nan("");
+      }
+    }
+    __syncthreads();
+    TT r;
+    if constexpr (sizeof(TT) == 8) r = A.lt.r[d.level];
+    else r = A.lt.rf[d.level];
+    for (int s = 1; s <= 4; ++s) {
+      // stage values y_s within m of the region, as the stage kernels' gather forms them
+      const int m = E - HW * (s - 1);
+      {
+        const int nx = cnt[0] + 2 * m, ny = cnt[1] + 2 * m;
+        for (int p = tid; p < nx * ny; p += blockDim.x) {
+          const int i = G::idx(E - m + p % nx, E - m + p / nx, 0);
+          double y = U[i];
+          if (s > 1) y = y + A.alpha[s - 1] * (double)K[(s - 2) * TSZ + i];
+          if constexpr (sizeof(TT) == 4) Y[i] = (TT)(y - A.off);
+          else Y[i] = y;
+        }
+      }
+      __syncthreads();
+      // k_s within m - HW of the region; the last stage forms u_new there (in place of
+      // u: a point's update reads only its own u) and stores it on the region
+      const int mr = m - HW;
+      const int nx = cnt[0] + 2 * mr, ny = cnt[1] + 2 * mr;
+      for (int p = tid; p < nx * ny; p += blockDim.x) {
+        const int ix = E - mr + p % nx, iy = E - mr + p / nx;
+        const int i[3] = {ix, iy, 0};
+        const int t[3] = {r0[0] - E + ix, r0[1] - E + iy, 0};
+        const int l[3] = {ix, iy, 0};
+        const int q = G::idx(ix, iy, 0);
+        const TT kv = rhs_adv<2, BS, S, E, TT, TW>(Y, i, t, d, r, A.ph, A.lt, A.cfac[s - 1],
+                                                   A.ph.kind == 1 ? sw : nullptr, l);
+        if (s < 4) {
+          K[(s - 1) * TSZ + q] = (KT)kv;
+        } else {
+          const double k1 = (double)K[q], k2 = (double)K[TSZ + q], k3 = (double)K[2 * TSZ + q];
+          const double k4 = (double)kv;
+          const double un = U[q] + A.h6 * ((k1 + k4) + 2.0 * (k2 + k3));
+          if (ANA) U[q] = un;
+          if (t[0] >= r0[0] && t[0] < r0[0] + cnt[0] && t[1] >= r0[1] && t[1] < r0[1] + cnt[1])
+            A.unew[(size_t)d.slot * NP + t[0] + BS * t[1]] = un;
+        }
+      }
+      __syncthreads();
+    }
+    if constexpr (ANA) {
+      double m[4] = {0.0, 0.0, 0.0, 0.0};
+      TileDetails<BS, S, E> det{U, r0, cnt, m};
+      for_odd_classes<2>(det);
+      double v = m[0];
+      for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
+      if ((tid & 63) == 0) red[tid >> 6] = v;
+      __syncthreads();
+      if (tid == 0) {
+        double vb = red[0];
+        for (int q = 1; q < TPB / 64; ++q) vb = nanmax(vb, red[q]);
+        bool last = true;
+        if constexpr (NSUBT > 1) {
+          // combine sub-tiles as the analysis kernel does (bit patterns of |d| >= 0)
+          atomicMax(&A.acc[b], (unsigned long long)__double_as_longlong(vb));
+          __threadfence();
+          last = atomicAdd(&A.done[b], 1) == NSUBT - 1;
+          if (last) {
+            __threadfence();
+            vb = __longlong_as_double((long long)atomicExch(&A.acc[b], 0ull));
+            atomicExch(&A.done[b], 0);
+          }
+        }
+        if (last) {
+          A.maxd[b] = vb;
+          A.flags[b] = d.level > 1 && vb < A.thr ? (int8_t)-1 : (int8_t)0;
+        }
+      }
+      // speculated coarsening: the mother's nodes this block supplies (every node of a
+      // forest on one level is the block's own value)
+      const int sm = A.smap ? A.smap[b] : -1;
+      if (sm >= 0) {
+        const int ch = sm & 7;
+        const size_t mbase = (size_t)(sm >> 3) * NP;
+        ParityClass<2> pc(0, r0, cnt);
+        for (int p = tid; p < pc.total; p += blockDim.x) {
+          int t[3];
+          pc.coords(p, t);
+          bool skip = false;
+          int mnode = 0, mul = 1;
+          for (int a = 0; a < 2; ++a) {
+            const int bit = (ch >> a) & 1;
+            if (bit && t[a] == 0) skip = true;
+            mnode += (t[a] / 2 + bit * (BS - 1) / 2) * mul;
+            mul *= BS;
+          }
+          if (!skip) A.unew[mbase + mnode] = U[G::idx(t[0] - r0[0] + E, t[1] - r0[1] + E, 0)];
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // plain form: ghost fill into HBM per level, then a separate RHS + update kernel
 // ---------------------------------------------------------------------------
 template <int DIM, int BS, int HW>
@@ -978,7 +1178,7 @@ __global__ void __launch_bounds__(256) k_rhs_plain(StageArgs A) {
     for (int p = threadIdx.x; p < NP; p += blockDim.x) {
       int t[3] = {p % BS, (p / BS) % BS, DIM > 2 ? p / (BS * BS) : 0};
       int i[3] = {t[0] + HW, t[1] + HW, DIM > 2 ? t[2] + HW : 0};
-      const double kv = rhs_adv<DIM, BS, BS, HW, double>(T, i, t, d, r, A, A.cfac, nullptr, t);
+      const double kv = rhs_adv<DIM, BS, BS, HW, double>(T, i, t, d, r, A.ph, A.lt, A.cfac, nullptr, t);
       if (A.stage < 4) {
         ((double*)A.kout)[base + p] = kv;
       } else {
@@ -1589,6 +1789,51 @@ hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, cons
   MRB_STAGE_VARIANTS(X)
 #undef X
   return hipErrorInvalidValue;
+}
+
+// overlapped-tile RK4 variants: shape (2D, one field, halo 2), precision, sub-tiles per axis
+#define MRB_RK4T_VARIANTS(X) \
+  X(17, 0, 1) X(17, 1, 1)    \
+  X(33, 0, 1) X(33, 0, 2) X(33, 0, 4) X(33, 1, 1) X(33, 1, 2) X(33, 1, 4)
+
+// with the analysis folded in, whole blocks may take 512 or 1024 threads (a forest
+// small enough for this form leaves most compute units idle otherwise)
+template <int B, int NS, typename TT, typename KT>
+static hipError_t rk4t_go(bool ana, int tpb, int grid, const Rk4tArgs& a, hipStream_t st) {
+  const size_t per = sizeof(double) + 3 * sizeof(KT) + sizeof(TT);
+  if (ana) {
+    const size_t lds = (size_t)TileGeo<B, NS, true>::TSZ * per;
+    if (tpb == 256) return go(k_rk4t<B, NS, TT, KT, true, 256>, grid, lds, st, a, 256);
+    if constexpr (NS == 1) {
+      if (tpb == 512) return go(k_rk4t<B, NS, TT, KT, true, 512>, grid, lds, st, a, 512);
+      if (tpb == 1024) return go(k_rk4t<B, NS, TT, KT, true, 1024>, grid, lds, st, a, 1024);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (tpb != 256) return hipErrorInvalidValue;
+  return go(k_rk4t<B, NS, TT, KT, false, 256>, grid, (size_t)TileGeo<B, NS, false>::TSZ * per, st, a);
+}
+
+hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, int tpb, int grid,
+                       const Rk4tArgs& a, hipStream_t st) {
+  if (s.dim != 2 || s.hw != 2 || s.nf != 1) return hipErrorInvalidValue;
+#define X(B, P, NS)                                                                             \
+  if (s.bs == B && precision == P && nsub == NS) {                                             \
+    if constexpr (P == 0) return rk4t_go<B, NS, double, double>(analysis, tpb, grid, a, st);   \
+    else return rk4t_go<B, NS, float, float>(analysis, tpb, grid, a, st);                      \
+  }
+  MRB_RK4T_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+int rk4t_variants(const Shape& s, int precision, int* nsub, int cap) {
+  int n = 0;
+  if (s.dim != 2 || s.hw != 2 || s.nf != 1) return 0;
+#define X(B, P, NS) if (s.bs == B && precision == P && n < cap) nsub[n++] = NS;
+  MRB_RK4T_VARIANTS(X)
+#undef X
+  return n;
 }
 
 hipError_t launch_sweep(const Shape& s, int precision, Variant v, int max_grid, const SweepArgs& a, hipStream_t st,

@@ -253,8 +253,13 @@ struct mrb_ctx {
   // whole-sweep launches: barrier words (device) and the time-out word (mapped host)
   unsigned* dbar = nullptr;
   int *h_err = nullptr, *d_err = nullptr;
-  int sweep_mode = 2;          // 0 four launches, 1 one launch with grid barriers, 2 the autotuner's choice
+  int sweep_mode = 2;          // 0 four launches, 1 one launch with grid barriers, 2 the autotuner's choice,
+                               // 3 overlapped-tile RK4 where the forest is on one level
   bool sweep_one_tuned = false;
+  int rk4t_nsub = 0;           // overlapped-tile RK4: tuned sub-tiles per axis (0: not tuned)
+  bool rk4t_tuned = false;     // the autotuner found it faster than the stage launches
+  int ana_nsub = 0;            // first analysis folded into it: tiling (0 not tuned: the RK4 tiling;
+  int ana_tpb = 256;           // -1: not folded) and threads per workgroup
   int sweep_grid = 0;          // workgroups of the last whole-sweep launch
   double *h_maxd2 = nullptr, *dmaxd2 = nullptr;
   int flag_set = 0;                    // set the next analysis writes
@@ -365,9 +370,9 @@ mrb_status fail(mrb_ctx* c, mrb_status s, const std::string& m) {
 
 // kernel kinds for timing
 enum { T_STAGE = 0, T_GHOST = 1, T_RHS_PLAIN = 2, T_MR = 3, T_REFINE = 4, T_COARSEN = 5, T_READ = 6, T_TOPO = 7,
-       T_FILTER = 8, T_NKIND = 9 };
+       T_FILTER = 8, T_RK4T = 9, T_NKIND = 10 };
 const char* kKindName[T_NKIND] = {"stage", "ghost", "rhs_plain", "mr", "refine", "coarsen", "read", "topology",
-                                  "filter"};
+                                  "filter", "rk4_tile"};
 
 hipEvent_t take_event(mrb_ctx* c) {
   if (!c->ev_pool.empty()) {
@@ -923,6 +928,74 @@ bool sweep_in_one(const mrb_ctx* c) {
   return c->cfg.form == MRB_FORM_FUSED && (c->sweep_mode == 1 || (c->sweep_mode == 2 && c->sweep_one_tuned));
 }
 
+// every leaf on one level (the overlapped-tile RK4 step's condition)
+bool one_level(const mrb_ctx* c) {
+  const long n = (long)nblk(c);
+  if (n == 0) return false;
+  if (c->dev.active) {
+    for (int l = 0; l < kMaxLevels; ++l)
+      if (c->dev.hist[l] == n) return true;
+    return false;
+  }
+  for (size_t l = 0; l + 1 < c->level_off.size(); ++l)
+    if (c->level_off[l + 1] - c->level_off[l] == n) return true;
+  return false;
+}
+
+// sub-tiles per axis of the overlapped-tile RK4 step, or 0 where it does not apply
+int rk4t_pick(const mrb_ctx* c) {
+  if (c->cfg.form != MRB_FORM_FUSED) return 0;
+  if (!(c->sweep_mode == 3 || (c->sweep_mode == 2 && c->rk4t_tuned))) return 0;
+  int v[8];
+  const int nv = rk4t_variants(c->shape, c->cfg.precision, v, 8);
+  if (nv == 0 || !one_level(c)) return 0;
+  for (int i = 0; i < nv; ++i)
+    if (v[i] == c->rk4t_nsub) return v[i];
+  return v[0];
+}
+
+// arguments of the overlapped-tile RK4 step (stage coefficients as in sweep)
+Rk4tArgs rk4t_args(mrb_ctx* c, double t, double dt) {
+  const double h2 = dt * 0.5;
+  const double ts[4] = {t, t + h2, t + h2, t + dt};
+  const double alpha[4] = {0.0, h2, h2, dt};
+  Rk4tArgs ra;
+  std::memset(&ra, 0, sizeof ra);
+  ra.topo = topo(c);
+  ra.u = c->u;
+  ra.unew = c->unew;
+  ra.h6 = dt / 6.0;
+  ra.off = c->off.empty() ? 0.0 : c->off[0];
+  ra.lt = c->lt;
+  ra.ph = c->ph;
+  for (int s = 0; s < 4; ++s) {
+    ra.alpha[s] = alpha[s];
+    ra.cfac[s] = 1.0;
+    if (c->cfg.physics == MRB_ADV_SWIRL && c->cfg.phys[0] > 0.0) ra.cfac[s] = std::cos(M_PI * ts[s] / c->cfg.phys[0]);
+  }
+  return ra;
+}
+
+// launch the overlapped-tile RK4 step (tn sub-tiles per axis), with the analysis of
+// u_new folded in or not
+mrb_status launch_tiled(mrb_ctx* c, int tn, const Rk4tArgs& ra, bool analysis, int tpb = 256) {
+  const long work = (long)nblk(c) * tn * tn;
+  // algorithmic bytes: u read once, u_new written once
+  TimeScope rs(c, T_RK4T, (double)nblk(c) * c->bsz * 16.0);
+  HIPCHK(c, launch_rk4t(c->shape, c->cfg.precision, tn, analysis, tpb, grid_for(c, work), ra, c->stream));
+  return MRB_OK;
+}
+
+// the analysis outputs of a folded first pass (flag set 0; no speculated mothers)
+void rk4t_analysis_args(mrb_ctx* c, Rk4tArgs& ra, const int* smap) {
+  ra.flags = c->dflags;
+  ra.maxd = c->dmaxd;
+  ra.acc = c->dacc;
+  ra.done = c->ddone;
+  ra.thr = c->thr.empty() ? 0.0 : c->thr[0];
+  ra.smap = smap;
+}
+
 // the four stages of one RK4 step; results go to k1..k3 and u_new (u is read only).
 // fixed_grid (graph capture) always takes the four-launch path.
 mrb_status sweep(mrb_ctx* c, double t, double dt, bool fixed_grid = false) {
@@ -931,6 +1004,8 @@ mrb_status sweep(mrb_ctx* c, double t, double dt, bool fixed_grid = false) {
   StageArgs a = stage_args(c);
   a.h6 = h6;
   const double alpha[4] = {0.0, h2, h2, dt};
+  const int tn = fixed_grid ? 0 : rk4t_pick(c);
+  if (tn > 0) return launch_tiled(c, tn, rk4t_args(c, t, dt), false);
   // fused form: one event pair around the four stage launches
   const bool fused = c->cfg.form == MRB_FORM_FUSED;
   double sweep_bytes = 0.0;
@@ -990,6 +1065,34 @@ mrb_status do_rk4(mrb_ctx* c, double t, double dt) {
   c->n_rk4++;
   c->n_block_updates += (long)nblk(c);
   return MRB_OK;
+}
+
+mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false, bool first_fused = false);
+mrb_ctx::Memo* spec_entry(mrb_ctx* c);
+
+// The RK4 step and the first analysis pass of its adapt as one overlapped-tile launch,
+// where the forest is on one level and that form is selected (else *done = false and
+// nothing is launched); then the rest of the adapt.
+mrb_status rk4_adapt_tiled(mrb_ctx* c, double t, double dt, bool* done) {
+  *done = false;
+  int tn = rk4t_pick(c), tpb = 256;
+  if (tn == 0 || filter_on(c) || c->ana_nsub < 0) return MRB_OK;
+  if (c->ana_nsub > 0) {
+    tn = c->ana_nsub;
+    tpb = c->ana_tpb;
+  }
+  mrb_ctx::Memo* e = spec_entry(c);
+  const bool fused = e && e->smap;
+  Rk4tArgs ra = rk4t_args(c, t, dt);
+  c->flag_set = 0;
+  rk4t_analysis_args(c, ra, fused ? e->smap : nullptr);
+  mrb_status r = launch_tiled(c, tn, ra, true, tpb);
+  if (r) return r;
+  std::swap(c->u, c->unew);
+  c->n_rk4++;
+  c->n_block_updates += (long)nblk(c);
+  *done = true;
+  return do_adapt(c, nullptr, true, fused);
 }
 
 // refinement kernel over the uploaded plan (nref parents); fixed_grid for graph capture
@@ -1392,9 +1495,10 @@ mrb_ctx::Memo* spec_entry(mrb_ctx* c) {
   return e && e->nfam > 0 ? e : nullptr;
 }
 
-// first_launched: the first pass is already queued (graph replay); first_fused: that
-// pass was given the speculated coarsening's map and wrote its mothers
-mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false, bool first_fused = false) {
+// first_launched: the first pass is already queued (graph replay, or folded into the
+// overlapped-tile RK4 step); first_fused: that pass was given the speculated
+// coarsening's map and wrote its mothers
+mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fused) {
   mrb_status s;
   int passes = 1;
   c->flag_set = 0;
@@ -2302,8 +2406,10 @@ mrb_status mrb_step(mrb_ctx* c, double t0, double dt, int nsteps) {
       if ((r = step_graph(c, t0 + s * dt, dt))) return r;
     } else {
       if ((r = do_refine_all(c))) return r;
-      if ((r = do_rk4(c, t0 + s * dt, dt))) return r;
-      if ((r = do_adapt(c, nullptr))) return r;
+      bool tiled = false;
+      if ((r = rk4_adapt_tiled(c, t0 + s * dt, dt, &tiled))) return r;
+      if (!tiled && (r = do_rk4(c, t0 + s * dt, dt))) return r;
+      if (!tiled && (r = do_adapt(c, nullptr, false, false))) return r;
     }
     if (probing) {
       c->probe_us[c->use_graph ? 1 : 0].push_back(now_us() - w0);
@@ -2415,7 +2521,7 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"rk4_tile_tiles\": %d, \"rk4_tile_tuned\": %d, \"rk4_tile_analysis\": [%d, %d], \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
                 "\"plan_entries\": %.1f, \"plan_entries_per_block\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
@@ -2423,7 +2529,9 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
                 c->dev.active ? (size_t)c->dev.top : c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
                 c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_tpb(c, pick_nsub(c)) : 256,
                 c->order ? "level-sorted" : "forest",
-                c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses, sweep_in_one(c) ? "one" : "four", c->sweep_grid, c->dev.active ? "device" : "host",
+                c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses,
+                c->have_forest && rk4t_pick(c) > 0 ? "rk4_tile" : (sweep_in_one(c) ? "one" : "four"), c->rk4t_nsub,
+                c->rk4t_tuned ? 1 : 0, c->ana_nsub, c->ana_tpb, c->sweep_grid, c->dev.active ? "device" : "host",
                 c->dev.mode, c->dev.steps, c->dev.passes, c->dev.pushes, c->dev.pulls, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
                 c->hus_launch, c->hus_index, c->hus_desc, c->hus_desc_par, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
@@ -2444,6 +2552,12 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     if (!ok) return fail(c, MRB_E_ARG, "tune: tiling not compiled for this shape and precision");
     c->nsub = nsub;
     c->tpb = 256;
+    int tv[8];
+    const int nt = rk4t_variants(c->shape, c->cfg.precision, tv, 8);
+    for (int i = 0; i < nt; ++i)
+      if (tv[i] == nsub) c->rk4t_nsub = nsub;
+    c->ana_nsub = 0;
+    c->ana_tpb = 256;
   } else if (reps > 0) {
     if (!check_state(c, true)) return MRB_E_STATE;
     if (!(dt > 0.0)) return fail(c, MRB_E_ARG, "tune: dt must be positive");
@@ -2537,6 +2651,107 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
                     one_ok ? best_m[1] : -1.0f);
       c->tune_log += buf;
     }
+    // the overlapped-tile RK4 step (forests on one level; every tiling compiled for the
+    // shape) against the stage launches chosen above
+    c->rk4t_tuned = false;
+    {
+      int tv[8];
+      const int nt = rk4t_variants(c->shape, c->cfg.precision, tv, 8);
+      if (nt > 0 && one_level(c)) {
+        const int mode0 = c->sweep_mode, nsub0 = c->rk4t_nsub;
+        float best_t[9];
+        for (int i = 0; i <= nt; ++i) best_t[i] = 1e30f;
+        mrb_status r = MRB_OK;
+        for (int round = 0; round < kRounds && !r; ++round)
+          for (int i = 0; i <= nt && !r; ++i) {
+            if (i < nt) {
+              c->sweep_mode = 3;
+              c->rk4t_nsub = tv[i];
+            } else {
+              c->sweep_mode = mode0 == 3 ? 2 : mode0;   // the stage launches
+            }
+            for (int k = 0; k < reps + 1 && !r; ++k) {   // the first is a warm-up
+              if (k == 1 && hipEventRecord(e0, c->stream) != hipSuccess) r = MRB_E_DEVICE;
+              if (!r) r = sweep(c, 0.0, dt);
+            }
+            float ms = 0.f;
+            if (!r && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                       hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+              r = fail(c, MRB_E_DEVICE, "tune: event");
+            if (!r) r = check_barrier(c);
+            if (!r) best_t[i] = std::min(best_t[i], ms / reps);
+          }
+        c->sweep_mode = mode0;
+        if (r) {
+          c->rk4t_nsub = nsub0;
+          return done(r);
+        }
+        int bi = 0;
+        c->tune_log += ", \"rk4_tile\": {";
+        for (int i = 0; i < nt; ++i) {
+          char buf[48];
+          std::snprintf(buf, sizeof buf, "\"%d\": %.4f, ", tv[i], best_t[i]);
+          c->tune_log += buf;
+          if (best_t[i] < best_t[bi]) bi = i;
+        }
+        char buf[48];
+        std::snprintf(buf, sizeof buf, "\"stages\": %.4f}", best_t[nt]);
+        c->tune_log += buf;
+        c->rk4t_nsub = tv[bi];
+        c->rk4t_tuned = best_t[bi] < best_t[nt];
+        // the first analysis folded into the tile launch (tilings x threads) against
+        // the tile launch followed by an analysis launch
+        c->ana_nsub = -1;
+        if (c->rk4t_tuned) {
+          struct AC { int nsub, tpb; float ms; };
+          std::vector<AC> ac;
+          for (int i = 0; i < nt; ++i)
+            for (int tp : {256, 512, 1024})
+              if (tp == 256 || tv[i] == 1) ac.push_back(AC{tv[i], tp, 1e30f});
+          float pair = 1e30f;
+          Rk4tArgs ra = rk4t_args(c, 0.0, dt);
+          rk4t_analysis_args(c, ra, nullptr);
+          for (int round = 0; round < kRounds && !r; ++round)
+            for (size_t i = 0; i <= ac.size() && !r; ++i) {
+              for (int k = 0; k < reps + 1 && !r; ++k) {   // the first is a warm-up
+                if (k == 1 && hipEventRecord(e0, c->stream) != hipSuccess) r = MRB_E_DEVICE;
+                if (r) break;
+                if (i < ac.size()) {
+                  r = launch_tiled(c, ac[i].nsub, ra, true, ac[i].tpb);
+                } else {
+                  r = launch_tiled(c, c->rk4t_nsub, ra, false);
+                  c->flag_set = 0;
+                  if (!r) r = launch_mr_kernel(c, false);
+                }
+              }
+              float ms = 0.f;
+              if (!r && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                r = fail(c, MRB_E_DEVICE, "tune: event");
+              if (r) break;
+              if (i < ac.size()) ac[i].ms = std::min(ac[i].ms, ms / reps);
+              else pair = std::min(pair, ms / reps);
+            }
+          if (r) return done(r);
+          size_t bj = 0;
+          c->tune_log += ", \"rk4_tile_analysis\": {";
+          for (size_t i = 0; i < ac.size(); ++i) {
+            char buf[48];
+            std::snprintf(buf, sizeof buf, "\"%d%s\": %.4f, ", ac[i].nsub,
+                          ac[i].tpb == 256 ? "" : (ac[i].tpb == 512 ? "t512" : "t1024"), ac[i].ms);
+            c->tune_log += buf;
+            if (ac[i].ms < ac[bj].ms) bj = i;
+          }
+          char buf[48];
+          std::snprintf(buf, sizeof buf, "\"separate\": %.4f}", pair);
+          c->tune_log += buf;
+          if (ac[bj].ms < pair) {
+            c->ana_nsub = ac[bj].nsub;
+            c->ana_tpb = ac[bj].tpb;
+          }
+        }
+      }
+    }
     // analysis and refinement tilings: several rounds over the candidates, the fastest
     // round of each counts (single launches of these kernels are a few microseconds on
     // small grids, where one round is at the mercy of noise)
@@ -2604,6 +2819,10 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->nsub_mr = -1;
     c->nsub_ref = 0;
     c->order = 0;
+    c->rk4t_nsub = 0;
+    c->rk4t_tuned = false;
+    c->ana_nsub = 0;
+    c->ana_tpb = 256;
   }
   if (chosen) *chosen = c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1;
   return MRB_OK;
@@ -2975,7 +3194,7 @@ mrb_status mrb_set_graph(mrb_ctx* c, int enable) {
 
 mrb_status mrb_set_sweep(mrb_ctx* c, int mode) {
   if (!c) return MRB_E_ARG;
-  if (mode < 0 || mode > 2) return fail(c, MRB_E_ARG, "set_sweep: mode must be 0, 1 or 2");
+  if (mode < 0 || mode > 3) return fail(c, MRB_E_ARG, "set_sweep: mode must be 0, 1, 2 or 3");
   c->sweep_mode = mode;
   return MRB_OK;
 }
@@ -2991,7 +3210,7 @@ mrb_status mrb_timing(mrb_ctx* c, int enable) {
   if (!c) return MRB_E_ARG;
   resolve_timing(c);
   c->timing = enable != 0;
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < T_NKIND; ++k) {
     c->t_ms[k] = 0.0;
     c->t_bytes[k] = 0.0;
     c->t_launches[k] = 0;

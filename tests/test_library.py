@@ -500,7 +500,148 @@ def test_one_launch_sweep_matches_oracle(case):
     s.set_sweep(0)
     assert s.stats()["sweep_launch"] == "four"
     with pytest.raises(M.MrbError):
-        s.set_sweep(3)
+        s.set_sweep(4)
+    s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", ["c2_fp64_1", "c2_fp64_2", "c2_fp64_4", "c2_reversal_4", "c1_uniform"])
+def test_overlapped_tile_rk4_matches_oracle(case):
+    """One launch per RK4 step over overlapped tiles (every leaf on one level) equals the
+    oracle bit for bit, for each compiled tiling: the 2D swirl at full size (its forest is
+    16 blocks on level 2, 64 after refine-all), the swirl with the time-reversal factor
+    cos(pi t / t_a) (a different factor per stage), and constant advection with Bs 17 on
+    a uniform grid (eps = 0)."""
+    if case.startswith("c2_fp64"):
+        cfg, n, nsub = W.C2(form=W.FORM_FUSED), 5, int(case[-1])
+    elif case == "c2_reversal_4":
+        cfg, n, nsub = W.C2(form=W.FORM_FUSED).replace(phys=(5.0,)), 5, 4
+    else:
+        cfg, n, nsub = W.C1(jmax=3, eps=0.0, form=W.FORM_FUSED), 4, 1
+    s, o = _pair(cfg)
+    s.set_graph(0)
+    s.set_sweep(3)
+    s.tune(nsub=nsub)
+    s.timing(True)
+    t = 0.0
+    for k in range(n):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    st = s.stats()
+    assert st["sweep_launch"] == "rk4_tile" and st["rk4_tile_tiles"] == nsub
+    assert st["kernels"]["rk4_tile"]["launches"] == n and st["kernels"]["stage"]["launches"] == 0
+    # the first analysis of every adapt runs inside the tile launch: the swirl's adapts
+    # take two passes (one analysis launch left), the uniform eps = 0 grid one
+    assert st["kernels"]["mr"]["launches"] == (0 if case == "c1_uniform" else n)
+    assert_same(s, o, f"{case}: {n} steps")
+    s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("nsub", [1, 4])
+def test_overlapped_tile_rk4_alone_matches_oracle(nsub):
+    """mrb_rk4 in mode 3 (the tile step without the analysis folded in), then an
+    analysis pass: values, flags and detail maxima equal the oracle's."""
+    cfg = W.C2(form=W.FORM_FUSED).replace(phys=(5.0,))
+    s, o = _pair(cfg)
+    s.set_sweep(3)
+    s.tune(nsub=nsub)
+    for x in (s, o):
+        x.refine_all()
+        x.rk4(0.25, cfg.dt)
+    assert_same(s, o, "refine-all + rk4")
+    fs, ms = s.mr_pass()
+    fo, mo = o.mr_pass()
+    assert np.array_equal(fs, fo) and np.array_equal(_bits(ms), _bits(mo))
+    s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotuned_tile_step_matches_oracle(prec):
+    """The headline workload's step loop with the autotuner's choices (the tile step and,
+    where faster, the first analysis folded into it, with the tuned threads per
+    workgroup): FP64 equals the oracle bit for bit, mixed stays within 1e-5 with the
+    oracle's forest."""
+    cfg = W.C2(form=W.FORM_FUSED, precision=W.FP64 if prec == "fp64" else W.MIXED)
+    s = M.Solver(cfg)
+    o = oracle.Oracle(cfg.replace(precision=W.FP64))
+    for x in (s, o):
+        x.init_grid()
+    s.refine_all()
+    s.tune(reps=2)
+    lv, co = o.read_forest()
+    s.init_forest(lv, co)
+    s.load_blocks(o.read_blocks())
+    s.set_graph(0)
+    t = 0.0
+    for _ in range(6):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    st = s.stats()
+    print(st["sweep_launch"], st["rk4_tile_tiles"], st["rk4_tile_analysis"], st["tune_ms"].get("rk4_tile_analysis"))
+    if prec == "fp64":
+        assert_same(s, o, "autotuned step loop")
+    else:
+        lv1, co1 = s.read_forest()
+        lv2, co2 = o.read_forest()
+        assert np.array_equal(lv1, lv2) and np.array_equal(co1, co2)
+        ref = o.read_blocks()
+        assert np.max(np.abs(s.read_blocks() - ref)) / np.max(np.abs(ref)) <= 1e-5
+    s.close()
+
+
+@pytest.mark.gpu
+def test_overlapped_tile_rk4_mixed_equals_stage_launches():
+    """In the mixed form the overlapped-tile step performs the stage kernels' operations
+    in the same order, so it equals the four stage launches bit for bit, and both stay
+    within 1e-5 of the FP64 oracle."""
+    cfg = W.C2(form=W.FORM_FUSED, precision=W.MIXED)
+    a = M.Solver(cfg)
+    b = M.Solver(cfg)
+    o = oracle.Oracle(cfg.replace(precision=W.FP64))
+    for x in (a, b, o):
+        x.init_grid()
+    for x in (a, b):
+        x.set_graph(0)
+    a.set_sweep(3)
+    a.tune(nsub=2)
+    b.set_sweep(0)
+    t = 0.0
+    for _ in range(6):
+        for x in (a, b, o):
+            x.step(t, cfg.dt)
+        t += cfg.dt
+    assert a.stats()["sweep_launch"] == "rk4_tile" and b.stats()["sweep_launch"] == "four"
+    assert np.array_equal(_bits(a.read_blocks()), _bits(b.read_blocks()))
+    lv1, co1 = a.read_forest()
+    lv2, co2 = o.read_forest()
+    assert np.array_equal(lv1, lv2) and np.array_equal(co1, co2)
+    ref = o.read_blocks()
+    assert np.max(np.abs(a.read_blocks() - ref)) / np.max(np.abs(ref)) <= 1e-5
+    a.close()
+    b.close()
+
+
+@pytest.mark.gpu
+def test_overlapped_tile_rk4_falls_back_on_several_levels():
+    """Mode 3 on a forest with two levels takes the four stage launches (and stays exact)."""
+    cfg = W.C1(jmax=4, eps=1e-3, form=W.FORM_FUSED)
+    s, o = _pair(cfg)
+    lv, _ = s.read_forest()
+    assert len(set(lv.tolist())) > 1
+    s.set_graph(0)
+    s.set_sweep(3)
+    s.timing(True)
+    t = 0.0
+    for _ in range(3):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    assert s.stats()["kernels"]["stage"]["launches"] == 12
+    assert_same(s, o, "two levels, mode 3")
     s.close()
 
 
@@ -511,9 +652,17 @@ def test_autotuner_times_both_sweep_launch_forms():
     s.init_grid()
     before = s.read_blocks()
     s.tune(reps=2)
-    sw = s.stats()["tune_ms"]["sweep"]
+    st = s.stats()
+    sw = st["tune_ms"]["sweep"]
     assert sw["four"] > 0 and sw["one"] > 0
-    assert s.stats()["sweep_launch"] == ("one" if sw["one"] < sw["four"] else "four")
+    # the initial grid is on one level, so the overlapped-tile step is timed as well
+    rt = st["tune_ms"]["rk4_tile"]
+    assert set(rt) == {"1", "2", "4", "stages"} and all(v > 0 for v in rt.values())
+    best = min(rt[k] for k in ("1", "2", "4"))
+    if best < rt["stages"]:
+        assert st["sweep_launch"] == "rk4_tile" and rt[str(st["rk4_tile_tiles"])] == best
+    else:
+        assert st["sweep_launch"] == ("one" if sw["one"] < sw["four"] else "four")
     assert np.array_equal(_bits(s.read_blocks()), _bits(before))
     s.close()
 
