@@ -227,7 +227,11 @@ mrb_status mrb_set_graph(mrb_ctx *ctx, int enable);
  * forced or tuned by mrb_tune, else whole blocks.  In mrb_step the same launch also
  * performs the first analysis pass of the step's adapt (its halo is then three points
  * wider, so that u_new is known where the details' prediction reads it), unless the
- * autotuner found an analysis launch after it faster.
+ * autotuner found an analysis launch after it faster; and where the forest before the
+ * step is on one level below jmax, the safety-zone refinement as well (the tile is
+ * built from the parents: the children's values at the children's level, the parent's
+ * value or its prediction, never reach HBM), unless the autotuner found the
+ * refinement launch faster.
  * mode 2 (default): the autotuner (mrb_tune with reps > 0) times these forms on the
  * tuned tiling and keeps the fastest; four launches until then.  Results are
  * identical in every mode.  MRB_E_ARG for other values; modes 1 and 3 on the plain

@@ -206,8 +206,10 @@ hipError_t launch_sweep(const Shape& s, int precision, Variant v, int max_grid, 
                         int* grid_out);
 hipError_t launch_plain(const Shape& s, int grid, const StageArgs& a, hipStream_t st);  // ghost + RHS kernels
 // overlapped-tile RK4 step; hipErrorInvalidValue if the shape has no such kernel
-// (threads per workgroup: 256; with the analysis on whole blocks also 512 or 1024)
-hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, int tpb, int grid,
+// (threads per workgroup: 256; with the analysis on whole blocks also 512 or 1024;
+// refine: the refinement of the parents (every one, a forest on one level) folded in,
+// with the analysis only)
+hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, bool refine, int tpb, int grid,
                        const Rk4tArgs& a, hipStream_t st);
 int rk4t_variants(const Shape& s, int precision, int* nsub, int cap);
 hipError_t launch_mr(const Shape& s, int nsub, int grid, const MrArgs& a, hipStream_t st);

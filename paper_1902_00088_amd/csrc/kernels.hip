@@ -773,15 +773,12 @@ __device__ __forceinline__ void stage_pass(const StageArgs& A, const StageVar& V
     if (sw_lds) load_swirl<BS, S>(swirl, d, r0, cnt, A);
     __syncthreads();
     const bool hasc = d.n_coarse > 0;
-    if (V.stage == 1) {
-      YSrc<TT, KT, false> src{A.u, nullptr, 0.0, A.off};
+    auto gather = [&](const auto& src) {
       if (hasc) sgather<DIM, BS, S, HW, NF, true, TT, SB, TPB>(tile, carr, g, se, d.slot, r0, cnt, src);
       else sgather<DIM, BS, S, HW, NF, false, TT, SB, TPB>(tile, carr, g, se, d.slot, r0, cnt, src);
-    } else {
-      YSrc<TT, KT, true> src{A.u, (const KT*)V.kprev, V.alpha, A.off};
-      if (hasc) sgather<DIM, BS, S, HW, NF, true, TT, SB, TPB>(tile, carr, g, se, d.slot, r0, cnt, src);
-      else sgather<DIM, BS, S, HW, NF, false, TT, SB, TPB>(tile, carr, g, se, d.slot, r0, cnt, src);
-    }
+    };
+    if (V.stage == 1) gather(YSrc<TT, KT, false>{A.u, nullptr, 0.0, A.off});
+    else gather(YSrc<TT, KT, true>{A.u, (const KT*)V.kprev, V.alpha, A.off});
     if (hasc) spredict<DIM, BS, S, HW, NF, TT>(tile, carr, g, r0, cnt);
     TT r;
     if constexpr (sizeof(TT) == 8) r = A.lt.r[d.level];
@@ -975,7 +972,34 @@ struct TileDetails {
   }
 };
 
-template <int BS, int NSUB, typename TT, typename KT, bool ANA, int TPB>
+// With REF (the refinement of a forest on one level folded in as well) the tile is
+// built from the parents: block b is child b % 4 of refinement work b / 4 (every
+// parent refines, so children follow their parents in forest order), and a child
+// point takes the synchronised value at the children's level on the parents' grid --
+// the parent's value at even points, its prediction elsewhere -- as the refinement
+// kernel computes it; the children's pre-step values never reach HBM.
+template <int BS, int S, int E>
+struct ChildFromParents {
+  using G = Geo<2, BS, S, E>;
+  double* U;
+  const double* PT;   // parent-level values, pw0 per row, first point plo (parent-local)
+  int pw0, plo[2], qlo[2], qn[2], off[2];   // fine box (parent-local) and its tile offset
+  template <int NX, int NY, int NZ>
+  __device__ __forceinline__ void go(int cls) {
+    ParityClass<2> pc(cls, qlo, qn);
+    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
+      int Q[3];
+      pc.coords(p, Q);
+      const int bb[3] = {(NX == 4 ? (Q[0] - 3) / 2 : Q[0] / 2) - plo[0],
+                         (NY == 4 ? (Q[1] - 3) / 2 : Q[1] / 2) - plo[1], 0};
+      const int stride[3] = {1, 1, 1};
+      auto at = [&](int x, int y, int) { return PT[x + pw0 * y]; };
+      U[G::idx(Q[0] - off[0], Q[1] - off[1], 0)] = tensor_fixed<NX, NY, NZ, double>(at, bb, stride);
+    }
+  }
+};
+
+template <int BS, int NSUB, typename TT, typename KT, bool ANA, int TPB, bool REF = false>
 __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
   using TG = TileGeo<BS, NSUB, ANA>;
   constexpr int HW = TG::HW, E = TG::E, S = TG::S, TW = TG::TW, TSZ = TG::TSZ, NP = BS * BS;
@@ -999,8 +1023,11 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
     subregion<2>(it.w % NSUBT, NSUB, S, BS, r0, cnt);
     if (tid < 9) tab[tid] = -1;
     __syncthreads();
-    const NbEntry* ent = A.topo.nb(b);
-    for (int e = tid; e < d.n_ent; e += blockDim.x) {
+    // same-level holders by direction: the block's (or, with REF, its parent's)
+    const int ri = b >> 2, ch = b & 3;
+    const BlockDesc P = REF ? A.topo.pblk()[ri] : d;
+    const NbEntry* ent = REF ? A.topo.pnb(ri) : A.topo.nb(b);
+    for (int e = tid; e < P.n_ent; e += blockDim.x) {
       const NbEntry q = ent[e];
       const int ox = q.o[0], oy = q.o[1];
       if (q.dl == 0 && ox % (BS - 1) == 0 && oy % (BS - 1) == 0 && ox >= -(BS - 1) && ox <= BS - 1 &&
@@ -1018,8 +1045,39 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
       }
     }
     __syncthreads();
-    // u over the region + E
-    {
+    if constexpr (REF) {
+      // parent-level values over the fine box [r0 + cb - E, r0 + cb + cnt - 1 + E] and
+      // the prediction's reach (3 fine points), into the slope space (unused until k1)
+      double* PT = reinterpret_cast<double*>(K);
+      const bool own = A.topo.ref()[ri].child[ch] == d.slot;
+      int cb[2], plo[2], pw[2];
+      for (int a = 0; a < 2; ++a) {
+        cb[a] = ((ch >> a) & 1) * (BS - 1);
+        plo[a] = (r0[a] + cb[a] - E - 3) >> 1;
+        pw[a] = ((r0[a] + cb[a] + cnt[a] - 1 + E + 3) >> 1) - plo[a] + 1;
+      }
+      for (int p = tid; p < pw[0] * pw[1]; p += blockDim.x) {
+        const int px = plo[0] + p % pw[0], py = plo[1] + p / pw[0];
+        const int dx = px < 0 ? 0 : (px > BS - 1 ? 2 : 1), dy = py < 0 ? 0 : (py > BS - 1 ? 2 : 1);
+        const int slot = own ? tab[dy * 3 + dx] : -1;
+        const int lx = px - (dx - 1) * (BS - 1), ly = py - (dy - 1) * (BS - 1);
+        PT[p] = slot >= 0 ? A.u[(size_t)slot * NP + lx + BS * ly] : __builtin_nan("");
+      }
+      __syncthreads();
+      ChildFromParents<BS, S, E> cf;
+      cf.U = U;
+      cf.PT = PT;
+      cf.pw0 = pw[0];
+      for (int a = 0; a < 2; ++a) {
+        cf.plo[a] = plo[a];
+        cf.qlo[a] = r0[a] + cb[a] - E;
+        cf.qn[a] = cnt[a] + 2 * E;
+        cf.off[a] = r0[a] + cb[a] - E;
+      }
+      cf.template go<1, 1, 1>(0);
+      for_odd_classes<2>(cf);
+    } else {
+      // u over the region + E
       const int nx = cnt[0] + 2 * E, ny = cnt[1] + 2 * E;
       for (int p = tid; p < nx * ny; p += blockDim.x) {
         const int ix = p % nx, iy = p / nx;
@@ -1799,10 +1857,18 @@ hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, cons
 // with the analysis folded in, whole blocks may take 512 or 1024 threads (a forest
 // small enough for this form leaves most compute units idle otherwise)
 template <int B, int NS, typename TT, typename KT>
-static hipError_t rk4t_go(bool ana, int tpb, int grid, const Rk4tArgs& a, hipStream_t st) {
+static hipError_t rk4t_go(bool ana, bool ref, int tpb, int grid, const Rk4tArgs& a, hipStream_t st) {
   const size_t per = sizeof(double) + 3 * sizeof(KT) + sizeof(TT);
   if (ana) {
     const size_t lds = (size_t)TileGeo<B, NS, true>::TSZ * per;
+    if (ref) {
+      if (tpb == 256) return go(k_rk4t<B, NS, TT, KT, true, 256, true>, grid, lds, st, a, 256);
+      if constexpr (NS == 1) {
+        if (tpb == 512) return go(k_rk4t<B, NS, TT, KT, true, 512, true>, grid, lds, st, a, 512);
+        if (tpb == 1024) return go(k_rk4t<B, NS, TT, KT, true, 1024, true>, grid, lds, st, a, 1024);
+      }
+      return hipErrorInvalidValue;
+    }
     if (tpb == 256) return go(k_rk4t<B, NS, TT, KT, true, 256>, grid, lds, st, a, 256);
     if constexpr (NS == 1) {
       if (tpb == 512) return go(k_rk4t<B, NS, TT, KT, true, 512>, grid, lds, st, a, 512);
@@ -1810,17 +1876,18 @@ static hipError_t rk4t_go(bool ana, int tpb, int grid, const Rk4tArgs& a, hipStr
     }
     return hipErrorInvalidValue;
   }
+  if (ref) return hipErrorInvalidValue;
   if (tpb != 256) return hipErrorInvalidValue;
   return go(k_rk4t<B, NS, TT, KT, false, 256>, grid, (size_t)TileGeo<B, NS, false>::TSZ * per, st, a);
 }
 
-hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, int tpb, int grid,
+hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, bool refine, int tpb, int grid,
                        const Rk4tArgs& a, hipStream_t st) {
   if (s.dim != 2 || s.hw != 2 || s.nf != 1) return hipErrorInvalidValue;
-#define X(B, P, NS)                                                                             \
-  if (s.bs == B && precision == P && nsub == NS) {                                             \
-    if constexpr (P == 0) return rk4t_go<B, NS, double, double>(analysis, tpb, grid, a, st);   \
-    else return rk4t_go<B, NS, float, float>(analysis, tpb, grid, a, st);                      \
+#define X(B, P, NS)                                                                                     \
+  if (s.bs == B && precision == P && nsub == NS) {                                                     \
+    if constexpr (P == 0) return rk4t_go<B, NS, double, double>(analysis, refine, tpb, grid, a, st);   \
+    else return rk4t_go<B, NS, float, float>(analysis, refine, tpb, grid, a, st);                      \
   }
   MRB_RK4T_VARIANTS(X)
 #undef X

@@ -260,6 +260,8 @@ struct mrb_ctx {
   bool rk4t_tuned = false;     // the autotuner found it faster than the stage launches
   int ana_nsub = 0;            // first analysis folded into it: tiling (0 not tuned: the RK4 tiling;
   int ana_tpb = 256;           // -1: not folded) and threads per workgroup
+  int ref_fold = 1;            // the safety-zone refinement folded in as well (0: the autotuner found
+                               // the refinement launch before it faster)
   int sweep_grid = 0;          // workgroups of the last whole-sweep launch
   double *h_maxd2 = nullptr, *dmaxd2 = nullptr;
   int flag_set = 0;                    // set the next analysis writes
@@ -978,11 +980,12 @@ Rk4tArgs rk4t_args(mrb_ctx* c, double t, double dt) {
 
 // launch the overlapped-tile RK4 step (tn sub-tiles per axis), with the analysis of
 // u_new folded in or not
-mrb_status launch_tiled(mrb_ctx* c, int tn, const Rk4tArgs& ra, bool analysis, int tpb = 256) {
+mrb_status launch_tiled(mrb_ctx* c, int tn, const Rk4tArgs& ra, bool analysis, int tpb = 256, bool refine = false) {
   const long work = (long)nblk(c) * tn * tn;
-  // algorithmic bytes: u read once, u_new written once
-  TimeScope rs(c, T_RK4T, (double)nblk(c) * c->bsz * 16.0);
-  HIPCHK(c, launch_rk4t(c->shape, c->cfg.precision, tn, analysis, tpb, grid_for(c, work), ra, c->stream));
+  // algorithmic bytes: u read once (with the refinement folded in: the parents', a
+  // quarter of the blocks), u_new written once
+  TimeScope rs(c, T_RK4T, (double)nblk(c) * c->bsz * (refine ? 10.0 : 16.0));
+  HIPCHK(c, launch_rk4t(c->shape, c->cfg.precision, tn, analysis, refine, tpb, grid_for(c, work), ra, c->stream));
   return MRB_OK;
 }
 
@@ -1073,10 +1076,12 @@ mrb_ctx::Memo* spec_entry(mrb_ctx* c);
 // The RK4 step and the first analysis pass of its adapt as one overlapped-tile launch,
 // where the forest is on one level and that form is selected (else *done = false and
 // nothing is launched); then the rest of the adapt.
-mrb_status rk4_adapt_tiled(mrb_ctx* c, double t, double dt, bool* done) {
+mrb_status rk4_adapt_tiled(mrb_ctx* c, double t, double dt, bool* done, bool refine) {
   *done = false;
   int tn = rk4t_pick(c), tpb = 256;
   if (tn == 0 || filter_on(c) || c->ana_nsub < 0) return MRB_OK;
+  if (refine && (long)c->pending_ref * (1 << c->cfg.dim) != (long)nblk(c))
+    return fail(c, MRB_E_STATE, "folded refinement: not every block was refined");
   if (c->ana_nsub > 0) {
     tn = c->ana_nsub;
     tpb = c->ana_tpb;
@@ -1086,13 +1091,25 @@ mrb_status rk4_adapt_tiled(mrb_ctx* c, double t, double dt, bool* done) {
   Rk4tArgs ra = rk4t_args(c, t, dt);
   c->flag_set = 0;
   rk4t_analysis_args(c, ra, fused ? e->smap : nullptr);
-  mrb_status r = launch_tiled(c, tn, ra, true, tpb);
+  mrb_status r = launch_tiled(c, tn, ra, true, tpb, refine);
   if (r) return r;
   std::swap(c->u, c->unew);
   c->n_rk4++;
   c->n_block_updates += (long)nblk(c);
   *done = true;
   return do_adapt(c, nullptr, true, fused);
+}
+
+// the step's refinement can be folded into the tile launch: the forest is on one level
+// below jmax (refine-all refines every block, the children are on one level) and the
+// tile step with the first analysis folded in is selected for them
+bool refine_foldable(const mrb_ctx* c) {
+  if (c->cfg.form != MRB_FORM_FUSED || c->cfg.dim != 2 || filter_on(c) || c->ana_nsub < 0 || !c->ref_fold)
+    return false;
+  if (!(c->sweep_mode == 3 || (c->sweep_mode == 2 && c->rk4t_tuned))) return false;
+  int v[8];
+  if (rk4t_variants(c->shape, c->cfg.precision, v, 8) == 0 || !one_level(c)) return false;
+  return !c->leaves.empty() && c->leaves[0].level < c->cfg.jmax && !c->dev.active;
 }
 
 // refinement kernel over the uploaded plan (nref parents); fixed_grid for graph capture
@@ -2405,9 +2422,11 @@ mrb_status mrb_step(mrb_ctx* c, double t0, double dt, int nsteps) {
     if (graph_ok(c)) {
       if ((r = step_graph(c, t0 + s * dt, dt))) return r;
     } else {
-      if ((r = do_refine_all(c))) return r;
+      const bool fold = refine_foldable(c);
+      if ((r = do_refine_all(c, !fold))) return r;
       bool tiled = false;
-      if ((r = rk4_adapt_tiled(c, t0 + s * dt, dt, &tiled))) return r;
+      if ((r = rk4_adapt_tiled(c, t0 + s * dt, dt, &tiled, fold))) return r;
+      if (fold && !tiled) return fail(c, MRB_E_STATE, "folded refinement was not launched");
       if (!tiled && (r = do_rk4(c, t0 + s * dt, dt))) return r;
       if (!tiled && (r = do_adapt(c, nullptr, false, false))) return r;
     }
@@ -2521,7 +2540,7 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"rk4_tile_tiles\": %d, \"rk4_tile_tuned\": %d, \"rk4_tile_analysis\": [%d, %d], \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"rk4_tile_tiles\": %d, \"rk4_tile_tuned\": %d, \"rk4_tile_analysis\": [%d, %d], \"rk4_tile_refine\": %d, \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
                 "\"plan_entries\": %.1f, \"plan_entries_per_block\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
@@ -2531,7 +2550,7 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
                 c->order ? "level-sorted" : "forest",
                 c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses,
                 c->have_forest && rk4t_pick(c) > 0 ? "rk4_tile" : (sweep_in_one(c) ? "one" : "four"), c->rk4t_nsub,
-                c->rk4t_tuned ? 1 : 0, c->ana_nsub, c->ana_tpb, c->sweep_grid, c->dev.active ? "device" : "host",
+                c->rk4t_tuned ? 1 : 0, c->ana_nsub, c->ana_tpb, c->ref_fold, c->sweep_grid, c->dev.active ? "device" : "host",
                 c->dev.mode, c->dev.steps, c->dev.passes, c->dev.pushes, c->dev.pulls, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
                 c->hus_launch, c->hus_index, c->hus_desc, c->hus_desc_par, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
@@ -2558,6 +2577,7 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
       if (tv[i] == nsub) c->rk4t_nsub = nsub;
     c->ana_nsub = 0;
     c->ana_tpb = 256;
+    c->ref_fold = 1;
   } else if (reps > 0) {
     if (!check_state(c, true)) return MRB_E_STATE;
     if (!(dt > 0.0)) return fail(c, MRB_E_ARG, "tune: dt must be positive");
@@ -2749,6 +2769,39 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
             c->ana_nsub = ac[bj].nsub;
             c->ana_tpb = ac[bj].tpb;
           }
+        }
+        // the refinement folded in as well, right after a refine-all of a forest on one
+        // level (its plan is the uploaded one and the parents' data is intact): one
+        // launch against the refinement launch and the tile launch
+        c->ref_fold = 1;
+        if (c->ana_nsub > 0 && (long)c->pending_ref * (1 << c->cfg.dim) == (long)nblk(c)) {
+          float best_f[2] = {1e30f, 1e30f};
+          Rk4tArgs ra = rk4t_args(c, 0.0, dt);
+          rk4t_analysis_args(c, ra, nullptr);
+          for (int round = 0; round < kRounds && !r; ++round)
+            for (int m = 0; m < 2 && !r; ++m) {
+              for (int k = 0; k < reps + 1 && !r; ++k) {   // the first is a warm-up
+                if (k == 1 && hipEventRecord(e0, c->stream) != hipSuccess) r = MRB_E_DEVICE;
+                if (r) break;
+                if (m == 0) {
+                  r = launch_tiled(c, c->ana_nsub, ra, true, c->ana_tpb, true);
+                } else {
+                  r = launch_refine_kernel(c, c->pending_ref, false);
+                  if (!r) r = launch_tiled(c, c->ana_nsub, ra, true, c->ana_tpb);
+                }
+              }
+              float ms = 0.f;
+              if (!r && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                r = fail(c, MRB_E_DEVICE, "tune: event");
+              if (!r) best_f[m] = std::min(best_f[m], ms / reps);
+            }
+          if (r) return done(r);
+          char buf[96];
+          std::snprintf(buf, sizeof buf, ", \"rk4_tile_refine\": {\"folded\": %.4f, \"separate\": %.4f}",
+                        best_f[0], best_f[1]);
+          c->tune_log += buf;
+          c->ref_fold = best_f[0] < best_f[1] ? 1 : 0;
         }
       }
     }

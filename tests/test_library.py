@@ -532,8 +532,10 @@ def test_overlapped_tile_rk4_matches_oracle(case):
     assert st["sweep_launch"] == "rk4_tile" and st["rk4_tile_tiles"] == nsub
     assert st["kernels"]["rk4_tile"]["launches"] == n and st["kernels"]["stage"]["launches"] == 0
     # the first analysis of every adapt runs inside the tile launch: the swirl's adapts
-    # take two passes (one analysis launch left), the uniform eps = 0 grid one
+    # take two passes (one analysis launch left), the uniform eps = 0 grid one; the
+    # swirl's refine-all (16 blocks on level 2) is folded in too
     assert st["kernels"]["mr"]["launches"] == (0 if case == "c1_uniform" else n)
+    assert st["kernels"]["refine"]["launches"] == 0
     assert_same(s, o, f"{case}: {n} steps")
     s.close()
 
