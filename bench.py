@@ -32,6 +32,8 @@ def counter_traffic(key):
     WRITE_SIZE runs, scaled by a copy calibration), or None if the kernel source
     changed since the counters were taken."""
     import hashlib
+    if key is None:
+        return None
     path = os.path.join(ROOT, "profiles", "stage_traffic_counters.md")
     src = os.path.join(ROOT, "paper_1902_00088_amd", "csrc", "kernels.hip")
     try:
@@ -48,6 +50,23 @@ def counter_traffic(key):
     if vals.get("sha") != sha or "bytes" not in vals:
         return None
     return vals["bytes"]
+
+
+def traffic_key(wl, form, kind):
+    """Key of the counter summary for the dominant kernel of a form's run (stage launches
+    or the overlapped-tile step with what it folds in), or None."""
+    if kind == "stage":
+        return f"{wl} nsub {form['stage_tiles']}" + tkey(form)
+    if kind == "rk4_tile":
+        r = form.get("rk4_tile") or {}
+        a = r.get("analysis_folded") or [0, 256]
+        f = r.get("refine_folded") or [0, 0, 256]
+        if a[0] > 0 and f[0] and f[1] > 0:
+            return f"{wl} rk4_tile nsub {f[1]} t{f[2]} analysis refine"
+        if a[0] > 0:
+            return f"{wl} rk4_tile nsub {a[0]} t{a[1]} analysis" + (" refine" if f[0] else "")
+        return f"{wl} rk4_tile nsub {r.get('tiles')}"
+    return None
 
 
 def tkey(form):
@@ -103,7 +122,9 @@ def run_form(M, W, torch, cfg, steps, warmup, tune=False):
     kst = s.stats()["kernels"]
     s.timing(False)
     s.close()
-    sweep_ms = sum(kst[k]["ms"] for k in ("stage", "ghost", "rhs_plain"))
+    # the RK4 sweep's kernels (the overlapped-tile launch also holds the refinement and
+    # the first analysis where those are folded in)
+    sweep_ms = sum(kst[k]["ms"] for k in ("stage", "ghost", "rhs_plain", "rk4_tile") if k in kst)
     return {
         "value": bu / wall,
         "ms_per_step": 1e3 * wall / steps,
@@ -115,6 +136,9 @@ def run_form(M, W, torch, cfg, steps, warmup, tune=False):
         "host_us_per_step": host_us,
         "stage_tiles": tiles,
         "stage_threads": st.get("stage_threads"),
+        "sweep_launch": st.get("sweep_launch"),
+        "rk4_tile": {"tiles": st.get("rk4_tile_tiles"), "analysis_folded": st.get("rk4_tile_analysis"),
+                     "refine_folded": st.get("rk4_tile_refine")},
         "tune_ms": st.get("tune_ms"),
         "graph_in_use": st.get("graph_in_use"),
         "memo_hits": st.get("memo_hits"),
@@ -239,7 +263,7 @@ def headline(args, res, acc=None):
     ach = ks[dom]["bytes"] / (ks[dom]["ms"] * 1e-3) / 1e9 if ks[dom]["ms"] > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach / PEAK_HBM_GBS,
-                "traffic": counter_traffic(f"c2 nsub {head['stage_tiles']}" + tkey(head)) if dom == "stage" else None,
+                "traffic": counter_traffic(traffic_key("c2", head, dom)),
                 "traffic_unit": "bytes per launch", "kernel": dom,
                 "algorithmic_bytes_per_launch": ks[dom]["bytes"] / max(1, ks[dom]["launches"]),
                 "launches": ks[dom]["launches"], "avg_launch_us": 1e3 * ks[dom]["ms"] / max(1, ks[dom]["launches"])}
@@ -282,6 +306,7 @@ def main():
     ap.add_argument("--acc-steps", type=int, default=40,
                     help="steps of the mixed-vs-FP64 accuracy runs (C2; C3 and C4 take half; 0 = skip)")
     ap.add_argument("--c3-steps", type=int, default=20, help="steps of the Navier-Stokes workload (0 = skip)")
+    ap.add_argument("--c3-forms", default="fp64_plain,fp64_fused,mixed_fused")
     ap.add_argument("--no-tune", action="store_true", help="default tilings instead of the autotuner")
     ap.add_argument("--c5-steps", type=int, default=2000,
                     help="recorded steps of the learned-predictor study (0 = skip)")
@@ -349,11 +374,11 @@ def main():
     if args.c3_steps > 0:
         # compressible Navier-Stokes mixing layer: 4 fields, halo 4, nested derivatives
         c3 = {}
-        for name in ("fp64_fused", "mixed_fused"):
+        for name in [f for f in args.c3_forms.split(",") if f]:
             prec, form = forms[name]
             print(f"bench: C3 {name} steps={args.c3_steps}", file=sys.stderr, flush=True)
             c3[name] = run_form(M, W, torch, W.C3().replace(precision=prec, form=form), args.c3_steps, 2,
-                                tune=not args.no_tune)
+                                tune=form == W.FORM_FUSED and not args.no_tune)
         acc3 = None
         if args.acc_steps > 0:
             print(f"bench: C3 mixed accuracy steps={max(1, args.acc_steps // 2)}", file=sys.stderr, flush=True)
@@ -361,15 +386,17 @@ def main():
         out["c3"] = {"workload": f"C3 2D compressible Navier-Stokes temporal mixing layer (rho, u, v, p), Bs=33, "
                                  f"Jmax=8, eps=1e-3, Re=1000, Mach 0.4; {args.c3_steps} timed steps",
                      "forms": c3, "mixed_accuracy": acc3,
+                     "speedup_mixed_fused_vs_fp64_plain": speedup_entry(c3, acc3),
                      "speedup_mixed_fused_vs_fp64_fused": speedup_entry(c3, acc3, base="fp64_fused")}
-        ks3 = c3["mixed_fused"]["kernels"]["stage"]
-        ach3 = ks3["bytes"] / (ks3["ms"] * 1e-3) / 1e9 if ks3["ms"] > 0 else 0.0
-        out["c3"]["roofline_stage_mixed"] = {
-            "bound": "hbm", "achieved": ach3, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach3 / PEAK_HBM_GBS,
-            "traffic": counter_traffic(f"c3 nsub {c3['mixed_fused']['stage_tiles']}" + tkey(c3['mixed_fused'])),
-            "traffic_unit": "bytes per launch",
-            "algorithmic_bytes_per_launch": ks3["bytes"] / max(1, ks3["launches"]),
-            "avg_launch_us": 1e3 * ks3["ms"] / max(1, ks3["launches"])}
+        if "mixed_fused" in c3:
+            ks3 = c3["mixed_fused"]["kernels"]["stage"]
+            ach3 = ks3["bytes"] / (ks3["ms"] * 1e-3) / 1e9 if ks3["ms"] > 0 else 0.0
+            out["c3"]["roofline_stage_mixed"] = {
+                "bound": "hbm", "achieved": ach3, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach3 / PEAK_HBM_GBS,
+                "traffic": counter_traffic(f"c3 nsub {c3['mixed_fused']['stage_tiles']}" + tkey(c3['mixed_fused'])),
+                "traffic_unit": "bytes per launch",
+                "algorithmic_bytes_per_launch": ks3["bytes"] / max(1, ks3["launches"]),
+                "avg_launch_us": 1e3 * ks3["ms"] / max(1, ks3["launches"])}
 
     if args.c5_steps > 0:
         from paper_1902_00088_amd import predictor as P

@@ -1188,7 +1188,7 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
 // ---------------------------------------------------------------------------
 // plain form: ghost fill into HBM per level, then a separate RHS + update kernel
 // ---------------------------------------------------------------------------
-template <int DIM, int BS, int HW>
+template <int DIM, int BS, int HW, int NF>
 __global__ void __launch_bounds__(256) k_ghost(StageArgs A) {
   constexpr int H = HW + 3, S = BS;
   using G = Geo<DIM, BS, S, H>;
@@ -1206,16 +1206,62 @@ __global__ void __launch_bounds__(256) k_ghost(StageArgs A) {
     const int h_even = d.n_coarse > 0 ? H : 0;
     if (A.stage == 1) {
       YSrc<double, double, false> src{A.u, nullptr, 0.0, A.off};
-      gfill<DIM, BS, S, H, 1, double>(tile, g, r0, cnt, HW, h_even, src);
+      gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, HW, h_even, src);
     } else {
       YSrc<double, double, true> src{A.u, (const double*)A.kprev, A.alpha, A.off};
-      gfill<DIM, BS, S, H, 1, double>(tile, g, r0, cnt, HW, h_even, src);
+      gfill<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, HW, h_even, src);
     }
-    if (d.n_coarse > 0) gpredict<DIM, BS, S, H, 1, double>(tile, g, r0, cnt, HW);
-    double* gh = A.ghost + (size_t)d.slot * GSZ;
-    for (int p = threadIdx.x; p < GSZ; p += blockDim.x) {
-      const int x = p % GW, y = (p / GW) % GW, z = DIM > 2 ? p / (GW * GW) : 0;
-      gh[p] = tile[G::idx(x + 3, y + 3, DIM > 2 ? z + 3 : 0)];
+    if (d.n_coarse > 0) gpredict<DIM, BS, S, H, NF, double>(tile, g, r0, cnt, HW);
+    double* gh = A.ghost + (size_t)d.slot * NF * GSZ;
+    for (int p = threadIdx.x; p < NF * GSZ; p += blockDim.x) {
+      const int f = p / GSZ, q = p % GSZ;
+      const int x = q % GW, y = (q / GW) % GW, z = DIM > 2 ? q / (GW * GW) : 0;
+      gh[p] = tile[f * G::TSZ + G::idx(x + 3, y + 3, DIM > 2 ? z + 3 : 0)];
+    }
+    __syncthreads();
+  }
+}
+
+// plain form, Navier-Stokes: the ghosted fields from HBM into LDS, then the fused
+// form's stresses, fluxes and RHS in FP64
+template <int BS, int HW>
+__global__ void __launch_bounds__(256) k_rhs_plain_ns(StageArgs A) {
+  constexpr int GW = BS + 2 * HW, NP = BS * BS, GSZ = GW * GW;
+  using G = Geo<2, BS, BS, HW>;
+  static_assert(G::TSZ == GSZ, "ghosted block layout");
+  extern __shared__ __align__(16) char smem[];
+  double* T = reinterpret_cast<double*>(smem);
+  double* W = T + 4 * GSZ;
+  const int n = A.lvl_end - A.lvl_begin;
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int b = A.topo.list()[A.lvl_begin + w];
+    const BlockDesc d = A.topo.blk()[b];
+    const double* gh = A.ghost + (size_t)d.slot * 4 * GSZ;
+    for (int p = threadIdx.x; p < 4 * GSZ; p += blockDim.x) T[p] = gh[p];
+    __syncthreads();
+    NsConst<double> K;
+    K.mu = A.ph.mu;
+    K.kap = A.ph.kap;
+    K.gam = A.ph.gamma;
+    K.c23 = 2.0 / 3.0;
+    K.r = A.lt.r[d.level];
+    const int cnt[3] = {BS, BS, 1};
+    ns_fluxes<BS, BS, HW, double>(T, W, cnt, K);
+    const size_t base = (size_t)d.slot * 4 * NP;
+    for (int p = threadIdx.x; p < NP; p += blockDim.x) {
+      double kv[4];
+      ns_rhs<BS, BS, HW, double>(T, W, p % BS, p / BS, K, kv);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const size_t q = base + (size_t)f * NP + p;
+        if (A.stage < 4) {
+          ((double*)A.kout)[q] = kv[f];
+        } else {
+          const double k1 = ((const double*)A.k1)[q], k2 = ((const double*)A.k2)[q];
+          const double k3 = ((const double*)A.k3)[q], k4 = kv[f];
+          A.unew[q] = A.u[q] + A.h6 * ((k1 + k4) + 2.0 * (k2 + k3));
+        }
+      }
     }
     __syncthreads();
   }
@@ -1913,17 +1959,21 @@ hipError_t launch_sweep(const Shape& s, int precision, Variant v, int max_grid, 
   return hipErrorInvalidValue;
 }
 
-template <int DIM, int BS, int HW>
+template <int DIM, int BS, int HW, int NF>
 static hipError_t plain_go(int grid, const StageArgs& a, hipStream_t st) {
   using G = Geo<DIM, BS, BS, HW + 3>;
-  hipError_t e = go(k_ghost<DIM, BS, HW>, grid, sizeof(double) * G::TSZ, st, a);
+  hipError_t e = go(k_ghost<DIM, BS, HW, NF>, grid, sizeof(double) * NF * G::TSZ, st, a);
   if (e != hipSuccess) return e;
-  return go(k_rhs_plain<DIM, BS, HW>, grid, 0, st, a);
+  if constexpr (NF == 4) {
+    constexpr int GW = BS + 2 * HW;
+    return go(k_rhs_plain_ns<BS, HW>, grid, sizeof(double) * (4 * GW * GW + 5 * (BS + 4) * (BS + 4)), st, a);
+  } else {
+    return go(k_rhs_plain<DIM, BS, HW>, grid, 0, st, a);
+  }
 }
 
 hipError_t launch_plain(const Shape& s, int grid, const StageArgs& a, hipStream_t st) {
-  if (s.nf != 1) return hipErrorInvalidValue;
-#define X(D, B, W, F) if (s.dim == D && s.bs == B && s.hw == W && F == 1) return plain_go<D, B, W>(grid, a, st);
+#define X(D, B, W, F) if (s.dim == D && s.bs == B && s.hw == W && s.nf == F) return plain_go<D, B, W, F>(grid, a, st);
   MRB_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;

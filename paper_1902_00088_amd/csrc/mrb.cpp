@@ -262,6 +262,8 @@ struct mrb_ctx {
   int ana_tpb = 256;           // -1: not folded) and threads per workgroup
   int ref_fold = 1;            // the safety-zone refinement folded in as well (0: the autotuner found
                                // the refinement launch before it faster)
+  int ref_nsub = 0;            // its tiling and threads per workgroup (0: those of the folded analysis)
+  int ref_tpb = 256;
   int sweep_grid = 0;          // workgroups of the last whole-sweep launch
   double *h_maxd2 = nullptr, *dmaxd2 = nullptr;
   int flag_set = 0;                    // set the next analysis writes
@@ -1082,7 +1084,10 @@ mrb_status rk4_adapt_tiled(mrb_ctx* c, double t, double dt, bool* done, bool ref
   if (tn == 0 || filter_on(c) || c->ana_nsub < 0) return MRB_OK;
   if (refine && (long)c->pending_ref * (1 << c->cfg.dim) != (long)nblk(c))
     return fail(c, MRB_E_STATE, "folded refinement: not every block was refined");
-  if (c->ana_nsub > 0) {
+  if (refine && c->ref_nsub > 0) {
+    tn = c->ref_nsub;
+    tpb = c->ref_tpb;
+  } else if (c->ana_nsub > 0) {
     tn = c->ana_nsub;
     tpb = c->ana_tpb;
   }
@@ -2104,7 +2109,6 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
   if (cfg->physics == MRB_NS2D && (cfg->phys[0] <= 1.0 || cfg->phys[1] < 0.0 || cfg->phys[2] <= 0.0 ||
                                     !(cfg->phys[3] >= 0.0)))
     return bad("Navier-Stokes needs gamma > 1, mu >= 0, Pr > 0 and a filter threshold >= 0");
-  if (cfg->form == MRB_FORM_PLAIN && cfg->nfields != 1) return bad("the plain form covers the advection shapes only");
   c->shape = Shape{cfg->dim, cfg->bs, cfg->hw, cfg->nfields};
   if (!shape_supported(c->shape)) return bad("unsupported (dim, bs, hw, nfields) combination");
   c->np = 1;
@@ -2540,7 +2544,7 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"rk4_tile_tiles\": %d, \"rk4_tile_tuned\": %d, \"rk4_tile_analysis\": [%d, %d], \"rk4_tile_refine\": %d, \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"rk4_tile_tiles\": %d, \"rk4_tile_tuned\": %d, \"rk4_tile_analysis\": [%d, %d], \"rk4_tile_refine\": [%d, %d, %d], \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
                 "\"plan_entries\": %.1f, \"plan_entries_per_block\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
@@ -2550,7 +2554,7 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
                 c->order ? "level-sorted" : "forest",
                 c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses,
                 c->have_forest && rk4t_pick(c) > 0 ? "rk4_tile" : (sweep_in_one(c) ? "one" : "four"), c->rk4t_nsub,
-                c->rk4t_tuned ? 1 : 0, c->ana_nsub, c->ana_tpb, c->ref_fold, c->sweep_grid, c->dev.active ? "device" : "host",
+                c->rk4t_tuned ? 1 : 0, c->ana_nsub, c->ana_tpb, c->ref_fold, c->ref_nsub, c->ref_tpb, c->sweep_grid, c->dev.active ? "device" : "host",
                 c->dev.mode, c->dev.steps, c->dev.passes, c->dev.pushes, c->dev.pulls, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
                 c->hus_launch, c->hus_index, c->hus_desc, c->hus_desc_par, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
@@ -2578,6 +2582,8 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->ana_nsub = 0;
     c->ana_tpb = 256;
     c->ref_fold = 1;
+    c->ref_nsub = 0;
+    c->ref_tpb = 256;
   } else if (reps > 0) {
     if (!check_state(c, true)) return MRB_E_STATE;
     if (!(dt > 0.0)) return fail(c, MRB_E_ARG, "tune: dt must be positive");
@@ -2722,9 +2728,9 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
         // the first analysis folded into the tile launch (tilings x threads) against
         // the tile launch followed by an analysis launch
         c->ana_nsub = -1;
+        struct AC { int nsub, tpb; float ms; };
+        std::vector<AC> ac;
         if (c->rk4t_tuned) {
-          struct AC { int nsub, tpb; float ms; };
-          std::vector<AC> ac;
           for (int i = 0; i < nt; ++i)
             for (int tp : {256, 512, 1024})
               if (tp == 256 || tv[i] == 1) ac.push_back(AC{tv[i], tp, 1e30f});
@@ -2772,19 +2778,22 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
         }
         // the refinement folded in as well, right after a refine-all of a forest on one
         // level (its plan is the uploaded one and the parents' data is intact): one
-        // launch against the refinement launch and the tile launch
+        // launch per tiling and thread count against the refinement launch followed by
+        // the chosen tile launch
         c->ref_fold = 1;
+        c->ref_nsub = 0;
+        c->ref_tpb = 256;
         if (c->ana_nsub > 0 && (long)c->pending_ref * (1 << c->cfg.dim) == (long)nblk(c)) {
-          float best_f[2] = {1e30f, 1e30f};
+          std::vector<float> best_f(ac.size() + 1, 1e30f);
           Rk4tArgs ra = rk4t_args(c, 0.0, dt);
           rk4t_analysis_args(c, ra, nullptr);
           for (int round = 0; round < kRounds && !r; ++round)
-            for (int m = 0; m < 2 && !r; ++m) {
+            for (size_t m = 0; m <= ac.size() && !r; ++m) {
               for (int k = 0; k < reps + 1 && !r; ++k) {   // the first is a warm-up
                 if (k == 1 && hipEventRecord(e0, c->stream) != hipSuccess) r = MRB_E_DEVICE;
                 if (r) break;
-                if (m == 0) {
-                  r = launch_tiled(c, c->ana_nsub, ra, true, c->ana_tpb, true);
+                if (m < ac.size()) {
+                  r = launch_tiled(c, ac[m].nsub, ra, true, ac[m].tpb, true);
                 } else {
                   r = launch_refine_kernel(c, c->pending_ref, false);
                   if (!r) r = launch_tiled(c, c->ana_nsub, ra, true, c->ana_tpb);
@@ -2797,11 +2806,21 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
               if (!r) best_f[m] = std::min(best_f[m], ms / reps);
             }
           if (r) return done(r);
-          char buf[96];
-          std::snprintf(buf, sizeof buf, ", \"rk4_tile_refine\": {\"folded\": %.4f, \"separate\": %.4f}",
-                        best_f[0], best_f[1]);
+          size_t bf = 0;
+          c->tune_log += ", \"rk4_tile_refine\": {";
+          for (size_t i = 0; i < ac.size(); ++i) {
+            char buf[48];
+            std::snprintf(buf, sizeof buf, "\"%d%s\": %.4f, ", ac[i].nsub,
+                          ac[i].tpb == 256 ? "" : (ac[i].tpb == 512 ? "t512" : "t1024"), best_f[i]);
+            c->tune_log += buf;
+            if (best_f[i] < best_f[bf]) bf = i;
+          }
+          char buf[48];
+          std::snprintf(buf, sizeof buf, "\"separate\": %.4f}", best_f[ac.size()]);
           c->tune_log += buf;
-          c->ref_fold = best_f[0] < best_f[1] ? 1 : 0;
+          c->ref_fold = best_f[bf] < best_f[ac.size()] ? 1 : 0;
+          c->ref_nsub = ac[bf].nsub;
+          c->ref_tpb = ac[bf].tpb;
         }
       }
     }
@@ -2876,6 +2895,9 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->rk4t_tuned = false;
     c->ana_nsub = 0;
     c->ana_tpb = 256;
+    c->ref_fold = 1;
+    c->ref_nsub = 0;
+    c->ref_tpb = 256;
   }
   if (chosen) *chosen = c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1;
   return MRB_OK;

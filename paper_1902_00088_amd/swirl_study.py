@@ -18,8 +18,10 @@ cos(pi t/t_a) over [0, t_a] vanishes).
 
 For each (beta, Jmax, eps) the run reports both errors, the compression rate (blocks of
 the adaptive grid relative to the uniform grid on Jmax: mean over the run and at the
-most refined instant) and the GPU wall time of the steps.  Every step runs in the
-library's kernels; this module only drives the entry points and measures.
+most refined instant) and the GPU wall time of the steps (the library's one-launch RK4
+step over overlapped tiles wherever the forest is on one level -- the equidistant runs --
+and stage launches elsewhere).  Every step runs in the library's kernels; this module
+only drives the entry points and measures.
 
 Usage: python -m paper_1902_00088_amd.swirl_study [--quick] > study.json
 """
@@ -65,6 +67,7 @@ def run(M, cfg, ref=None, chunk: int = 32):
     half = cfg.steps // 2
     s = M.Solver(cfg)
     s.set_graph(0)
+    s.set_sweep(3)   # one launch per RK4 step wherever the forest is on one level
     s.init_grid()
     counts = [s.num_blocks()]
     torch.cuda.synchronize()
@@ -97,6 +100,7 @@ def reference(M, beta: float, jref: int):
     cfg = swirl_config(jref, 0.0, beta)
     s = M.Solver(cfg)
     s.set_graph(0)
+    s.set_sweep(3)
     s.init_grid()
     _advance(s, cfg, 0, cfg.steps // 2, 64, [], log_every=4096)
     out = s.read_uniform(jref)

@@ -30,6 +30,18 @@ def test_counter_traffic_reads_the_line_of_the_tiling_while_the_source_matches(t
     assert bench.tkey({"stage_threads": 256}) == "" and bench.tkey({}) == ""
 
 
+def test_traffic_key_names_the_kernel_the_run_used():
+    stage = {"stage_tiles": 4, "stage_threads": 256}
+    assert bench.traffic_key("c2", stage, "stage") == "c2 nsub 4"
+    tile = {"rk4_tile": {"tiles": 2, "analysis_folded": [1, 1024], "refine_folded": [1, 1, 512]}}
+    assert bench.traffic_key("c2", tile, "rk4_tile") == "c2 rk4_tile nsub 1 t512 analysis refine"
+    tile["rk4_tile"]["refine_folded"] = [0, 1, 512]
+    assert bench.traffic_key("c2", tile, "rk4_tile") == "c2 rk4_tile nsub 1 t1024 analysis"
+    tile["rk4_tile"]["analysis_folded"] = [-1, 256]
+    assert bench.traffic_key("c2", tile, "rk4_tile") == "c2 rk4_tile nsub 2"
+    assert bench.traffic_key("c2", stage, "mr") is None and bench.counter_traffic(None) is None
+
+
 def test_counter_traffic_is_void_once_the_kernel_source_changes(tmp_path, monkeypatch):
     src = b"// kernel source\n"
     _fake_tree(tmp_path, src, hashlib.sha256(b"// older source\n").hexdigest(),

@@ -316,10 +316,12 @@ def test_error_paths_leave_state_unchanged():
 
 
 @pytest.mark.gpu
-def test_ns_mixing_layer_fp64_is_bitwise():
+@pytest.mark.parametrize("form", [W.FORM_FUSED, W.FORM_PLAIN])
+def test_ns_mixing_layer_fp64_is_bitwise(form):
     """C3 set-up (compressible NS mixing layer) at Jmax 4 with eps = 1e-4, so that the
-    grid has two levels (at eps = 1e-3 it is uniform on level 3): initial grid, 3 steps."""
-    cfg = W.C3(jmax=4, eps=1e-4, form=W.FORM_FUSED)
+    grid has two levels (at eps = 1e-3 it is uniform on level 3): initial grid, 3 steps,
+    in the fused form and in the plain form (ghosts stored, per-level launches)."""
+    cfg = W.C3(jmax=4, eps=1e-4, form=form)
     s, o = _pair(cfg)
     lv, _ = s.read_forest()
     assert len(np.unique(lv)) >= 2
@@ -537,6 +539,27 @@ def test_overlapped_tile_rk4_matches_oracle(case):
     assert st["kernels"]["mr"]["launches"] == (0 if case == "c1_uniform" else n)
     assert st["kernels"]["refine"]["launches"] == 0
     assert_same(s, o, f"{case}: {n} steps")
+    s.close()
+
+
+@pytest.mark.gpu
+def test_overlapped_tile_rk4_with_device_topology_matches_oracle():
+    """The tile step on a uniform grid planned on the device (eps = 0: every step's
+    analysis leaves the grid as it is) equals the oracle bit for bit."""
+    cfg = W.C2(jmax=4, eps=0.0, form=W.FORM_FUSED).replace(phys=(5.0,))
+    s, o = _pair(cfg)
+    s.set_graph(0)
+    s.set_topology(1)
+    s.set_sweep(3)
+    s.timing(True)
+    t = 0.0
+    for _ in range(4):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    st = s.stats()
+    assert st["topology"] == "device" and st["kernels"]["rk4_tile"]["launches"] == 4
+    assert_same(s, o, "device topology, tile step")
     s.close()
 
 
