@@ -61,6 +61,9 @@ def traffic_key(wl, form, kind):
         r = form.get("rk4_tile") or {}
         a = r.get("analysis_folded") or [0, 256]
         f = r.get("refine_folded") or [0, 0, 256]
+        mo = r.get("mothers_folded") or [0, 256]
+        if a[0] > 0 and f[0] and mo[0] > 0:
+            return f"{wl} rk4_tile nsub {mo[0]} t{mo[1]} analysis refine mothers"
         if a[0] > 0 and f[0] and f[1] > 0:
             return f"{wl} rk4_tile nsub {f[1]} t{f[2]} analysis refine"
         if a[0] > 0:
@@ -138,7 +141,7 @@ def run_form(M, W, torch, cfg, steps, warmup, tune=False):
         "stage_threads": st.get("stage_threads"),
         "sweep_launch": st.get("sweep_launch"),
         "rk4_tile": {"tiles": st.get("rk4_tile_tiles"), "analysis_folded": st.get("rk4_tile_analysis"),
-                     "refine_folded": st.get("rk4_tile_refine")},
+                     "refine_folded": st.get("rk4_tile_refine"), "mothers_folded": st.get("rk4_tile_mothers")},
         "tune_ms": st.get("tune_ms"),
         "graph_in_use": st.get("graph_in_use"),
         "memo_hits": st.get("memo_hits"),

@@ -231,7 +231,10 @@ mrb_status mrb_set_graph(mrb_ctx *ctx, int enable);
  * step is on one level below jmax, the safety-zone refinement as well (the tile is
  * built from the parents: the children's values at the children's level, the parent's
  * value or its prediction, never reach HBM), unless the autotuner found the
- * refinement launch faster.
+ * refinement launch faster; and where the adapt's coarsening is speculated and merges
+ * every block, its second analysis pass too (each workgroup computes the details of
+ * its share of the mother's nodes on a halo six points wider; the host takes the
+ * maximum over the shares), so such a step is one launch.
  * mode 2 (default): the autotuner (mrb_tune with reps > 0) times these forms on the
  * tuned tiling and keeps the fastest; four launches until then.  Results are
  * identical in every mode.  MRB_E_ARG for other values; modes 1 and 3 on the plain

@@ -148,6 +148,10 @@ struct Rk4tArgs {
   int* done;
   double thr;
   const int* smap;
+  // with the speculated coarsening's second analysis folded in as well (every block
+  // merges): per block and sub-tile, the maximum |detail| of the mother's nodes the
+  // sub-tile holds (mapped host memory, plain stores)
+  double* mq;
 };
 
 struct MrArgs {
@@ -208,9 +212,10 @@ hipError_t launch_plain(const Shape& s, int grid, const StageArgs& a, hipStream_
 // overlapped-tile RK4 step; hipErrorInvalidValue if the shape has no such kernel
 // (threads per workgroup: 256; with the analysis on whole blocks also 512 or 1024;
 // refine: the refinement of the parents (every one, a forest on one level) folded in,
-// with the analysis only)
-hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, bool refine, int tpb, int grid,
-                       const Rk4tArgs& a, hipStream_t st);
+// with the analysis only; mothers: the second analysis of a speculated coarsening that
+// merges every block, with refine only)
+hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, bool refine, bool mothers, int tpb,
+                       int grid, const Rk4tArgs& a, hipStream_t st);
 int rk4t_variants(const Shape& s, int precision, int* nsub, int cap);
 hipError_t launch_mr(const Shape& s, int nsub, int grid, const MrArgs& a, hipStream_t st);
 hipError_t launch_refine(const Shape& s, int nsub, int grid, const RefineArgs& a, hipStream_t st);

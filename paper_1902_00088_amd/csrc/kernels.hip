@@ -941,9 +941,11 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs S) {
 // on one level (no finer neighbour, so no redundant node to write back).  A missing
 // neighbour (a forest not on one level) yields NaN.
 // ---------------------------------------------------------------------------
-template <int BS, int NSUB, bool ANA>
+template <int BS, int NSUB, bool ANA, bool MA = false>
 struct TileGeo {
-  static constexpr int HW = 2, E = 4 * HW + (ANA ? 3 : 0);
+  // halo: four stages of HW, plus the reach of the details' prediction on the
+  // children (3) or on the mothers (6 child nodes)
+  static constexpr int HW = 2, E = 4 * HW + (MA ? 6 : (ANA ? 3 : 0));
   static constexpr int S = (BS + NSUB - 1) / NSUB, TW = S + 2 * E, TSZ = TW * TW;
 };
 
@@ -999,9 +1001,35 @@ struct ChildFromParents {
   }
 };
 
-template <int BS, int NSUB, typename TT, typename KT, bool ANA, int TPB, bool REF = false>
+// details of the mothers' nodes that lie in the region (a mother node M is the
+// child's even node t = 2M - bit (BS-1)): mother-level stencils reach M +- 1, +- 3,
+// i.e. child nodes t +- 2, +- 6 (stride 4 in the tile)
+template <int BS, int S, int E>
+struct MotherDetails {
+  using G = Geo<2, BS, S, E>;
+  const double* U;
+  int m0[2], mn[2], off[2], r0[2];
+  double* m;
+  template <int NX, int NY, int NZ>
+  __device__ __forceinline__ void go(int cls) {
+    ParityClass<2> pc(cls, m0, mn);
+    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
+      int M[3];
+      pc.coords(p, M);
+      const int i0 = 2 * M[0] - off[0] - r0[0] + E, i1 = 2 * M[1] - off[1] - r0[1] + E;
+      const int bb[3] = {NX == 4 ? i0 - 6 : i0, NY == 4 ? i1 - 6 : i1, 0};
+      const int stride[3] = {4, 4, 4};
+      auto at = [&](int x, int y, int) { return U[G::idx(x, y, 0)]; };
+      const double pred = tensor_fixed<NX, NY, NZ, double>(at, bb, stride);
+      m[0] = nanmax(m[0], fabs(U[G::idx(i0, i1, 0)] - pred));
+    }
+  }
+};
+
+template <int BS, int NSUB, typename TT, typename KT, bool ANA, int TPB, bool REF = false, bool MA = false>
 __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
-  using TG = TileGeo<BS, NSUB, ANA>;
+  static_assert(!MA || (ANA && REF), "the mothers' analysis comes with the folded refinement");
+  using TG = TileGeo<BS, NSUB, ANA, MA>;
   constexpr int HW = TG::HW, E = TG::E, S = TG::S, TW = TG::TW, TSZ = TG::TSZ, NP = BS * BS;
   constexpr int NSUBT = NSUB * NSUB;
   using G = Geo<2, BS, S, E>;
@@ -1157,6 +1185,36 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
         if (last) {
           A.maxd[b] = vb;
           A.flags[b] = d.level > 1 && vb < A.thr ? (int8_t)-1 : (int8_t)0;
+        }
+      }
+      if constexpr (MA) {
+        // second analysis of the speculated coarsening: this region's share of its
+        // mother's nodes; the host takes the maximum over the shares
+        const int sq = A.smap ? A.smap[b] : -1;
+        double mm[1] = {sq >= 0 ? 0.0 : __builtin_nan("")};
+        if (sq >= 0) {
+          MotherDetails<BS, S, E> md;
+          md.U = U;
+          md.m = mm;
+          for (int a = 0; a < 2; ++a) {
+            md.off[a] = ((sq >> a) & 1) * (BS - 1);
+            md.r0[a] = r0[a];
+            // mother nodes whose child node lies in [r0, r0 + cnt)
+            const int lo = (r0[a] + md.off[a] + 1) >> 1, hi = (r0[a] + cnt[a] - 1 + md.off[a]) >> 1;
+            md.m0[a] = lo;
+            md.mn[a] = hi - lo + 1;
+          }
+          for_odd_classes<2>(md);
+        }
+        double v2 = mm[0];
+        for (int off = 32; off > 0; off >>= 1) v2 = nanmax(v2, __shfl_xor(v2, off, 64));
+        __syncthreads();
+        if ((tid & 63) == 0) red[tid >> 6] = v2;
+        __syncthreads();
+        if (tid == 0) {
+          double vm = red[0];
+          for (int q = 1; q < TPB / 64; ++q) vm = nanmax(vm, red[q]);
+          A.mq[(size_t)b * NSUBT + it.w % NSUBT] = vm;
         }
       }
       // speculated coarsening: the mother's nodes this block supplies (every node of a
@@ -1903,8 +1961,18 @@ hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, cons
 // with the analysis folded in, whole blocks may take 512 or 1024 threads (a forest
 // small enough for this form leaves most compute units idle otherwise)
 template <int B, int NS, typename TT, typename KT>
-static hipError_t rk4t_go(bool ana, bool ref, int tpb, int grid, const Rk4tArgs& a, hipStream_t st) {
+static hipError_t rk4t_go(bool ana, bool ref, bool ma, int tpb, int grid, const Rk4tArgs& a, hipStream_t st) {
   const size_t per = sizeof(double) + 3 * sizeof(KT) + sizeof(TT);
+  if (ma) {
+    if (!ana || !ref) return hipErrorInvalidValue;
+    const size_t lds = (size_t)TileGeo<B, NS, true, true>::TSZ * per;
+    if (tpb == 256) return go(k_rk4t<B, NS, TT, KT, true, 256, true, true>, grid, lds, st, a, 256);
+    if constexpr (NS == 1) {
+      if (tpb == 512) return go(k_rk4t<B, NS, TT, KT, true, 512, true, true>, grid, lds, st, a, 512);
+      if (tpb == 1024) return go(k_rk4t<B, NS, TT, KT, true, 1024, true, true>, grid, lds, st, a, 1024);
+    }
+    return hipErrorInvalidValue;
+  }
   if (ana) {
     const size_t lds = (size_t)TileGeo<B, NS, true>::TSZ * per;
     if (ref) {
@@ -1927,13 +1995,13 @@ static hipError_t rk4t_go(bool ana, bool ref, int tpb, int grid, const Rk4tArgs&
   return go(k_rk4t<B, NS, TT, KT, false, 256>, grid, (size_t)TileGeo<B, NS, false>::TSZ * per, st, a);
 }
 
-hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, bool refine, int tpb, int grid,
-                       const Rk4tArgs& a, hipStream_t st) {
+hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, bool refine, bool mothers, int tpb,
+                       int grid, const Rk4tArgs& a, hipStream_t st) {
   if (s.dim != 2 || s.hw != 2 || s.nf != 1) return hipErrorInvalidValue;
-#define X(B, P, NS)                                                                                     \
-  if (s.bs == B && precision == P && nsub == NS) {                                                     \
-    if constexpr (P == 0) return rk4t_go<B, NS, double, double>(analysis, refine, tpb, grid, a, st);   \
-    else return rk4t_go<B, NS, float, float>(analysis, refine, tpb, grid, a, st);                      \
+#define X(B, P, NS)                                                                                              \
+  if (s.bs == B && precision == P && nsub == NS) {                                                              \
+    if constexpr (P == 0) return rk4t_go<B, NS, double, double>(analysis, refine, mothers, tpb, grid, a, st);   \
+    else return rk4t_go<B, NS, float, float>(analysis, refine, mothers, tpb, grid, a, st);                      \
   }
   MRB_RK4T_VARIANTS(X)
 #undef X

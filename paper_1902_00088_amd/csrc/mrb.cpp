@@ -264,8 +264,12 @@ struct mrb_ctx {
                                // the refinement launch before it faster)
   int ref_nsub = 0;            // its tiling and threads per workgroup (0: those of the folded analysis)
   int ref_tpb = 256;
+  int ma_nsub = 0;             // with the speculated coarsening's second analysis folded in as well:
+  int ma_tpb = 256;            // tiling and threads (0: those of the folded refinement)
   int sweep_grid = 0;          // workgroups of the last whole-sweep launch
   double *h_maxd2 = nullptr, *dmaxd2 = nullptr;
+  double *h_mq = nullptr, *dmq = nullptr;   // mothers' detail maxima per child sub-tile (folded second analysis)
+  int mq_parts = 0;                         // sub-tiles per block of the last folded second analysis
   int flag_set = 0;                    // set the next analysis writes
   std::vector<int8_t> spec_flags;      // first-pass flags of the last adapt
   long spec_hits = 0, spec_misses = 0;
@@ -982,12 +986,22 @@ Rk4tArgs rk4t_args(mrb_ctx* c, double t, double dt) {
 
 // launch the overlapped-tile RK4 step (tn sub-tiles per axis), with the analysis of
 // u_new folded in or not
-mrb_status launch_tiled(mrb_ctx* c, int tn, const Rk4tArgs& ra, bool analysis, int tpb = 256, bool refine = false) {
+mrb_status launch_tiled(mrb_ctx* c, int tn, const Rk4tArgs& ra, bool analysis, int tpb = 256, bool refine = false,
+                        bool mothers = false) {
   const long work = (long)nblk(c) * tn * tn;
-  // algorithmic bytes: u read once (with the refinement folded in: the parents', a
-  // quarter of the blocks), u_new written once
-  TimeScope rs(c, T_RK4T, (double)nblk(c) * c->bsz * (refine ? 10.0 : 16.0));
-  HIPCHK(c, launch_rk4t(c->shape, c->cfg.precision, tn, analysis, refine, tpb, grid_for(c, work), ra, c->stream));
+  // algorithmic bytes of the work the launch performs, counted as for the stage,
+  // analysis and refinement launches it replaces (an RK4 step: the four stages' bytes
+  // per node; the analysis: 8 per node; the refinement: 8 (1 + 2^d) per parent node).
+  // The launch itself reads u (or the parents' u) once and writes u_new once.
+  double per_node = 0.0;
+  for (int s = 1; s <= 4; ++s) per_node += stage_bytes(c, s);
+  if (analysis) per_node += 8.0;
+  const double n = (double)nblk(c), nch = (double)(1 << c->cfg.dim);
+  double bytes = n * c->bsz * per_node + (refine ? n / nch * c->bsz * 8.0 * (1.0 + nch) : 0.0);
+  if (mothers) bytes += n / nch * c->bsz * 8.0;   // the second analysis, on the mothers
+  TimeScope rs(c, T_RK4T, bytes);
+  HIPCHK(c, launch_rk4t(c->shape, c->cfg.precision, tn, analysis, refine, mothers, tpb, grid_for(c, work), ra,
+                        c->stream));
   return MRB_OK;
 }
 
@@ -1072,8 +1086,16 @@ mrb_status do_rk4(mrb_ctx* c, double t, double dt) {
   return MRB_OK;
 }
 
-mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false, bool first_fused = false);
+mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false, bool first_fused = false,
+                    bool second_folded = false);
 mrb_ctx::Memo* spec_entry(mrb_ctx* c);
+
+// the speculated coarsening of the current grid merges every block (and writes its
+// mothers in the first analysis pass)
+bool spec_all_merge(mrb_ctx* c) {
+  mrb_ctx::Memo* e = spec_entry(c);
+  return e && e->smap && c->dmq && (long)e->nfam * (1 << c->cfg.dim) == (long)nblk(c);
+}
 
 // The RK4 step and the first analysis pass of its adapt as one overlapped-tile launch,
 // where the forest is on one level and that form is selected (else *done = false and
@@ -1084,7 +1106,10 @@ mrb_status rk4_adapt_tiled(mrb_ctx* c, double t, double dt, bool* done, bool ref
   if (tn == 0 || filter_on(c) || c->ana_nsub < 0) return MRB_OK;
   if (refine && (long)c->pending_ref * (1 << c->cfg.dim) != (long)nblk(c))
     return fail(c, MRB_E_STATE, "folded refinement: not every block was refined");
-  if (refine && c->ref_nsub > 0) {
+  if (refine && c->ma_nsub > 0 && spec_all_merge(c)) {
+    tn = c->ma_nsub;
+    tpb = c->ma_tpb;
+  } else if (refine && c->ref_nsub > 0) {
     tn = c->ref_nsub;
     tpb = c->ref_tpb;
   } else if (c->ana_nsub > 0) {
@@ -1093,16 +1118,21 @@ mrb_status rk4_adapt_tiled(mrb_ctx* c, double t, double dt, bool* done, bool ref
   }
   mrb_ctx::Memo* e = spec_entry(c);
   const bool fused = e && e->smap;
+  // the speculated coarsening merges every block (the mothers are on one level again):
+  // its second analysis can be folded in too
+  const bool mothers = refine && spec_all_merge(c);
   Rk4tArgs ra = rk4t_args(c, t, dt);
   c->flag_set = 0;
   rk4t_analysis_args(c, ra, fused ? e->smap : nullptr);
-  mrb_status r = launch_tiled(c, tn, ra, true, tpb, refine);
+  ra.mq = mothers ? c->dmq : nullptr;
+  c->mq_parts = tn * tn;
+  mrb_status r = launch_tiled(c, tn, ra, true, tpb, refine, mothers);
   if (r) return r;
   std::swap(c->u, c->unew);
   c->n_rk4++;
   c->n_block_updates += (long)nblk(c);
   *done = true;
-  return do_adapt(c, nullptr, true, fused);
+  return do_adapt(c, nullptr, true, fused, mothers);
 }
 
 // the step's refinement can be folded into the tile launch: the forest is on one level
@@ -1267,12 +1297,11 @@ mrb_status check_barrier(mrb_ctx* c) {
   return fail(c, MRB_E_DEVICE, "sweep: a grid barrier wait timed out; the block data is void (load new data)");
 }
 
+mrb_status wait_stream(mrb_ctx* c);
+
 mrb_status mr_readback(mrb_ctx* c) {
   const int n = (int)nblk(c);
-  {
-    HostTimer ht(&c->hus_wait);
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-  }
+  if (mrb_status r = wait_stream(c)) return r;
   if (mrb_status r = check_barrier(c)) return r;
   c->last_flags.assign(c->h_flags, c->h_flags + n);
   c->last_maxd.assign(c->h_maxd, c->h_maxd + (size_t)n * c->cfg.nfields);
@@ -1484,6 +1513,13 @@ mrb_status do_coarsen(mrb_ctx* c, const int8_t* flags, int* ncoarse) {
   return MRB_OK;
 }
 
+// wait for the stream's work so far (the adapt's read-back)
+mrb_status wait_stream(mrb_ctx* c) {
+  HostTimer ht(&c->hus_wait);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MRB_OK;
+}
+
 // flags and maxima of the analysis just finished (mapped set `set`, n blocks)
 mrb_status take_flags(mrb_ctx* c, int set, size_t n) {
   if (mrb_status r = check_barrier(c)) return r;
@@ -1520,7 +1556,7 @@ mrb_ctx::Memo* spec_entry(mrb_ctx* c) {
 // first_launched: the first pass is already queued (graph replay, or folded into the
 // overlapped-tile RK4 step); first_fused: that pass was given the speculated
 // coarsening's map and wrote its mothers
-mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fused) {
+mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fused, bool second_folded) {
   mrb_status s;
   int passes = 1;
   c->flag_set = 0;
@@ -1530,10 +1566,7 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fuse
   const bool fused = e && e->smap && (first_launched ? first_fused : true);
   if (!first_launched && (s = launch_mr_kernel(c, false, fused ? e : nullptr))) return s;
   if (!e) {
-    {
-      HostTimer ht(&c->hus_wait);
-      HIPCHK(c, hipStreamSynchronize(c->stream));
-    }
+    if ((s = wait_stream(c))) return s;
     if ((s = take_flags(c, 0, n1))) return s;
     c->spec_flags = c->last_flags;
   } else {
@@ -1550,17 +1583,30 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fuse
     const bool ref_zero0 = c->hcount_ref_zero;
     const int nfam = e->nfam;
     if ((s = coarsen_from_memo(c, *e, fused))) return s;
-    c->flag_set = 1;
-    s = launch_mr_kernel(c, false);
-    c->flag_set = 0;
-    if (s) return s;
-    {
-      HostTimer ht(&c->hus_wait);
-      HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!second_folded) {
+      c->flag_set = 1;
+      s = launch_mr_kernel(c, false);
+      c->flag_set = 0;
+      if (s) return s;
     }
+    if ((s = wait_stream(c))) return s;
     if (std::equal(c->h_flags, c->h_flags + n1, c->spec_flags.begin())) {
       ++c->spec_hits;
       if ((s = take_flags(c, 0, n1))) return s;
+      if (second_folded) {
+        // the mothers' detail maxima: the maximum over their children's sub-tile shares
+        // (NaN-propagating, as the analysis kernel's reduction), then the flag rule
+        const int nch = 1 << c->cfg.dim, parts = nch * c->mq_parts;
+        for (size_t m = 0; m < c->leaves.size(); ++m) {
+          double v = c->h_mq[m * parts];
+          for (int q = 1; q < parts; ++q) {
+            const double w = c->h_mq[m * parts + q];
+            v = v != v ? v : (w != w ? w : (v > w ? v : w));
+          }
+          c->h_maxd2[m] = v;
+          c->h_flags2[m] = c->leaves[m].level > 1 && v < c->thr[0] ? (int8_t)-1 : (int8_t)0;
+        }
+      }
       if ((s = take_flags(c, 1, c->leaves.size()))) return s;
       passes = 2;
     } else {
@@ -2179,7 +2225,10 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
          hipHostGetDevicePointer((void**)&c->dflags2, c->h_flags2, 0) == hipSuccess &&
          hipHostGetDevicePointer((void**)&c->dmaxd2, c->h_maxd2, 0) == hipSuccess &&
          hipHostMalloc((void**)&c->h_err, sizeof(int), fl) == hipSuccess &&
-         hipHostGetDevicePointer((void**)&c->d_err, c->h_err, 0) == hipSuccess;
+         hipHostGetDevicePointer((void**)&c->d_err, c->h_err, 0) == hipSuccess &&
+         (cfg->dim != 2 || cfg->nfields != 1 ||
+          (hipHostMalloc((void**)&c->h_mq, mb * 16 * sizeof(double), fl) == hipSuccess &&
+           hipHostGetDevicePointer((void**)&c->dmq, c->h_mq, 0) == hipSuccess));
     if (!ok) c->err = "hipHostMalloc (mapped) failed";
     if (ok) *c->h_err = 0;
     ok = ok && dev((void**)&c->dbar, kBarWords * sizeof(unsigned)) &&
@@ -2229,6 +2278,7 @@ mrb_status mrb_destroy(mrb_ctx* c) {
   if (c->h_flags2) (void)hipHostFree(c->h_flags2);
   if (c->h_maxd2) (void)hipHostFree(c->h_maxd2);
   if (c->h_err) (void)hipHostFree(c->h_err);
+  if (c->h_mq) (void)hipHostFree(c->h_mq);
   delete c;
   return MRB_OK;
 }
@@ -2544,7 +2594,7 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"rk4_tile_tiles\": %d, \"rk4_tile_tuned\": %d, \"rk4_tile_analysis\": [%d, %d], \"rk4_tile_refine\": [%d, %d, %d], \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"rk4_tile_tiles\": %d, \"rk4_tile_tuned\": %d, \"rk4_tile_analysis\": [%d, %d], \"rk4_tile_refine\": [%d, %d, %d], \"rk4_tile_mothers\": [%d, %d], \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
                 "\"plan_entries\": %.1f, \"plan_entries_per_block\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
@@ -2554,7 +2604,7 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
                 c->order ? "level-sorted" : "forest",
                 c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses,
                 c->have_forest && rk4t_pick(c) > 0 ? "rk4_tile" : (sweep_in_one(c) ? "one" : "four"), c->rk4t_nsub,
-                c->rk4t_tuned ? 1 : 0, c->ana_nsub, c->ana_tpb, c->ref_fold, c->ref_nsub, c->ref_tpb, c->sweep_grid, c->dev.active ? "device" : "host",
+                c->rk4t_tuned ? 1 : 0, c->ana_nsub, c->ana_tpb, c->ref_fold, c->ref_nsub, c->ref_tpb, c->ma_nsub, c->ma_tpb, c->sweep_grid, c->dev.active ? "device" : "host",
                 c->dev.mode, c->dev.steps, c->dev.passes, c->dev.pushes, c->dev.pulls, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,
                 c->hus_launch, c->hus_index, c->hus_desc, c->hus_desc_par, c->hus_fixed, c->tune_log.c_str(), kern.c_str());
   if (w < 0 || w >= cap) return fail(c, MRB_E_ARG, "stats: buffer too small");
@@ -2584,6 +2634,8 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->ref_fold = 1;
     c->ref_nsub = 0;
     c->ref_tpb = 256;
+    c->ma_nsub = 0;
+    c->ma_tpb = 256;
   } else if (reps > 0) {
     if (!check_state(c, true)) return MRB_E_STATE;
     if (!(dt > 0.0)) return fail(c, MRB_E_ARG, "tune: dt must be positive");
@@ -2821,6 +2873,52 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
           c->ref_fold = best_f[bf] < best_f[ac.size()] ? 1 : 0;
           c->ref_nsub = ac[bf].nsub;
           c->ref_tpb = ac[bf].tpb;
+          // with the second analysis of a coarsening that merges every block folded in
+          // too: timed with a map that sends each block's mother nodes into its own
+          // slot of u_new (scratch during tuning) and its child index from forest order
+          c->ma_nsub = 0;
+          c->ma_tpb = 256;
+          if (c->dmq) {
+            const int n = (int)nblk(c), nch = 1 << c->cfg.dim;
+            std::vector<int> hm(n);
+            for (int b = 0; b < n; ++b) hm[b] = c->hblk[b].slot * 8 + b % nch;
+            int* dm = nullptr;
+            if (hipMalloc((void**)&dm, n * sizeof(int)) != hipSuccess) return done(fail(c, MRB_E_DEVICE, "tune: map"));
+            if (hipMemcpy(dm, hm.data(), n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+              (void)hipFree(dm);
+              return done(fail(c, MRB_E_DEVICE, "tune: map"));
+            }
+            std::vector<float> best_m(ac.size(), 1e30f);
+            Rk4tArgs rm = ra;
+            rm.smap = dm;
+            rm.mq = c->dmq;
+            for (int round = 0; round < kRounds && !r; ++round)
+              for (size_t m = 0; m < ac.size() && !r; ++m) {
+                for (int k = 0; k < reps + 1 && !r; ++k) {
+                  if (k == 1 && hipEventRecord(e0, c->stream) != hipSuccess) r = MRB_E_DEVICE;
+                  if (!r) r = launch_tiled(c, ac[m].nsub, rm, true, ac[m].tpb, true, true);
+                }
+                float ms = 0.f;
+                if (!r && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                  r = fail(c, MRB_E_DEVICE, "tune: event");
+                if (!r) best_m[m] = std::min(best_m[m], ms / reps);
+              }
+            (void)hipFree(dm);
+            if (r) return done(r);
+            size_t bm = 0;
+            c->tune_log += ", \"rk4_tile_mothers\": {";
+            for (size_t i = 0; i < ac.size(); ++i) {
+              char buf[48];
+              std::snprintf(buf, sizeof buf, "%s\"%d%s\": %.4f", i ? ", " : "", ac[i].nsub,
+                            ac[i].tpb == 256 ? "" : (ac[i].tpb == 512 ? "t512" : "t1024"), best_m[i]);
+              c->tune_log += buf;
+              if (best_m[i] < best_m[bm]) bm = i;
+            }
+            c->tune_log += "}";
+            c->ma_nsub = ac[bm].nsub;
+            c->ma_tpb = ac[bm].tpb;
+          }
         }
       }
     }
@@ -2898,6 +2996,8 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->ref_fold = 1;
     c->ref_nsub = 0;
     c->ref_tpb = 256;
+    c->ma_nsub = 0;
+    c->ma_tpb = 256;
   }
   if (chosen) *chosen = c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1;
   return MRB_OK;

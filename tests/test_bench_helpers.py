@@ -33,7 +33,10 @@ def test_counter_traffic_reads_the_line_of_the_tiling_while_the_source_matches(t
 def test_traffic_key_names_the_kernel_the_run_used():
     stage = {"stage_tiles": 4, "stage_threads": 256}
     assert bench.traffic_key("c2", stage, "stage") == "c2 nsub 4"
-    tile = {"rk4_tile": {"tiles": 2, "analysis_folded": [1, 1024], "refine_folded": [1, 1, 512]}}
+    tile = {"rk4_tile": {"tiles": 2, "analysis_folded": [1, 1024], "refine_folded": [1, 1, 512],
+                         "mothers_folded": [1, 256]}}
+    assert bench.traffic_key("c2", tile, "rk4_tile") == "c2 rk4_tile nsub 1 t256 analysis refine mothers"
+    tile["rk4_tile"]["mothers_folded"] = [0, 256]
     assert bench.traffic_key("c2", tile, "rk4_tile") == "c2 rk4_tile nsub 1 t512 analysis refine"
     tile["rk4_tile"]["refine_folded"] = [0, 1, 512]
     assert bench.traffic_key("c2", tile, "rk4_tile") == "c2 rk4_tile nsub 1 t1024 analysis"
