@@ -234,7 +234,11 @@ mrb_status mrb_set_graph(mrb_ctx *ctx, int enable);
  * refinement launch faster; and where the adapt's coarsening is speculated and merges
  * every block, its second analysis pass too (each workgroup computes the details of
  * its share of the mother's nodes on a halo six points wider; the host takes the
- * maximum over the shares), so such a step is one launch.
+ * maximum over the shares), so such a step is one launch.  Where such steps repeat
+ * (the forest returns to the same blocks and slots after each), mrb_step with
+ * nsteps > 1 queues each step's launch before reading the previous step's flags; a
+ * step whose flags miss the speculation takes the queued one back (results are the
+ * same either way; mrb_stats counts queued and taken-back steps).
  * mode 2 (default): the autotuner (mrb_tune with reps > 0) times these forms on the
  * tuned tiling and keeps the fastest; four launches until then.  Results are
  * identical in every mode.  MRB_E_ARG for other values; modes 1 and 3 on the plain

@@ -269,6 +269,13 @@ struct mrb_ctx {
   int sweep_grid = 0;          // workgroups of the last whole-sweep launch
   double *h_maxd2 = nullptr, *dmaxd2 = nullptr;
   double *h_mq = nullptr, *dmq = nullptr;   // mothers' detail maxima per child sub-tile (folded second analysis)
+  // second bank of the first pass's flags and maxima and of the mothers' shares (queued
+  // steps alternate between the banks), and the events the queued steps are waited on
+  int8_t *h_flags_b = nullptr, *dflags_b = nullptr;
+  double *h_maxd_b = nullptr, *dmaxd_b = nullptr;
+  double *h_mq_b = nullptr, *dmq_b = nullptr;
+  hipEvent_t ev_issue[2] = {nullptr, nullptr};
+  long n_queued = 0, n_taken_back = 0;      // steps launched ahead of the previous read-back; taken back
   int mq_parts = 0;                         // sub-tiles per block of the last folded second analysis
   int flag_set = 0;                    // set the next analysis writes
   std::vector<int8_t> spec_flags;      // first-pass flags of the last adapt
@@ -1556,78 +1563,86 @@ mrb_ctx::Memo* spec_entry(mrb_ctx* c) {
 // first_launched: the first pass is already queued (graph replay, or folded into the
 // overlapped-tile RK4 step); first_fused: that pass was given the speculated
 // coarsening's map and wrote its mothers
-mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fused, bool second_folded) {
+// The uncoarsened grid's host state, kept while a speculated coarsening is applied
+// (put back if the speculation misses).
+struct SpecSnap {
+  std::vector<Leaf> leaves;
+  std::vector<BlockDesc> hblk;
+  std::vector<NbEntry> hnb;
+  std::vector<int> hlist, level_off, popped;
+  size_t npushed = 0, n1 = 0;
+  char* arena = nullptr;
+  TopoHeader hdr;
+  size_t arena_bytes = 0;
+  bool ref_zero = false;
+  int nfam = 0;
+};
+
+// snapshot the grid, then apply the memoised coarsening e (its mothers already written
+// when `written`)
+mrb_status spec_begin(mrb_ctx* c, mrb_ctx::Memo* e, bool written, SpecSnap& sn) {
+  sn.leaves = c->leaves;
+  sn.hblk = c->hblk;
+  sn.hnb = c->hnb;
+  sn.hlist = c->hlist;
+  sn.level_off = c->level_off;
+  sn.popped.assign(c->free_slots.end() - (long)e->pop, c->free_slots.end());
+  sn.npushed = e->pushed.size();
+  sn.n1 = c->leaves.size();
+  sn.arena = c->arena;
+  sn.hdr = c->arena_hdr;
+  sn.arena_bytes = c->arena_bytes;
+  sn.ref_zero = c->hcount_ref_zero;
+  sn.nfam = e->nfam;
+  return coarsen_from_memo(c, *e, written);
+}
+
+// the mothers' detail maxima of a folded second analysis: the maximum over their
+// children's sub-tile shares (NaN-propagating, as the analysis kernel's reduction), then
+// the flag rule, into flag set 1
+void mother_flags(mrb_ctx* c) {
+  const int nch = 1 << c->cfg.dim, parts = nch * c->mq_parts;
+  for (size_t m = 0; m < c->leaves.size(); ++m) {
+    double v = c->h_mq[m * parts];
+    for (int q = 1; q < parts; ++q) {
+      const double w = c->h_mq[m * parts + q];
+      v = v != v ? v : (w != w ? w : (v > w ? v : w));
+    }
+    c->h_maxd2[m] = v;
+    c->h_flags2[m] = c->leaves[m].level > 1 && v < c->thr[0] ? (int8_t)-1 : (int8_t)0;
+  }
+}
+
+// After the wait: keep the speculated coarsening if the first pass's flags are the ones it
+// was made from, else put the uncoarsened grid back; then coarsen until nothing merges.
+mrb_status spec_finish(mrb_ctx* c, SpecSnap& sn, bool second_folded, int* npass) {
   mrb_status s;
   int passes = 1;
-  c->flag_set = 0;
-  const size_t n1 = c->leaves.size();
-  mrb_ctx::Memo* e = spec_entry(c);
-  // a first pass launched here also writes the speculated mothers
-  const bool fused = e && e->smap && (first_launched ? first_fused : true);
-  if (!first_launched && (s = launch_mr_kernel(c, false, fused ? e : nullptr))) return s;
-  if (!e) {
-    if ((s = wait_stream(c))) return s;
+  const size_t n1 = sn.n1;
+  if (std::equal(c->h_flags, c->h_flags + n1, c->spec_flags.begin())) {
+    ++c->spec_hits;
+    if ((s = take_flags(c, 0, n1))) return s;
+    if (second_folded) mother_flags(c);
+    if ((s = take_flags(c, 1, c->leaves.size()))) return s;
+    passes = 2;
+  } else {
+    ++c->spec_misses;
+    c->leaves.swap(sn.leaves);
+    c->index.clear();
+    for (size_t i = 0; i < c->leaves.size(); ++i) c->index.set(pack_key(c->leaves[i].level, c->leaves[i].c), (int)i);
+    c->hblk.swap(sn.hblk);
+    c->hnb.swap(sn.hnb);
+    c->hlist.swap(sn.hlist);
+    c->level_off.swap(sn.level_off);
+    c->free_slots.resize(c->free_slots.size() - sn.npushed);
+    c->free_slots.insert(c->free_slots.end(), sn.popped.begin(), sn.popped.end());
+    c->arena = sn.arena;
+    c->arena_hdr = sn.hdr;
+    c->arena_bytes = sn.arena_bytes;
+    c->hcount_ref_zero = sn.ref_zero;
+    c->n_fam -= sn.nfam;
     if ((s = take_flags(c, 0, n1))) return s;
     c->spec_flags = c->last_flags;
-  } else {
-    // state of the uncoarsened grid, to put back if the speculation fails
-    std::vector<Leaf> leaves0 = c->leaves;
-    std::vector<BlockDesc> hblk0 = c->hblk;
-    std::vector<NbEntry> hnb0 = c->hnb;
-    std::vector<int> hlist0 = c->hlist, level0 = c->level_off;
-    std::vector<int> popped(c->free_slots.end() - (long)e->pop, c->free_slots.end());
-    const size_t npushed = e->pushed.size();
-    char* arena0 = c->arena;
-    const TopoHeader hdr0 = c->arena_hdr;
-    const size_t arena_bytes0 = c->arena_bytes;
-    const bool ref_zero0 = c->hcount_ref_zero;
-    const int nfam = e->nfam;
-    if ((s = coarsen_from_memo(c, *e, fused))) return s;
-    if (!second_folded) {
-      c->flag_set = 1;
-      s = launch_mr_kernel(c, false);
-      c->flag_set = 0;
-      if (s) return s;
-    }
-    if ((s = wait_stream(c))) return s;
-    if (std::equal(c->h_flags, c->h_flags + n1, c->spec_flags.begin())) {
-      ++c->spec_hits;
-      if ((s = take_flags(c, 0, n1))) return s;
-      if (second_folded) {
-        // the mothers' detail maxima: the maximum over their children's sub-tile shares
-        // (NaN-propagating, as the analysis kernel's reduction), then the flag rule
-        const int nch = 1 << c->cfg.dim, parts = nch * c->mq_parts;
-        for (size_t m = 0; m < c->leaves.size(); ++m) {
-          double v = c->h_mq[m * parts];
-          for (int q = 1; q < parts; ++q) {
-            const double w = c->h_mq[m * parts + q];
-            v = v != v ? v : (w != w ? w : (v > w ? v : w));
-          }
-          c->h_maxd2[m] = v;
-          c->h_flags2[m] = c->leaves[m].level > 1 && v < c->thr[0] ? (int8_t)-1 : (int8_t)0;
-        }
-      }
-      if ((s = take_flags(c, 1, c->leaves.size()))) return s;
-      passes = 2;
-    } else {
-      ++c->spec_misses;
-      c->leaves.swap(leaves0);
-      c->index.clear();
-      for (size_t i = 0; i < c->leaves.size(); ++i) c->index.set(pack_key(c->leaves[i].level, c->leaves[i].c), (int)i);
-      c->hblk.swap(hblk0);
-      c->hnb.swap(hnb0);
-      c->hlist.swap(hlist0);
-      c->level_off.swap(level0);
-      c->free_slots.resize(c->free_slots.size() - npushed);
-      c->free_slots.insert(c->free_slots.end(), popped.begin(), popped.end());
-      c->arena = arena0;
-      c->arena_hdr = hdr0;
-      c->arena_bytes = arena_bytes0;
-      c->hcount_ref_zero = ref_zero0;
-      c->n_fam -= nfam;
-      if ((s = take_flags(c, 0, n1))) return s;
-      c->spec_flags = c->last_flags;
-    }
   }
   for (;;) {
     int nc = 0;
@@ -1640,6 +1655,214 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fuse
   }
   if (npass) *npass = passes;
   return MRB_OK;
+}
+
+mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fused, bool second_folded) {
+  mrb_status s;
+  c->flag_set = 0;
+  const size_t n1 = c->leaves.size();
+  mrb_ctx::Memo* e = spec_entry(c);
+  // a first pass launched here also writes the speculated mothers
+  const bool fused = e && e->smap && (first_launched ? first_fused : true);
+  if (!first_launched && (s = launch_mr_kernel(c, false, fused ? e : nullptr))) return s;
+  if (!e) {
+    if ((s = wait_stream(c))) return s;
+    if ((s = take_flags(c, 0, n1))) return s;
+    c->spec_flags = c->last_flags;
+    for (int passes = 1;; ++passes) {
+      int nc = 0;
+      std::vector<int8_t> fl = c->last_flags;
+      if ((s = do_coarsen(c, fl.data(), &nc))) return s;
+      if (nc == 0) {
+        if (npass) *npass = passes;
+        return MRB_OK;
+      }
+      if (passes > c->cfg.jmax + 2) return fail(c, MRB_E_STATE, "adapt did not reach a fixed point");
+      if ((s = do_mr_pass(c))) return s;
+    }
+  }
+  SpecSnap sn;
+  if ((s = spec_begin(c, e, fused, sn))) return s;
+  if (!second_folded) {
+    c->flag_set = 1;
+    s = launch_mr_kernel(c, false);
+    c->flag_set = 0;
+    if (s) return s;
+  }
+  if ((s = wait_stream(c))) return s;
+  return spec_finish(c, sn, second_folded, npass);
+}
+
+// ---------------------------------------------------------------------------
+// Steps of a forest that cycles through the one-launch step: before each step it is on
+// one level below jmax, refine-all, RK4 and both analysis passes run in one tile
+// launch, and the speculated coarsening merges every block back into the same forest
+// with the same slots.  The next step's launch is then queued before this step's flags
+// are read, so the device never waits for the host: the host state after the queued
+// step's refinement and speculated coarsening is the same as before, and only the
+// data buffers (u and u_new swap each step) and the flag outputs (two banks, alternating)
+// differ.  If a step's flags miss the speculation, or its second pass would merge
+// more, the queued step is taken back -- it wrote only the other data buffer and free
+// slots, so the step's own results are intact -- and the step finishes the usual way.
+// ---------------------------------------------------------------------------
+struct StepCounters {
+  long n_rk4, n_block_updates, n_refined, n_fam, memo_hits;
+};
+
+StepCounters counters_of(const mrb_ctx* c) {
+  return StepCounters{c->n_rk4, c->n_block_updates, c->n_refined, c->n_fam, c->memo_hits};
+}
+
+void restore_counters(mrb_ctx* c, const StepCounters& k) {
+  c->n_rk4 = k.n_rk4;
+  c->n_block_updates = k.n_block_updates;
+  c->n_refined = k.n_refined;
+  c->n_fam = k.n_fam;
+  c->memo_hits = k.memo_hits;
+}
+
+void switch_banks(mrb_ctx* c) {
+  std::swap(c->h_flags, c->h_flags_b);
+  std::swap(c->dflags, c->dflags_b);
+  std::swap(c->h_maxd, c->h_maxd_b);
+  std::swap(c->dmaxd, c->dmaxd_b);
+  std::swap(c->h_mq, c->h_mq_b);
+  std::swap(c->dmq, c->dmq_b);
+}
+
+struct Issued {
+  SpecSnap sn;
+  std::vector<Leaf> pre;      // forest before the step
+  std::vector<int> pre_free;
+  char* pre_arena = nullptr;
+  StepCounters cnt{};
+  hipEvent_t ev = nullptr;
+};
+
+bool same_forest(const std::vector<Leaf>& a, const std::vector<Leaf>& b) {
+  if (a.size() != b.size()) return false;
+  for (size_t i = 0; i < a.size(); ++i)
+    if (a[i].level != b[i].level || a[i].slot != b[i].slot || a[i].c[0] != b[i].c[0] || a[i].c[1] != b[i].c[1] ||
+        a[i].c[2] != b[i].c[2])
+      return false;
+  return true;
+}
+
+// refinement, the one tile launch and the speculated coarsening of one step, without
+// reading anything back: *state 1.  Where the step is not of that kind: *state 0 and
+// nothing done, or *state 2 and the step done the usual way (the refinement had been
+// applied when that showed).
+mrb_status issue_step(mrb_ctx* c, double t, double dt, Issued& is, int* state) {
+  *state = 0;
+  if (!refine_foldable(c) || c->leaves.size() > kMemoMaxLeaves) return MRB_OK;
+  // the refinement and the coarsening must both come from the memo (then the step is a
+  // replay of host state): check before changing anything
+  std::vector<int> mat;
+  memo_material(c, 0, nullptr, mat);
+  if (!memo_find(c, 0, mat)) return MRB_OK;
+  is.pre = c->leaves;
+  is.pre_free = c->free_slots;
+  is.pre_arena = c->arena;
+  is.cnt = counters_of(c);
+  mrb_status r = do_refine_all(c, false);
+  if (r) return r;
+  if (!spec_all_merge(c)) {
+    // the refinement is done but the step cannot be one launch: finish it the usual way
+    if ((r = launch_refine_kernel(c, c->pending_ref, false))) return r;
+    bool tiled = false;
+    if ((r = rk4_adapt_tiled(c, t, dt, &tiled, false))) return r;
+    if (!tiled && (r = do_rk4(c, t, dt))) return r;
+    if (!tiled && (r = do_adapt(c, nullptr, false, false))) return r;
+    *state = 2;
+    return MRB_OK;
+  }
+  mrb_ctx::Memo* e = spec_entry(c);
+  const int tn = c->ma_nsub > 0 ? c->ma_nsub : rk4t_pick(c), tpb = c->ma_nsub > 0 ? c->ma_tpb : 256;
+  Rk4tArgs ra = rk4t_args(c, t, dt);
+  c->flag_set = 0;
+  rk4t_analysis_args(c, ra, e->smap);
+  ra.mq = c->dmq;
+  c->mq_parts = tn * tn;
+  if ((r = launch_tiled(c, tn, ra, true, tpb, true, true))) return r;
+  std::swap(c->u, c->unew);
+  c->n_rk4++;
+  c->n_block_updates += (long)nblk(c);
+  if ((r = spec_begin(c, e, true, is.sn))) return r;
+  HIPCHK(c, hipEventRecord(is.ev, c->stream));
+  *state = 1;
+  return MRB_OK;
+}
+
+// take back a queued step (its launch has finished or is waited for here)
+mrb_status take_back(mrb_ctx* c, Issued& q) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::swap(c->u, c->unew);
+  restore_counters(c, q.cnt);
+  return MRB_OK;
+}
+
+// the second pass's flags would merge families (the memo's answer where it has one)
+bool would_merge(mrb_ctx* c, const int8_t* flags) {
+  if (c->leaves.size() <= kMemoMaxLeaves) {
+    std::vector<int> mat;
+    memo_material(c, 1, flags, mat);
+    if (mrb_ctx::Memo* e = memo_find(c, 1, mat)) return e->nfam > 0;
+  }
+  return !coarsenable(c, flags).empty();
+}
+
+// up to nsteps steps with the next launch queued ahead; *done steps are complete on return
+mrb_status steps_cycled(mrb_ctx* c, double t0, double dt, int nsteps, int* done) {
+  *done = 0;
+  if (nsteps < 2 || !c->ev_issue[0] || !c->h_flags_b || !c->h_mq_b) return MRB_OK;
+  Issued is[2];
+  is[0].ev = c->ev_issue[0];
+  is[1].ev = c->ev_issue[1];
+  int st = 0;
+  mrb_status r = issue_step(c, t0, dt, is[0], &st);
+  if (r) return r;
+  if (st != 1) {
+    if (st == 2) {
+      c->n_steps++;
+      *done = 1;
+    }
+    return MRB_OK;
+  }
+  for (int k = 0;; ++k) {
+    Issued& cur = is[k & 1];
+    Issued& nxt = is[(k + 1) & 1];
+    // queue the next step if this one returned the forest to where it started (then the
+    // next step replays the same memoised transitions)
+    bool queued = false;
+    if (k + 1 < nsteps && c->arena == cur.pre_arena && same_forest(c->leaves, cur.pre) &&
+        c->free_slots == cur.pre_free) {
+      switch_banks(c);
+      if ((r = issue_step(c, t0 + (k + 1) * dt, dt, nxt, &st))) return r;
+      if (st != 1) return fail(c, MRB_E_STATE, "a cycling step could not be queued");
+      queued = true;
+      ++c->n_queued;
+    }
+    if (queued) switch_banks(c);   // this step's outputs
+    {
+      HostTimer ht(&c->hus_wait);
+      HIPCHK(c, hipEventSynchronize(cur.ev));
+    }
+    bool keep = true;
+    if (queued) {
+      const bool hit = std::equal(c->h_flags, c->h_flags + cur.sn.n1, c->spec_flags.begin());
+      if (hit) mother_flags(c);
+      keep = hit && !would_merge(c, c->h_flags2);
+      if (!keep) {
+        if ((r = take_back(c, nxt))) return r;
+        ++c->n_taken_back;
+      }
+    }
+    if ((r = spec_finish(c, cur.sn, true, nullptr))) return r;
+    c->n_steps++;
+    ++*done;
+    if (!queued || !keep) return MRB_OK;
+    switch_banks(c);   // the queued step's outputs again
+  }
 }
 
 mrb_status ensure_scratch(mrb_ctx* c, size_t bytes) {
@@ -2228,7 +2451,15 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
          hipHostGetDevicePointer((void**)&c->d_err, c->h_err, 0) == hipSuccess &&
          (cfg->dim != 2 || cfg->nfields != 1 ||
           (hipHostMalloc((void**)&c->h_mq, mb * 16 * sizeof(double), fl) == hipSuccess &&
-           hipHostGetDevicePointer((void**)&c->dmq, c->h_mq, 0) == hipSuccess));
+           hipHostGetDevicePointer((void**)&c->dmq, c->h_mq, 0) == hipSuccess &&
+           hipHostMalloc((void**)&c->h_mq_b, mb * 16 * sizeof(double), fl) == hipSuccess &&
+           hipHostGetDevicePointer((void**)&c->dmq_b, c->h_mq_b, 0) == hipSuccess &&
+           hipHostMalloc((void**)&c->h_flags_b, mb, fl) == hipSuccess &&
+           hipHostGetDevicePointer((void**)&c->dflags_b, c->h_flags_b, 0) == hipSuccess &&
+           hipHostMalloc((void**)&c->h_maxd_b, mb * sizeof(double), fl) == hipSuccess &&
+           hipHostGetDevicePointer((void**)&c->dmaxd_b, c->h_maxd_b, 0) == hipSuccess &&
+           hipEventCreateWithFlags(&c->ev_issue[0], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&c->ev_issue[1], hipEventDisableTiming) == hipSuccess));
     if (!ok) c->err = "hipHostMalloc (mapped) failed";
     if (ok) *c->h_err = 0;
     ok = ok && dev((void**)&c->dbar, kBarWords * sizeof(unsigned)) &&
@@ -2279,6 +2510,11 @@ mrb_status mrb_destroy(mrb_ctx* c) {
   if (c->h_maxd2) (void)hipHostFree(c->h_maxd2);
   if (c->h_err) (void)hipHostFree(c->h_err);
   if (c->h_mq) (void)hipHostFree(c->h_mq);
+  if (c->h_mq_b) (void)hipHostFree(c->h_mq_b);
+  if (c->h_flags_b) (void)hipHostFree(c->h_flags_b);
+  if (c->h_maxd_b) (void)hipHostFree(c->h_maxd_b);
+  for (hipEvent_t ev : c->ev_issue)
+    if (ev) (void)hipEventDestroy(ev);
   delete c;
   return MRB_OK;
 }
@@ -2476,6 +2712,15 @@ mrb_status mrb_step(mrb_ctx* c, double t0, double dt, int nsteps) {
     if (graph_ok(c)) {
       if ((r = step_graph(c, t0 + s * dt, dt))) return r;
     } else {
+      if (!probing && s + 1 < nsteps) {
+        // forests that cycle through the one-launch step: queued steps (counted inside)
+        int done = 0;
+        if ((r = steps_cycled(c, t0 + s * dt, dt, nsteps - s, &done))) return r;
+        if (done > 0) {
+          s += done - 1;
+          continue;
+        }
+      }
       const bool fold = refine_foldable(c);
       if ((r = do_refine_all(c, !fold))) return r;
       bool tiled = false;
@@ -2594,7 +2839,7 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"sweep_launch\": \"%s\", \"rk4_tile_tiles\": %d, \"rk4_tile_tuned\": %d, \"rk4_tile_analysis\": [%d, %d], \"rk4_tile_refine\": [%d, %d, %d], \"rk4_tile_mothers\": [%d, %d], \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"queued_steps\": %ld, \"queued_taken_back\": %ld, \"sweep_launch\": \"%s\", \"rk4_tile_tiles\": %d, \"rk4_tile_tuned\": %d, \"rk4_tile_analysis\": [%d, %d], \"rk4_tile_refine\": [%d, %d, %d], \"rk4_tile_mothers\": [%d, %d], \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
                 "\"plan_entries\": %.1f, \"plan_entries_per_block\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
@@ -2602,7 +2847,7 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
                 c->dev.active ? (size_t)c->dev.top : c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
                 c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_tpb(c, pick_nsub(c)) : 256,
                 c->order ? "level-sorted" : "forest",
-                c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses,
+                c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses, c->n_queued, c->n_taken_back,
                 c->have_forest && rk4t_pick(c) > 0 ? "rk4_tile" : (sweep_in_one(c) ? "one" : "four"), c->rk4t_nsub,
                 c->rk4t_tuned ? 1 : 0, c->ana_nsub, c->ana_tpb, c->ref_fold, c->ref_nsub, c->ref_tpb, c->ma_nsub, c->ma_tpb, c->sweep_grid, c->dev.active ? "device" : "host",
                 c->dev.mode, c->dev.steps, c->dev.passes, c->dev.pushes, c->dev.pulls, c->hus_refine_plan, c->hus_coarsen_plan, c->hus_upload, c->hus_wait,

@@ -702,12 +702,16 @@ def test_autotuner_times_both_sweep_launch_forms():
 
 
 @pytest.mark.gpu
-def test_multi_step_calls_match_oracle():
+@pytest.mark.parametrize("sweep", [2, 3])
+def test_multi_step_calls_match_oracle(sweep):
     """The library's own step loop (several steps per call, direct launches) equals
-    single oracle steps bit for bit."""
-    cfg = W.C2(form=W.FORM_FUSED)
+    single oracle steps bit for bit: with the default launches, and with the one-launch
+    tile step, where the swirl's forest cycles and each step's launch is queued before
+    the previous step's flags are read."""
+    cfg = W.C2(form=W.FORM_FUSED).replace(phys=(5.0,))
     s, o = _pair(cfg)
     s.set_graph(0)
+    s.set_sweep(sweep)
     t = 0.0
     for chunk in range(3):
         s.step(t, cfg.dt, 10)
@@ -715,16 +719,26 @@ def test_multi_step_calls_match_oracle():
             o.step(t, cfg.dt)
             t += cfg.dt
         assert_same(s, o, f"after {10 * (chunk + 1)} steps")
-    assert s.stats()["spec_hits"] >= 25
+    st = s.stats()
+    assert st["spec_hits"] >= 25
+    if sweep == 3:
+        assert st["queued_steps"] >= 25 and st["queued_taken_back"] == 0
+    else:
+        assert st["queued_steps"] == 0
+    fs, ms = s.get_flags()
+    assert_own_flags(s, cfg, fs, ms)
 
 
 @pytest.mark.gpu
-def test_multi_step_call_after_a_perturbation_matches_oracle():
+@pytest.mark.parametrize("sweep", [2, 3])
+def test_multi_step_call_after_a_perturbation_matches_oracle(sweep):
     """A perturbation between calls makes the first adapt of the next call miss its
-    speculation (the host state is put back); the run must equal the oracle's."""
+    speculation (the host state is put back; with the one-launch tile step the step
+    queued behind it is taken back as well); the run must equal the oracle's."""
     cfg = W.C2(form=W.FORM_FUSED)
     s, o = _pair(cfg)
     s.set_graph(0)
+    s.set_sweep(sweep)
     t = 0.0
     s.step(t, cfg.dt, 4)
     for _ in range(4):
@@ -743,6 +757,8 @@ def test_multi_step_call_after_a_perturbation_matches_oracle():
         t += cfg.dt
     assert_same(s, o, "3 steps after the perturbation")
     assert s.stats()["spec_misses"] > miss0
+    if sweep == 3:
+        assert s.stats()["queued_taken_back"] >= 1
 
 
 @pytest.mark.gpu
