@@ -947,6 +947,11 @@ struct TileGeo {
   // children (3) or on the mothers (6 child nodes)
   static constexpr int HW = 2, E = 4 * HW + (MA ? 6 : (ANA ? 3 : 0));
   static constexpr int S = (BS + NSUB - 1) / NSUB, TW = S + 2 * E, TSZ = TW * TW;
+  // slopes are kept where the last stage combines them: the region + E - 4 HW
+  static constexpr int KW = S + 2 * (E - 4 * HW), KSZ = KW * KW;
+  // LDS bytes: u (FP64), three slope arrays, two stage-value arrays
+  template <typename TT, typename KT>
+  static constexpr size_t lds() { return (size_t)TSZ * sizeof(double) + 3 * (size_t)KSZ * sizeof(KT) + 2 * (size_t)TSZ * sizeof(TT); }
 };
 
 // details of u_new at the region's nodes with an odd coordinate, from the tile's even
@@ -1034,10 +1039,12 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
   constexpr int NSUBT = NSUB * NSUB;
   using G = Geo<2, BS, S, E>;
   static_assert(G::TW == TW, "tile geometry");
+  constexpr int KW = TG::KW, KSZ = TG::KSZ, KO = E - 4 * HW;   // slope zone: tile index - (E - KO)
   extern __shared__ __align__(16) char smem[];
   double* U = reinterpret_cast<double*>(smem);
-  KT* K = reinterpret_cast<KT*>(U + TSZ);          // k1, k2, k3
-  TT* Y = reinterpret_cast<TT*>(K + 3 * TSZ);
+  KT* K = reinterpret_cast<KT*>(U + TSZ);          // k1, k2, k3 on the slope zone
+  TT* Ya = reinterpret_cast<TT*>(K + 3 * KSZ);     // stage values: this stage's and the next
+  TT* Yb = Ya + TSZ;
   __shared__ int tab[9];                            // same-level holder by direction
   __shared__ double sw[4 * TW];
   __shared__ double red[TPB / 64];
@@ -1075,8 +1082,9 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
     __syncthreads();
     if constexpr (REF) {
       // parent-level values over the fine box [r0 + cb - E, r0 + cb + cnt - 1 + E] and
-      // the prediction's reach (3 fine points), into the slope space (unused until k1)
-      double* PT = reinterpret_cast<double*>(K);
+      // the prediction's reach (3 fine points), in the second stage-value array (a
+      // quarter of its bytes; unused until the first stage's pass)
+      double* PT = reinterpret_cast<double*>(Yb);
       const bool own = A.topo.ref()[ri].child[ch] == d.slot;
       int cb[2], plo[2], pw[2];
       for (int a = 0; a < 2; ++a) {
@@ -1120,23 +1128,27 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
     TT r;
     if constexpr (sizeof(TT) == 8) r = A.lt.r[d.level];
     else r = A.lt.rf[d.level];
-    for (int s = 1; s <= 4; ++s) {
-      // stage values y_s within m of the region, as the stage kernels' gather forms them
-      const int m = E - HW * (s - 1);
-      {
-        const int nx = cnt[0] + 2 * m, ny = cnt[1] + 2 * m;
-        for (int p = tid; p < nx * ny; p += blockDim.x) {
-          const int i = G::idx(E - m + p % nx, E - m + p / nx, 0);
-          double y = U[i];
-          if (s > 1) y = y + A.alpha[s - 1] * (double)K[(s - 2) * TSZ + i];
-          if constexpr (sizeof(TT) == 4) Y[i] = (TT)(y - A.off);
-          else Y[i] = y;
-        }
+    // stage values as the stage kernels' gather forms them: y = u + alpha k_{s-1} (in
+    // FP64, from the stored slope), minus the field offset in FP32 tiles
+    auto stage_value = [&](double y) -> TT {
+      if constexpr (sizeof(TT) == 4) return (TT)(y - A.off);
+      else return y;
+    };
+    {
+      const int nx = cnt[0] + 2 * E, ny = cnt[1] + 2 * E;
+      for (int p = tid; p < nx * ny; p += blockDim.x) {
+        const int i = G::idx(p % nx, p / nx, 0);
+        Ya[i] = stage_value(U[i]);
       }
-      __syncthreads();
-      // k_s within m - HW of the region; the last stage forms u_new there (in place of
-      // u: a point's update reads only its own u) and stores it on the region
-      const int mr = m - HW;
+    }
+    __syncthreads();
+    TT* Y = Ya;
+    TT* Yn = Yb;
+    for (int s = 1; s <= 4; ++s) {
+      // k_s within E - s HW of the region, and in the same pass the next stage's values
+      // there; the last stage forms u_new (in place of u: a point's update reads only
+      // its own u) and stores it on the region
+      const int mr = E - HW * s;
       const int nx = cnt[0] + 2 * mr, ny = cnt[1] + 2 * mr;
       for (int p = tid; p < nx * ny; p += blockDim.x) {
         const int ix = E - mr + p % nx, iy = E - mr + p / nx;
@@ -1144,12 +1156,17 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
         const int t[3] = {r0[0] - E + ix, r0[1] - E + iy, 0};
         const int l[3] = {ix, iy, 0};
         const int q = G::idx(ix, iy, 0);
+        const int kx = ix - (E - KO), ky = iy - (E - KO);
+        const bool kz = kx >= 0 && kx < cnt[0] + 2 * KO && ky >= 0 && ky < cnt[1] + 2 * KO;
+        const int kq = kx + KW * ky;
         const TT kv = rhs_adv<2, BS, S, E, TT, TW>(Y, i, t, d, r, A.ph, A.lt, A.cfac[s - 1],
                                                    A.ph.kind == 1 ? sw : nullptr, l);
         if (s < 4) {
-          K[(s - 1) * TSZ + q] = (KT)kv;
+          const KT ks = (KT)kv;
+          if (kz) K[(s - 1) * KSZ + kq] = ks;
+          Yn[q] = stage_value(U[q] + A.alpha[s] * (double)ks);
         } else {
-          const double k1 = (double)K[q], k2 = (double)K[TSZ + q], k3 = (double)K[2 * TSZ + q];
+          const double k1 = (double)K[kq], k2 = (double)K[KSZ + kq], k3 = (double)K[2 * KSZ + kq];
           const double k4 = (double)kv;
           const double un = U[q] + A.h6 * ((k1 + k4) + 2.0 * (k2 + k3));
           if (ANA) U[q] = un;
@@ -1158,6 +1175,9 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
         }
       }
       __syncthreads();
+      TT* tmp = Y;
+      Y = Yn;
+      Yn = tmp;
     }
     if constexpr (ANA) {
       double m[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1962,10 +1982,9 @@ hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, cons
 // small enough for this form leaves most compute units idle otherwise)
 template <int B, int NS, typename TT, typename KT>
 static hipError_t rk4t_go(bool ana, bool ref, bool ma, int tpb, int grid, const Rk4tArgs& a, hipStream_t st) {
-  const size_t per = sizeof(double) + 3 * sizeof(KT) + sizeof(TT);
   if (ma) {
     if (!ana || !ref) return hipErrorInvalidValue;
-    const size_t lds = (size_t)TileGeo<B, NS, true, true>::TSZ * per;
+    const size_t lds = TileGeo<B, NS, true, true>::template lds<TT, KT>();
     if (tpb == 256) return go(k_rk4t<B, NS, TT, KT, true, 256, true, true>, grid, lds, st, a, 256);
     if constexpr (NS == 1) {
       if (tpb == 512) return go(k_rk4t<B, NS, TT, KT, true, 512, true, true>, grid, lds, st, a, 512);
@@ -1974,7 +1993,7 @@ static hipError_t rk4t_go(bool ana, bool ref, bool ma, int tpb, int grid, const 
     return hipErrorInvalidValue;
   }
   if (ana) {
-    const size_t lds = (size_t)TileGeo<B, NS, true>::TSZ * per;
+    const size_t lds = TileGeo<B, NS, true>::template lds<TT, KT>();
     if (ref) {
       if (tpb == 256) return go(k_rk4t<B, NS, TT, KT, true, 256, true>, grid, lds, st, a, 256);
       if constexpr (NS == 1) {
@@ -1992,7 +2011,7 @@ static hipError_t rk4t_go(bool ana, bool ref, bool ma, int tpb, int grid, const 
   }
   if (ref) return hipErrorInvalidValue;
   if (tpb != 256) return hipErrorInvalidValue;
-  return go(k_rk4t<B, NS, TT, KT, false, 256>, grid, (size_t)TileGeo<B, NS, false>::TSZ * per, st, a);
+  return go(k_rk4t<B, NS, TT, KT, false, 256>, grid, TileGeo<B, NS, false>::template lds<TT, KT>(), st, a);
 }
 
 hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, bool refine, bool mothers, int tpb,
