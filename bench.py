@@ -410,6 +410,11 @@ def main():
             s.init_grid()
             c5[name] = P.gain_study(s, W.mlp_init_params(64 * cfg.nf, 5), nsteps=args.c5_steps, guard=[0.0, 4.0])
             s.close()
+            present = [int(v) > 0 for v in c5[name]["labels_train"]]
+            c5[name]["degenerate"] = sum(present) < 2
+            if c5[name]["degenerate"]:
+                c5[name]["note"] = ("every training label is the same class (the recorded grid never changes), so the "
+                                    "test accuracy says nothing about the predictor")
         out["predictor"] = c5
     if not args.no_cpu:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
