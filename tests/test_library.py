@@ -573,6 +573,38 @@ def test_overlapped_tile_rk4_with_device_topology_matches_oracle():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("sweep", [2, 3])
+@pytest.mark.parametrize("case", ["2d_at_jmax", "2d_level1_below_jmax", "3d_level1_below_jmax"])
+def test_smallest_forests_match_oracle(case, sweep):
+    """Edge cases on the smallest forests (the library takes Jmax >= 2): the uniform
+    grid at Jmax 2 (nothing refines), and two blocks per direction (level 1, where the
+    neighbour across either face is the same block through a periodic image) one level
+    below Jmax (every block refines; in mode 3 the refinement folds into the tile step),
+    several steps per call, 2D and 3D."""
+    if case == "2d_at_jmax":
+        cfg = W.C2(jmax=2, form=W.FORM_FUSED).replace(phys=(5.0,))
+        lv, co = W.uniform_forest(cfg, 2)
+    elif case == "2d_level1_below_jmax":
+        cfg = W.C2(jmax=2, eps=1e-2, form=W.FORM_FUSED).replace(phys=(5.0,))
+        lv, co = W.uniform_forest(cfg, 1)
+    else:
+        cfg = W.C4(jmax=2, eps=1e-3, form=W.FORM_FUSED)
+        lv, co = W.uniform_forest(cfg, 1)
+    s, o = _pair(cfg, lv, co)
+    s.set_graph(0)
+    s.set_sweep(sweep)
+    t = 0.0
+    s.step(t, cfg.dt, 4)
+    for _ in range(4):
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    assert_same(s, o, f"{case}, 4 steps")
+    fs, ms = s.get_flags()
+    assert_own_flags(s, cfg, fs, ms)
+    s.close()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("nsub", [1, 4])
 def test_overlapped_tile_rk4_alone_matches_oracle(nsub):
     """mrb_rk4 in mode 3 (the tile step without the analysis folded in), then an
