@@ -141,11 +141,13 @@ struct Rk4tArgs {
   double off;             // FP32 tile offset (one field)
   LevelTab lt;
   Physics ph;
-  // with the analysis of u_new folded in (the first pass of an adapt): as MrArgs
+  // with the analysis of u_new folded in (the first pass of an adapt): flags and
+  // maxima as MrArgs where a block is one workgroup's region; with sub-tiles, each
+  // sub-tile's maximum |detail| instead, per block and sub-tile (mapped host memory,
+  // plain stores), and the host takes the maximum and applies the flag rule
   int8_t* flags;
   double* maxd;
-  unsigned long long* acc;
-  int* done;
+  double* part;
   double thr;
   const int* smap;
   // with the speculated coarsening's second analysis folded in as well (every block

@@ -572,7 +572,11 @@ __device__ __forceinline__ void subregion(int sub, int nsub, int S, int BS, int*
 // advection right-hand side at block-local node t (tile coordinates i)
 // ---------------------------------------------------------------------------
 // (sw: the swirl tables' slices along the region, SWS entries apart; see load_swirl)
-template <int DIM, int BS, int S, int H, typename TT, int SWS = S>
+// VK: where the velocity comes from -- 0 by ph.kind at run time (the swirl from its
+// tables in HBM, or from the LDS slices sw where given), 1 the swirl from the LDS slices
+// sw, 2 the constant velocity.  Callers that know the kind pass 1 or 2, so that no
+// generic load (an LDS slice or an HBM table) is left in the stencil loop.
+template <int DIM, int BS, int S, int H, typename TT, int SWS = S, int VK = 0>
 __device__ __forceinline__ TT rhs_adv(const TT* T, const int* i, const int* t, const BlockDesc& d, TT r,
                                       const Physics& ph, const LevelTab& lt, double cfac, const double* sw,
                                       const int* l) {
@@ -580,7 +584,7 @@ __device__ __forceinline__ TT rhs_adv(const TT* T, const int* i, const int* t, c
   const int x = i[0], y = i[1], z = i[2];
   const TT dx = D4(T[G::idx(x - 2, y, z)], T[G::idx(x - 1, y, z)], T[G::idx(x + 1, y, z)], T[G::idx(x + 2, y, z)], r);
   const TT dy = D4(T[G::idx(x, y - 2, z)], T[G::idx(x, y - 1, z)], T[G::idx(x, y + 1, z)], T[G::idx(x, y + 2, z)], r);
-  if (ph.kind == 0) {
+  if (VK == 2 || (VK == 0 && ph.kind == 0)) {
     TT acc = (TT)ph.c[0] * dx;
     acc = acc + (TT)ph.c[1] * dy;
     if constexpr (DIM > 2) {
@@ -592,7 +596,7 @@ __device__ __forceinline__ TT rhs_adv(const TT* T, const int* i, const int* t, c
   // swirl: u = sin^2(pi x) sin(2 pi y), v = -sin^2(pi y) sin(2 pi x) from tables on the
   // finest lattice; sw (LDS) holds the region's slices: s2(x), s(x), s2(y), s(y)
   double s2x, sx, s2y, sy;
-  if (sw) {
+  if (VK == 1 || sw) {
     s2x = sw[l[0]];
     sx = sw[SWS + l[0]];
     s2y = sw[2 * SWS + l[1]];
@@ -849,7 +853,11 @@ __device__ __forceinline__ void stage_pass(const StageArgs& A, const StageVar& V
           if (!ok[e]) continue;
           int l[3] = {lx, tq[e][1] - r0[1], DIM > 2 ? tq[e][2] - r0[2] : 0};
           int i[3] = {l[0] + HW, l[1] + HW, DIM > 2 ? l[2] + HW : 0};
-          const TT kv = rhs_adv<DIM, BS, S, HW, TT>(tile, i, tq[e], d, r, A.ph, A.lt, V.cfac, sw_lds ? swirl : nullptr, l);
+          // (one field in 2D: the swirl reads its LDS slices, any other kind is the
+          // constant velocity)
+          constexpr int VK0 = DIM == 2 && NF == 1 ? 2 : 0;
+          const TT kv = sw_lds ? rhs_adv<DIM, BS, S, HW, TT, S, 1>(tile, i, tq[e], d, r, A.ph, A.lt, V.cfac, swirl, l)
+                               : rhs_adv<DIM, BS, S, HW, TT, S, VK0>(tile, i, tq[e], d, r, A.ph, A.lt, V.cfac, nullptr, l);
           if (V.stage < 4) {
             ((KT*)V.kout)[qa[e]] = (KT)kv;
           } else {
@@ -941,6 +949,61 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs S) {
 // on one level (no finer neighbour, so no redundant node to write back).  A missing
 // neighbour (a forest not on one level) yields NaN.
 // ---------------------------------------------------------------------------
+// A 64-bit value moved between lanes of a row by a DPP pattern (both halves; every lane
+// active).
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long x) {
+  const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)x, CTRL, 0xF, 0xF, false);
+  const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(x >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long x, int lane) {
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)x, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(x >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+
+// Maximum over the 64 lanes of a wave (every lane active) of values that are +0, positive
+// or NaN with the sign bit clear (|detail| maxima): as unsigned integers such bit patterns
+// order as the values do and every NaN lies above +inf, so the integer maximum is the
+// NaN-propagating maximum, without branches.  Within rows of 16 lanes by DPP moves (swap
+// neighbours, swap pairs, mirror the half rows, mirror the rows), then the four rows'
+// results read out; every lane returns it.
+__device__ __forceinline__ double wave_nanmax(double v) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  u = umax64(u, dpp_u64<0xB1>(u));    // quad_perm [1, 0, 3, 2]
+  u = umax64(u, dpp_u64<0x4E>(u));    // quad_perm [2, 3, 0, 1]
+  u = umax64(u, dpp_u64<0x141>(u));   // row_half_mirror
+  u = umax64(u, dpp_u64<0x140>(u));   // row_mirror
+  u = umax64(umax64(lane_u64(u, 0), lane_u64(u, 16)), umax64(lane_u64(u, 32), lane_u64(u, 48)));
+  return __longlong_as_double((long long)u);
+}
+
+// NaN-propagating maxima of two values over a workgroup of TPB threads (values as for
+// wave_nanmax): wave maxima through red (2 TPB / 64 doubles of LDS; a barrier must lie
+// between two calls), one barrier, then the first wave combines them; only the first
+// wave's threads receive the results.
+template <int TPB>
+__device__ __forceinline__ void wg_nanmax2(double& a, double& b, double* red) {
+  a = wave_nanmax(a);
+  b = wave_nanmax(b);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = a;
+    red[TPB / 64 + (threadIdx.x >> 6)] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    a = wave_nanmax(l < TPB / 64 ? red[l] : 0.0);
+    b = wave_nanmax(l < TPB / 64 ? red[TPB / 64 + l] : 0.0);
+  }
+}
+
 template <int BS, int NSUB, bool ANA, bool MA = false>
 struct TileGeo {
   // halo: four stages of HW, plus the reach of the details' prediction on the
@@ -954,6 +1017,46 @@ struct TileGeo {
   static constexpr size_t lds() { return (size_t)TSZ * sizeof(double) + 3 * (size_t)KSZ * sizeof(KT) + 2 * (size_t)TSZ * sizeof(TT); }
 };
 
+// Every node of [lo, lo + n) in the 2D parity classes C0..3 in one pass, each class on
+// waves of its own: class c's q-th node is item base_c + q, where base_c is the previous
+// classes' nodes rounded up to whole waves, and item p goes to thread
+// (p - rot) mod blockDim.x (a power of two).  So the classes run side by side instead of
+// one after another, no wave takes two classes' stencils, and passes that need no barrier
+// between them can start on different waves.  body.template at<NX, NY, 1>(t) gets each
+// node.
+template <int C0, typename B>
+__device__ __forceinline__ void for_classes_2d(B& body, const int* lo, const int* n, int rot = 0) {
+  int fx[2], nx[2], fy[2], ny[2];   // per axis: first node and count of the even, odd nodes
+  for (int odd = 0; odd < 2; ++odd) {
+    fx[odd] = lo[0] + (((lo[0] & 1) != odd) ? 1 : 0);
+    fy[odd] = lo[1] + (((lo[1] & 1) != odd) ? 1 : 0);
+    nx[odd] = fx[odd] <= lo[0] + n[0] - 1 ? (lo[0] + n[0] - 1 - fx[odd]) / 2 + 1 : 0;
+    ny[odd] = fy[odd] <= lo[1] + n[1] - 1 ? (lo[1] + n[1] - 1 - fy[odd]) / 2 + 1 : 0;
+  }
+  int base[5], num[4];
+  base[0] = 0;
+  for (int c = 0; c < 4; ++c) {
+    num[c] = c >= C0 ? nx[c & 1] * ny[c >> 1] : 0;
+    base[c + 1] = base[c] + ((num[c] + 63) & ~63);
+  }
+  // row and column of a class's q-th node by a float reciprocal (q < 2^12 and a row of
+  // at most 64 nodes keep (q + 1/2) / n at least 1 / 128 away from an integer, far more
+  // than the rounding error, so the truncation is exact)
+  const float rx[2] = {1.0f / (float)max(nx[0], 1), 1.0f / (float)max(nx[1], 1)};
+  for (int p = (threadIdx.x + rot) & (blockDim.x - 1); p < base[4]; p += blockDim.x) {
+    int c = C0;
+    while (c < 3 && p >= base[c + 1]) ++c;
+    const int q = p - base[c], ox = c & 1, oy = c >> 1;
+    if (q >= num[c]) continue;
+    const int qy = (int)(((float)q + 0.5f) * rx[ox]);
+    const int t[3] = {fx[ox] + 2 * (q - qy * nx[ox]), fy[oy] + 2 * qy, 0};
+    if (c == 0) body.template at<1, 1, 1>(t);
+    else if (c == 1) body.template at<4, 1, 1>(t);
+    else if (c == 2) body.template at<1, 4, 1>(t);
+    else body.template at<4, 4, 1>(t);
+  }
+}
+
 // details of u_new at the region's nodes with an odd coordinate, from the tile's even
 // points (stride 2): the analysis kernel's prediction, on the tile's indexing
 template <int BS, int S, int E>
@@ -961,48 +1064,15 @@ struct TileDetails {
   using G = Geo<2, BS, S, E>;
   const double* U;
   const int* r0;
-  const int* cnt;
   double* m;
   template <int NX, int NY, int NZ>
-  __device__ __forceinline__ void go(int cls) {
-    ParityClass<2> pc(cls, r0, cnt);
-    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
-      int t[3];
-      pc.coords(p, t);
-      const int i0 = t[0] - r0[0] + E, i1 = t[1] - r0[1] + E;
-      const int bb[3] = {NX == 4 ? i0 - 3 : i0, NY == 4 ? i1 - 3 : i1, 0};
-      const int stride[3] = {2, 2, 2};
-      auto at = [&](int x, int y, int) { return U[G::idx(x, y, 0)]; };
-      const double pred = tensor_fixed<NX, NY, NZ, double>(at, bb, stride);
-      m[0] = nanmax(m[0], fabs(U[G::idx(i0, i1, 0)] - pred));
-    }
-  }
-};
-
-// With REF (the refinement of a forest on one level folded in as well) the tile is
-// built from the parents: block b is child b % 4 of refinement work b / 4 (every
-// parent refines, so children follow their parents in forest order), and a child
-// point takes the synchronised value at the children's level on the parents' grid --
-// the parent's value at even points, its prediction elsewhere -- as the refinement
-// kernel computes it; the children's pre-step values never reach HBM.
-template <int BS, int S, int E>
-struct ChildFromParents {
-  using G = Geo<2, BS, S, E>;
-  double* U;
-  const double* PT;   // parent-level values, pw0 per row, first point plo (parent-local)
-  int pw0, plo[2], qlo[2], qn[2], off[2];   // fine box (parent-local) and its tile offset
-  template <int NX, int NY, int NZ>
-  __device__ __forceinline__ void go(int cls) {
-    ParityClass<2> pc(cls, qlo, qn);
-    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
-      int Q[3];
-      pc.coords(p, Q);
-      const int bb[3] = {(NX == 4 ? (Q[0] - 3) / 2 : Q[0] / 2) - plo[0],
-                         (NY == 4 ? (Q[1] - 3) / 2 : Q[1] / 2) - plo[1], 0};
-      const int stride[3] = {1, 1, 1};
-      auto at = [&](int x, int y, int) { return PT[x + pw0 * y]; };
-      U[G::idx(Q[0] - off[0], Q[1] - off[1], 0)] = tensor_fixed<NX, NY, NZ, double>(at, bb, stride);
-    }
+  __device__ __forceinline__ void at(const int* t) {
+    const int i0 = t[0] - r0[0] + E, i1 = t[1] - r0[1] + E;
+    const int bb[3] = {NX == 4 ? i0 - 3 : i0, NY == 4 ? i1 - 3 : i1, 0};
+    const int stride[3] = {2, 2, 2};
+    auto u = [&](int x, int y, int) { return U[G::idx(x, y, 0)]; };
+    const double pred = tensor_fixed<NX, NY, NZ, double>(u, bb, stride);
+    m[0] = nanmax(m[0], fabs(U[G::idx(i0, i1, 0)] - pred));
   }
 };
 
@@ -1013,21 +1083,16 @@ template <int BS, int S, int E>
 struct MotherDetails {
   using G = Geo<2, BS, S, E>;
   const double* U;
-  int m0[2], mn[2], off[2], r0[2];
+  int off[2], r0[2];
   double* m;
   template <int NX, int NY, int NZ>
-  __device__ __forceinline__ void go(int cls) {
-    ParityClass<2> pc(cls, m0, mn);
-    for (int p = threadIdx.x; p < pc.total; p += blockDim.x) {
-      int M[3];
-      pc.coords(p, M);
-      const int i0 = 2 * M[0] - off[0] - r0[0] + E, i1 = 2 * M[1] - off[1] - r0[1] + E;
-      const int bb[3] = {NX == 4 ? i0 - 6 : i0, NY == 4 ? i1 - 6 : i1, 0};
-      const int stride[3] = {4, 4, 4};
-      auto at = [&](int x, int y, int) { return U[G::idx(x, y, 0)]; };
-      const double pred = tensor_fixed<NX, NY, NZ, double>(at, bb, stride);
-      m[0] = nanmax(m[0], fabs(U[G::idx(i0, i1, 0)] - pred));
-    }
+  __device__ __forceinline__ void at(const int* M) {
+    const int i0 = 2 * M[0] - off[0] - r0[0] + E, i1 = 2 * M[1] - off[1] - r0[1] + E;
+    const int bb[3] = {NX == 4 ? i0 - 6 : i0, NY == 4 ? i1 - 6 : i1, 0};
+    const int stride[3] = {4, 4, 4};
+    auto u = [&](int x, int y, int) { return U[G::idx(x, y, 0)]; };
+    const double pred = tensor_fixed<NX, NY, NZ, double>(u, bb, stride);
+    m[0] = nanmax(m[0], fabs(U[G::idx(i0, i1, 0)] - pred));
   }
 };
 
@@ -1047,28 +1112,39 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
   TT* Yb = Ya + TSZ;
   __shared__ int tab[9];                            // same-level holder by direction
   __shared__ double sw[4 * TW];
-  __shared__ double red[TPB / 64];
+  __shared__ double red[2 * (TPB / 64)];
   const int nblk = A.topo.h.n_blocks;
   const BlockDesc* blk = A.topo.blk();
   const int tid = threadIdx.x;
   for (XcdWork it(nblk * NSUBT); it.ok(); it.next()) {
     const int b = it.w / NSUBT;
+    // everything the work item's addresses depend on, requested at once: the block, its
+    // (or, with REF, its parent's) entry row up to the row stride -- entries past the
+    // count are ignored --, the speculation map and the refinement plan's child slot
+    const int ri = b >> 2, ch = b & 3;
     const BlockDesc d = blk[b];
+    const BlockDesc P = REF ? A.topo.pblk()[ri] : d;
+    const NbEntry* ent = REF ? A.topo.pnb(ri) : A.topo.nb(b);
+    const int erow = REF ? A.topo.h.pnb_stride : A.topo.h.nb_stride;
+    NbEntry q0;
+    if (tid < erow) q0 = ent[tid];
+    const int sm = ANA && A.smap ? A.smap[b] : -1;
+    const int kslot = REF ? A.topo.ref()[ri].child[ch] : -1;
     int r0[3], cnt[3];
     subregion<2>(it.w % NSUBT, NSUB, S, BS, r0, cnt);
     if (tid < 9) tab[tid] = -1;
     __syncthreads();
-    // same-level holders by direction: the block's (or, with REF, its parent's)
-    const int ri = b >> 2, ch = b & 3;
-    const BlockDesc P = REF ? A.topo.pblk()[ri] : d;
-    const NbEntry* ent = REF ? A.topo.pnb(ri) : A.topo.nb(b);
-    for (int e = tid; e < P.n_ent; e += blockDim.x) {
-      const NbEntry q = ent[e];
+    // same-level holders by direction
+    auto take = [&](const NbEntry& q) {
       const int ox = q.o[0], oy = q.o[1];
       if (q.dl == 0 && ox % (BS - 1) == 0 && oy % (BS - 1) == 0 && ox >= -(BS - 1) && ox <= BS - 1 &&
           oy >= -(BS - 1) && oy <= BS - 1)
         tab[(oy / (BS - 1) + 1) * 3 + ox / (BS - 1) + 1] = q.slot;
-    }
+    };
+    if (tid < P.n_ent) take(q0);
+    for (int e = tid + TPB; e < P.n_ent; e += TPB) take(ent[e]);
+    __syncthreads();
+    // swirl table slices (first read by the first stage, several barriers on)
     if (A.ph.kind == 1) {
       const int nl = A.lt.nl[d.level], shift = A.ph.jmax - d.level;
       for (int q = tid; q < 4 * TW; q += blockDim.x) {
@@ -1079,13 +1155,24 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
         sw[q] = (k & 1) ? A.ph.s[gg] : A.ph.s2[gg];
       }
     }
-    __syncthreads();
+    // stage values as the stage kernels' gather forms them: y = u + alpha k_{s-1} (in
+    // FP64, from the stored slope), minus the field offset in FP32 tiles
+    auto stage_value = [&](double y) -> TT {
+      if constexpr (sizeof(TT) == 4) return (TT)(y - A.off);
+      else return y;
+    };
     if constexpr (REF) {
-      // parent-level values over the fine box [r0 + cb - E, r0 + cb + cnt - 1 + E] and
+      // The refinement of a forest on one level folded in: the tile is built from the
+      // parents.  Block b is child b % 4 of refinement work b / 4 (every parent refines,
+      // so children follow their parents in forest order), and a child point takes the
+      // synchronised value at the children's level on the parents' grid -- the parent's
+      // value at even points, its prediction elsewhere -- as the refinement kernel
+      // computes it; the children's pre-step values never reach HBM.
+      // Parent-level values over the fine box [r0 + cb - E, r0 + cb + cnt - 1 + E] and
       // the prediction's reach (3 fine points), in the second stage-value array (a
       // quarter of its bytes; unused until the first stage's pass)
       double* PT = reinterpret_cast<double*>(Yb);
-      const bool own = A.topo.ref()[ri].child[ch] == d.slot;
+      const bool own = kslot == d.slot;
       int cb[2], plo[2], pw[2];
       for (int a = 0; a < 2; ++a) {
         cb[a] = ((ch >> a) & 1) * (BS - 1);
@@ -1100,18 +1187,36 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
         PT[p] = slot >= 0 ? A.u[(size_t)slot * NP + lx + BS * ly] : __builtin_nan("");
       }
       __syncthreads();
-      ChildFromParents<BS, S, E> cf;
-      cf.U = U;
-      cf.PT = PT;
-      cf.pw0 = pw[0];
+      // the children's values on the fine box, a quad of fine points (2X + {0, 1},
+      // 2Y + {0, 1}) per thread: the parent's value, its prediction along x, along y and
+      // along both, each as the refinement kernel's per-class tensor stencil forms it (the
+      // quad shares the parent values and the x-prediction of row Y)
+      int qlo[2], qhi[2], x0[2], nq[2];
       for (int a = 0; a < 2; ++a) {
-        cf.plo[a] = plo[a];
-        cf.qlo[a] = r0[a] + cb[a] - E;
-        cf.qn[a] = cnt[a] + 2 * E;
-        cf.off[a] = r0[a] + cb[a] - E;
+        qlo[a] = r0[a] + cb[a] - E;
+        qhi[a] = qlo[a] + cnt[a] + 2 * E - 1;
+        x0[a] = qlo[a] >> 1;
+        nq[a] = (qhi[a] >> 1) - x0[a] + 1;
       }
-      cf.template go<1, 1, 1>(0);
-      for_odd_classes<2>(cf);
+      auto pt = [&](int X, int Y) { return PT[(X - plo[0]) + pw[0] * (Y - plo[1])]; };
+      auto put = [&](int qx, int qy, double v) {
+        const int i = G::idx(qx - qlo[0], qy - qlo[1], 0);
+        U[i] = v;
+        Ya[i] = stage_value(v);
+      };
+      auto row = [&](int X, int Y) { return P4(pt(X - 1, Y), pt(X, Y), pt(X + 1, Y), pt(X + 2, Y)); };
+      for (int p = tid; p < nq[0] * nq[1]; p += blockDim.x) {
+        const int X = x0[0] + p % nq[0], Y = x0[1] + p / nq[0];
+        const bool ex = 2 * X >= qlo[0], ox = 2 * X + 1 <= qhi[0];
+        const bool ey = 2 * Y >= qlo[1], oy = 2 * Y + 1 <= qhi[1];
+        if (ex && ey) put(2 * X, 2 * Y, pt(X, Y));
+        if (ex && oy) put(2 * X, 2 * Y + 1, P4(pt(X, Y - 1), pt(X, Y), pt(X, Y + 1), pt(X, Y + 2)));
+        if (ox) {
+          const double ry = row(X, Y);
+          if (ey) put(2 * X + 1, 2 * Y, ry);
+          if (oy) put(2 * X + 1, 2 * Y + 1, P4(row(X, Y - 1), ry, row(X, Y + 1), row(X, Y + 2)));
+        }
+      }
     } else {
       // u over the region + E
       const int nx = cnt[0] + 2 * E, ny = cnt[1] + 2 * E;
@@ -1121,27 +1226,15 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
         const int dx = tx < 0 ? 0 : (tx > BS - 1 ? 2 : 1), dy = ty < 0 ? 0 : (ty > BS - 1 ? 2 : 1);
         const int slot = tab[dy * 3 + dx];
         const int lx = tx - (dx - 1) * (BS - 1), ly = ty - (dy - 1) * (BS - 1);
-        U[G::idx(ix, iy, 0)] = slot >= 0 ? A.u[(size_t)slot * NP + lx + BS * ly] : __builtin_nan("");
+        const double v = slot >= 0 ? A.u[(size_t)slot * NP + lx + BS * ly] : __builtin_nan("");
+        U[G::idx(ix, iy, 0)] = v;
+        Ya[G::idx(ix, iy, 0)] = stage_value(v);
       }
     }
     __syncthreads();
     TT r;
     if constexpr (sizeof(TT) == 8) r = A.lt.r[d.level];
     else r = A.lt.rf[d.level];
-    // stage values as the stage kernels' gather forms them: y = u + alpha k_{s-1} (in
-    // FP64, from the stored slope), minus the field offset in FP32 tiles
-    auto stage_value = [&](double y) -> TT {
-      if constexpr (sizeof(TT) == 4) return (TT)(y - A.off);
-      else return y;
-    };
-    {
-      const int nx = cnt[0] + 2 * E, ny = cnt[1] + 2 * E;
-      for (int p = tid; p < nx * ny; p += blockDim.x) {
-        const int i = G::idx(p % nx, p / nx, 0);
-        Ya[i] = stage_value(U[i]);
-      }
-    }
-    __syncthreads();
     TT* Y = Ya;
     TT* Yn = Yb;
     for (int s = 1; s <= 4; ++s) {
@@ -1159,8 +1252,10 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
         const int kx = ix - (E - KO), ky = iy - (E - KO);
         const bool kz = kx >= 0 && kx < cnt[0] + 2 * KO && ky >= 0 && ky < cnt[1] + 2 * KO;
         const int kq = kx + KW * ky;
-        const TT kv = rhs_adv<2, BS, S, E, TT, TW>(Y, i, t, d, r, A.ph, A.lt, A.cfac[s - 1],
-                                                   A.ph.kind == 1 ? sw : nullptr, l);
+        // (the swirl reads its LDS slices, the other kind is the constant velocity)
+        const TT kv = A.ph.kind == 1
+                          ? rhs_adv<2, BS, S, E, TT, TW, 1>(Y, i, t, d, r, A.ph, A.lt, A.cfac[s - 1], sw, l)
+                          : rhs_adv<2, BS, S, E, TT, TW, 2>(Y, i, t, d, r, A.ph, A.lt, A.cfac[s - 1], nullptr, l);
         if (s < 4) {
           const KT ks = (KT)kv;
           if (kz) K[(s - 1) * KSZ + kq] = ks;
@@ -1180,77 +1275,57 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
       Yn = tmp;
     }
     if constexpr (ANA) {
-      double m[4] = {0.0, 0.0, 0.0, 0.0};
-      TileDetails<BS, S, E> det{U, r0, cnt, m};
-      for_odd_classes<2>(det);
-      double v = m[0];
-      for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
-      if ((tid & 63) == 0) red[tid >> 6] = v;
-      __syncthreads();
-      if (tid == 0) {
-        double vb = red[0];
-        for (int q = 1; q < TPB / 64; ++q) vb = nanmax(vb, red[q]);
-        bool last = true;
-        if constexpr (NSUBT > 1) {
-          // combine sub-tiles as the analysis kernel does (bit patterns of |d| >= 0)
-          atomicMax(&A.acc[b], (unsigned long long)__double_as_longlong(vb));
-          __threadfence();
-          last = atomicAdd(&A.done[b], 1) == NSUBT - 1;
-          if (last) {
-            __threadfence();
-            vb = __longlong_as_double((long long)atomicExch(&A.acc[b], 0ull));
-            atomicExch(&A.done[b], 0);
-          }
-        }
-        if (last) {
-          A.maxd[b] = vb;
-          A.flags[b] = d.level > 1 && vb < A.thr ? (int8_t)-1 : (int8_t)0;
-        }
-      }
+      // the analysis and the mothers' analysis read u_new only: one pass over both (no
+      // barrier between them), then one reduction for both maxima
+      double m[1] = {0.0};
+      TileDetails<BS, S, E> det{U, r0, m};
+      for_classes_2d<1>(det, r0, cnt);
+      double mm[1] = {sm >= 0 ? 0.0 : __builtin_nan("")};
       if constexpr (MA) {
         // second analysis of the speculated coarsening: this region's share of its
         // mother's nodes; the host takes the maximum over the shares
-        const int sq = A.smap ? A.smap[b] : -1;
-        double mm[1] = {sq >= 0 ? 0.0 : __builtin_nan("")};
-        if (sq >= 0) {
+        if (sm >= 0) {
           MotherDetails<BS, S, E> md;
           md.U = U;
           md.m = mm;
+          int m0[2], mn[2];
           for (int a = 0; a < 2; ++a) {
-            md.off[a] = ((sq >> a) & 1) * (BS - 1);
+            md.off[a] = ((sm >> a) & 1) * (BS - 1);
             md.r0[a] = r0[a];
             // mother nodes whose child node lies in [r0, r0 + cnt)
             const int lo = (r0[a] + md.off[a] + 1) >> 1, hi = (r0[a] + cnt[a] - 1 + md.off[a]) >> 1;
-            md.m0[a] = lo;
-            md.mn[a] = hi - lo + 1;
+            m0[a] = lo;
+            mn[a] = hi - lo + 1;
           }
-          for_odd_classes<2>(md);
-        }
-        double v2 = mm[0];
-        for (int off = 32; off > 0; off >>= 1) v2 = nanmax(v2, __shfl_xor(v2, off, 64));
-        __syncthreads();
-        if ((tid & 63) == 0) red[tid >> 6] = v2;
-        __syncthreads();
-        if (tid == 0) {
-          double vm = red[0];
-          for (int q = 1; q < TPB / 64; ++q) vm = nanmax(vm, red[q]);
-          A.mq[(size_t)b * NSUBT + it.w % NSUBT] = vm;
+          for_classes_2d<1>(md, m0, mn, (TPB - 384) & (TPB - 1));   // from thread 384 on
         }
       }
+      double vb = m[0], vm = mm[0];
+      wg_nanmax2<TPB>(vb, vm, red);
+      if (tid == 0) {
+        if constexpr (NSUBT > 1) {
+          A.part[(size_t)b * NSUBT + it.w % NSUBT] = vb;
+        } else {
+          A.maxd[b] = vb;
+          A.flags[b] = d.level > 1 && vb < A.thr ? (int8_t)-1 : (int8_t)0;
+        }
+        if constexpr (MA) A.mq[(size_t)b * NSUBT + it.w % NSUBT] = vm;
+      }
       // speculated coarsening: the mother's nodes this block supplies (every node of a
-      // forest on one level is the block's own value)
-      const int sm = A.smap ? A.smap[b] : -1;
+      // forest on one level is the block's own value); after the reduction, so that no
+      // barrier waits for these stores (the next work item rewrites u only after two
+      // barriers)
       if (sm >= 0) {
-        const int ch = sm & 7;
+        const int mch = sm & 7;
         const size_t mbase = (size_t)(sm >> 3) * NP;
         ParityClass<2> pc(0, r0, cnt);
-        for (int p = tid; p < pc.total; p += blockDim.x) {
+        for (int p = (tid + TPB - 576) & (TPB - 1); p < pc.total; p += TPB) {   // from thread 576 on
           int t[3];
           pc.coords(p, t);
           bool skip = false;
           int mnode = 0, mul = 1;
           for (int a = 0; a < 2; ++a) {
-            const int bit = (ch >> a) & 1;
+            const int bit = (mch >> a) & 1;
             if (bit && t[a] == 0) skip = true;
             mnode += (t[a] / 2 + bit * (BS - 1) / 2) * mul;
             mul *= BS;
@@ -1258,7 +1333,6 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
           if (!skip) A.unew[mbase + mnode] = U[G::idx(t[0] - r0[0] + E, t[1] - r0[1] + E, 0)];
         }
       }
-      __syncthreads();
     }
   }
 }
@@ -1978,15 +2052,15 @@ hipError_t launch_stage(const Shape& s, int precision, Variant v, int grid, cons
   X(17, 0, 1) X(17, 1, 1)    \
   X(33, 0, 1) X(33, 0, 2) X(33, 0, 4) X(33, 1, 1) X(33, 1, 2) X(33, 1, 4)
 
-// with the analysis folded in, whole blocks may take 512 or 1024 threads (a forest
-// small enough for this form leaves most compute units idle otherwise)
+// with the analysis folded in, whole blocks and quarters may take 512 or 1024 threads (a
+// forest small enough for this form leaves most compute units idle otherwise)
 template <int B, int NS, typename TT, typename KT>
 static hipError_t rk4t_go(bool ana, bool ref, bool ma, int tpb, int grid, const Rk4tArgs& a, hipStream_t st) {
   if (ma) {
     if (!ana || !ref) return hipErrorInvalidValue;
     const size_t lds = TileGeo<B, NS, true, true>::template lds<TT, KT>();
     if (tpb == 256) return go(k_rk4t<B, NS, TT, KT, true, 256, true, true>, grid, lds, st, a, 256);
-    if constexpr (NS == 1) {
+    if constexpr (NS <= 2) {
       if (tpb == 512) return go(k_rk4t<B, NS, TT, KT, true, 512, true, true>, grid, lds, st, a, 512);
       if (tpb == 1024) return go(k_rk4t<B, NS, TT, KT, true, 1024, true, true>, grid, lds, st, a, 1024);
     }
@@ -1996,14 +2070,14 @@ static hipError_t rk4t_go(bool ana, bool ref, bool ma, int tpb, int grid, const 
     const size_t lds = TileGeo<B, NS, true>::template lds<TT, KT>();
     if (ref) {
       if (tpb == 256) return go(k_rk4t<B, NS, TT, KT, true, 256, true>, grid, lds, st, a, 256);
-      if constexpr (NS == 1) {
+      if constexpr (NS <= 2) {
         if (tpb == 512) return go(k_rk4t<B, NS, TT, KT, true, 512, true>, grid, lds, st, a, 512);
         if (tpb == 1024) return go(k_rk4t<B, NS, TT, KT, true, 1024, true>, grid, lds, st, a, 1024);
       }
       return hipErrorInvalidValue;
     }
     if (tpb == 256) return go(k_rk4t<B, NS, TT, KT, true, 256>, grid, lds, st, a, 256);
-    if constexpr (NS == 1) {
+    if constexpr (NS <= 2) {
       if (tpb == 512) return go(k_rk4t<B, NS, TT, KT, true, 512>, grid, lds, st, a, 512);
       if (tpb == 1024) return go(k_rk4t<B, NS, TT, KT, true, 1024>, grid, lds, st, a, 1024);
     }

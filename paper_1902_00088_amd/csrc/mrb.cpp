@@ -277,6 +277,13 @@ struct mrb_ctx {
   hipEvent_t ev_issue[2] = {nullptr, nullptr};
   long n_queued = 0, n_taken_back = 0;      // steps launched ahead of the previous read-back; taken back
   int mq_parts = 0;                         // sub-tiles per block of the last folded second analysis
+  // a tile launch with sub-tiles and the first analysis folded in leaves each sub-tile's
+  // maximum |detail| here (mapped; two banks like the flags), for the host to combine
+  struct PartState {
+    int parts = 0, n = 0, level = 0;   // parts 0: nothing to combine
+  };
+  double *h_part = nullptr, *dpart = nullptr, *h_part_b = nullptr, *dpart_b = nullptr;
+  PartState part_st, part_st_b;
   int flag_set = 0;                    // set the next analysis writes
   std::vector<int8_t> spec_flags;      // first-pass flags of the last adapt
   long spec_hits = 0, spec_misses = 0;
@@ -1006,6 +1013,13 @@ mrb_status launch_tiled(mrb_ctx* c, int tn, const Rk4tArgs& ra, bool analysis, i
   const double n = (double)nblk(c), nch = (double)(1 << c->cfg.dim);
   double bytes = n * c->bsz * per_node + (refine ? n / nch * c->bsz * 8.0 * (1.0 + nch) : 0.0);
   if (mothers) bytes += n / nch * c->bsz * 8.0;   // the second analysis, on the mothers
+  if (analysis) {
+    // sub-tiles leave partial maxima for the host (the launch's flag bank)
+    if (tn > 1 && !ra.part) return fail(c, MRB_E_STATE, "tile analysis: no partial-maximum buffer");
+    c->part_st.parts = tn > 1 ? tn * tn : 0;
+    c->part_st.n = (int)nblk(c);
+    c->part_st.level = c->leaves.empty() ? 0 : c->leaves[0].level;
+  }
   TimeScope rs(c, T_RK4T, bytes);
   HIPCHK(c, launch_rk4t(c->shape, c->cfg.precision, tn, analysis, refine, mothers, tpb, grid_for(c, work), ra,
                         c->stream));
@@ -1016,8 +1030,7 @@ mrb_status launch_tiled(mrb_ctx* c, int tn, const Rk4tArgs& ra, bool analysis, i
 void rk4t_analysis_args(mrb_ctx* c, Rk4tArgs& ra, const int* smap) {
   ra.flags = c->dflags;
   ra.maxd = c->dmaxd;
-  ra.acc = c->dacc;
-  ra.done = c->ddone;
+  ra.part = c->dpart;
   ra.thr = c->thr.empty() ? 0.0 : c->thr[0];
   ra.smap = smap;
 }
@@ -1597,6 +1610,25 @@ mrb_status spec_begin(mrb_ctx* c, mrb_ctx::Memo* e, bool written, SpecSnap& sn) 
   return coarsen_from_memo(c, *e, written);
 }
 
+// the first analysis of a tile launch with sub-tiles: each block's maximum over its
+// sub-tiles' shares (NaN-propagating, as the analysis kernel's reduction), then the flag
+// rule (every block of that launch is on one level), into flag set 0
+void ana_combine(mrb_ctx* c) {
+  mrb_ctx::PartState& ps = c->part_st;
+  if (ps.parts <= 1) return;
+  for (int b = 0; b < ps.n; ++b) {
+    const double* q = c->h_part + (size_t)b * ps.parts;
+    double v = q[0];
+    for (int k = 1; k < ps.parts; ++k) {
+      const double w = q[k];
+      v = v != v ? v : (w != w ? w : (v > w ? v : w));
+    }
+    c->h_maxd[b] = v;
+    c->h_flags[b] = ps.level > 1 && v < c->thr[0] ? (int8_t)-1 : (int8_t)0;
+  }
+  ps.parts = 0;
+}
+
 // the mothers' detail maxima of a folded second analysis: the maximum over their
 // children's sub-tile shares (NaN-propagating, as the analysis kernel's reduction), then
 // the flag rule, into flag set 1
@@ -1667,6 +1699,7 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fuse
   if (!first_launched && (s = launch_mr_kernel(c, false, fused ? e : nullptr))) return s;
   if (!e) {
     if ((s = wait_stream(c))) return s;
+    if (first_launched) ana_combine(c);
     if ((s = take_flags(c, 0, n1))) return s;
     c->spec_flags = c->last_flags;
     for (int passes = 1;; ++passes) {
@@ -1690,6 +1723,7 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fuse
     if (s) return s;
   }
   if ((s = wait_stream(c))) return s;
+  if (first_launched) ana_combine(c);
   return spec_finish(c, sn, second_folded, npass);
 }
 
@@ -1722,6 +1756,9 @@ void restore_counters(mrb_ctx* c, const StepCounters& k) {
 }
 
 void switch_banks(mrb_ctx* c) {
+  std::swap(c->h_part, c->h_part_b);
+  std::swap(c->dpart, c->dpart_b);
+  std::swap(c->part_st, c->part_st_b);
   std::swap(c->h_flags, c->h_flags_b);
   std::swap(c->dflags, c->dflags_b);
   std::swap(c->h_maxd, c->h_maxd_b);
@@ -1847,6 +1884,7 @@ mrb_status steps_cycled(mrb_ctx* c, double t0, double dt, int nsteps, int* done)
       HostTimer ht(&c->hus_wait);
       HIPCHK(c, hipEventSynchronize(cur.ev));
     }
+    ana_combine(c);
     bool keep = true;
     if (queued) {
       const bool hit = std::equal(c->h_flags, c->h_flags + cur.sn.n1, c->spec_flags.begin());
@@ -2458,6 +2496,10 @@ mrb_status mrb_create(const mrb_config* cfg, double* u, double* u_new, void* k1,
            hipHostGetDevicePointer((void**)&c->dflags_b, c->h_flags_b, 0) == hipSuccess &&
            hipHostMalloc((void**)&c->h_maxd_b, mb * sizeof(double), fl) == hipSuccess &&
            hipHostGetDevicePointer((void**)&c->dmaxd_b, c->h_maxd_b, 0) == hipSuccess &&
+           hipHostMalloc((void**)&c->h_part, mb * 16 * sizeof(double), fl) == hipSuccess &&
+           hipHostGetDevicePointer((void**)&c->dpart, c->h_part, 0) == hipSuccess &&
+           hipHostMalloc((void**)&c->h_part_b, mb * 16 * sizeof(double), fl) == hipSuccess &&
+           hipHostGetDevicePointer((void**)&c->dpart_b, c->h_part_b, 0) == hipSuccess &&
            hipEventCreateWithFlags(&c->ev_issue[0], hipEventDisableTiming) == hipSuccess &&
            hipEventCreateWithFlags(&c->ev_issue[1], hipEventDisableTiming) == hipSuccess));
     if (!ok) c->err = "hipHostMalloc (mapped) failed";
@@ -2511,6 +2553,8 @@ mrb_status mrb_destroy(mrb_ctx* c) {
   if (c->h_err) (void)hipHostFree(c->h_err);
   if (c->h_mq) (void)hipHostFree(c->h_mq);
   if (c->h_mq_b) (void)hipHostFree(c->h_mq_b);
+  if (c->h_part) (void)hipHostFree(c->h_part);
+  if (c->h_part_b) (void)hipHostFree(c->h_part_b);
   if (c->h_flags_b) (void)hipHostFree(c->h_flags_b);
   if (c->h_maxd_b) (void)hipHostFree(c->h_maxd_b);
   for (hipEvent_t ev : c->ev_issue)
@@ -2881,6 +2925,14 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->ref_tpb = 256;
     c->ma_nsub = 0;
     c->ma_tpb = 256;
+    if (reps < 0) {
+      // the tile step's folded forms forced too: nsub with -reps threads per workgroup
+      const int tpb = -reps;
+      if (c->rk4t_nsub != nsub || !(tpb == 256 || ((tpb == 512 || tpb == 1024) && nsub <= 2)))
+        return fail(c, MRB_E_ARG, "tune: that tile step form is not compiled");
+      c->ana_nsub = c->ref_nsub = c->ma_nsub = nsub;
+      c->ana_tpb = c->ref_tpb = c->ma_tpb = tpb;
+    }
   } else if (reps > 0) {
     if (!check_state(c, true)) return MRB_E_STATE;
     if (!(dt > 0.0)) return fail(c, MRB_E_ARG, "tune: dt must be positive");
@@ -3030,7 +3082,7 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
         if (c->rk4t_tuned) {
           for (int i = 0; i < nt; ++i)
             for (int tp : {256, 512, 1024})
-              if (tp == 256 || tv[i] == 1) ac.push_back(AC{tv[i], tp, 1e30f});
+              if (tp == 256 || tv[i] <= 2) ac.push_back(AC{tv[i], tp, 1e30f});
           float pair = 1e30f;
           Rk4tArgs ra = rk4t_args(c, 0.0, dt);
           rk4t_analysis_args(c, ra, nullptr);

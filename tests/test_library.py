@@ -762,6 +762,35 @@ def test_multi_step_calls_match_oracle(sweep):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("form", [(1, 1024), (2, 256), (2, 1024), (4, 256)])
+def test_queued_tile_steps_with_each_form_match_oracle(form):
+    """The queued one-launch steps with the tile step's folded forms forced to each
+    tiling and workgroup size: whole blocks write their flags, sub-tiles leave partial
+    detail maxima that the host combines; either way the run equals the oracle bit for
+    bit and the last analysis is the oracle's analysis of the final state."""
+    nsub, tpb = form
+    cfg = W.C2(form=W.FORM_FUSED).replace(phys=(5.0,))
+    s, o = _pair(cfg)
+    s.set_graph(0)
+    s.set_sweep(3)
+    s.tune(nsub=nsub, reps=-tpb)
+    t = 0.0
+    s.step(t, cfg.dt, 30)
+    for _ in range(30):
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    st = s.stats()
+    assert st["rk4_tile_mothers"] == [nsub, tpb] and st["rk4_tile_tiles"] == nsub
+    assert st["queued_steps"] >= 25 and st["queued_taken_back"] == 0
+    assert_same(s, o, f"tile form {form}: 30 steps")
+    fs, ms = s.get_flags()
+    assert_own_flags(s, cfg, fs, ms)
+    with pytest.raises(M.MrbError):
+        s.tune(nsub=4, reps=-1024)   # not compiled
+    s.close()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("sweep", [2, 3])
 def test_multi_step_call_after_a_perturbation_matches_oracle(sweep):
     """A perturbation between calls makes the first adapt of the next call miss its
