@@ -195,11 +195,11 @@ mrb_status mrb_timing(mrb_ctx *ctx, int enable);
  * if every leaf is on one level and the shape has the kernel, every tiling of the
  * overlapped-tile RK4 step against the stage launches (see mrb_set_sweep).  Every
  * candidate is timed over five rounds and its fastest round
- * counts.  nsub > 0 with reps < 0 also forces the tile step's folded forms (first
- * analysis, refinement, second analysis) to nsub sub-tiles with -reps threads per
- * workgroup (256; 512 or 1024 for nsub 1 or 2), MRB_E_ARG where that form is not
- * compiled.  nsub = 0 with reps = 0 returns to the built-in choices.  *chosen (may be
- * NULL) receives the stage tiling in use.
+ * counts.  nsub > 0 with reps < 0 also sets -reps threads per workgroup for the stage
+ * sweep and for the tile step's folded forms (first analysis, refinement, second
+ * analysis, then also on nsub sub-tiles), each where that form is compiled; MRB_E_ARG
+ * if neither is.  nsub = 0 with reps = 0 returns to the built-in choices.  *chosen (may
+ * be NULL) receives the stage tiling in use.
  * Not a step of the method: a schedule choice. */
 mrb_status mrb_tune(mrb_ctx *ctx, int nsub, int reps, double dt, int *chosen);
 /* Graph replay in mrb_step: the refinement, the four RK stages and the first analysis

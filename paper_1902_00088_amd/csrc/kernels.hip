@@ -1994,9 +1994,13 @@ static hipError_t sweep_pick(int max_grid, const SweepArgs& a, hipStream_t st, i
   X(2, 33, 2, 1, 1, 2, 256)   \
   X(2, 33, 2, 1, 1, 4, 256)   \
   X(2, 33, 4, 4, 0, 2, 256)   \
+  X(2, 33, 4, 4, 0, 2, 512)   \
   X(2, 33, 4, 4, 0, 4, 256)   \
   X(2, 33, 4, 4, 1, 1, 256)   \
+  X(2, 33, 4, 4, 1, 1, 512)   \
+  X(2, 33, 4, 4, 1, 1, 1024)  \
   X(2, 33, 4, 4, 1, 2, 256)   \
+  X(2, 33, 4, 4, 1, 2, 512)   \
   X(2, 33, 4, 4, 1, 4, 256)   \
   X(3, 17, 2, 1, 0, 2, 256)   \
   X(3, 17, 2, 1, 0, 2, 512)   \

@@ -2926,12 +2926,23 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->ma_nsub = 0;
     c->ma_tpb = 256;
     if (reps < 0) {
-      // the tile step's folded forms forced too: nsub with -reps threads per workgroup
+      // -reps threads per workgroup for the stage sweep and for the tile step's folded
+      // forms, each where that form is compiled
       const int tpb = -reps;
-      if (c->rk4t_nsub != nsub || !(tpb == 256 || ((tpb == 512 || tpb == 1024) && nsub <= 2)))
-        return fail(c, MRB_E_ARG, "tune: that tile step form is not compiled");
-      c->ana_nsub = c->ref_nsub = c->ma_nsub = nsub;
-      c->ana_tpb = c->ref_tpb = c->ma_tpb = tpb;
+      int tp[8];
+      const int ntp = stage_threads(c->shape, c->cfg.precision, nsub, tp, 8);
+      bool any = false;
+      for (int i = 0; i < ntp; ++i)
+        if (tp[i] == tpb) {
+          c->tpb = tpb;
+          any = true;
+        }
+      if (c->rk4t_nsub == nsub && (tpb == 256 || ((tpb == 512 || tpb == 1024) && nsub <= 2))) {
+        c->ana_nsub = c->ref_nsub = c->ma_nsub = nsub;
+        c->ana_tpb = c->ref_tpb = c->ma_tpb = tpb;
+        any = true;
+      }
+      if (!any) return fail(c, MRB_E_ARG, "tune: no form compiled with that tiling and workgroup size");
     }
   } else if (reps > 0) {
     if (!check_state(c, true)) return MRB_E_STATE;

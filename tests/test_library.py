@@ -347,6 +347,46 @@ def test_ns_tilings_agree_bitwise(nsub):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("form", [(1, 512), (1, 1024), (2, 512)])
+def test_ns_stage_workgroup_sizes_agree_bitwise(form):
+    """The Navier-Stokes stage kernel with larger workgroups performs the same operations
+    as with 256 threads: mixed, its steps equal the 256-thread ones bit for bit; FP64
+    (compiled for quarter blocks), they equal the oracle."""
+    nsub, tpb = form
+    cfg = W.C3(jmax=4, eps=1e-4, form=W.FORM_FUSED)
+    ref = M.Solver(cfg.replace(precision=W.MIXED))
+    ref.init_grid()
+    lv, co = ref.read_forest()
+    data = ref.read_blocks()
+    ref.tune(nsub=nsub)
+    s = M.Solver(cfg.replace(precision=W.MIXED))
+    s.init_forest(lv, co)
+    s.load_blocks(data)
+    s.tune(nsub=nsub, reps=-tpb)
+    assert s.stats()["stage_threads"] == tpb
+    t = 0.0
+    for _ in range(3):
+        s.step(t, cfg.dt)
+        ref.step(t, cfg.dt)
+        t += cfg.dt
+    a, b = s.read_forest(), ref.read_forest()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(_bits(s.read_blocks()), _bits(ref.read_blocks()))
+    s.close()
+    ref.close()
+    if nsub == 2:
+        s, o = _pair(cfg)
+        s.tune(nsub=nsub, reps=-tpb)
+        t = 0.0
+        for _ in range(2):
+            s.step(t, cfg.dt)
+            o.step(t, cfg.dt)
+            t += cfg.dt
+        assert_same(s, o, f"FP64 stage, {tpb} threads")
+        s.close()
+
+
+@pytest.mark.gpu
 def test_ns_mixed_within_1e5():
     cfg = W.C3(jmax=4, eps=1e-4)
     s = M.Solver(cfg.replace(precision=W.MIXED, form=W.FORM_FUSED))
