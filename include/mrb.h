@@ -190,15 +190,16 @@ mrb_status mrb_timing(mrb_ctx *ctx, int enable);
  * current forest and keeps the fastest pair, then does the
  * same for the analysis kernel (one pass; flags are recomputed) and, if the last
  * refinement plan is still the uploaded one (right after mrb_refine_all), for the
- * refinement kernel (re-run on the same parents); on the chosen stage tiling it also
+ * refinement kernel (re-run on the same parents), and the analysis of whole blocks with
+ * larger workgroups where compiled; on the chosen stage tiling it also
  * times the whole sweep as four launches against one launch with grid barriers, and,
  * if every leaf is on one level and the shape has the kernel, every tiling of the
  * overlapped-tile RK4 step against the stage launches (see mrb_set_sweep).  Every
  * candidate is timed over five rounds and its fastest round
  * counts.  nsub > 0 with reps < 0 also sets -reps threads per workgroup for the stage
- * sweep and for the tile step's folded forms (first analysis, refinement, second
- * analysis, then also on nsub sub-tiles), each where that form is compiled; MRB_E_ARG
- * if neither is.  nsub = 0 with reps = 0 returns to the built-in choices.  *chosen (may
+ * sweep, for the analysis of whole blocks and for the tile step's folded forms (first
+ * analysis, refinement, second analysis, then also on nsub sub-tiles), each where that
+ * form is compiled; MRB_E_ARG if none is.  nsub = 0 with reps = 0 returns to the built-in choices.  *chosen (may
  * be NULL) receives the stage tiling in use.
  * Not a step of the method: a schedule choice. */
 mrb_status mrb_tune(mrb_ctx *ctx, int nsub, int reps, double dt, int *chosen);

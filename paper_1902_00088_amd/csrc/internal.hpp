@@ -219,7 +219,8 @@ hipError_t launch_plain(const Shape& s, int grid, const StageArgs& a, hipStream_
 hipError_t launch_rk4t(const Shape& s, int precision, int nsub, bool analysis, bool refine, bool mothers, int tpb,
                        int grid, const Rk4tArgs& a, hipStream_t st);
 int rk4t_variants(const Shape& s, int precision, int* nsub, int cap);
-hipError_t launch_mr(const Shape& s, int nsub, int grid, const MrArgs& a, hipStream_t st);
+hipError_t launch_mr(const Shape& s, int nsub, int tpb, int grid, const MrArgs& a, hipStream_t st);
+int mr_threads(const Shape& s, int nsub, int* tpb, int cap);   // compiled workgroup sizes (256 first)
 hipError_t launch_refine(const Shape& s, int nsub, int grid, const RefineArgs& a, hipStream_t st);
 hipError_t launch_coarsen(const Shape& s, int grid, const CoarsenArgs& a, hipStream_t st);
 hipError_t launch_read(const Shape& s, int grid, const ReadArgs& a, hipStream_t st);

@@ -1556,8 +1556,8 @@ struct DetailsBodyC {
   }
 };
 
-template <int DIM, int BS, int NF, int NSUB>
-__global__ void __launch_bounds__(256) k_mr(MrArgs A) {
+template <int DIM, int BS, int NF, int NSUB, int TPB = 256>
+__global__ void __launch_bounds__(TPB) k_mr(MrArgs A) {
   // the region's nodes in the tile; the even nodes up to H = 3 around it (a region may
   // start at an odd node, whose coarse stencil reaches 3 back) in the coarse array
   constexpr int S = (BS + NSUB - 1) / NSUB, H = 3;
@@ -1566,7 +1566,7 @@ __global__ void __launch_bounds__(256) k_mr(MrArgs A) {
   constexpr int NSUBT = Pow<DIM, NSUB>::v;
   __shared__ GState<DIM, S + 2 * H> g;
   __shared__ SEnt se[kMaxEnt];
-  __shared__ double red[4][4];
+  __shared__ double red[TPB / 64][4];
   extern __shared__ __align__(16) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
   double* carr = tile + NF * TSZ;
@@ -1583,7 +1583,7 @@ __global__ void __launch_bounds__(256) k_mr(MrArgs A) {
     sent_setup<DIM, BS, NF>(se, g.ent, d.n_ent);
     __syncthreads();
     YSrc<double, double, false> src{A.u, nullptr, 0.0, nullptr};
-    sgather<DIM, BS, S, 0, NF, true, double>(tile, carr, g, se, d.slot, r0, cnt, src);
+    sgather<DIM, BS, S, 0, NF, true, double, 8, TPB>(tile, carr, g, se, d.slot, r0, cnt, src);
     double m[4] = {0.0, 0.0, 0.0, 0.0};
     const size_t base = (size_t)d.slot * NF * NP;
     const int nn = cnt[0] * cnt[1] * (DIM > 2 ? cnt[2] : 1);
@@ -2165,11 +2165,29 @@ int aux_variants(const Shape& s, int kind, int* nsub, int cap) {
   return n;
 }
 
-template <int D, int B, int F, int NS>
+template <int D, int B, int F, int NS, int T = 256>
 static hipError_t mr_go(int grid, const MrArgs& a, hipStream_t st) {
   constexpr int S = (B + NS - 1) / NS;
   using SG = SGeo<D, B, S, 0>;
-  return go(k_mr<D, B, F, NS>, grid, sizeof(double) * F * (SG::TSZ + SG::CSZ), st, a);
+  return go(k_mr<D, B, F, NS, T>, grid, sizeof(double) * F * (SG::TSZ + SG::CSZ), st, a, T);
+}
+
+// the analysis of whole 2D blocks with larger workgroups (a small forest leaves most
+// compute units idle with 256 threads per block): shape, threads per workgroup
+#define MRB_MR_WIDE(X) \
+  X(2, 33, 2, 1, 512)  \
+  X(2, 33, 2, 1, 1024) \
+  X(2, 33, 4, 4, 512)  \
+  X(2, 33, 4, 4, 1024)
+
+int mr_threads(const Shape& s, int nsub, int* tpb, int cap) {
+  int n = 0;
+  if (cap > 0) tpb[n++] = 256;
+  if (nsub != 1) return n;
+#define X(D, B, W, F, T) if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && n < cap) tpb[n++] = T;
+  MRB_MR_WIDE(X)
+#undef X
+  return n;
 }
 
 template <int D, int B, int F, int NS>
@@ -2179,7 +2197,14 @@ static hipError_t refine_go(int grid, const RefineArgs& a, hipStream_t st) {
   return go(k_refine<D, B, F, NS>, grid, sizeof(double) * F * (SG::TSZ + SG::CSZ), st, a);
 }
 
-hipError_t launch_mr(const Shape& s, int nsub, int grid, const MrArgs& a, hipStream_t st) {
+hipError_t launch_mr(const Shape& s, int nsub, int tpb, int grid, const MrArgs& a, hipStream_t st) {
+  if (tpb != 256) {
+#define X(D, B, W, F, T) \
+    if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && nsub == 1 && tpb == T) return mr_go<D, B, F, 1, T>(grid, a, st);
+    MRB_MR_WIDE(X)
+#undef X
+    return hipErrorInvalidValue;
+  }
 #define X(D, B, W, F, NS) \
   if (s.dim == D && s.bs == B && s.hw == W && s.nf == F && nsub == NS) return mr_go<D, B, F, NS>(grid, a, st);
   MRB_AUX_VARIANTS(X)

@@ -291,6 +291,7 @@ struct mrb_ctx {
   int nsub = 0;                // stage sub-tiles per axis (0 = choose by block count)
   int tpb = 256;               // stage threads per workgroup (for the tuned nsub)
   int nsub_mr = -1;            // analysis sub-tiles per axis (-1 = whole blocks, measured best)
+  int tpb_mr = 256;            // analysis threads per workgroup for whole blocks (tuned)
   int nsub_ref = 0;            // refinement sub-tiles per axis (0 = choose by work count)
   int order = 0;               // stage processing order: 0 forest (Morton), 1 level-sorted
   std::string tune_log;
@@ -885,6 +886,9 @@ int pick_nsub(const mrb_ctx* c) {
 // threads per workgroup of the stage kernel: the tuned choice for the tuned tiling
 int pick_tpb(const mrb_ctx* c, int nsub) { return c->nsub == nsub ? c->tpb : 256; }
 
+// threads per workgroup of the analysis kernel: the tuned choice for whole blocks
+int mr_tpb(const mrb_ctx* c, int nsub) { return nsub == 1 ? c->tpb_mr : 256; }
+
 // sub-tiles per axis for the analysis / refinement kernels: the smallest count whose
 // workgroups (n_items each) cover the chip twice
 int pick_aux(const mrb_ctx* c, long n_items, int forced = 0) {
@@ -1299,7 +1303,7 @@ mrb_status launch_mr_kernel(mrb_ctx* c, bool fixed_grid, const mrb_ctx::Memo* sp
   long work = n;
   for (int q = 0; q < c->cfg.dim; ++q) work *= ns;
   TimeScope ts(c, T_MR, (double)n * c->bsz * 8.0);
-  HIPCHK(c, launch_mr(c->shape, ns, fixed_grid ? c->grid : grid_for(c, work), a, c->stream));
+  HIPCHK(c, launch_mr(c->shape, ns, mr_tpb(c, ns), fixed_grid ? c->grid : grid_for(c, work), a, c->stream));
   return MRB_OK;
 }
 
@@ -2303,7 +2307,7 @@ mrb_status dev_adapt(mrb_ctx* c, int* npass) {
       long work = n;
       for (int q = 0; q < c->cfg.dim; ++q) work *= ns;
       TimeScope ts(c, T_MR, (double)n * c->bsz * 8.0);
-      HIPCHK(c, launch_mr(c->shape, ns, grid_for(c, work), m, c->stream));
+      HIPCHK(c, launch_mr(c->shape, ns, mr_tpb(c, ns), grid_for(c, work), m, c->stream));
     }
     ++passes;
     c->n_mr++;
@@ -2696,7 +2700,7 @@ mrb_status mrb_mr_pass_noalloc(mrb_ctx* c, int8_t* flags, double* maxd) {
   a.done = (int*)(base + acc_bytes);
   long work = (long)n;
   for (int q = 0; q < c->cfg.dim; ++q) work *= ns;
-  HIPCHK(c, launch_mr(c->shape, ns, grid_for(c, work), a, c->stream));
+  HIPCHK(c, launch_mr(c->shape, ns, 256, grid_for(c, work), a, c->stream));
   mrb_status r = mr_readback(c);
   c->dev.have_flags = false;   // the newest analysis is the host's copy
   if (flags) std::memcpy(flags, c->last_flags.data(), c->last_flags.size());
@@ -2883,14 +2887,14 @@ mrb_status mrb_stats(mrb_ctx* c, char* json, int cap) {
   int w = std::snprintf(json, cap,
                 "{\"blocks\": %zu, \"steps\": %ld, \"rk4\": %ld, \"block_updates\": %ld, \"mr_passes\": %ld, "
                 "\"families_coarsened\": %ld, \"blocks_refined\": %ld, \"free_slots\": %zu, \"grid\": %d, "
-                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"queued_steps\": %ld, \"queued_taken_back\": %ld, \"sweep_launch\": \"%s\", \"rk4_tile_tiles\": %d, \"rk4_tile_tuned\": %d, \"rk4_tile_analysis\": [%d, %d], \"rk4_tile_refine\": [%d, %d, %d], \"rk4_tile_mothers\": [%d, %d], \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
+                "\"stage_tiles\": %d, \"stage_threads\": %d, \"stage_order\": \"%s\", \"analysis_threads\": %d, \"graph_launches\": %ld, \"graph_mode\": %d, \"graph_in_use\": %d, \"memo_hits\": %ld, \"spec_hits\": %ld, \"spec_misses\": %ld, \"queued_steps\": %ld, \"queued_taken_back\": %ld, \"sweep_launch\": \"%s\", \"rk4_tile_tiles\": %d, \"rk4_tile_tuned\": %d, \"rk4_tile_analysis\": [%d, %d], \"rk4_tile_refine\": [%d, %d, %d], \"rk4_tile_mothers\": [%d, %d], \"sweep_grid\": %d, \"topology\": \"%s\", \"topology_mode\": %d, \"device_topology\": {\"steps\": %ld, \"passes\": %ld, \"pushes\": %ld, \"pulls\": %ld}, \"host_us\": {\"refine_plan\": %.1f, "
                 "\"coarsen_plan\": %.1f, \"upload\": %.1f, \"wait\": %.1f, \"graph_launch\": %.1f, \"plan_ordering\": %.1f, "
                 "\"plan_entries\": %.1f, \"plan_entries_per_block\": %.1f, \"plan_fixed_point\": %.1f}, "
                 "\"tune_ms\": {%s}, \"kernels\": %s}",
                 nblk(c), c->n_steps, c->n_rk4, c->n_block_updates, c->n_mr, c->n_fam, c->n_refined,
                 c->dev.active ? (size_t)c->dev.top : c->free_slots.size(), c->grid, c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_nsub(c) : 1,
                 c->have_forest && c->cfg.form == MRB_FORM_FUSED ? pick_tpb(c, pick_nsub(c)) : 256,
-                c->order ? "level-sorted" : "forest",
+                c->order ? "level-sorted" : "forest", c->tpb_mr,
                 c->n_graph_launches, c->graph_mode, c->use_graph ? 1 : 0, c->memo_hits, c->spec_hits, c->spec_misses, c->n_queued, c->n_taken_back,
                 c->have_forest && rk4t_pick(c) > 0 ? "rk4_tile" : (sweep_in_one(c) ? "one" : "four"), c->rk4t_nsub,
                 c->rk4t_tuned ? 1 : 0, c->ana_nsub, c->ana_tpb, c->ref_fold, c->ref_nsub, c->ref_tpb, c->ma_nsub, c->ma_tpb, c->sweep_grid, c->dev.active ? "device" : "host",
@@ -2925,9 +2929,10 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->ref_tpb = 256;
     c->ma_nsub = 0;
     c->ma_tpb = 256;
+    c->tpb_mr = 256;
     if (reps < 0) {
-      // -reps threads per workgroup for the stage sweep and for the tile step's folded
-      // forms, each where that form is compiled
+      // -reps threads per workgroup for the stage sweep, the whole-block analysis and the
+      // tile step's folded forms, each where that form is compiled
       const int tpb = -reps;
       int tp[8];
       const int ntp = stage_threads(c->shape, c->cfg.precision, nsub, tp, 8);
@@ -2935,6 +2940,12 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
       for (int i = 0; i < ntp; ++i)
         if (tp[i] == tpb) {
           c->tpb = tpb;
+          any = true;
+        }
+      const int nmt = mr_threads(c->shape, 1, tp, 8);
+      for (int i = 1; i < nmt; ++i)
+        if (tp[i] == tpb) {
+          c->tpb_mr = tpb;
           any = true;
         }
       if (c->rk4t_nsub == nsub && (tpb == 256 || ((tpb == 512 || tpb == 1024) && nsub <= 2))) {
@@ -3274,10 +3285,42 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
       const int n = (int)c->hblk.size();
       long work = n;
       for (int q = 0; q < c->cfg.dim; ++q) work *= v;
-      for (int j = 0; j < k; ++j) HIPCHK(c, launch_mr(c->shape, v, grid_for(c, work), a, c->stream));
+      for (int j = 0; j < k; ++j) HIPCHK(c, launch_mr(c->shape, v, 256, grid_for(c, work), a, c->stream));
       return MRB_OK;
     });
     if (tr) return done(tr);
+    // whole blocks: the analysis with larger workgroups where compiled
+    c->tpb_mr = 256;
+    if (c->nsub_mr == 1) {
+      int tp[4];
+      const int nt = mr_threads(c->shape, 1, tp, 4);
+      if (nt > 1) {
+        float best[4] = {1e30f, 1e30f, 1e30f, 1e30f};
+        MrArgs a = mr_args(c);
+        const long work = (long)c->hblk.size();
+        for (int round = 0; round < kRounds; ++round)
+          for (int i = 0; i < nt; ++i) {
+            HIPCHK(c, launch_mr(c->shape, 1, tp[i], grid_for(c, work), a, c->stream));   // warm-up
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            for (int j = 0; j < reps; ++j) HIPCHK(c, launch_mr(c->shape, 1, tp[i], grid_for(c, work), a, c->stream));
+            float ms = 0.f;
+            if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+              return done(fail(c, MRB_E_DEVICE, "tune: event"));
+            best[i] = std::min(best[i], ms / reps);
+          }
+        int bi = 0;
+        c->tune_log += ", \"mr_threads\": {";
+        for (int i = 0; i < nt; ++i) {
+          char buf[48];
+          std::snprintf(buf, sizeof buf, "%s\"%d\": %.4f", i ? ", " : "", tp[i], best[i]);
+          c->tune_log += buf;
+          if (best[i] < best[bi]) bi = i;
+        }
+        c->tune_log += "}";
+        c->tpb_mr = tp[bi];
+      }
+    }
     // refinement, while the last refinement plan is still the uploaded one: re-running
     // it rewrites the same children from the untouched parents
     if (c->pending_ref > 0) {
@@ -3295,6 +3338,7 @@ mrb_status mrb_tune(mrb_ctx* c, int nsub, int reps, double dt, int* chosen) {
     c->nsub = 0;
     c->tpb = 256;
     c->nsub_mr = -1;
+    c->tpb_mr = 256;
     c->nsub_ref = 0;
     c->order = 0;
     c->rk4t_nsub = 0;

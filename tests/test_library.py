@@ -363,7 +363,7 @@ def test_ns_stage_workgroup_sizes_agree_bitwise(form):
     s.init_forest(lv, co)
     s.load_blocks(data)
     s.tune(nsub=nsub, reps=-tpb)
-    assert s.stats()["stage_threads"] == tpb
+    assert s.stats()["stage_threads"] == tpb and s.stats()["analysis_threads"] == tpb
     t = 0.0
     for _ in range(3):
         s.step(t, cfg.dt)
@@ -384,6 +384,30 @@ def test_ns_stage_workgroup_sizes_agree_bitwise(form):
             t += cfg.dt
         assert_same(s, o, f"FP64 stage, {tpb} threads")
         s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("tpb", [512, 1024])
+def test_analysis_workgroup_sizes_match_oracle(tpb):
+    """The analysis of whole one-field blocks with larger workgroups, on a forest on two
+    levels (coarse-to-fine prediction and finer-owned redundant nodes in play): steps,
+    flags and detail maxima equal the oracle's bit for bit."""
+    cfg = W.C2(jmax=4, form=W.FORM_FUSED)
+    lv, co = _two_level()
+    s, o = _pair(cfg, lv, co)
+    s.set_graph(0)
+    s.tune(nsub=1, reps=-tpb)
+    assert s.stats()["analysis_threads"] == tpb
+    t = 0.0
+    for _ in range(3):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    assert_same(s, o, f"analysis with {tpb} threads")
+    fs, ms = s.mr_pass()
+    fo, mo = o.mr_pass()
+    assert np.array_equal(fs, fo) and np.array_equal(_bits(ms), _bits(mo))
+    s.close()
 
 
 @pytest.mark.gpu
@@ -826,7 +850,7 @@ def test_queued_tile_steps_with_each_form_match_oracle(form):
     fs, ms = s.get_flags()
     assert_own_flags(s, cfg, fs, ms)
     with pytest.raises(M.MrbError):
-        s.tune(nsub=4, reps=-1024)   # not compiled
+        s.tune(nsub=4, reps=-768)    # no form has that workgroup size
     s.close()
 
 
