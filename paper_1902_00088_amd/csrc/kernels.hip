@@ -1104,6 +1104,8 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
   constexpr int NSUBT = NSUB * NSUB;
   using G = Geo<2, BS, S, E>;
   static_assert(G::TW == TW, "tile geometry");
+  static_assert(S + 2 * (E - HW) <= 64 && (S + 2 * (E - HW)) * (S + 2 * (E - HW)) < 4096,
+                "the stage loops' float row split needs rows of at most 64 points, fewer than 2^12 in all");
   constexpr int KW = TG::KW, KSZ = TG::KSZ, KO = E - 4 * HW;   // slope zone: tile index - (E - KO)
   extern __shared__ __align__(16) char smem[];
   double* U = reinterpret_cast<double*>(smem);
@@ -1243,8 +1245,12 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
       // its own u) and stores it on the region
       const int mr = E - HW * s;
       const int nx = cnt[0] + 2 * mr, ny = cnt[1] + 2 * mr;
+      // row of the p-th point by a float reciprocal (p < 2^12, rows of at most 64
+      // points: exact, as in for_classes_2d)
+      const float rnx = 1.0f / (float)nx;
       for (int p = tid; p < nx * ny; p += blockDim.x) {
-        const int ix = E - mr + p % nx, iy = E - mr + p / nx;
+        const int qy = (int)(((float)p + 0.5f) * rnx);
+        const int ix = E - mr + (p - qy * nx), iy = E - mr + qy;
         const int i[3] = {ix, iy, 0};
         const int t[3] = {r0[0] - E + ix, r0[1] - E + iy, 0};
         const int l[3] = {ix, iy, 0};
