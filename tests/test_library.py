@@ -855,6 +855,34 @@ def test_queued_tile_steps_with_each_form_match_oracle(form):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("tpb", [256, 512, 1024])
+def test_queued_tile_steps_bs17_match_oracle(tpb):
+    """The queued one-launch steps on 17-point blocks (constant advection): a smooth field on
+    16 level-2 blocks whose refine-all and coarsening cycle (eps between the details of the
+    two levels), with each compiled workgroup size; bitwise equal to the oracle."""
+    fn = lambda x, y: 0.5 + 0.1 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+    cfg = W.C1(jmax=4, eps=3e-6, form=W.FORM_FUSED)
+    lv = np.full(16, 2, np.int8)
+    co = np.array([[x, y] for y in range(4) for x in range(4)], np.int32)
+    s, o = _pair(cfg, lv, co, fn=fn)
+    s.set_graph(0)
+    s.set_sweep(3)
+    s.tune(nsub=1, reps=-tpb)
+    t = 0.0
+    s.step(t, cfg.dt, 20)
+    for _ in range(20):
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    st = s.stats()
+    assert st["rk4_tile_mothers"] == [1, tpb] and st["blocks"] == 16
+    assert st["queued_steps"] >= 15 and st["queued_taken_back"] == 0
+    assert_same(s, o, f"Bs 17, {tpb} threads: 20 steps")
+    fs, ms = s.get_flags()
+    assert_own_flags(s, cfg, fs, ms)
+    s.close()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("sweep", [2, 3])
 def test_multi_step_call_after_a_perturbation_matches_oracle(sweep):
     """A perturbation between calls makes the first adapt of the next call miss its
