@@ -1111,7 +1111,7 @@ mrb_status do_rk4(mrb_ctx* c, double t, double dt) {
 }
 
 mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched = false, bool first_fused = false,
-                    bool second_folded = false);
+                    bool second_folded = false, bool first_tiled = false);
 mrb_ctx::Memo* spec_entry(mrb_ctx* c);
 
 // the speculated coarsening of the current grid merges every block (and writes its
@@ -1156,7 +1156,7 @@ mrb_status rk4_adapt_tiled(mrb_ctx* c, double t, double dt, bool* done, bool ref
   c->n_rk4++;
   c->n_block_updates += (long)nblk(c);
   *done = true;
-  return do_adapt(c, nullptr, true, fused, mothers);
+  return do_adapt(c, nullptr, true, fused, mothers, true);
 }
 
 // the step's refinement can be folded into the tile launch: the forest is on one level
@@ -1693,7 +1693,10 @@ mrb_status spec_finish(mrb_ctx* c, SpecSnap& sn, bool second_folded, int* npass)
   return MRB_OK;
 }
 
-mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fused, bool second_folded) {
+// first_tiled: the first pass ran inside the tile launch just made (its sub-tiles, if any,
+// left partial maxima for ana_combine)
+mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fused, bool second_folded,
+                    bool first_tiled) {
   mrb_status s;
   c->flag_set = 0;
   const size_t n1 = c->leaves.size();
@@ -1703,7 +1706,7 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fuse
   if (!first_launched && (s = launch_mr_kernel(c, false, fused ? e : nullptr))) return s;
   if (!e) {
     if ((s = wait_stream(c))) return s;
-    if (first_launched) ana_combine(c);
+    if (first_tiled) ana_combine(c);
     if ((s = take_flags(c, 0, n1))) return s;
     c->spec_flags = c->last_flags;
     for (int passes = 1;; ++passes) {
@@ -1727,7 +1730,7 @@ mrb_status do_adapt(mrb_ctx* c, int* npass, bool first_launched, bool first_fuse
     if (s) return s;
   }
   if ((s = wait_stream(c))) return s;
-  if (first_launched) ana_combine(c);
+  if (first_tiled) ana_combine(c);
   return spec_finish(c, sn, second_folded, npass);
 }
 

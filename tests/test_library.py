@@ -883,6 +883,31 @@ def test_queued_tile_steps_bs17_match_oracle(tpb):
 
 
 @pytest.mark.gpu
+def test_graph_steps_after_autotuning_match_oracle():
+    """Regression: the autotuner times the tile step's sub-tiled analyses, whose partial
+    maxima are combined by the host only after a tile launch of its own; graph-replayed
+    steps afterwards (their first analysis pass is the analysis kernel, which writes its
+    flags itself) must keep those flags: the run equals the oracle bit for bit."""
+    cfg = W.C2(form=W.FORM_FUSED)
+    s, o = _pair(cfg)
+    lv, co = o.read_forest()
+    data = o.read_blocks()
+    s.refine_all()
+    s.tune(reps=2)
+    s.init_forest(lv, co)
+    s.load_blocks(data)
+    s.set_graph(1)
+    t = 0.0
+    for _ in range(4):
+        s.step(t, cfg.dt)
+        o.step(t, cfg.dt)
+        t += cfg.dt
+    assert s.stats()["graph_launches"] >= 4
+    assert_same(s, o, "graph steps after autotuning")
+    s.close()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("sweep", [2, 3])
 def test_multi_step_call_after_a_perturbation_matches_oracle(sweep):
     """A perturbation between calls makes the first adapt of the next call miss its
