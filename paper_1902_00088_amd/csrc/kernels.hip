@@ -67,11 +67,19 @@ __device__ __forceinline__ T tensor_fixed(const AT& at, const int* base, const i
   return NZ == 4 ? P4(vz[0], vz[1], vz[2], vz[3]) : vz[0];
 }
 
+// p / d for 0 <= p < 2^21 and d >= 1, through the float reciprocal rd = fl(1/d):
+// (p + 1/2)/d lies at least 1/(2d) from an integer, and the two roundings (of 1/d and
+// of the product) move it by at most (p + 1/2)/d * 2^-23, less than that.  Index splits
+// by sizes known only at run time use it: an integer division costs tens of
+// instructions per point.
+__device__ __forceinline__ int fdiv(int p, float rd) { return (int)(((float)p + 0.5f) * rd); }
+
 // Nodes of [r0, r0+cnt) whose parity pattern is `cls` (bit a set: odd along axis a):
 // per-axis first coordinate and count, for a loop without divergence between classes.
 template <int DIM>
 struct ParityClass {
   int first[3], n[3], total;
+  float rn0, rn01;
   __device__ __forceinline__ ParityClass(int cls, const int* r0, const int* cnt) {
     total = 1;
     for (int a = 0; a < 3; ++a) { first[a] = 0; n[a] = 1; }
@@ -82,14 +90,19 @@ struct ParityClass {
       n[a] = first[a] <= last ? (last - first[a]) / 2 + 1 : 0;
       total *= n[a];
     }
+    // (an empty class runs no point, its reciprocals are unused)
+    rn0 = 1.0f / (float)n[0];
+    rn01 = 1.0f / (float)(n[0] * n[1]);
   }
   __device__ __forceinline__ void coords(int p, int* t) const {
-    t[0] = first[0] + 2 * (p % n[0]);
+    const int q0 = fdiv(p, rn0);  // p / n[0]
+    t[0] = first[0] + 2 * (p - q0 * n[0]);
     if (DIM > 2) {
-      t[1] = first[1] + 2 * ((p / n[0]) % n[1]);
-      t[2] = first[2] + 2 * (p / (n[0] * n[1]));
+      const int q1 = fdiv(p, rn01);  // p / (n[0] n[1])
+      t[1] = first[1] + 2 * (q0 - q1 * n[1]);
+      t[2] = first[2] + 2 * q1;
     } else {
-      t[1] = first[1] + 2 * (p / n[0]);
+      t[1] = first[1] + 2 * q0;
       t[2] = 0;
     }
   }
@@ -157,16 +170,18 @@ __device__ void gsetup(GState<DIM, S + 2 * H>& g, const BlockDesc& d, const NbEn
   for (int i = threadIdx.x; i < stride; i += blockDim.x) g.ent[i] = ent[i];
   const int ne = d.n_ent;
   __syncthreads();
-  for (int q = threadIdx.x; q < DIM * TW; q += blockDim.x) {
+  // one coordinate per wave and step: lane e tests entry e (at most 64 entries), the
+  // wave's ballot is the coordinate's mask
+  static_assert(kMaxEnt <= 64, "one entry per lane");
+  const int lane = threadIdx.x & 63;
+  const NbEntry E = g.ent[lane];
+  const bool live = lane < ne;
+  const int ext = E.dl > 0 ? (BS - 1) / 2 : (E.dl == 0 ? BS - 1 : 2 * (BS - 1));
+  for (int q = threadIdx.x >> 6; q < DIM * TW; q += blockDim.x >> 6) {
     const int a = q / TW, it = q % TW, t = r0[a] - H + it;
-    unsigned long long mm = 0;
-    for (int e = 0; e < ne; ++e) {
-      const int dl = g.ent[e].dl;
-      const int ext = dl > 0 ? (BS - 1) / 2 : (dl == 0 ? BS - 1 : 2 * (BS - 1));
-      const int l = t - g.ent[e].o[a];
-      if (l >= 0 && l <= ext && (dl >= 0 || (l & 1) == 0)) mm |= 1ull << e;
-    }
-    g.m[a][it] = mm;
+    const int l = t - (a == 0 ? E.o[0] : (a == 1 ? E.o[1] : E.o[DIM - 1]));
+    const unsigned long long mm = __ballot(live && l >= 0 && l <= ext && (E.dl >= 0 || (l & 1) == 0));
+    if (lane == 0) g.m[a][it] = mm;
   }
   __syncthreads();
 }
@@ -222,6 +237,8 @@ __device__ void gfill(TT* tile, const GState<DIM, S + 2 * H>& g, const int* r0, 
     }
   }
   const int total = nA + nB;
+  const float ra0 = 1.0f / (float)an[0], ra01 = 1.0f / (float)(an[0] * an[1]);
+  const float rb0 = 1.0f / (float)bn[0], rb01 = 1.0f / (float)(bn[0] * bn[1]);
   for (int base = 0; base < total; base += B * blockDim.x) {
     size_t addr[B];
     int pos[B];
@@ -233,21 +250,25 @@ __device__ void gfill(TT* tile, const GState<DIM, S + 2 * H>& g, const int* r0, 
       if (p >= total) continue;
       int t[3] = {0, 0, 0};
       if (p < nA) {
-        t[0] = a0[0] + p % an[0];
+        const int q0 = fdiv(p, ra0);
+        t[0] = a0[0] + p - q0 * an[0];
         if (DIM > 2) {
-          t[1] = a0[1] + (p / an[0]) % an[1];
-          t[2] = a0[2] + p / (an[0] * an[1]);
+          const int q1 = fdiv(p, ra01);
+          t[1] = a0[1] + q0 - q1 * an[1];
+          t[2] = a0[2] + q1;
         } else {
-          t[1] = a0[1] + p / an[0];
+          t[1] = a0[1] + q0;
         }
       } else {
         const int pb = p - nA;
-        t[0] = b0[0] + 2 * (pb % bn[0]);
+        const int q0 = fdiv(pb, rb0);
+        t[0] = b0[0] + 2 * (pb - q0 * bn[0]);
         if (DIM > 2) {
-          t[1] = b0[1] + 2 * ((pb / bn[0]) % bn[1]);
-          t[2] = b0[2] + 2 * (pb / (bn[0] * bn[1]));
+          const int q1 = fdiv(pb, rb01);
+          t[1] = b0[1] + 2 * (q0 - q1 * bn[1]);
+          t[2] = b0[2] + 2 * q1;
         } else {
-          t[1] = b0[1] + 2 * (pb / bn[0]);
+          t[1] = b0[1] + 2 * q0;
         }
         bool inA = true;
         for (int a = 0; a < DIM; ++a)
@@ -355,11 +376,11 @@ struct SGeo {
 };
 
 // Source address of a held point as base + sum_a f(t_a) BS^a, with f(t) = 2t for a
-// finer holder, t for a same-level one and t/2 for a coarser one (its points are even);
-// the holder's origin is folded into base.
+// finer holder, t for a same-level one and t/2 (floor) for a coarser one (its points are
+// even); f(t) = (2t) >> sh with sh = 1 - dl.  The holder's origin is folded into base.
 struct SEnt {
   int base;
-  int mode;   // 0 coarser, 1 same level, 2 finer
+  int sh;   // 2 coarser, 1 same level, 0 finer
 };
 
 template <int DIM, int BS, int NF>
@@ -367,18 +388,15 @@ __device__ __forceinline__ void sent_setup(SEnt* se, const NbEntry* ent, int ne)
   constexpr int NP = Pow<DIM, BS>::v;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
     const NbEntry E = ent[e];
-    const int mode = E.dl + 1;
+    const int sh = 1 - E.dl;
     int b = E.slot * NF * NP, mul = 1;
     for (int a = 0; a < DIM; ++a) {
-      const int o = E.o[a];
-      b -= (mode == 2 ? 2 * o : (mode == 1 ? o : (o >> 1))) * mul;
+      b -= ((2 * E.o[a]) >> sh) * mul;
       mul *= BS;
     }
-    se[e] = SEnt{b, mode};
+    se[e] = SEnt{b, sh};
   }
 }
-
-__device__ __forceinline__ int sf(int t, int mode) { return mode == 2 ? 2 * t : (mode == 1 ? t : (t >> 1)); }
 
 // Fill box A (and, for blocks with coarser neighbours, the coarse-lattice array).
 // Points strictly inside the block are the block's own; the others take their
@@ -433,7 +451,7 @@ __device__ void sgather(TT* tile, TT* carr, const GState<DIM, S + 2 * (HW + 3)>&
         continue;
       }
       const SEnt E = se[63 - __clzll((long long)cand)];
-      addr[q] = E.base + sf(tx, E.mode) + BS * sf(ty, E.mode) + (DIM > 2 ? BS * BS * sf(tz, E.mode) : 0);
+      addr[q] = E.base + ((2 * tx) >> E.sh) + BS * ((2 * ty) >> E.sh) + (DIM > 2 ? BS * BS * ((2 * tz) >> E.sh) : 0);
     }
     TT v[B][NF];
 #pragma unroll
@@ -478,7 +496,8 @@ __device__ void sgather(TT* tile, TT* carr, const GState<DIM, S + 2 * (HW + 3)>&
         if (DIM > 2) cand &= g.m[2][tcz - r0[2] + H];
         if (cand == 0) continue;
         const SEnt E = se[63 - __clzll((long long)cand)];
-        addr[q] = E.base + sf(tcx, E.mode) + BS * sf(tcy, E.mode) + (DIM > 2 ? BS * BS * sf(tcz, E.mode) : 0);
+        addr[q] = E.base + ((2 * tcx) >> E.sh) + BS * ((2 * tcy) >> E.sh) +
+                  (DIM > 2 ? BS * BS * ((2 * tcz) >> E.sh) : 0);
         cpos[q] = G::cidx(cxl, cy, cz);
       }
       TT v[B][NF];
@@ -663,8 +682,10 @@ __device__ void ns_fluxes(const double* T, CT* W, const int* cnt, const NsConst<
   const double* fv = T + 2 * TSZ;
   const double* fp = T + 3 * TSZ;
   const int nx = cnt[0] + 4, ny = cnt[1] + 4;
+  const float rnx = 1.0f / (float)nx;
   for (int p = threadIdx.x; p < nx * ny; p += blockDim.x) {
-    const int ux0 = p % nx - 2, uy0 = p / nx - 2;       // region-local position
+    const int qy = fdiv(p, rnx);
+    const int ux0 = p - qy * nx - 2, uy0 = qy - 2;       // region-local position
     const int x = ux0 + H, y = uy0 + H;                  // tile coordinates
     auto A = [&](const double* F, int xx, int yy) { return F[G::idx(xx, yy, 0)]; };
     auto Tt = [&](int xx, int yy) { return A(fp, xx, yy) / A(fr, xx, yy); };
@@ -799,8 +820,9 @@ __device__ __forceinline__ void stage_pass(const StageArgs& A, const StageVar& V
       if constexpr (sizeof(CT) == 8) K.r = A.lt.r[d.level];
       else K.r = A.lt.rf[d.level];
       ns_fluxes<BS, S, HW, CT>(tile, W, cnt, K);
+      const float rc0 = 1.0f / (float)cnt[0];
       for (int p = threadIdx.x; p < nn; p += blockDim.x) {
-        const int lx = p % cnt[0], ly = p / cnt[0];
+        const int ly = fdiv(p, rc0), lx = p - ly * cnt[0];
         CT kv[4];
         ns_rhs<BS, S, HW, CT>(tile, W, lx, ly, K, kv);
         const int node = (r0[0] + lx) + BS * (r0[1] + ly);
@@ -1181,8 +1203,10 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
         plo[a] = (r0[a] + cb[a] - E - 3) >> 1;
         pw[a] = ((r0[a] + cb[a] + cnt[a] - 1 + E + 3) >> 1) - plo[a] + 1;
       }
+      const float rpw = 1.0f / (float)pw[0];
       for (int p = tid; p < pw[0] * pw[1]; p += blockDim.x) {
-        const int px = plo[0] + p % pw[0], py = plo[1] + p / pw[0];
+        const int qy = fdiv(p, rpw);
+        const int px = plo[0] + p - qy * pw[0], py = plo[1] + qy;
         const int dx = px < 0 ? 0 : (px > BS - 1 ? 2 : 1), dy = py < 0 ? 0 : (py > BS - 1 ? 2 : 1);
         const int slot = own ? tab[dy * 3 + dx] : -1;
         const int lx = px - (dx - 1) * (BS - 1), ly = py - (dy - 1) * (BS - 1);
@@ -1207,8 +1231,10 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
         Ya[i] = stage_value(v);
       };
       auto row = [&](int X, int Y) { return P4(pt(X - 1, Y), pt(X, Y), pt(X + 1, Y), pt(X + 2, Y)); };
+      const float rnq = 1.0f / (float)nq[0];
       for (int p = tid; p < nq[0] * nq[1]; p += blockDim.x) {
-        const int X = x0[0] + p % nq[0], Y = x0[1] + p / nq[0];
+        const int qy = fdiv(p, rnq);
+        const int X = x0[0] + p - qy * nq[0], Y = x0[1] + qy;
         const bool ex = 2 * X >= qlo[0], ox = 2 * X + 1 <= qhi[0];
         const bool ey = 2 * Y >= qlo[1], oy = 2 * Y + 1 <= qhi[1];
         if (ex && ey) put(2 * X, 2 * Y, pt(X, Y));
@@ -1222,8 +1248,9 @@ __global__ void __launch_bounds__(TPB) k_rk4t(Rk4tArgs A) {
     } else {
       // u over the region + E
       const int nx = cnt[0] + 2 * E, ny = cnt[1] + 2 * E;
+      const float rnx = 1.0f / (float)nx;
       for (int p = tid; p < nx * ny; p += blockDim.x) {
-        const int ix = p % nx, iy = p / nx;
+        const int iy = fdiv(p, rnx), ix = p - iy * nx;
         const int tx = r0[0] - E + ix, ty = r0[1] - E + iy;
         const int dx = tx < 0 ? 0 : (tx > BS - 1 ? 2 : 1), dy = ty < 0 ? 0 : (ty > BS - 1 ? 2 : 1);
         const int slot = tab[dy * 3 + dx];
@@ -1594,8 +1621,10 @@ __global__ void __launch_bounds__(TPB) k_mr(MrArgs A) {
     const size_t base = (size_t)d.slot * NF * NP;
     const int nn = cnt[0] * cnt[1] * (DIM > 2 ? cnt[2] : 1);
     // redundant nodes owned by a finer neighbour: store the synchronised value
+    const float rc0 = 1.0f / (float)cnt[0], rc01 = 1.0f / (float)(cnt[0] * cnt[1]);
     for (int p = threadIdx.x; p < nn; p += blockDim.x) {
-      const int l[3] = {p % cnt[0], DIM > 2 ? (p / cnt[0]) % cnt[1] : p / cnt[0], DIM > 2 ? p / (cnt[0] * cnt[1]) : 0};
+      const int q0 = fdiv(p, rc0), q1 = DIM > 2 ? fdiv(p, rc01) : 0;
+      const int l[3] = {p - q0 * cnt[0], DIM > 2 ? q0 - q1 * cnt[1] : q0, q1};
       const int t[3] = {r0[0] + l[0], r0[1] + l[1], DIM > 2 ? r0[2] + l[2] : 0};
       bool bnd = false;
       unsigned long long cand = ~0ull;

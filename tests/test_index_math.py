@@ -5,7 +5,11 @@ a column with a float reciprocal of the row length n: row = trunc((q + 1/2) * fl
 all in IEEE single precision (correctly rounded reciprocal and product, truncating
 conversion).  The kernels assert at compile time that rows hold at most 64 points and
 that q stays below 4096; the first test checks every such pair against the integer
-quotient.  The second checks the reductions' 64-bit integer maximum of |detail| values.
+quotient.  The other index splits (parity classes, gathers, write-backs) divide by row
+and plane sizes known only at run time, with the same formula; the second test checks
+it for every divisor of a tile (rows and planes of up to 64 x 64 points) and indices
+below 2^14, and near the bound 2^21 the error analysis gives.  The third checks the
+reductions' 64-bit integer maximum of |detail| values.
 """
 import numpy as np
 
@@ -17,6 +21,24 @@ def test_float_row_split_is_exact_for_the_kernel_sizes():
         rn = np.float32(1.0) / np.float32(n)
         row = (qf * rn).astype(np.float32).astype(np.int64)   # float32 product, truncation
         assert np.array_equal(row, q // n), n
+
+
+def _fdiv(p, d):
+    pf = p.astype(np.float32) + np.float32(0.5)
+    return (pf * (np.float32(1.0) / np.float32(d))).astype(np.float32).astype(np.int64)
+
+
+def test_float_split_by_run_time_sizes_is_exact():
+    p = np.arange(1 << 14, dtype=np.int64)
+    for n0 in range(1, 65):
+        assert np.array_equal(_fdiv(p, n0), p // n0), n0
+        for n1 in range(1, 65):
+            d = n0 * n1
+            assert np.array_equal(_fdiv(p, d), p // d), (n0, n1)
+    # near the bound, for divisors up to 4096
+    top = np.arange((1 << 21) - 4096, 1 << 21, dtype=np.int64)
+    for d in range(1, 4097):
+        assert np.array_equal(_fdiv(top, d), top // d), d
 
 
 def test_unsigned_maximum_of_detail_magnitudes_propagates_nan():
