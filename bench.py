@@ -228,14 +228,24 @@ def _oracle_rate(oracle, cfg, budget_s):
 
 
 def cpu_model():
+    """The host CPU's model name, with its family, model and clock as /proc/cpuinfo gives them
+    (a virtual machine may shorten the name)."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                info.setdefault(k.strip(), v.strip())
     except OSError:
         pass
-    import platform
-    return platform.processor() or None
+    name = info.get("model name")
+    if not name:
+        import platform
+        return platform.processor() or None
+    extra = [f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info]
+    if "cpu MHz" in info:
+        extra.append(f"{float(info['cpu MHz']):.0f} MHz")
+    return name + (f" ({', '.join(extra)})" if extra else "")
 
 
 def cpu_baseline(W, cfg, budget_s):

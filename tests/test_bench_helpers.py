@@ -1,5 +1,5 @@
-"""Host-side pieces of bench.py (no GPU): the counter-summary lookup and the
-multi-GPU refusal."""
+"""Host-side pieces of bench.py (no GPU): the counter-summary lookup, the
+multi-GPU refusal and the CPU model of the baseline."""
 import hashlib
 import os
 import subprocess
@@ -68,3 +68,12 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_cpu_model_names_the_host_processor():
+    name = bench.cpu_model()
+    assert name is None or (isinstance(name, str) and name.strip())
+    if name and os.path.exists("/proc/cpuinfo"):
+        want = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")), None)
+        if want:
+            assert name.startswith(want)
