@@ -174,8 +174,8 @@ __device__ void gsetup(GState<DIM, S + 2 * H>& g, const BlockDesc& d, const NbEn
   // wave's ballot is the coordinate's mask
   static_assert(kMaxEnt <= 64, "one entry per lane");
   const int lane = threadIdx.x & 63;
-  const NbEntry E = g.ent[lane];
   const bool live = lane < ne;
+  const NbEntry E = live ? g.ent[lane] : NbEntry{};   // (lanes past the entries read nothing)
   const int ext = E.dl > 0 ? (BS - 1) / 2 : (E.dl == 0 ? BS - 1 : 2 * (BS - 1));
   for (int q = threadIdx.x >> 6; q < DIM * TW; q += blockDim.x >> 6) {
     const int a = q / TW, it = q % TW, t = r0[a] - H + it;
